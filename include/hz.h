@@ -1,0 +1,226 @@
+/*
+ * hz.h -- C-ABI of the nested polarized-traces Helmholtz solver for one AMD
+ * MI355X (gfx950).
+ *
+ * Method: L. Zepeda-Nunez and L. Demanet, "Nested domain decomposition with
+ * polarized traces for the 2D Helmholtz equation" (arXiv 1510.01831).
+ *
+ * Problem (Sec. 2, App. A).  -Laplace(u) - omega^2 m u = f on the unit square
+ * discretised by the 5-point stencil on n interior nodes per side
+ * (h = 1/(n+1)), truncated by a quadratic stretched-coordinate PML of n_pml
+ * nodes per side (sigma = (C/delta)(d/delta)^2, C = pml_beta * omega * delta,
+ * homogeneous Dirichlet beyond), with m = 1/c^2 extended into the PML by
+ * copying the nearest physical value.  Rows are scaled by 1/(alpha_x alpha_z)
+ * so the operator H is complex symmetric; inside the physical square the
+ * rows are exactly the paper's stencil.  A point source is f = 1/h^2 at a node
+ * (the discrete delta of Sec. 2.1).
+ *
+ * Method (Sec. 3-4).  The extended grid is cut into `layers` slabs in depth
+ * and each slab into `cells` in x; every cell is factorised (offline), every
+ * layer's Green's integrals are factorised through its cells (eq.
+ * factorization + block LU of the inner SIE, Sec. 4.2.2), and the polarized
+ * SIE on the layer interfaces is solved by GMRES preconditioned with the
+ * Gauss-Seidel sweeps (Sec. 3.1, Alg. 6).
+ *
+ * Conventions for every entry point.
+ *  - Arrays are row-major; a field on the physical grid is f[z][x] with z the
+ *    depth index (x fastest, Sec. 2.1 ordering).  A batch of B fields is
+ *    f[b][z][x], i.e. each right-hand side contiguous.
+ *  - Complex data are interleaved (re, im) pairs of double, i.e. the memory
+ *    layout of `double _Complex` / torch.complex128.
+ *  - Pointers named *_dev are device pointers (hipMalloc'd or torch CUDA
+ *    tensors); *_host are host pointers.  The caller owns every pointer it
+ *    passes; the library copies what it keeps.  The context owns all device
+ *    memory it allocates and frees it in hz_destroy.
+ *  - All device work is enqueued on the context's stream (default: the null
+ *    stream, see hz_set_stream).  Every call returns only after its work has
+ *    completed on that stream, unless stated otherwise.
+ *  - No call throws across the ABI.  Errors are returned as hz_status; the
+ *    text of the last error of the calling thread is in hz_last_error().
+ */
+#ifndef HZ_H
+#define HZ_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hz_ctx hz_ctx;
+
+typedef enum {
+    HZ_OK = 0,
+    HZ_EINVAL = -1,     /* bad argument: sizes, NaN / non-positive model, partition */
+    HZ_ENOMEM = -2,     /* device allocation failed */
+    HZ_ESTATE = -3,     /* call out of order (e.g. hz_solve before hz_factor) */
+    HZ_ENOCONV = -4,    /* some right-hand side missed tol within max_iter */
+    HZ_ESINGULAR = -5,  /* exactly zero pivot in a factorisation */
+    HZ_EDEVICE = -6     /* a HIP runtime error */
+} hz_status;
+
+typedef enum {
+    HZ_FP64 = 0,        /* everything in complex128 */
+    HZ_MIXED = 1        /* complex64 local operators as an approximate inverse,
+                           complex128 GMRES, residual and refinement */
+} hz_precision;
+
+typedef enum {
+    HZ_MODEL_VELOCITY = 0,   /* model array holds c */
+    HZ_MODEL_SLOWNESS2 = 1   /* model array holds m = 1/c^2 */
+} hz_model_kind;
+
+typedef struct {
+    int n_x, n_z;            /* physical nodes per side (must be equal) */
+    double h;                /* grid step; must equal 1/(n+1) (unit square) */
+    double omega;            /* angular frequency, > 0 */
+    int n_pml;               /* PML nodes per side, >= 0 */
+    double pml_beta;         /* sigma_max = pml_beta * omega at the Dirichlet node; <= 0 -> 2 */
+    int layers;              /* L: 1..n_z, each layer >= 2 rows */
+    int cells;               /* L_c: 1..n_x, each cell >= 2 columns */
+    hz_precision precision;
+    hz_model_kind model_kind;
+    int max_batch;           /* largest B accepted by hz_solve; <= 0 -> 1 */
+} hz_params;
+
+typedef struct {
+    int iters;               /* outer GMRES iterations (summed over refinement steps) */
+    double rel_resid;        /* final preconditioned relative residual of the SIE */
+    double vol_resid;        /* ||f - H u|| / ||f|| on the extended grid (FP64) */
+    int refine_steps;        /* HZ_MIXED: refinement steps; HZ_FP64: 0 */
+} hz_rhs_stats;
+
+typedef struct {
+    double t_setup, t_factor;          /* seconds, last hz_setup / hz_factor */
+    double t_rhs, t_gmres, t_recon;    /* seconds, last hz_solve, by phase */
+    double t_solve;                    /* seconds, whole last hz_solve */
+    int gmres_iters;                   /* max over the batch, last hz_solve */
+} hz_timing;
+
+typedef struct {
+    int n, n_pml, W;                   /* W = n + 2 n_pml, the trace width */
+    int layers, cells;
+    int trace_len;                     /* 4 (L-1) W: length of a polarized vector */
+    int max_batch;
+    long long device_bytes;            /* device memory held by the context */
+} hz_info_t;
+
+/* ---- life cycle ------------------------------------------------------- */
+
+/* Validate prm and the model (n_z x n_x doubles on the device: c or m per
+ * prm->model_kind; NaN or <= 0 -> HZ_EINVAL), copy the model, build the
+ * coefficients of the global, layer and cell grids (App. A, Fig. 1 and 5).
+ * *out receives a new context; on error *out is NULL. */
+hz_status hz_setup(const double* model_dev, const hz_params* prm, hz_ctx** out);
+
+/* Offline stage (Sec. 4.3.1, Table 2 rows 1-2): factor every cell
+ * (block-tridiagonal Schur recursion along x with explicitly inverted
+ * diagonal blocks), precompute every cell's interface operators (eq.
+ * factorization: M_f, M_u and the cell-local term) and factor every layer's
+ * inner SIE by block LU without pivoting (Sec. 4.2.2).  HZ_ESINGULAR on an
+ * exactly zero pivot.  May be called again after hz_update_model. */
+hz_status hz_factor(hz_ctx* ctx);
+
+/* Online stage (Alg. 6): solve H u = f for B right-hand sides.
+ * rhs_dev: B x n_z x n_x complex128 (physical grid, zero-extended into the
+ * PML); u_dev: B x n_z x n_x complex128 output (may not alias rhs_dev).
+ * tol: relative tolerance of the preconditioned SIE residual per RHS
+ * (HZ_FP64), or target of the relative refinement update (HZ_MIXED).
+ * max_iter: GMRES iterations per solve (also the Krylov dimension).
+ * stats_host: B entries or NULL.  timing: or NULL.
+ * HZ_ENOCONV: u_dev holds the last iterate; stats say which RHS failed. */
+hz_status hz_solve(hz_ctx* ctx, const void* rhs_dev, int B, void* u_dev,
+                   double tol, int max_iter, hz_rhs_stats* stats_host,
+                   hz_timing* timing);
+
+/* Adjoint solve H^H lam = rhs (same layout and semantics as hz_solve).  H is
+ * complex symmetric, so this is conj(H^{-1} conj(rhs)) on the same factors. */
+hz_status hz_adjoint(hz_ctx* ctx, const void* rhs_dev, int B, void* lam_dev,
+                     double tol, int max_iter, hz_rhs_stats* stats_host);
+
+/* Same as hz_solve / hz_adjoint, but the output holds the whole extended
+ * grid: B x W x W complex128 with W = n + 2 n_pml (PML nodes included). */
+hz_status hz_solve_ext(hz_ctx* ctx, const void* rhs_dev, int B, void* u_ext_dev,
+                       double tol, int max_iter, hz_rhs_stats* stats_host,
+                       hz_timing* timing);
+hz_status hz_adjoint_ext(hz_ctx* ctx, const void* rhs_dev, int B, void* lam_ext_dev,
+                         double tol, int max_iter, hz_rhs_stats* stats_host);
+
+/* Adjoint-state gradient of J = 1/2 sum_b ||P u_b - d_b||^2 with respect to
+ * m on the physical grid (derived from H's dependence on m, the diagonal term
+ * -omega^2 m / (alpha_x alpha_z)):
+ *   g[k] = omega^2 Re sum_b sum_{e -> k} w_e u_b[e] conj(lam_b[e]),
+ * with w = 1/(alpha_x alpha_z), e running over the extended nodes whose m
+ * copies physical node k (PML nodes fold onto the edge nodes they copy),
+ * u_b the forward fields and lam_b the adjoint fields
+ * H^H lam_b = P^T (P u_b - d_b), both B x W x W complex128 on the extended
+ * grid (from hz_solve_ext / hz_adjoint_ext).  g_dev: n_z x n_x double,
+ * overwritten.  Needs state "set up" or later. */
+hz_status hz_misfit_gradient(hz_ctx* ctx, const void* u_ext_dev, const void* lam_ext_dev,
+                             int B, double* g_dev);
+
+/* Least-squares data misfit for receivers on every physical node of depth
+ * row rec_row (1-based): r_b = P u_b - d_b, J = 1/2 sum_b ||r_b||^2.
+ * u_ext_dev: B x W x W complex128 (from hz_solve_ext); d_obs_dev: B x n_x
+ * complex128; adj_src_dev: B x n_z x n_x complex128, overwritten with the
+ * adjoint source P^T r_b (zero off the receiver row); *J_host receives J. */
+hz_status hz_misfit(hz_ctx* ctx, const void* u_ext_dev, const void* d_obs_dev, int rec_row,
+                    int B, void* adj_src_dev, double* J_host);
+
+/* Replace the model (same size and kind) and rebuild the coefficients; the
+ * context returns to the "set up" state (hz_factor must be called again). */
+hz_status hz_update_model(hz_ctx* ctx, const double* model_dev);
+
+/* Enqueue all further work of ctx on `hip_stream` (a hipStream_t, or NULL for
+ * the null stream). */
+hz_status hz_set_stream(hz_ctx* ctx, void* hip_stream);
+
+hz_status hz_get_info(const hz_ctx* ctx, hz_info_t* info);
+hz_status hz_get_timing(const hz_ctx* ctx, hz_timing* timing);
+
+void hz_destroy(hz_ctx* ctx);
+const char* hz_strerror(hz_status s);
+const char* hz_last_error(void);
+
+/* ---- building blocks, exposed for parity tests ----------------------------
+ * These run single steps of the online path on the factors of a context in
+ * state "factored".  Polarized vectors use the layout
+ *   x[i][b], i in [0, 4 (L-1) W): (d_0, ..., d_{L-2}, q_0, ..., q_{L-2}),
+ * each d_k / q_k a pair (trace on row a, trace on row b) of length 2W;
+ * interface k lies between layers k and k+1 (0-based), row a is the last row
+ * of layer k and row b the first row of layer k+1.  B is the fastest index. */
+
+/* R_side (H^l)^{-1}[T_l(top) + B_l(bot)]: layer l's Green's integrals
+ * applied to a top pair and a bottom pair (App. C equivalent sources),
+ * sampled on the top rows (side = 0: local rows 0, 1) or bottom rows
+ * (side = 1: local rows n_l, n_l + 1).  top/bot/out: [2][W][B] complex128;
+ * top or bot may be NULL (absent). */
+hz_status hz_apply_layer(hz_ctx* ctx, int layer, const void* top_dev,
+                         const void* bot_dev, int side, void* out_dev, int B);
+
+/* y = M x, the polarized SIE matrix (eq. M_polarized, jump conditions). */
+hz_status hz_apply_sie(hz_ctx* ctx, const void* x_dev, void* y_dev, int B);
+
+/* y = P^GS x, the Gauss-Seidel preconditioner (eq. preconditioner_GS):
+ * downward sweep, up-going reflections, upward sweep. */
+hz_status hz_apply_precond(hz_ctx* ctx, const void* x_dev, void* y_dev, int B);
+
+/* Right-hand side of the polarized system (Alg. 6 lines 2-7) for the B
+ * sources rhs_dev (B x n_z x n_x): y = (R_bot N^k f ; R_top N^{k+1} f). */
+hz_status hz_sie_rhs(hz_ctx* ctx, const void* rhs_dev, void* y_dev, int B);
+
+/* (H^{l,c})^{-1} g on the full grid of cell c of layer l.  g, x:
+ * [HL][Wc][B] complex128, HL = rows of the layer grid, Wc = columns of the
+ * cell grid (cell-local, artificial PML included). */
+hz_status hz_cell_solve(hz_ctx* ctx, int layer, int cell, const void* g_dev,
+                        void* x_dev, int B);
+
+/* Grid sizes of layer l / cell c: *HL, *Wc. */
+hz_status hz_cell_shape(const hz_ctx* ctx, int layer, int cell, int* HL, int* Wc);
+
+/* r = f - H u on the extended grid (W x W per RHS), complex128, [b][z][x]. */
+hz_status hz_residual(hz_ctx* ctx, const void* u_ext_dev, const void* f_ext_dev,
+                      void* r_ext_dev, int B);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HZ_H */

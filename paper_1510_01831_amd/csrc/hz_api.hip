@@ -1,0 +1,1793 @@
+// Host orchestration of the nested polarized-traces solver behind the C-ABI
+// of include/hz.h.
+//
+//  hz_setup   -- partitions (layers, cells, Sec. 4 / Fig. 5), coefficients (App. A)
+//  hz_factor  -- cell Schur factors, cell Green's-function probes giving the
+//                interface operators of eq. factorization, inner block LU
+//                (Sec. 4.2.2)
+//  hz_solve   -- Alg. 6: RHS formation (Alg. 7 volume mode in the layers that
+//                hold sources), GMRES on P^GS M (Sec. 3.1), reconstruction
+//                (Alg. 7 volume mode in every layer); HZ_MIXED wraps it in an
+//                FP64 iterative refinement on the volume.
+//
+// Every dense operator application is a list of GemmTask records executed by
+// the segmented GEMM kernels; the lists of the GMRES operators (M and P^GS)
+// are built once per batch size ("plans") and replayed.
+#include "hz.h"
+#include "hz_common.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+using namespace hz;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct HzError {
+    hz_status s;
+    std::string msg;
+};
+
+[[noreturn]] void raise(hz_status s, const std::string& m) { throw HzError{s, m}; }
+
+#define HIPCHK(x)                                                                        \
+    do {                                                                                 \
+        hipError_t e_ = (x);                                                             \
+        if (e_ != hipSuccess)                                                            \
+            raise(HZ_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_) + " (line " + \
+                                  std::to_string(__LINE__) + ")");                       \
+    } while (0)
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// device allocations owned by a context
+struct Arena {
+    std::vector<void*> ptrs;
+    long long bytes = 0;
+    void* alloc(size_t n) {
+        if (n == 0) n = 16;
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            raise(HZ_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
+        }
+        ptrs.push_back(p);
+        bytes += (long long)n;
+        return p;
+    }
+    void release(void* p, size_t n) {
+        if (!p) return;
+        auto it = std::find(ptrs.begin(), ptrs.end(), p);
+        if (it != ptrs.end()) {
+            ptrs.erase(it);
+            (void)hipFree(p);
+            bytes -= (long long)n;
+        }
+    }
+    void free_all() {
+        for (void* p : ptrs) (void)hipFree(p);
+        ptrs.clear();
+        bytes = 0;
+    }
+};
+
+template <typename T>
+struct Ops {                       // factors and interface operators in precision T
+    C2<T>* X = nullptr;
+    C2<T>* e = nullptr;
+    C2<T>* Q = nullptr;
+    C2<T>* CS = nullptr;
+    C2<T>* Sinv = nullptr;
+    C2<T>* Lfac = nullptr;
+};
+
+enum LaunchKind { L_GEMM = 0, L_AXPBY = 1, L_COPY = 2 };
+
+template <typename T>
+struct LaunchRec {
+    int kind;
+    long long off;        // first task
+    int ntasks, max_m;
+    C2<T>* y; const C2<T>* x; double2 a, b; long long n;   // vector ops
+};
+
+template <typename T>
+struct Plan {
+    GemmTask<T>* dev = nullptr;
+    size_t dev_bytes = 0;
+    std::vector<GemmTask<T>> tasks;
+    std::vector<LaunchRec<T>> launches;
+};
+
+template <typename T>
+struct LayerJob {
+    int layer = 0;
+    const C2<T>* top = nullptr;
+    const C2<T>* bot = nullptr;
+    const C2<T>* inner_add = nullptr;
+    C2<T>* iy = nullptr;
+    C2<T>* ix = nullptr;
+    int side = 1;
+    C2<T>* out = nullptr;
+    const C2<T>* add0 = nullptr;
+    const C2<T>* add1 = nullptr;
+    int add1_row = 0;
+    T c1 = 0;
+    T alpha = 1;
+    bool use_x = true;
+    bool phase3 = true;
+};
+
+template <typename T>
+struct Work {
+    int Bcap = 0;
+    C2<T>* f_ext = nullptr;    // [W][W][B]
+    C2<T>* u_ext = nullptr;    // [W][W][B]
+    C2<T>* rows_out = nullptr; // [L][4][W][B]
+    C2<T>* gf = nullptr;       // [L][J][2][HLmax][B]
+    C2<T>* iy[2] = {nullptr, nullptr};
+    C2<T>* ix[2] = {nullptr, nullptr};
+    C2<T>* pA = nullptr;       // polarized vectors [4KW][B]
+    C2<T>* pB = nullptr;
+    C2<T>* pC = nullptr;
+    C2<T>* sv = nullptr;       // s = d + q, [K][2W][B]
+    C2<T>* Y = nullptr;        // forward-sweep scratch of the cell solves
+    long long y_stride = 0;
+    int y_wgs = 0;
+    const C2<T>** pair_tab = nullptr;   // device [2L]: top pairs then bottom pairs
+    std::map<int, std::unique_ptr<Plan<T>>> sie, pre;
+};
+
+}  // namespace
+
+struct hz_ctx {
+    hz_params prm{};
+    Dims d{};
+    int state = 0;                 // 1 set up, 2 factored
+    hipStream_t st = nullptr;
+    Arena arena;
+    std::vector<LayerDesc> layers;
+    std::vector<CellDesc> cells;
+    LayerDesc* d_layers = nullptr;
+    CellDesc* d_cells = nullptr;
+    double* model = nullptr;
+    double2 *diag = nullptr, *cz = nullptr, *e = nullptr;
+    double2 *ax_pool = nullptr, *az_pool = nullptr;
+    double2 *gdiag = nullptr, *gcx = nullptr, *gcz = nullptr, *wext = nullptr;
+    int* flags = nullptr;          // [0] bad model, [1] singular
+    int* layer_active = nullptr;   // [L]
+    long long coef_elems = 0, X_elems = 0, Q_elems = 0, CS_elems = 0, Sinv_elems = 0, Lfac_elems = 0;
+    long long inner_per_layer = 0; // J * 2 * HLmax
+    Ops<double> o64;
+    Ops<float> o32;
+    Work<double> w64;
+    Work<float> w32;
+    // FP64 GMRES / refinement workspace
+    int g_cap_B = 0, g_cap_m = 0;
+    double2 *V = nullptr, *gw = nullptr, *gb = nullptr, *gx = nullptr, *gpart = nullptr,
+            *gsmall = nullptr, *gcoef = nullptr;
+    int gpart_chunks = 0;
+    double2 *u64 = nullptr, *f64 = nullptr, *r64 = nullptr;   // refinement [W][W][B]
+    hz_timing timing{};
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// small helpers
+
+template <typename T> Ops<T>& ops(hz_ctx* c);
+template <> Ops<double>& ops<double>(hz_ctx* c) { return c->o64; }
+template <> Ops<float>& ops<float>(hz_ctx* c) { return c->o32; }
+template <typename T> Work<T>& work(hz_ctx* c);
+template <> Work<double>& work<double>(hz_ctx* c) { return c->w64; }
+template <> Work<float>& work<float>(hz_ctx* c) { return c->w32; }
+
+template <typename T>
+C2<T>* alloc_c(hz_ctx* c, long long n) {
+    return (C2<T>*)c->arena.alloc((size_t)n * sizeof(C2<T>));
+}
+
+std::vector<std::pair<int, int>> partition(int n, int parts) {
+    std::vector<std::pair<int, int>> out;
+    int base = n / parts, extra = n % parts, start = 1;
+    for (int k = 0; k < parts; ++k) {
+        int size = base + (k < extra ? 1 : 0);
+        out.push_back({start, start + size - 1});
+        start += size;
+    }
+    return out;
+}
+
+// ---------------------------------------------------------------------------
+// partitions and descriptors
+
+void build_descriptors(hz_ctx* c) {
+    const Dims& d = c->d;
+    const int p = d.p;
+    auto lparts = partition(d.n, d.L);
+    auto cparts = partition(d.n, d.Lc);
+    c->layers.clear();
+    c->cells.clear();
+    int HLmax = 0, Wcmax = 0;
+    for (auto& lp : lparts) HLmax = std::max(HLmax, lp.second - lp.first + 1 + 2 * p);
+    for (auto& cp : cparts) Wcmax = std::max(Wcmax, cp.second - cp.first + 1 + 2 * p);
+    c->d.HLmax = HLmax;
+    c->d.Wcmax = Wcmax;
+    const int J = d.Lc - 1;
+    c->inner_per_layer = (long long)J * 2 * HLmax;
+    long long off_coef = 0, off_X = 0, off_Q = 0, off_CS = 0, off_Sinv = 0, off_Lfac = 0;
+    for (int l = 0; l < d.L; ++l) {
+        LayerDesc ld{};
+        ld.index = l;
+        ld.first = lparts[l].first;
+        ld.last = lparts[l].second;
+        ld.nl = ld.last - ld.first + 1;
+        ld.HL = ld.nl + 2 * p;
+        ld.row0 = ld.first - 1;
+        ld.own_r0 = (l == 0) ? 0 : p;
+        ld.own_r1 = (l == d.L - 1) ? ld.HL - 1 : p + ld.nl - 1;
+        ld.has_top = l > 0;
+        ld.has_bot = l < d.L - 1;
+        ld.nslot = 0;
+        for (int s = 0; s < MAXSLOT; ++s) { ld.slot_of[s] = -1; ld.slot_row[s] = -1; ld.slot_id[s] = -1; }
+        auto add_slot = [&](int lid, int row) {
+            ld.slot_of[lid] = ld.nslot;
+            ld.slot_row[ld.nslot] = row;
+            ld.slot_id[ld.nslot] = lid;
+            ld.nslot++;
+        };
+        if (ld.has_top) { add_slot(0, p - 1); add_slot(1, p); }
+        if (ld.has_bot) { add_slot(2, p + ld.nl - 1); add_slot(3, p + ld.nl); }
+        ld.cell_begin = l * d.Lc;
+        ld.J = J;
+        ld.off_Sinv = off_Sinv;
+        off_Sinv += (long long)J * (2LL * ld.HL) * (2LL * ld.HL);
+        ld.off_Lfac = off_Lfac;
+        off_Lfac += (long long)std::max(J - 1, 0) * ld.HL * (2LL * ld.HL);
+        ld.off_inner = (long long)l * c->inner_per_layer;
+        c->layers.push_back(ld);
+        for (int k = 0; k < d.Lc; ++k) {
+            CellDesc cd{};
+            cd.layer = l;
+            cd.cell = k;
+            cd.gidx = l * d.Lc + k;
+            cd.HL = ld.HL;
+            cd.first = cparts[k].first;
+            cd.nc = cparts[k].second - cparts[k].first + 1;
+            cd.Wc = cd.nc + 2 * p;
+            cd.col0 = cd.first - 1;
+            cd.own_c0 = (k == 0) ? 0 : p;
+            cd.own_c1 = (k == d.Lc - 1) ? cd.Wc - 1 : p + cd.nc - 1;
+            cd.s = cd.own_c1 - cd.own_c0 + 1;
+            cd.has_left = k > 0;
+            cd.has_right = k < d.Lc - 1;
+            cd.adj = cd.has_left + cd.has_right;
+            cd.nslot = ld.nslot;
+            cd.ncol = cd.adj * 2 * cd.HL;
+            cd.R = cd.ncol + cd.nslot * cd.s;
+            cd.off_coef = off_coef;
+            off_coef += (long long)cd.Wc * cd.HL;
+            cd.off_X = off_X;
+            off_X += (long long)cd.Wc * cd.HL * cd.HL;
+            cd.off_Q = off_Q;
+            off_Q += (long long)cd.nslot * cd.s * cd.R;
+            cd.off_CS = off_CS;
+            off_CS += (long long)cd.adj * cd.HL * cd.R;
+            c->cells.push_back(cd);
+        }
+    }
+    c->coef_elems = off_coef;
+    c->X_elems = off_X;
+    c->Q_elems = off_Q;
+    c->CS_elems = off_CS;
+    c->Sinv_elems = off_Sinv;
+    c->Lfac_elems = off_Lfac;
+}
+
+void sync(hz_ctx* c) { HIPCHK(hipStreamSynchronize(c->st)); }
+
+void upload(hz_ctx* c, void* dst, const void* src, size_t bytes) {
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->st));
+    sync(c);
+}
+
+// ---------------------------------------------------------------------------
+// GEMM plans for layer jobs (design: phases M_f -> inner LU -> [M_u | D_loc])
+
+template <typename T>
+GemmTask<T> blank_task() {
+    GemmTask<T> t;
+    std::memset(&t, 0, sizeof(t));
+    t.alpha = (T)1;
+    return t;
+}
+
+template <typename T>
+const C2<T>* pair_row(const C2<T>* pair, int row, int col, int W, int B) {
+    return pair ? pair + ((long long)row * W + col) * B : nullptr;
+}
+
+template <typename T>
+void add_launch(Plan<T>& pl, long long first, int maxm) {
+    LaunchRec<T> r{};
+    r.kind = L_GEMM;
+    r.off = first;
+    r.ntasks = (int)(pl.tasks.size() - first);
+    r.max_m = maxm;
+    if (r.ntasks > 0) pl.launches.push_back(r);
+}
+
+template <typename T>
+void add_vec(Plan<T>& pl, int kind, C2<T>* y, const C2<T>* x, double2 a, double2 b, long long n) {
+    LaunchRec<T> r{};
+    r.kind = kind;
+    r.y = y; r.x = x; r.a = a; r.b = b; r.n = n;
+    pl.launches.push_back(r);
+}
+
+// Append the three phases of a set of independent layer jobs to a plan.
+template <typename T>
+void plan_jobs(hz_ctx* c, Plan<T>& pl, const std::vector<LayerJob<T>>& jobs, int B) {
+    const Dims& d = c->d;
+    const int W = d.W;
+    const int J = d.Lc - 1;
+    Ops<T>& o = ops<T>(c);
+    // ---- phase 1: inner right-hand sides from the interface-row sources
+    if (J > 0) {
+        long long first = pl.tasks.size();
+        int maxm = 0;
+        for (const auto& jb : jobs) {
+            const LayerDesc& ld = c->layers[jb.layer];
+            for (int k = 0; k < d.Lc; ++k) {
+                const CellDesc& cd = c->cells[ld.cell_begin + k];
+                GemmTask<T> t = blank_task<T>();
+                t.A = o.CS + cd.off_CS + cd.ncol;
+                t.lda = cd.R;
+                t.m = cd.adj * cd.HL;
+                t.k = cd.nslot * cd.s;
+                t.ldx = B;
+                t.ldo = B;
+                t.nseg = 0;
+                for (int si = 0; si < ld.nslot; ++si) {
+                    const int lid = ld.slot_id[si];
+                    const C2<T>* pr = lid < 2 ? jb.top : jb.bot;
+                    t.seg_k0[t.nseg] = si * cd.s;
+                    t.seg_len[t.nseg] = cd.s;
+                    t.seg_ptr[t.nseg] = pair_row<T>(pr, lid % 2, cd.col0 + cd.own_c0, W, B);
+                    t.nseg++;
+                }
+                t.noseg = 0;
+                const long long HLB = (long long)cd.HL * B;
+                if (cd.has_left) {
+                    const long long off = ((long long)(k - 1) * 2 + 1) * HLB;
+                    t.oseg_i0[t.noseg] = 0;
+                    t.oseg_len[t.noseg] = cd.HL;
+                    t.oseg_ptr[t.noseg] = jb.iy + off;
+                    t.oseg_add0[t.noseg] = jb.inner_add ? jb.inner_add + off : nullptr;
+                    t.noseg++;
+                }
+                if (cd.has_right) {
+                    const long long off = ((long long)k * 2 + 0) * HLB;
+                    t.oseg_i0[t.noseg] = cd.has_left ? cd.HL : 0;
+                    t.oseg_len[t.noseg] = cd.HL;
+                    t.oseg_ptr[t.noseg] = jb.iy + off;
+                    t.oseg_add0[t.noseg] = jb.inner_add ? jb.inner_add + off : nullptr;
+                    t.noseg++;
+                }
+                maxm = std::max(maxm, t.m);
+                pl.tasks.push_back(t);
+            }
+        }
+        add_launch(pl, first, maxm);
+        // ---- phase 2: block LU substitutions across the cells (inner sweeps)
+        for (int j = 1; j < J; ++j) {                       // forward
+            long long f2 = pl.tasks.size();
+            int mm = 0;
+            for (const auto& jb : jobs) {
+                const LayerDesc& ld = c->layers[jb.layer];
+                const int HL = ld.HL;
+                const long long blk = 2LL * HL * B;
+                GemmTask<T> t = blank_task<T>();
+                t.A = o.Lfac + ld.off_Lfac + (long long)(j - 1) * HL * 2 * HL;
+                t.lda = 2 * HL;
+                t.m = HL;
+                t.k = 2 * HL;
+                t.ldx = B; t.ldo = B;
+                t.nseg = 1;
+                t.seg_k0[0] = 0; t.seg_len[0] = 2 * HL; t.seg_ptr[0] = jb.iy + (j - 1) * blk;
+                t.noseg = 1;
+                t.oseg_i0[0] = 0; t.oseg_len[0] = HL; t.oseg_ptr[0] = jb.iy + j * blk;
+                t.oseg_add0[0] = jb.iy + j * blk;
+                t.alpha = (T)-1;
+                mm = std::max(mm, t.m);
+                pl.tasks.push_back(t);
+            }
+            add_launch(pl, f2, mm);
+        }
+        for (int j = J - 1; j >= 0; --j) {                  // backward
+            if (j < J - 1) {
+                long long f2 = pl.tasks.size();
+                int mm = 0;
+                for (const auto& jb : jobs) {
+                    const LayerDesc& ld = c->layers[jb.layer];
+                    const int HL = ld.HL;
+                    const long long blk = 2LL * HL * B;
+                    const CellDesc& cn = c->cells[ld.cell_begin + j + 1];   // cell right of iface j
+                    GemmTask<T> t = blank_task<T>();
+                    // y_j.b - C_j x_{j+1},  C_j = -(left-column samples of cell j+1, right probes)
+                    t.A = o.CS + cn.off_CS + 2LL * HL;      // left rows, right probes
+                    t.lda = cn.R;
+                    t.m = HL;
+                    t.k = 2 * HL;
+                    t.ldx = B; t.ldo = B;
+                    t.nseg = 1;
+                    t.seg_k0[0] = 0; t.seg_len[0] = 2 * HL; t.seg_ptr[0] = jb.ix + (j + 1) * blk;
+                    t.noseg = 1;
+                    t.oseg_i0[0] = 0; t.oseg_len[0] = HL;
+                    t.oseg_ptr[0] = jb.iy + j * blk + (long long)HL * B;
+                    t.oseg_add0[0] = jb.iy + j * blk + (long long)HL * B;
+                    t.alpha = (T)1;
+                    mm = std::max(mm, t.m);
+                    pl.tasks.push_back(t);
+                }
+                add_launch(pl, f2, mm);
+            }
+            long long f2 = pl.tasks.size();
+            int mm = 0;
+            for (const auto& jb : jobs) {
+                const LayerDesc& ld = c->layers[jb.layer];
+                const int HL = ld.HL;
+                const long long blk = 2LL * HL * B;
+                GemmTask<T> t = blank_task<T>();
+                t.A = o.Sinv + ld.off_Sinv + (long long)j * 4 * HL * HL;
+                t.lda = 2 * HL;
+                t.m = 2 * HL;
+                t.k = 2 * HL;
+                t.ldx = B; t.ldo = B;
+                t.nseg = 1;
+                t.seg_k0[0] = 0; t.seg_len[0] = 2 * HL; t.seg_ptr[0] = jb.iy + j * blk;
+                t.noseg = 1;
+                t.oseg_i0[0] = 0; t.oseg_len[0] = 2 * HL; t.oseg_ptr[0] = jb.ix + j * blk;
+                mm = std::max(mm, t.m);
+                pl.tasks.push_back(t);
+            }
+            add_launch(pl, f2, mm);
+        }
+    }
+    // ---- phase 3: samples on the requested interface rows
+    long long first = pl.tasks.size();
+    int maxm = 0;
+    for (const auto& jb : jobs) {
+        if (!jb.phase3) continue;
+        const LayerDesc& ld = c->layers[jb.layer];
+        const int so_a = ld.slot_of[jb.side == 0 ? 0 : 2];
+        if (so_a < 0) raise(HZ_EINVAL, "layer has no interface on the requested side");
+        for (int k = 0; k < d.Lc; ++k) {
+            const CellDesc& cd = c->cells[ld.cell_begin + k];
+            GemmTask<T> t = blank_task<T>();
+            t.A = o.Q + cd.off_Q + (long long)so_a * cd.s * cd.R;
+            t.lda = cd.R;
+            t.m = 2 * cd.s;
+            t.k = cd.R;
+            t.ldx = B; t.ldo = B;
+            t.nseg = 0;
+            const long long HLB = (long long)cd.HL * B;
+            if (cd.has_left) {
+                t.seg_k0[t.nseg] = 0;
+                t.seg_len[t.nseg] = 2 * cd.HL;
+                t.seg_ptr[t.nseg] = jb.ix + (long long)(k - 1) * 2 * HLB;
+                t.nseg++;
+            }
+            if (cd.has_right) {
+                t.seg_k0[t.nseg] = cd.has_left ? 2 * cd.HL : 0;
+                t.seg_len[t.nseg] = 2 * cd.HL;
+                t.seg_ptr[t.nseg] = jb.ix + (long long)k * 2 * HLB;
+                t.nseg++;
+            }
+            if (jb.use_x) {
+                for (int si = 0; si < ld.nslot; ++si) {
+                    const int lid = ld.slot_id[si];
+                    const C2<T>* pr = lid < 2 ? jb.top : jb.bot;
+                    t.seg_k0[t.nseg] = cd.ncol + si * cd.s;
+                    t.seg_len[t.nseg] = cd.s;
+                    t.seg_ptr[t.nseg] = pair_row<T>(pr, lid % 2, cd.col0 + cd.own_c0, W, B);
+                    t.nseg++;
+                }
+            }
+            t.noseg = 2;
+            for (int r = 0; r < 2; ++r) {
+                const long long off = ((long long)r * W + cd.col0 + cd.own_c0) * B;
+                t.oseg_i0[r] = r * cd.s;
+                t.oseg_len[r] = cd.s;
+                t.oseg_ptr[r] = jb.out + off;
+                t.oseg_add0[r] = jb.add0 ? jb.add0 + off : nullptr;
+                t.oseg_add1[r] = (jb.add1 && jb.add1_row == r) ? jb.add1 + off : nullptr;
+                t.c1[r] = jb.c1;
+            }
+            t.alpha = jb.alpha;
+            maxm = std::max(maxm, t.m);
+            pl.tasks.push_back(t);
+        }
+    }
+    add_launch(pl, first, maxm);
+}
+
+template <typename T>
+void plan_upload(hz_ctx* c, Plan<T>& pl) {
+    const size_t bytes = pl.tasks.size() * sizeof(GemmTask<T>);
+    if (bytes == 0) return;
+    if (pl.dev_bytes < bytes) {
+        if (pl.dev) c->arena.release(pl.dev, pl.dev_bytes);
+        pl.dev = (GemmTask<T>*)c->arena.alloc(bytes);
+        pl.dev_bytes = bytes;
+    }
+    upload(c, pl.dev, pl.tasks.data(), bytes);
+}
+
+template <typename T>
+void plan_run(hz_ctx* c, const Plan<T>& pl, int B) {
+    for (const auto& r : pl.launches) {
+        if (r.kind == L_GEMM) {
+            launch_gemm<T>(pl.dev + r.off, r.ntasks, r.max_m, B, c->st);
+        } else if (r.kind == L_AXPBY) {
+            launch_axpby<T>(r.y, r.x, r.a, r.b, r.n, c->st);
+        } else if (r.kind == L_COPY) {
+            HIPCHK(hipMemcpyAsync(r.y, r.x, (size_t)r.n * sizeof(C2<T>), hipMemcpyDeviceToDevice, c->st));
+        }
+    }
+    HIPCHK(hipGetLastError());
+}
+
+// polarized vector helpers: d_k / q_k pairs
+template <typename T>
+C2<T>* dvec(hz_ctx* c, C2<T>* v, int k, int B) { return v + (long long)k * 2 * c->d.W * B; }
+template <typename T>
+C2<T>* qvec(hz_ctx* c, C2<T>* v, int k, int B) { return v + (long long)(c->d.K + k) * 2 * c->d.W * B; }
+
+template <typename T>
+C2<T>* iy_of(hz_ctx* c, int set, int layer, int B) {
+    return work<T>(c).iy[set] + c->layers[layer].off_inner * B;
+}
+template <typename T>
+C2<T>* ix_of(hz_ctx* c, int set, int layer, int B) {
+    return work<T>(c).ix[set] + c->layers[layer].off_inner * B;
+}
+
+// M: pA -> pB (eq. M_polarized via the jump conditions)
+template <typename T>
+void build_sie_plan(hz_ctx* c, Plan<T>& pl, int B) {
+    Work<T>& w = work<T>(c);
+    const int K = c->d.K;
+    const long long pairn = 2LL * c->d.W * B;
+    const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
+    // s = d + q
+    add_vec<T>(pl, L_COPY, w.sv, w.pA, zero, zero, K * pairn);
+    add_vec<T>(pl, L_AXPBY, w.sv, qvec<T>(c, w.pA, 0, B), one, one, K * pairn);
+    std::vector<LayerJob<T>> jobs;
+    for (int k = 0; k < K; ++k) {
+        LayerJob<T> dn;
+        dn.layer = k;
+        dn.top = k > 0 ? w.sv + (k - 1) * pairn : nullptr;
+        dn.bot = qvec<T>(c, w.pA, k, B);
+        dn.iy = iy_of<T>(c, 0, k, B);
+        dn.ix = ix_of<T>(c, 0, k, B);
+        dn.side = 1;
+        dn.out = dvec<T>(c, w.pB, k, B);
+        dn.add0 = dvec<T>(c, w.pA, k, B);
+        dn.add1 = qvec<T>(c, w.pA, k, B);
+        dn.add1_row = 0;
+        dn.c1 = (T)1;
+        dn.alpha = (T)-1;
+        jobs.push_back(dn);
+        LayerJob<T> up;
+        up.layer = k + 1;
+        up.top = dvec<T>(c, w.pA, k, B);
+        up.bot = k + 1 < K ? w.sv + (k + 1) * pairn : nullptr;
+        up.iy = iy_of<T>(c, 1, k + 1, B);
+        up.ix = ix_of<T>(c, 1, k + 1, B);
+        up.side = 0;
+        up.out = qvec<T>(c, w.pB, k, B);
+        up.add0 = qvec<T>(c, w.pA, k, B);
+        up.add1 = dvec<T>(c, w.pA, k, B);
+        up.add1_row = 1;
+        up.c1 = (T)1;
+        up.alpha = (T)-1;
+        jobs.push_back(up);
+    }
+    plan_jobs<T>(c, pl, jobs, B);
+}
+
+// P^GS: pB -> pC (downward sweep, up-going reflections, upward sweep)
+template <typename T>
+void build_pre_plan(hz_ctx* c, Plan<T>& pl, int B) {
+    Work<T>& w = work<T>(c);
+    const int K = c->d.K;
+    const long long pairn = 2LL * c->d.W * B;
+    const double2 zero = make_double2(0.0, 0.0);
+    add_vec<T>(pl, L_COPY, dvec<T>(c, w.pC, 0, B), dvec<T>(c, w.pB, 0, B), zero, zero, pairn);
+    for (int k = 1; k < K; ++k) {                       // downward sweep (D_down^{-1})
+        LayerJob<T> jb;
+        jb.layer = k;
+        jb.top = dvec<T>(c, w.pC, k - 1, B);
+        jb.bot = nullptr;
+        jb.iy = iy_of<T>(c, 0, k, B);
+        jb.ix = ix_of<T>(c, 0, k, B);
+        jb.side = 1;
+        jb.out = dvec<T>(c, w.pC, k, B);
+        jb.add0 = dvec<T>(c, w.pB, k, B);
+        jb.alpha = (T)1;
+        plan_jobs<T>(c, pl, {jb}, B);
+    }
+    {                                                   // t = v_up - L x_down (parallel)
+        std::vector<LayerJob<T>> jobs;
+        for (int k = 0; k < K; ++k) {
+            LayerJob<T> jb;
+            jb.layer = k + 1;
+            jb.top = dvec<T>(c, w.pC, k, B);
+            jb.bot = k + 1 < K ? dvec<T>(c, w.pC, k + 1, B) : nullptr;
+            jb.iy = iy_of<T>(c, 0, k + 1, B);
+            jb.ix = ix_of<T>(c, 0, k + 1, B);
+            jb.side = 0;
+            jb.out = qvec<T>(c, w.pC, k, B);
+            jb.add0 = qvec<T>(c, w.pB, k, B);
+            jb.add1 = dvec<T>(c, w.pC, k, B);
+            jb.add1_row = 1;
+            jb.c1 = (T)-1;
+            jb.alpha = (T)1;
+            jobs.push_back(jb);
+        }
+        plan_jobs<T>(c, pl, jobs, B);
+    }
+    for (int k = K - 2; k >= 0; --k) {                  // upward sweep (D_up^{-1})
+        LayerJob<T> jb;
+        jb.layer = k + 1;
+        jb.top = nullptr;
+        jb.bot = qvec<T>(c, w.pC, k + 1, B);
+        jb.iy = iy_of<T>(c, 0, k + 1, B);
+        jb.ix = ix_of<T>(c, 0, k + 1, B);
+        jb.side = 0;
+        jb.out = qvec<T>(c, w.pC, k, B);
+        jb.add0 = qvec<T>(c, w.pC, k, B);
+        jb.alpha = (T)1;
+        plan_jobs<T>(c, pl, {jb}, B);
+    }
+    (void)pairn;
+}
+
+template <typename T>
+Plan<T>& get_plan(hz_ctx* c, bool sie, int B) {
+    Work<T>& w = work<T>(c);
+    auto& mp = sie ? w.sie : w.pre;
+    auto it = mp.find(B);
+    if (it != mp.end()) return *it->second;
+    auto pl = std::make_unique<Plan<T>>();
+    if (sie) build_sie_plan<T>(c, *pl, B);
+    else build_pre_plan<T>(c, *pl, B);
+    plan_upload<T>(c, *pl);
+    Plan<T>& ref = *pl;
+    mp[B] = std::move(pl);
+    return ref;
+}
+
+// ---------------------------------------------------------------------------
+// workspaces
+
+template <typename T>
+void ensure_work(hz_ctx* c, int B) {
+    Work<T>& w = work<T>(c);
+    if (w.Bcap >= B) return;
+    if (w.Bcap > 0) raise(HZ_EINVAL, "batch larger than max_batch");
+    const Dims& d = c->d;
+    const long long W = d.W;
+    B = std::max(B, c->prm.max_batch);
+    w.Bcap = B;
+    w.f_ext = alloc_c<T>(c, W * W * B);
+    w.u_ext = alloc_c<T>(c, W * W * B);
+    w.rows_out = alloc_c<T>(c, (long long)d.L * MAXSLOT * W * B);
+    const long long inner = std::max<long long>((long long)d.L * c->inner_per_layer * B, 1);
+    w.gf = alloc_c<T>(c, inner);
+    for (int s = 0; s < 2; ++s) {
+        w.iy[s] = alloc_c<T>(c, inner);
+        w.ix[s] = alloc_c<T>(c, inner);
+    }
+    const long long pol = std::max<long long>(4LL * d.K * W * B, 1);
+    w.pA = alloc_c<T>(c, pol);
+    w.pB = alloc_c<T>(c, pol);
+    w.pC = alloc_c<T>(c, pol);
+    w.sv = alloc_c<T>(c, std::max<long long>(2LL * d.K * W * B, 1));
+    // cell-solve scratch: one region per workgroup of a volume solve
+    const int nb = cs_nb(B);
+    const int chunks = (B + nb - 1) / nb;
+    w.y_stride = (long long)d.Wcmax * d.HLmax * nb;
+    w.y_wgs = (int)c->cells.size() * chunks;
+    w.Y = alloc_c<T>(c, w.y_stride * w.y_wgs);
+    w.pair_tab = (const C2<T>**)c->arena.alloc(sizeof(C2<T>*) * 2 * d.L);
+}
+
+// per-layer (top, bottom) trace pairs inside w.sv for the current batch size
+template <typename T>
+void upload_pair_tab(hz_ctx* c, int B) {
+    Work<T>& w = work<T>(c);
+    const Dims& d = c->d;
+    std::vector<const C2<T>*> tab(2 * d.L, nullptr);
+    const long long pairn = 2LL * d.W * B;
+    for (int l = 0; l < d.L; ++l) {
+        if (l > 0) tab[l] = w.sv + (long long)(l - 1) * pairn;
+        if (l < d.L - 1) tab[d.L + l] = w.sv + (long long)l * pairn;
+    }
+    upload(c, (void*)w.pair_tab, tab.data(), sizeof(C2<T>*) * 2 * d.L);
+}
+
+void ensure_gmres(hz_ctx* c, int B, int m) {
+    if (c->g_cap_B >= B && c->g_cap_m >= m) return;
+    const long long n = 4LL * c->d.K * c->d.W;
+    if (c->V) {
+        c->arena.release(c->V, 0);
+        c->arena.release(c->gw, 0);
+        c->arena.release(c->gb, 0);
+        c->arena.release(c->gx, 0);
+        c->arena.release(c->gpart, 0);
+        c->arena.release(c->gsmall, 0);
+        c->arena.release(c->gcoef, 0);
+    }
+    B = std::max(B, c->g_cap_B);
+    m = std::max(m, c->g_cap_m);
+    c->g_cap_B = B;
+    c->g_cap_m = m;
+    const long long nb = std::max<long long>(n * B, 1);
+    c->V = (double2*)c->arena.alloc(sizeof(double2) * nb * (m + 1));
+    c->gw = (double2*)c->arena.alloc(sizeof(double2) * nb);
+    c->gb = (double2*)c->arena.alloc(sizeof(double2) * nb);
+    c->gx = (double2*)c->arena.alloc(sizeof(double2) * nb);
+    c->gpart_chunks = 256;
+    c->gpart = (double2*)c->arena.alloc(sizeof(double2) * c->gpart_chunks * (m + 2) * B);
+    c->gsmall = (double2*)c->arena.alloc(sizeof(double2) * (m + 2) * B);
+    c->gcoef = (double2*)c->arena.alloc(sizeof(double2) * (m + 2) * B);
+}
+
+// ---------------------------------------------------------------------------
+// offline stage
+
+template <typename T>
+void cell_solve_launch(hz_ctx* c, CellSolveArgs<T> a, const std::vector<int>& list, int Bcols) {
+    // groups limited by the scratch available
+    Work<T>& w = work<T>(c);
+    const int nb = cs_nb(Bcols);
+    const int chunks = (Bcols + nb - 1) / nb;
+    const int per = std::max(1, w.y_wgs / chunks);
+    int* d_list = (int*)c->arena.alloc(sizeof(int) * list.size());
+    upload(c, d_list, list.data(), sizeof(int) * list.size());
+    for (size_t g = 0; g < list.size(); g += per) {
+        const int cnt = (int)std::min<size_t>(per, list.size() - g);
+        a.cell_list = d_list + g;
+        a.B = Bcols;
+        a.Y = w.Y;
+        a.y_stride = (long long)c->d.Wcmax * c->d.HLmax * nb;
+        launch_cell_solve<T>(a, cnt, chunks, c->st);
+        HIPCHK(hipGetLastError());
+    }
+    sync(c);
+    c->arena.release(d_list, sizeof(int) * list.size());
+}
+
+template <typename T>
+CellSolveArgs<T> base_args(hz_ctx* c) {
+    CellSolveArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    Ops<T>& o = ops<T>(c);
+    a.cells = c->d_cells;
+    a.layers = c->d_layers;
+    a.X = o.X;
+    a.coef_e = o.e;
+    a.alpha_x = c->ax_pool;
+    a.alpha_z = c->az_pool;
+    a.h = c->d.h;
+    a.n = c->d.n;
+    a.p = c->d.p;
+    a.W = c->d.W;
+    a.HLmax = c->d.HLmax;
+    a.Wcmax = c->d.Wcmax;
+    return a;
+}
+
+__global__ void k_inner_diag(const LayerDesc* layers, const CellDesc* cells, const double2* CS,
+                             int j, double2* out, long long out_stride) {
+    const LayerDesc ld = layers[blockIdx.y];
+    const int HL = ld.HL;
+    const int n2 = 2 * HL;
+    const CellDesc cl = cells[ld.cell_begin + j];        // left of interface j
+    const CellDesc cr = cells[ld.cell_begin + j + 1];    // right of interface j
+    double2* o = out + (long long)blockIdx.y * out_stride;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < (long long)n2 * n2;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int r = (int)(q / n2), col = (int)(q % n2);
+        double2 v;
+        if (r < HL) {       // row a: right-column samples of cell j, its right probes
+            const int row = (cl.has_left ? HL : 0) + r;
+            const int pc = (cl.has_left ? 2 * HL : 0) + col;
+            v = CS[cl.off_CS + (long long)row * cl.R + pc];
+        } else {            // row b: left-column samples of cell j+1, its left probes
+            v = CS[cr.off_CS + (long long)(r - HL) * cr.R + col];
+        }
+        v.x = -v.x; v.y = -v.y;
+        if (r == col) v.x += 1.0;
+        o[q] = v;
+    }
+}
+
+template <typename T>
+__global__ void k_cast_pool(C2<T>* y, const double2* x, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        y[i] = mk<T>((T)x[i].x, (T)x[i].y);
+    }
+}
+
+void factor_impl(hz_ctx* c) {
+    const Dims& d = c->d;
+    const int ncells = (int)c->cells.size();
+    Ops<double>& o = c->o64;
+    if (!o.X) {
+        o.X = alloc_c<double>(c, c->X_elems);
+        o.Q = alloc_c<double>(c, std::max<long long>(c->Q_elems, 1));
+        o.CS = alloc_c<double>(c, std::max<long long>(c->CS_elems, 1));
+        o.Sinv = alloc_c<double>(c, std::max<long long>(c->Sinv_elems, 1));
+        o.Lfac = alloc_c<double>(c, std::max<long long>(c->Lfac_elems, 1));
+    }
+    o.e = c->e;
+    HIPCHK(hipMemsetAsync(c->flags, 0, 2 * sizeof(int), c->st));
+    // 1. cell Schur factors
+    {
+        const long long ws = (long long)d.HLmax * d.HLmax;
+        const int batch = std::min(ncells, 1024);
+        double2* workbuf = alloc_c<double>(c, ws * batch);
+        for (int c0 = 0; c0 < ncells; c0 += batch) {
+            const int cnt = std::min(batch, ncells - c0);
+            launch_cell_factor<double>(c->d_cells + c0, cnt, d, c->diag, c->cz, c->e, o.X,
+                                       workbuf, ws, c->flags + 1, c->st);
+            HIPCHK(hipGetLastError());
+        }
+        sync(c);
+        c->arena.release(workbuf, sizeof(double2) * ws * batch);
+    }
+    int fl[2];
+    HIPCHK(hipMemcpy(fl, c->flags, sizeof(fl), hipMemcpyDeviceToHost));
+    if (fl[1]) raise(HZ_ESINGULAR, "zero pivot in a cell factorisation");
+    // 2. probes: cell Green's functions sampled on the interface rows / columns
+    int Rmax = 0;
+    for (auto& cd : c->cells) Rmax = std::max(Rmax, cd.R);
+    if (Rmax > 0) {
+        const int nb = cs_nb(Rmax);
+        const int chunks = (Rmax + nb - 1) / nb;
+        const long long ystride = (long long)d.Wcmax * d.HLmax * nb;
+        // scratch budget ~ 4 GiB
+        long long budget_wgs = std::max<long long>(chunks, (4LL << 30) / (ystride * (long long)sizeof(double2)));
+        const int per = (int)std::max<long long>(1, budget_wgs / chunks);
+        double2* Y = alloc_c<double>(c, ystride * (long long)per * chunks);
+        std::vector<int> list(ncells);
+        for (int i = 0; i < ncells; ++i) list[i] = i;
+        int* d_list = (int*)c->arena.alloc(sizeof(int) * ncells);
+        upload(c, d_list, list.data(), sizeof(int) * ncells);
+        CellSolveArgs<double> a = base_args<double>(c);
+        a.mode = SOLVE_PROBE;
+        a.Qpool = o.Q;
+        a.CSpool = o.CS;
+        a.probe0 = 0;
+        a.B = Rmax;
+        a.Y = Y;
+        a.y_stride = ystride;
+        for (int g = 0; g < ncells; g += per) {
+            const int cnt = std::min(per, ncells - g);
+            a.cell_list = d_list + g;
+            launch_cell_solve<double>(a, cnt, chunks, c->st);
+            HIPCHK(hipGetLastError());
+        }
+        sync(c);
+        c->arena.release(Y, sizeof(double2) * ystride * (long long)per * chunks);
+        c->arena.release(d_list, sizeof(int) * ncells);
+    }
+    // 3. inner SIE block LU without pivoting (per layer, sequential over interfaces)
+    const int J = d.Lc - 1;
+    if (J > 0) {
+        const int L = d.L;
+        const long long bs = 4LL * d.HLmax * d.HLmax;       // (2 HLmax)^2
+        double2* A = alloc_c<double>(c, bs * L);
+        double2* wk = alloc_c<double>(c, bs * L);
+        double2** mats = (double2**)c->arena.alloc(sizeof(void*) * L);
+        double2** outs = (double2**)c->arena.alloc(sizeof(void*) * L);
+        int* ns = (int*)c->arena.alloc(sizeof(int) * L);
+        std::vector<int> hn(L);
+        std::vector<double2*> hm(L), ho(L);
+        for (int l = 0; l < L; ++l) { hn[l] = 2 * c->layers[l].HL; hm[l] = A + bs * l; }
+        upload(c, ns, hn.data(), sizeof(int) * L);
+        upload(c, mats, hm.data(), sizeof(void*) * L);
+        GemmTask<double>* tdev = (GemmTask<double>*)c->arena.alloc(sizeof(GemmTask<double>) * 2 * L);
+        for (int j = 0; j < J; ++j) {
+            hipLaunchKernelGGL(k_inner_diag, dim3(64, L), dim3(256), 0, c->st, c->d_layers,
+                               c->d_cells, o.CS, j, A, bs);
+            HIPCHK(hipGetLastError());
+            if (j > 0) {
+                // L_j^a = B_j^a Sinv_{j-1},  B_j^a = -(right-column samples of cell j, left probes)
+                std::vector<GemmTask<double>> t1, t2;
+                int mm = 0;
+                for (int l = 0; l < L; ++l) {
+                    const LayerDesc& ld = c->layers[l];
+                    const int HL = ld.HL;
+                    const CellDesc& cj = c->cells[ld.cell_begin + j];
+                    GemmTask<double> t = blank_task<double>();
+                    t.A = o.CS + cj.off_CS + (long long)HL * cj.R;    // right rows, left probes
+                    t.lda = cj.R;
+                    t.m = HL; t.k = 2 * HL;
+                    t.ldx = 2 * HL; t.ldo = 2 * HL;
+                    t.nseg = 1; t.seg_k0[0] = 0; t.seg_len[0] = 2 * HL;
+                    t.seg_ptr[0] = o.Sinv + ld.off_Sinv + (long long)(j - 1) * 4 * HL * HL;
+                    t.noseg = 1; t.oseg_i0[0] = 0; t.oseg_len[0] = HL;
+                    t.oseg_ptr[0] = o.Lfac + ld.off_Lfac + (long long)(j - 1) * HL * 2 * HL;
+                    t.alpha = -1.0;
+                    t.ncol = 2 * HL;
+                    t1.push_back(t);
+                    // S_j^a = A_j^a - L_j^a[:, b] C_{j-1}^b,  C_{j-1}^b = -(left-column samples
+                    // of cell j, right probes)  ->  A_j^a + L_j^a[:, b] * samples
+                    GemmTask<double> u = blank_task<double>();
+                    u.A = o.Lfac + ld.off_Lfac + (long long)(j - 1) * HL * 2 * HL + HL;
+                    u.lda = 2 * HL;
+                    u.m = HL; u.k = HL;
+                    u.ldx = cj.R; u.ldo = 2 * HL;
+                    u.nseg = 1; u.seg_k0[0] = 0; u.seg_len[0] = HL;
+                    u.seg_ptr[0] = o.CS + cj.off_CS + 2LL * HL;      // left rows, right probes
+                    u.noseg = 1; u.oseg_i0[0] = 0; u.oseg_len[0] = HL;
+                    u.oseg_ptr[0] = A + bs * l;
+                    u.oseg_add0[0] = A + bs * l;
+                    u.alpha = 1.0;
+                    u.ncol = 2 * HL;
+                    t2.push_back(u);
+                    mm = std::max(mm, 2 * HL);
+                }
+                upload(c, tdev, t1.data(), sizeof(GemmTask<double>) * L);
+                launch_gemm<double>(tdev, L, mm, 2 * d.HLmax, c->st);
+                HIPCHK(hipGetLastError());
+                sync(c);
+                upload(c, tdev + L, t2.data(), sizeof(GemmTask<double>) * L);
+                launch_gemm<double>(tdev + L, L, mm, 2 * d.HLmax, c->st);
+                HIPCHK(hipGetLastError());
+                sync(c);
+            }
+            for (int l = 0; l < L; ++l)
+                ho[l] = o.Sinv + c->layers[l].off_Sinv + (long long)j * 4 * c->layers[l].HL * c->layers[l].HL;
+            upload(c, outs, ho.data(), sizeof(void*) * L);
+            // inverse of an order-2HL block: pack with row stride 2HL (the A buffer is already)
+            launch_invert_batch<double>(mats, outs, ns, L, wk, bs, c->flags + 1, c->st);
+            HIPCHK(hipGetLastError());
+            sync(c);
+        }
+        HIPCHK(hipMemcpy(fl, c->flags, sizeof(fl), hipMemcpyDeviceToHost));
+        if (fl[1]) raise(HZ_ESINGULAR, "zero pivot in the inner block LU");
+        c->arena.release(A, sizeof(double2) * bs * L);
+        c->arena.release(wk, sizeof(double2) * bs * L);
+        c->arena.release(mats, sizeof(void*) * L);
+        c->arena.release(outs, sizeof(void*) * L);
+        c->arena.release(ns, sizeof(int) * L);
+        c->arena.release(tdev, sizeof(GemmTask<double>) * 2 * L);
+    }
+    // 4. mixed precision: keep complex64 copies of every operator
+    if (c->prm.precision == HZ_MIXED) {
+        Ops<float>& f = c->o32;
+        auto cast = [&](float2*& dst, const double2* src, long long n) {
+            if (!dst) dst = alloc_c<float>(c, std::max<long long>(n, 1));
+            if (n > 0)
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cast_pool<float>), dim3(4096), dim3(256), 0,
+                                   c->st, dst, src, n);
+        };
+        cast(f.X, o.X, c->X_elems);
+        cast(f.e, c->e, c->coef_elems);
+        cast(f.Q, o.Q, c->Q_elems);
+        cast(f.CS, o.CS, c->CS_elems);
+        cast(f.Sinv, o.Sinv, c->Sinv_elems);
+        cast(f.Lfac, o.Lfac, c->Lfac_elems);
+        HIPCHK(hipGetLastError());
+        sync(c);
+        c->arena.release(o.X, sizeof(double2) * c->X_elems);
+        c->arena.release(o.Q, sizeof(double2) * std::max<long long>(c->Q_elems, 1));
+        c->arena.release(o.CS, sizeof(double2) * std::max<long long>(c->CS_elems, 1));
+        c->arena.release(o.Sinv, sizeof(double2) * std::max<long long>(c->Sinv_elems, 1));
+        c->arena.release(o.Lfac, sizeof(double2) * std::max<long long>(c->Lfac_elems, 1));
+        o = Ops<double>();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// online stage, precision T for the local operators
+
+template <typename T>
+void run_jobs(hz_ctx* c, const std::vector<LayerJob<T>>& jobs, int B) {
+    Plan<T> pl;
+    plan_jobs<T>(c, pl, jobs, B);
+    plan_upload<T>(c, pl);
+    plan_run<T>(c, pl, B);
+    sync(c);
+    if (pl.dev) c->arena.release(pl.dev, pl.dev_bytes);
+}
+
+// Cell Newton potentials of the volume source in the layers that hold one
+// (Alg. 7 lines 3-9): inner right-hand sides -> w.gf, samples on the
+// interface rows -> w.rows_out.  Returns false if no layer is active.
+template <typename T>
+bool sample_sources(hz_ctx* c, int B, const int* active_host) {
+    Work<T>& w = work<T>(c);
+    const Dims& d = c->d;
+    std::vector<int> list;
+    for (int l = 0; l < d.L; ++l)
+        if (active_host[l])
+            for (int k = 0; k < d.Lc; ++k) list.push_back(c->layers[l].cell_begin + k);
+    if (list.empty()) return false;
+    CellSolveArgs<T> a = base_args<T>(c);
+    a.mode = SOLVE_SAMPLE;
+    a.f_ext = w.f_ext;
+    a.layer_active = nullptr;
+    a.inner_rhs = w.gf;
+    a.rows_out = w.rows_out;
+    cell_solve_launch<T>(c, a, list, B);
+    return true;
+}
+
+// RHS of the polarized system from w.f_ext into polarized vector `out` (T)
+template <typename T>
+void sie_rhs_impl(hz_ctx* c, int B, C2<T>* out, const int* active_host) {
+    Work<T>& w = work<T>(c);
+    const Dims& d = c->d;
+    const long long pol = 4LL * d.K * d.W * B;
+    HIPCHK(hipMemsetAsync(out, 0, sizeof(C2<T>) * pol, c->st));
+    if (!sample_sources<T>(c, B, active_host)) return;
+    std::vector<LayerJob<T>> jobs;
+    for (int l = 0; l < d.L; ++l) {
+        if (!active_host[l]) continue;
+        const LayerDesc& ld = c->layers[l];
+        for (int side = 0; side < 2; ++side) {
+            if (side == 0 && !ld.has_top) continue;
+            if (side == 1 && !ld.has_bot) continue;
+            LayerJob<T> jb;
+            jb.layer = l;
+            jb.inner_add = w.gf + ld.off_inner * B;
+            jb.iy = iy_of<T>(c, side, l, B);
+            jb.ix = ix_of<T>(c, side, l, B);
+            jb.side = side;
+            jb.out = side == 1 ? dvec<T>(c, out, l, B) : qvec<T>(c, out, l - 1, B);
+            const int so_a = ld.slot_of[side == 0 ? 0 : 2];
+            jb.add0 = w.rows_out + ((long long)l * MAXSLOT + so_a) * d.W * B;
+            jb.use_x = false;
+            jb.alpha = (T)1;
+            jobs.push_back(jb);
+        }
+    }
+    run_jobs<T>(c, jobs, B);
+}
+
+// volume reconstruction from traces in w.sv (s = d + q) into w.u_ext
+template <typename T>
+void reconstruct_impl(hz_ctx* c, int B, const int* active_host) {
+    Work<T>& w = work<T>(c);
+    const Dims& d = c->d;
+    const long long pairn = 2LL * d.W * B;
+    const int J = d.Lc - 1;
+    if (J > 0) {
+        std::vector<LayerJob<T>> jobs;
+        for (int l = 0; l < d.L; ++l) {
+            LayerJob<T> jb;
+            jb.layer = l;
+            jb.top = l > 0 ? w.sv + (long long)(l - 1) * pairn : nullptr;
+            jb.bot = l < d.L - 1 ? w.sv + (long long)l * pairn : nullptr;
+            jb.inner_add = active_host[l] ? w.gf + c->layers[l].off_inner * B : nullptr;
+            jb.iy = iy_of<T>(c, 0, l, B);
+            jb.ix = ix_of<T>(c, 0, l, B);
+            jb.phase3 = false;
+            jobs.push_back(jb);
+        }
+        run_jobs<T>(c, jobs, B);
+    }
+    std::vector<int> list(c->cells.size());
+    for (size_t i = 0; i < list.size(); ++i) list[i] = (int)i;
+    upload_pair_tab<T>(c, B);
+    CellSolveArgs<T> a = base_args<T>(c);
+    a.mode = SOLVE_VOLUME;
+    a.f_ext = w.f_ext;
+    a.layer_active = c->layer_active;
+    a.top_pair = w.pair_tab;
+    a.bot_pair = w.pair_tab + d.L;
+    a.inner_v = J > 0 ? w.ix[0] : nullptr;
+    a.u_ext = w.u_ext;
+    cell_solve_launch<T>(c, a, list, B);
+}
+
+// y = P M x on FP64 vectors (x, y: [n][B]); T selects the operator precision
+template <typename T>
+void apply_PM(hz_ctx* c, const double2* x, double2* y, int B) {
+    Work<T>& w = work<T>(c);
+    const long long n = 4LL * c->d.K * c->d.W * B;
+    Plan<T>& ps = get_plan<T>(c, true, B);
+    Plan<T>& pp = get_plan<T>(c, false, B);
+    if constexpr (sizeof(T) == sizeof(double)) {
+        HIPCHK(hipMemcpyAsync(w.pA, x, sizeof(double2) * n, hipMemcpyDeviceToDevice, c->st));
+    } else {
+        launch_cast_d2f((float2*)w.pA, x, n, c->st);
+    }
+    plan_run<T>(c, ps, B);
+    plan_run<T>(c, pp, B);
+    if constexpr (sizeof(T) == sizeof(double)) {
+        HIPCHK(hipMemcpyAsync(y, w.pC, sizeof(double2) * n, hipMemcpyDeviceToDevice, c->st));
+    } else {
+        launch_cast_f2d(y, (const float2*)w.pC, n, c->st);
+    }
+}
+
+// P on FP64 vectors (used for the preconditioned right-hand side)
+template <typename T>
+void apply_P(hz_ctx* c, const double2* x, double2* y, int B) {
+    Work<T>& w = work<T>(c);
+    const long long n = 4LL * c->d.K * c->d.W * B;
+    Plan<T>& pp = get_plan<T>(c, false, B);
+    if constexpr (sizeof(T) == sizeof(double)) {
+        HIPCHK(hipMemcpyAsync(w.pB, x, sizeof(double2) * n, hipMemcpyDeviceToDevice, c->st));
+    } else {
+        launch_cast_d2f((float2*)w.pB, x, n, c->st);
+    }
+    plan_run<T>(c, pp, B);
+    if constexpr (sizeof(T) == sizeof(double)) {
+        HIPCHK(hipMemcpyAsync(y, w.pC, sizeof(double2) * n, hipMemcpyDeviceToDevice, c->st));
+    } else {
+        launch_cast_f2d(y, (const float2*)w.pC, n, c->st);
+    }
+}
+
+void givens(std::complex<double> a, std::complex<double> b, double& cs, std::complex<double>& sn) {
+    if (std::abs(b) == 0.0) { cs = 1.0; sn = 0.0; return; }
+    if (std::abs(a) == 0.0) { cs = 0.0; sn = std::conj(b) / std::abs(b); return; }
+    const double t = std::hypot(std::abs(a), std::abs(b));
+    cs = std::abs(a) / t;
+    sn = (a / std::abs(a)) * std::conj(b) / t;
+}
+
+// dots h[v][b] = V_v^H w for v < nv (device -> host)
+void dots(hz_ctx* c, const double2* V, long long vstride, int nv, const double2* w, long long n,
+          int B, std::vector<std::complex<double>>& out) {
+    const int chunks = (int)std::min<long long>(c->gpart_chunks, std::max<long long>(1, n / 256));
+    launch_dots(V, vstride, nv, w, n, B, c->gpart, chunks, c->st);
+    launch_reduce_partials(c->gpart, chunks, nv * B, c->gsmall, c->st);
+    out.resize((size_t)nv * B);
+    HIPCHK(hipMemcpyAsync(out.data(), c->gsmall, sizeof(double2) * nv * B, hipMemcpyDeviceToHost, c->st));
+    sync(c);
+}
+
+void norms(hz_ctx* c, const double2* w, long long n, int B, std::vector<double>& out) {
+    std::vector<std::complex<double>> t;
+    dots(c, nullptr, 0, 1, w, n, B, t);
+    out.resize(B);
+    for (int b = 0; b < B; ++b) out[b] = std::sqrt(std::max(0.0, t[b].real()));
+}
+
+// Left-preconditioned GMRES (Alg. 6) on FP64 vectors, x0 = 0, no restart,
+// classical Gram-Schmidt with one re-orthogonalisation, Givens rotations.
+template <typename T>
+void gmres(hz_ctx* c, const double2* b, double2* x, int B, double tol, int maxit,
+           std::vector<int>& iters, std::vector<double>& relres) {
+    const long long n = 4LL * c->d.K * c->d.W;
+    const long long nB = n * B;
+    ensure_gmres(c, B, maxit);
+    double2* V = c->V;
+    const long long vs = nB;
+    apply_P<T>(c, b, V, B);
+    std::vector<double> beta;
+    norms(c, V, n, B, beta);
+    std::vector<std::vector<std::complex<double>>> Hm(B, std::vector<std::complex<double>>((size_t)(maxit + 1) * maxit));
+    std::vector<std::vector<std::complex<double>>> g(B, std::vector<std::complex<double>>(maxit + 1));
+    std::vector<std::vector<double>> cs(B, std::vector<double>(maxit));
+    std::vector<std::vector<std::complex<double>>> sn(B, std::vector<std::complex<double>>(maxit));
+    std::vector<int> done(B, 0), kfin(B, 0);
+    iters.assign(B, 0);
+    relres.assign(B, 0.0);
+    std::vector<double2> sc(B);
+    for (int bb = 0; bb < B; ++bb) {
+        g[bb][0] = beta[bb];
+        if (beta[bb] == 0.0) { done[bb] = 1; relres[bb] = 0.0; }
+        sc[bb] = make_double2(beta[bb] > 0 ? 1.0 / beta[bb] : 0.0, 0.0);
+    }
+    upload(c, c->gcoef, sc.data(), sizeof(double2) * B);
+    launch_scale_cols(V, V, c->gcoef, n, B, c->st);
+    std::vector<std::complex<double>> h1, h2;
+    std::vector<double> nrm;
+    std::vector<double2> coef;
+    int j = 0;
+    for (; j < maxit; ++j) {
+        if (std::all_of(done.begin(), done.end(), [](int v) { return v != 0; })) break;
+        double2* Vj = V + (long long)j * vs;
+        double2* Vn = V + (long long)(j + 1) * vs;
+        apply_PM<T>(c, Vj, c->gw, B);
+        // two passes of classical Gram-Schmidt
+        std::vector<std::complex<double>> hsum((size_t)(j + 1) * B, 0.0);
+        for (int pass = 0; pass < 2; ++pass) {
+            dots(c, V, vs, j + 1, c->gw, n, B, h1);
+            coef.assign((size_t)(j + 1) * B, make_double2(0, 0));
+            for (size_t q = 0; q < h1.size(); ++q) {
+                hsum[q] += h1[q];
+                coef[q] = make_double2(-h1[q].real(), -h1[q].imag());
+            }
+            upload(c, c->gcoef, coef.data(), sizeof(double2) * coef.size());
+            launch_update_basis(c->gw, V, vs, j + 1, c->gcoef, n, B, c->st);
+        }
+        norms(c, c->gw, n, B, nrm);
+        for (int bb = 0; bb < B; ++bb) {
+            sc[bb] = make_double2(0.0, 0.0);
+            if (done[bb]) continue;
+            auto& H = Hm[bb];
+            auto Hat = [&](int r, int col) -> std::complex<double>& { return H[(size_t)r * maxit + col]; };
+            for (int i = 0; i <= j; ++i) Hat(i, j) = hsum[(size_t)i * B + bb];
+            Hat(j + 1, j) = nrm[bb];
+            for (int i = 0; i < j; ++i) {
+                std::complex<double> a = Hat(i, j), b2 = Hat(i + 1, j);
+                Hat(i, j) = cs[bb][i] * a + sn[bb][i] * b2;
+                Hat(i + 1, j) = -std::conj(sn[bb][i]) * a + cs[bb][i] * b2;
+            }
+            givens(Hat(j, j), Hat(j + 1, j), cs[bb][j], sn[bb][j]);
+            std::complex<double> a = Hat(j, j), b2 = Hat(j + 1, j);
+            Hat(j, j) = cs[bb][j] * a + sn[bb][j] * b2;
+            Hat(j + 1, j) = 0.0;
+            g[bb][j + 1] = -std::conj(sn[bb][j]) * g[bb][j];
+            g[bb][j] = cs[bb][j] * g[bb][j];
+            kfin[bb] = j + 1;
+            relres[bb] = std::abs(g[bb][j + 1]) / beta[bb];
+            if (relres[bb] <= tol || nrm[bb] == 0.0) done[bb] = 1;
+            else sc[bb] = make_double2(1.0 / nrm[bb], 0.0);
+        }
+        upload(c, c->gcoef, sc.data(), sizeof(double2) * B);
+        launch_scale_cols(Vn, c->gw, c->gcoef, n, B, c->st);
+    }
+    // x = V y
+    const int kmax = *std::max_element(kfin.begin(), kfin.end());
+    coef.assign((size_t)std::max(kmax, 1) * B, make_double2(0, 0));
+    for (int bb = 0; bb < B; ++bb) {
+        const int k = kfin[bb];
+        iters[bb] = k;
+        std::vector<std::complex<double>> y(k);
+        auto& H = Hm[bb];
+        for (int i = k - 1; i >= 0; --i) {
+            std::complex<double> s = g[bb][i];
+            for (int q = i + 1; q < k; ++q) s -= H[(size_t)i * maxit + q] * y[q];
+            y[i] = s / H[(size_t)i * maxit + i];
+        }
+        for (int i = 0; i < k; ++i) coef[(size_t)i * B + bb] = make_double2(y[i].real(), y[i].imag());
+    }
+    HIPCHK(hipMemsetAsync(x, 0, sizeof(double2) * nB, c->st));
+    if (kmax > 0) {
+        upload(c, c->gcoef, coef.data(), sizeof(double2) * (size_t)kmax * B);
+        launch_update_basis(x, V, vs, kmax, c->gcoef, n, B, c->st);
+    }
+    sync(c);
+}
+
+// One DD solve of H u = f with f already in work<T>.f_ext; result in work<T>.u_ext.
+template <typename T>
+void dd_solve(hz_ctx* c, int B, double tol, int maxit, const std::vector<int>& active,
+              std::vector<int>& iters, std::vector<double>& relres, double* t_rhs,
+              double* t_gm, double* t_rec) {
+    Work<T>& w = work<T>(c);
+    const Dims& d = c->d;
+    double t0 = now_s();
+    upload(c, c->layer_active, active.data(), sizeof(int) * d.L);
+    if (d.K == 0) {
+        // single layer: the layer solve is the global solve (Alg. 7 volume mode)
+        if (d.Lc > 1) sample_sources<T>(c, B, active.data());
+        reconstruct_impl<T>(c, B, active.data());
+        iters.assign(B, 0);
+        relres.assign(B, 0.0);
+        *t_rec += now_s() - t0;
+        return;
+    }
+    const long long n = 4LL * d.K * d.W;
+    sie_rhs_impl<T>(c, B, w.pB, active.data());
+    // FP64 copy of the polarized RHS
+    if constexpr (sizeof(T) == sizeof(double)) {
+        HIPCHK(hipMemcpyAsync(c->gb, w.pB, sizeof(double2) * n * B, hipMemcpyDeviceToDevice, c->st));
+    } else {
+        launch_cast_f2d(c->gb, (const float2*)w.pB, n * B, c->st);
+    }
+    sync(c);
+    double t1 = now_s();
+    *t_rhs += t1 - t0;
+    gmres<T>(c, c->gb, c->gx, B, tol, maxit, iters, relres);
+    double t2 = now_s();
+    *t_gm += t2 - t1;
+    // s = d + q  (in T)
+    const long long half = 2LL * d.K * d.W * B;
+    if constexpr (sizeof(T) == sizeof(double)) {
+        HIPCHK(hipMemcpyAsync(w.sv, c->gx, sizeof(double2) * half, hipMemcpyDeviceToDevice, c->st));
+        launch_axpby<double>((double2*)w.sv, c->gx + half, make_double2(1, 0), make_double2(1, 0), half, c->st);
+    } else {
+        launch_axpby<double>(c->gx, c->gx + half, make_double2(1, 0), make_double2(1, 0), half, c->st);
+        launch_cast_d2f((float2*)w.sv, c->gx, half, c->st);
+    }
+    reconstruct_impl<T>(c, B, active.data());
+    sync(c);
+    *t_rec += now_s() - t2;
+}
+
+void check_state(hz_ctx* c, int need) {
+    if (!c) raise(HZ_EINVAL, "null context");
+    if (c->state < need) raise(HZ_ESTATE, need == 2 ? "call hz_factor first" : "context not set up");
+}
+
+// volume residual norms ||f - H u|| / ||f|| per RHS, fields [W][W][B] FP64
+void vol_resid(hz_ctx* c, const double2* u, const double2* f, int B, std::vector<double>& out) {
+    const long long N = (long long)c->d.W * c->d.W;
+    double2* r = c->r64;
+    launch_residual(u, f, r, c->gdiag, c->gcx, c->gcz, c->d.W, B, 1, c->st);
+    std::vector<double> nr, nf;
+    norms(c, r, N, B, nr);
+    norms(c, f, N, B, nf);
+    out.resize(B);
+    for (int b = 0; b < B; ++b) out[b] = nf[b] > 0 ? nr[b] / nf[b] : 0.0;
+}
+
+void ensure_refine(hz_ctx* c) {
+    if (c->u64) return;
+    const long long N = (long long)c->d.W * c->d.W * std::max(c->prm.max_batch, 1);
+    c->u64 = (double2*)c->arena.alloc(sizeof(double2) * N);
+    c->f64 = (double2*)c->arena.alloc(sizeof(double2) * N);
+    c->r64 = (double2*)c->arena.alloc(sizeof(double2) * N);
+}
+
+hz_status solve_impl(hz_ctx* c, const void* rhs_dev, int B, void* out_dev, double tol,
+                     int max_iter, hz_rhs_stats* stats, hz_timing* timing, int ext_out,
+                     int adjoint) {
+    check_state(c, 2);
+    if (!rhs_dev || !out_dev || B < 1) raise(HZ_EINVAL, "bad solve arguments");
+    if (B > std::max(c->prm.max_batch, 1)) raise(HZ_EINVAL, "B exceeds max_batch");
+    if (!(tol > 0.0) || max_iter < 1) raise(HZ_EINVAL, "bad tol / max_iter");
+    const Dims& d = c->d;
+    const long long N = (long long)d.W * d.W;
+    double t0 = now_s();
+    double t_rhs = 0, t_gm = 0, t_rec = 0;
+    ensure_refine(c);
+    ensure_gmres(c, B, max_iter);
+    const double2* rhs = (const double2*)rhs_dev;
+    // f64 = rhs on the extended grid (batch fastest); adjoint: conj(rhs)
+    HIPCHK(hipMemsetAsync(c->layer_active, 0, sizeof(int) * d.L, c->st));
+    if (adjoint) {
+        double2* tmp = c->r64;
+        launch_conj_copy(tmp, rhs, (long long)B * d.n * d.n, c->st);
+        launch_rhs_to_ext(tmp, B, d.n, d.p, d.W, c->f64, c->d_layers, d.L, c->layer_active, c->st);
+    } else {
+        launch_rhs_to_ext(rhs, B, d.n, d.p, d.W, c->f64, c->d_layers, d.L, c->layer_active, c->st);
+    }
+    std::vector<int> active(d.L);
+    HIPCHK(hipMemcpyAsync(active.data(), c->layer_active, sizeof(int) * d.L, hipMemcpyDeviceToHost, c->st));
+    sync(c);
+    std::vector<int> iters(B, 0), it1;
+    std::vector<double> relres(B, 0.0), vres;
+    int refine_steps = 0;
+    bool conv = true;
+    if (c->prm.precision == HZ_FP64) {
+        ensure_work<double>(c, B);
+        Work<double>& w = c->w64;
+        HIPCHK(hipMemcpyAsync(w.f_ext, c->f64, sizeof(double2) * N * B, hipMemcpyDeviceToDevice, c->st));
+        dd_solve<double>(c, B, tol, max_iter, active, iters, relres, &t_rhs, &t_gm, &t_rec);
+        for (int b = 0; b < B; ++b) if (!(relres[b] <= tol)) conv = false;
+        HIPCHK(hipMemcpyAsync(c->u64, w.u_ext, sizeof(double2) * N * B, hipMemcpyDeviceToDevice, c->st));
+    } else {
+        // FP64 iterative refinement around the complex64 nested solver
+        ensure_work<float>(c, B);
+        Work<float>& w = c->w32;
+        HIPCHK(hipMemsetAsync(c->u64, 0, sizeof(double2) * N * B, c->st));
+        std::vector<int> all(d.L, 1);
+        const double inner_tol = std::max(1e-6, tol);
+        const int max_refine = 30;
+        std::vector<double> un, dn;
+        for (int step = 0; step < max_refine; ++step) {
+            launch_residual(c->u64, c->f64, c->r64, c->gdiag, c->gcx, c->gcz, d.W, B, 1, c->st);
+            launch_cast_d2f(w.f_ext, c->r64, N * B, c->st);
+            dd_solve<float>(c, B, inner_tol, max_iter, step == 0 ? active : all, it1, relres,
+                            &t_rhs, &t_gm, &t_rec);
+            for (int b = 0; b < B; ++b) iters[b] += it1[b];
+            launch_cast_f2d(c->r64, w.u_ext, N * B, c->st);          // delta
+            launch_axpby<double>(c->u64, c->r64, make_double2(1, 0), make_double2(1, 0), N * B, c->st);
+            norms(c, c->r64, N, B, dn);
+            norms(c, c->u64, N, B, un);
+            refine_steps = step + 1;
+            bool ok = true;
+            for (int b = 0; b < B; ++b)
+                if (un[b] > 0 && dn[b] > tol * un[b]) ok = false;
+            if (ok) break;
+            if (step == max_refine - 1) conv = false;
+        }
+    }
+    if (stats) vol_resid(c, c->u64, c->f64, B, vres);
+    launch_ext_to_out(c->u64, B, d.n, d.p, d.W, (double2*)out_dev, ext_out ? 0 : 1, adjoint, c->st);
+    HIPCHK(hipGetLastError());
+    sync(c);
+    const double t_all = now_s() - t0;
+    c->timing.t_rhs = t_rhs;
+    c->timing.t_gmres = t_gm;
+    c->timing.t_recon = t_rec;
+    c->timing.t_solve = t_all;
+    c->timing.gmres_iters = *std::max_element(iters.begin(), iters.end());
+    if (timing) *timing = c->timing;
+    if (stats) {
+        for (int b = 0; b < B; ++b) {
+            stats[b].iters = iters[b];
+            stats[b].rel_resid = relres[b];
+            stats[b].vol_resid = vres.empty() ? -1.0 : vres[b];
+            stats[b].refine_steps = refine_steps;
+        }
+    }
+    return conv ? HZ_OK : HZ_ENOCONV;
+}
+
+hz_status setup_coef(hz_ctx* c, const double* model_dev) {
+    const Dims& d = c->d;
+    HIPCHK(hipMemcpyAsync(c->model, model_dev, sizeof(double) * d.n * d.n, hipMemcpyDeviceToDevice, c->st));
+    HIPCHK(hipMemsetAsync(c->flags, 0, 2 * sizeof(int), c->st));
+    launch_build_coef(c->model, (int)c->prm.model_kind, d, c->d_cells, c->d_layers,
+                      (int)c->cells.size(), c->cells.data(), c->diag, c->cz, c->e, c->ax_pool,
+                      c->az_pool, c->gdiag, c->gcx, c->gcz, c->wext, c->flags, c->st);
+    HIPCHK(hipGetLastError());
+    int fl[2];
+    HIPCHK(hipMemcpyAsync(fl, c->flags, sizeof(fl), hipMemcpyDeviceToHost, c->st));
+    sync(c);
+    if (fl[0]) raise(HZ_EINVAL, "model has NaN, infinite or non-positive entries");
+    return HZ_OK;
+}
+
+#define API_BEGIN try {
+#define API_END                                   \
+    }                                             \
+    catch (const HzError& e) {                    \
+        g_err = e.msg;                            \
+        return e.s;                               \
+    }                                             \
+    catch (const std::exception& e) {             \
+        g_err = e.what();                         \
+        return HZ_EDEVICE;                        \
+    }                                             \
+    catch (...) {                                 \
+        g_err = "unknown error";                  \
+        return HZ_EDEVICE;                        \
+    }
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+
+extern "C" {
+
+const char* hz_strerror(hz_status s) {
+    switch (s) {
+    case HZ_OK: return "ok";
+    case HZ_EINVAL: return "invalid argument";
+    case HZ_ENOMEM: return "out of device memory";
+    case HZ_ESTATE: return "call out of order";
+    case HZ_ENOCONV: return "GMRES did not converge";
+    case HZ_ESINGULAR: return "singular factorisation";
+    case HZ_EDEVICE: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+const char* hz_last_error(void) { return g_err.c_str(); }
+
+hz_status hz_setup(const double* model_dev, const hz_params* prm, hz_ctx** out) {
+    if (out) *out = nullptr;
+    hz_ctx* c = nullptr;
+    API_BEGIN
+    if (!prm || !out || !model_dev) raise(HZ_EINVAL, "null argument");
+    const int n = prm->n_x;
+    if (n < 2 || prm->n_z != n) raise(HZ_EINVAL, "n_x must equal n_z and be >= 2");
+    if (std::fabs(prm->h * (n + 1) - 1.0) > 1e-9) raise(HZ_EINVAL, "h must be 1/(n+1)");
+    if (!(prm->omega > 0.0) || !std::isfinite(prm->omega)) raise(HZ_EINVAL, "omega must be > 0");
+    if (prm->n_pml < 0) raise(HZ_EINVAL, "n_pml must be >= 0");
+    if (prm->layers < 1 || prm->layers > n / 2) raise(HZ_EINVAL, "layers must be in 1..n/2 (>= 2 rows each)");
+    if (prm->cells < 1 || prm->cells > n / 2) raise(HZ_EINVAL, "cells must be in 1..n/2 (>= 2 columns each)");
+    if (prm->precision != HZ_FP64 && prm->precision != HZ_MIXED) raise(HZ_EINVAL, "bad precision");
+    if (prm->model_kind != HZ_MODEL_VELOCITY && prm->model_kind != HZ_MODEL_SLOWNESS2)
+        raise(HZ_EINVAL, "bad model kind");
+    c = new hz_ctx();
+    c->prm = *prm;
+    if (c->prm.pml_beta <= 0.0) c->prm.pml_beta = 2.0;
+    if (c->prm.max_batch <= 0) c->prm.max_batch = 1;
+    Dims& d = c->d;
+    d.n = n;
+    d.p = prm->n_pml;
+    d.W = n + 2 * d.p;
+    d.L = prm->layers;
+    d.Lc = prm->cells;
+    d.K = d.L - 1;
+    d.h = 1.0 / (n + 1);
+    d.omega = prm->omega;
+    d.beta = c->prm.pml_beta;
+    build_descriptors(c);
+    if (d.HLmax > 224) raise(HZ_EINVAL, "layer grid taller than 224 rows: use more layers");
+    if (2 * d.HLmax > 448) raise(HZ_EINVAL, "inner block too large");
+    double t0 = now_s();
+    c->d_layers = (LayerDesc*)c->arena.alloc(sizeof(LayerDesc) * d.L);
+    c->d_cells = (CellDesc*)c->arena.alloc(sizeof(CellDesc) * c->cells.size());
+    upload(c, c->d_layers, c->layers.data(), sizeof(LayerDesc) * d.L);
+    upload(c, c->d_cells, c->cells.data(), sizeof(CellDesc) * c->cells.size());
+    c->model = (double*)c->arena.alloc(sizeof(double) * n * n);
+    c->diag = alloc_c<double>(c, c->coef_elems);
+    c->cz = alloc_c<double>(c, c->coef_elems);
+    c->e = alloc_c<double>(c, c->coef_elems);
+    c->ax_pool = alloc_c<double>(c, (long long)c->cells.size() * d.Wcmax);
+    c->az_pool = alloc_c<double>(c, (long long)d.L * d.HLmax);
+    const long long N = (long long)d.W * d.W;
+    c->gdiag = alloc_c<double>(c, N);
+    c->gcx = alloc_c<double>(c, N);
+    c->gcz = alloc_c<double>(c, N);
+    c->wext = alloc_c<double>(c, N);
+    c->flags = (int*)c->arena.alloc(sizeof(int) * 4);
+    c->layer_active = (int*)c->arena.alloc(sizeof(int) * d.L);
+    setup_coef(c, model_dev);
+    c->state = 1;
+    c->timing.t_setup = now_s() - t0;
+    *out = c;
+    return HZ_OK;
+    }
+    catch (const HzError& e) {
+        g_err = e.msg;
+        if (c) { c->arena.free_all(); delete c; }
+        return e.s;
+    }
+    catch (...) {
+        g_err = "unknown error in hz_setup";
+        if (c) { c->arena.free_all(); delete c; }
+        return HZ_EDEVICE;
+    }
+}
+
+hz_status hz_update_model(hz_ctx* c, const double* model_dev) {
+    API_BEGIN
+    check_state(c, 1);
+    if (!model_dev) raise(HZ_EINVAL, "null model");
+    setup_coef(c, model_dev);
+    c->state = 1;
+    return HZ_OK;
+    API_END
+}
+
+hz_status hz_factor(hz_ctx* c) {
+    API_BEGIN
+    check_state(c, 1);
+    double t0 = now_s();
+    c->state = 1;
+    factor_impl(c);
+    c->w64.sie.clear(); c->w64.pre.clear();
+    c->w32.sie.clear(); c->w32.pre.clear();
+    c->state = 2;
+    c->timing.t_factor = now_s() - t0;
+    return HZ_OK;
+    API_END
+}
+
+hz_status hz_solve(hz_ctx* c, const void* rhs, int B, void* u, double tol, int max_iter,
+                   hz_rhs_stats* stats, hz_timing* timing) {
+    API_BEGIN
+    return solve_impl(c, rhs, B, u, tol, max_iter, stats, timing, 0, 0);
+    API_END
+}
+
+hz_status hz_solve_ext(hz_ctx* c, const void* rhs, int B, void* u, double tol, int max_iter,
+                       hz_rhs_stats* stats, hz_timing* timing) {
+    API_BEGIN
+    return solve_impl(c, rhs, B, u, tol, max_iter, stats, timing, 1, 0);
+    API_END
+}
+
+hz_status hz_adjoint(hz_ctx* c, const void* rhs, int B, void* lam, double tol, int max_iter,
+                     hz_rhs_stats* stats) {
+    API_BEGIN
+    return solve_impl(c, rhs, B, lam, tol, max_iter, stats, nullptr, 0, 1);
+    API_END
+}
+
+hz_status hz_adjoint_ext(hz_ctx* c, const void* rhs, int B, void* lam, double tol, int max_iter,
+                         hz_rhs_stats* stats) {
+    API_BEGIN
+    return solve_impl(c, rhs, B, lam, tol, max_iter, stats, nullptr, 1, 1);
+    API_END
+}
+
+hz_status hz_misfit_gradient(hz_ctx* c, const void* u_ext, const void* lam_ext, int B, double* g) {
+    API_BEGIN
+    check_state(c, 1);
+    if (!u_ext || !lam_ext || !g || B < 1) raise(HZ_EINVAL, "bad gradient arguments");
+    launch_misfit_grad((const double2*)u_ext, (const double2*)lam_ext, B, c->d.W, c->d.n, c->d.p,
+                       c->wext, c->d.omega, g, c->st);
+    HIPCHK(hipGetLastError());
+    sync(c);
+    return HZ_OK;
+    API_END
+}
+
+hz_status hz_misfit(hz_ctx* c, const void* u_ext, const void* d_obs, int rec_row, int B,
+                    void* adj, double* J) {
+    API_BEGIN
+    check_state(c, 1);
+    if (!u_ext || !d_obs || !adj || !J || B < 1 || rec_row < 1 || rec_row > c->d.n)
+        raise(HZ_EINVAL, "bad misfit arguments");
+    double* part = (double*)c->arena.alloc(sizeof(double) * 256);
+    launch_misfit((const double2*)u_ext, (const double2*)d_obs, rec_row, B, c->d.n, c->d.p,
+                  c->d.W, (double2*)adj, part, c->st);
+    HIPCHK(hipGetLastError());
+    std::vector<double> hp(256);
+    HIPCHK(hipMemcpyAsync(hp.data(), part, sizeof(double) * 256, hipMemcpyDeviceToHost, c->st));
+    sync(c);
+    c->arena.release(part, sizeof(double) * 256);
+    double s = 0.0;
+    for (double v : hp) s += v;
+    *J = 0.5 * s;
+    return HZ_OK;
+    API_END
+}
+
+hz_status hz_set_stream(hz_ctx* c, void* s) {
+    API_BEGIN
+    if (!c) raise(HZ_EINVAL, "null context");
+    c->st = (hipStream_t)s;
+    return HZ_OK;
+    API_END
+}
+
+hz_status hz_get_info(const hz_ctx* c, hz_info_t* info) {
+    if (!c || !info) return HZ_EINVAL;
+    info->n = c->d.n;
+    info->n_pml = c->d.p;
+    info->W = c->d.W;
+    info->layers = c->d.L;
+    info->cells = c->d.Lc;
+    info->trace_len = 4 * c->d.K * c->d.W;
+    info->max_batch = c->prm.max_batch;
+    info->device_bytes = c->arena.bytes;
+    return HZ_OK;
+}
+
+hz_status hz_get_timing(const hz_ctx* c, hz_timing* t) {
+    if (!c || !t) return HZ_EINVAL;
+    *t = c->timing;
+    return HZ_OK;
+}
+
+void hz_destroy(hz_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->st);
+    c->arena.free_all();
+    delete c;
+}
+
+// ---- building blocks ---------------------------------------------------------
+
+hz_status hz_apply_layer(hz_ctx* c, int layer, const void* top, const void* bot, int side,
+                         void* out, int B) {
+    API_BEGIN
+    check_state(c, 2);
+    if (c->prm.precision != HZ_FP64) raise(HZ_EINVAL, "building blocks need HZ_FP64");
+    if (layer < 0 || layer >= c->d.L || !out || B < 1 || B > c->prm.max_batch) raise(HZ_EINVAL, "bad arguments");
+    const LayerDesc& ld = c->layers[layer];
+    if ((side == 0 && !ld.has_top) || (side == 1 && !ld.has_bot) || side < 0 || side > 1)
+        raise(HZ_EINVAL, "layer has no interface on that side");
+    if ((top && !ld.has_top) || (bot && !ld.has_bot)) raise(HZ_EINVAL, "no such input pair");
+    ensure_work<double>(c, B);
+    LayerJob<double> jb;
+    jb.layer = layer;
+    jb.top = (const double2*)top;
+    jb.bot = (const double2*)bot;
+    jb.iy = iy_of<double>(c, 0, layer, B);
+    jb.ix = ix_of<double>(c, 0, layer, B);
+    jb.side = side;
+    jb.out = (double2*)out;
+    jb.alpha = 1.0;
+    run_jobs<double>(c, {jb}, B);
+    return HZ_OK;
+    API_END
+}
+
+hz_status hz_apply_sie(hz_ctx* c, const void* x, void* y, int B) {
+    API_BEGIN
+    check_state(c, 2);
+    if (c->prm.precision != HZ_FP64) raise(HZ_EINVAL, "building blocks need HZ_FP64");
+    if (!x || !y || B < 1 || B > c->prm.max_batch || c->d.K == 0) raise(HZ_EINVAL, "bad arguments");
+    ensure_work<double>(c, B);
+    Work<double>& w = c->w64;
+    const long long n = 4LL * c->d.K * c->d.W * B;
+    HIPCHK(hipMemcpyAsync(w.pA, x, sizeof(double2) * n, hipMemcpyDeviceToDevice, c->st));
+    plan_run<double>(c, get_plan<double>(c, true, B), B);
+    HIPCHK(hipMemcpyAsync(y, w.pB, sizeof(double2) * n, hipMemcpyDeviceToDevice, c->st));
+    sync(c);
+    return HZ_OK;
+    API_END
+}
+
+hz_status hz_apply_precond(hz_ctx* c, const void* x, void* y, int B) {
+    API_BEGIN
+    check_state(c, 2);
+    if (c->prm.precision != HZ_FP64) raise(HZ_EINVAL, "building blocks need HZ_FP64");
+    if (!x || !y || B < 1 || B > c->prm.max_batch || c->d.K == 0) raise(HZ_EINVAL, "bad arguments");
+    ensure_work<double>(c, B);
+    Work<double>& w = c->w64;
+    const long long n = 4LL * c->d.K * c->d.W * B;
+    HIPCHK(hipMemcpyAsync(w.pB, x, sizeof(double2) * n, hipMemcpyDeviceToDevice, c->st));
+    plan_run<double>(c, get_plan<double>(c, false, B), B);
+    HIPCHK(hipMemcpyAsync(y, w.pC, sizeof(double2) * n, hipMemcpyDeviceToDevice, c->st));
+    sync(c);
+    return HZ_OK;
+    API_END
+}
+
+hz_status hz_sie_rhs(hz_ctx* c, const void* rhs, void* y, int B) {
+    API_BEGIN
+    check_state(c, 2);
+    if (c->prm.precision != HZ_FP64) raise(HZ_EINVAL, "building blocks need HZ_FP64");
+    if (!rhs || !y || B < 1 || B > c->prm.max_batch || c->d.K == 0) raise(HZ_EINVAL, "bad arguments");
+    ensure_work<double>(c, B);
+    ensure_refine(c);
+    const Dims& d = c->d;
+    HIPCHK(hipMemsetAsync(c->layer_active, 0, sizeof(int) * d.L, c->st));
+    launch_rhs_to_ext((const double2*)rhs, B, d.n, d.p, d.W, c->w64.f_ext, c->d_layers, d.L,
+                      c->layer_active, c->st);
+    std::vector<int> active(d.L);
+    HIPCHK(hipMemcpyAsync(active.data(), c->layer_active, sizeof(int) * d.L, hipMemcpyDeviceToHost, c->st));
+    sync(c);
+    sie_rhs_impl<double>(c, B, (double2*)y, active.data());
+    sync(c);
+    return HZ_OK;
+    API_END
+}
+
+hz_status hz_cell_shape(const hz_ctx* c, int layer, int cell, int* HL, int* Wc) {
+    if (!c || layer < 0 || layer >= c->d.L || cell < 0 || cell >= c->d.Lc || !HL || !Wc)
+        return HZ_EINVAL;
+    const CellDesc& cd = c->cells[layer * c->d.Lc + cell];
+    *HL = cd.HL;
+    *Wc = cd.Wc;
+    return HZ_OK;
+}
+
+hz_status hz_cell_solve(hz_ctx* c, int layer, int cell, const void* g, void* x, int B) {
+    API_BEGIN
+    check_state(c, 2);
+    if (c->prm.precision != HZ_FP64) raise(HZ_EINVAL, "building blocks need HZ_FP64");
+    if (layer < 0 || layer >= c->d.L || cell < 0 || cell >= c->d.Lc || !g || !x || B < 1 ||
+        B > c->prm.max_batch)
+        raise(HZ_EINVAL, "bad arguments");
+    ensure_work<double>(c, B);
+    CellSolveArgs<double> a = base_args<double>(c);
+    a.mode = SOLVE_GRID;
+    a.g_grid = (const double2*)g;
+    a.x_grid = (double2*)x;
+    cell_solve_launch<double>(c, a, {layer * c->d.Lc + cell}, B);
+    return HZ_OK;
+    API_END
+}
+
+hz_status hz_residual(hz_ctx* c, const void* u, const void* f, void* r, int B) {
+    API_BEGIN
+    check_state(c, 1);
+    if (!u || !r || B < 1) raise(HZ_EINVAL, "bad arguments");
+    launch_residual((const double2*)u, (const double2*)f, (double2*)r, c->gdiag, c->gcx, c->gcz,
+                    c->d.W, B, 0, c->st);
+    HIPCHK(hipGetLastError());
+    sync(c);
+    return HZ_OK;
+    API_END
+}
+
+}  // extern "C"

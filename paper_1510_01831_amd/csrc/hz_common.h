@@ -1,0 +1,232 @@
+// Internal declarations shared by the HIP kernels and the host orchestration.
+//
+// Storage conventions (all device arrays):
+//  * complex numbers are interleaved (double2 / float2);
+//  * every online vector is stored "batch fastest": element (i, b) of a batch
+//    of B vectors lives at [i * B + b];
+//  * a cell grid is stored column by column (x slowest): node (row j, col k)
+//    at [k * HL + j], because the cell factorisation eliminates whole columns;
+//  * dense operators are row-major.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace hz {
+
+template <typename T> struct cplx_t;
+template <> struct cplx_t<double> { using type = double2; };
+template <> struct cplx_t<float> { using type = float2; };
+template <typename T> using C2 = typename cplx_t<T>::type;
+
+template <typename T> __host__ __device__ inline C2<T> mk(T x, T y) { C2<T> r; r.x = x; r.y = y; return r; }
+template <typename C> __host__ __device__ inline C cadd(C a, C b) { C r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <typename C> __host__ __device__ inline C csub(C a, C b) { C r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+template <typename C> __host__ __device__ inline C cmul(C a, C b) {
+    C r; r.x = a.x * b.x - a.y * b.y; r.y = a.x * b.y + a.y * b.x; return r;
+}
+// c + a * b
+template <typename C> __host__ __device__ inline C cfma(C a, C b, C c) {
+    C r; r.x = c.x + a.x * b.x - a.y * b.y; r.y = c.y + a.x * b.y + a.y * b.x; return r;
+}
+template <typename C> __host__ __device__ inline C cconj(C a) { C r; r.x = a.x; r.y = -a.y; return r; }
+template <typename C, typename S> __host__ __device__ inline C cscale(C a, S s) { C r; r.x = a.x * s; r.y = a.y * s; return r; }
+
+// alpha = 1/(1 + i beta (d/delta)^2) at a (possibly half-integer) position of
+// an axis whose own nodes are 1..n_own (quadratic PML of App. A with
+// C = beta omega delta; sigma = 0 on the closed physical interval).
+__host__ __device__ inline double2 pml_alpha(double pos, int n_own, int p, double beta) {
+    double2 r; r.x = 1.0; r.y = 0.0;
+    if (p == 0) return r;
+    double d = pos < 0.0 ? -pos : 0.0;
+    double dr = pos - (n_own + 1);
+    if (dr > d) d = dr;
+    d /= p;
+    double s = beta * d * d;
+    double den = 1.0 / (1.0 + s * s);
+    r.x = den; r.y = -s * den;
+    return r;
+}
+
+__host__ __device__ inline double2 cinv(double2 a) {
+    double den = 1.0 / (a.x * a.x + a.y * a.y);
+    double2 r; r.x = a.x * den; r.y = -a.y * den; return r;
+}
+
+// ---------------------------------------------------------------------------
+// descriptors (plain structs, copied to the device)
+
+constexpr int MAXSLOT = 4;
+
+struct LayerDesc {
+    int index;           // 0-based layer index
+    int first, last;     // owned physical rows (1-based, global)
+    int nl, HL;          // owned physical rows, grid rows (nl + 2 p)
+    int row0;            // extended-grid array row of local array row 0 (= first - 1)
+    int own_r0, own_r1;  // owned local array rows (inclusive)
+    int has_top, has_bot;
+    int nslot;           // interface rows of this layer (0, 2 or 4)
+    int slot_row[MAXSLOT];   // stored slot -> local array row
+    int slot_id[MAXSLOT];    // stored slot -> logical slot (0 top-a, 1 top-b, 2 bot-a, 3 bot-b)
+    int slot_of[MAXSLOT];    // logical slot -> stored slot or -1
+    int cell_begin;      // global index of the layer's first cell
+    int J;               // inner interfaces (cells - 1)
+    long long off_Sinv;  // inner LU: Sinv_j [2HL][2HL], j < J
+    long long off_Lfac;  // L_j^a [HL][2HL], j = 1..J-1 (slot j-1)
+    long long off_inner; // offset (complex elements, per batch column) of the layer's inner vector
+};
+
+struct CellDesc {
+    int layer, cell, gidx;   // layer index, cell index in the layer, global cell index
+    int HL, Wc, nc;          // grid rows, grid columns, owned physical columns
+    int first;               // first owned physical column (1-based, global)
+    int col0;                // extended-grid array column of cell-local array column 0
+    int own_c0, own_c1, s;   // owned cell-local array columns (inclusive), count
+    int has_left, has_right, adj;
+    int nslot;               // = layer nslot
+    int ncol;                // column probes = adj * 2 HL
+    int R;                   // probes = ncol + nslot * s
+    long long off_coef;      // diag/cz/e: [Wc][HL] each
+    long long off_X;         // X_k = S_k^{-1}: [Wc][HL][HL]
+    long long off_Q;         // Q = [M_u | D_loc]: [nslot * s][R]
+    long long off_CS;        // column samples: [adj * HL][R] (left side first)
+};
+
+struct Dims {
+    int n, p, W, L, Lc, K;   // K = L - 1 interfaces
+    double h, omega, beta;
+    int HLmax, Wcmax;
+};
+
+// ---------------------------------------------------------------------------
+// generic segmented GEMM:  out[i] = add0[i] + c1 * add1[i] + alpha * sum_k A[i][k] x[k]
+// for one right-hand-side batch; x rows come from up to NSEG contiguous
+// segments, output rows go to up to NOSEG contiguous segments.
+
+constexpr int NSEG = 6;
+constexpr int NOSEG = 4;
+
+template <typename T>
+struct GemmTask {
+    const C2<T>* A;      // row-major, row stride lda
+    long long lda;
+    int m, k;            // rows, columns (k counts the gathered x rows)
+    int nseg;
+    int seg_k0[NSEG];
+    int seg_len[NSEG];
+    const C2<T>* seg_ptr[NSEG];   // x row r of the segment at seg_ptr + r * ldx (NULL = zeros)
+    int noseg;
+    int oseg_i0[NOSEG];
+    int oseg_len[NOSEG];
+    C2<T>* oseg_ptr[NOSEG];
+    const C2<T>* oseg_add0[NOSEG];
+    const C2<T>* oseg_add1[NOSEG];
+    T c1[NOSEG];
+    T alpha;
+    long long ldx;       // row stride of every x segment (complex elements)
+    long long ldo;       // row stride of the output / add0 / add1 segments
+    int ncol;            // batch columns of this task (0 = the launch's B)
+};
+
+// ---------------------------------------------------------------------------
+// cell solve (Schur recursion) arguments
+
+enum SolveMode { SOLVE_GRID = 0, SOLVE_PROBE = 1, SOLVE_SAMPLE = 2, SOLVE_VOLUME = 3 };
+
+template <typename T>
+struct CellSolveArgs {
+    int mode;
+    int B;               // batch columns handled in total (per cell)
+    const CellDesc* cells;
+    const LayerDesc* layers;
+    const int* cell_list;        // cells handled by this launch (grid.x index -> global cell)
+    const C2<T>* X;              // factor pool
+    const C2<T>* coef_e;         // e pool (same layout as coef, complex)
+    const double2* alpha_x;      // per cell: alpha_x at own nodes [Wcmax] (cell profile), FP64
+    const double2* alpha_z;      // per layer: alpha_z at nodes [HLmax], FP64
+    C2<T>* Y;                    // scratch for the forward sweep: per launch-cell [Wc][HL][B]
+    long long y_stride;          // complex elements per launch-cell in Y
+    // SOLVE_GRID: g/x on the cell grid [HL][Wc][B] (row-major grid) for one cell
+    const C2<T>* g_grid; C2<T>* x_grid;
+    // SOLVE_PROBE: outputs Q (row samples) and CS (column samples) into the pools
+    C2<T>* Qpool; C2<T>* CSpool;
+    int probe0;                  // first probe handled (chunking over R)
+    // SOLVE_SAMPLE / SOLVE_VOLUME: volume source on the extended grid [W][W][B] (or NULL)
+    const C2<T>* f_ext;
+    const int* layer_active;     // per layer: source present (may be NULL = all)
+    // interface-row sources (reconstruction): polarized-style pairs per layer,
+    // top pair / bottom pair pointers given per layer through a table
+    const C2<T>* const* top_pair;   // [L] -> [2][W][B] or NULL
+    const C2<T>* const* bot_pair;   // [L] -> [2][W][B] or NULL
+    const C2<T>* inner_v;        // inner traces (column sources), base of per-layer vectors
+    long long inner_ld;          // per-layer stride in complex elements (J*2*HLmax*B)
+    // outputs
+    C2<T>* inner_rhs;            // SOLVE_SAMPLE: column samples -> inner rhs (per layer)
+    C2<T>* rows_out;             // SOLVE_SAMPLE: row samples [L][nslot=4][W][B]
+    C2<T>* u_ext;                // SOLVE_VOLUME: [W][W][B]
+    double h;
+    int n, p, W, HLmax, Wcmax;
+};
+
+// ---------------------------------------------------------------------------
+// launchers (defined in the .hip files)
+
+void launch_build_coef(const double* model, int model_kind, const Dims& d,
+                       const CellDesc* cells_dev, const LayerDesc* layers_dev, int ncells,
+                       const CellDesc* cells_host, double2* diag, double2* cz, double2* e,
+                       double2* ax_pool, double2* az_pool, double2* gdiag, double2* gcx,
+                       double2* gcz, double2* wext, int* bad_flag, hipStream_t st);
+
+template <typename T>
+void launch_cell_factor(const CellDesc* cells_dev, int ncells, const Dims& d,
+                        const double2* diag, const double2* cz, const double2* e,
+                        C2<T>* Xpool, C2<T>* work, long long work_stride, int* sing_flag,
+                        hipStream_t st);
+
+template <typename T>
+void launch_invert_batch(C2<T>* const* mats, C2<T>* const* outs, const int* ns, int count,
+                         C2<T>* work, long long work_stride, int* sing_flag, hipStream_t st);
+
+template <typename T>
+void launch_cell_solve(const CellSolveArgs<T>& a, int ncells_launch, int nb_chunks,
+                       hipStream_t st);
+
+// B = number of batch columns; ldx/ldo come from the tasks.
+template <typename T>
+void launch_gemm(const GemmTask<T>* tasks_dev, int ntasks, int max_m, int B, hipStream_t st);
+
+// number of right-hand sides one cell-solve workgroup handles for a batch B
+inline int cs_nb(int B) { return B <= 1 ? 1 : (B <= 4 ? 4 : 16); }
+
+// vector / reduction kernels (FP64 unless templated)
+template <typename T>
+void launch_axpby(C2<T>* y, const C2<T>* x, double2 a, double2 b, long long n, hipStream_t st);
+void launch_cast_d2f(float2* y, const double2* x, long long n, hipStream_t st);
+void launch_cast_f2d(double2* y, const float2* x, long long n, hipStream_t st);
+void launch_dots(const double2* V, long long vstride, int nv, const double2* w, long long n,
+                 int B, double2* partial, int nchunks, hipStream_t st);
+void launch_reduce_partials(const double2* partial, int nchunks, int count, double2* out,
+                            hipStream_t st);
+void launch_update_basis(double2* w, const double2* V, long long vstride, int nv,
+                         const double2* coef, long long n, int B, hipStream_t st);
+void launch_scale_cols(double2* y, const double2* x, const double2* s, long long n, int B,
+                       hipStream_t st);
+void launch_norms(const double2* w, long long n, int B, double2* partial, int nchunks,
+                  hipStream_t st);
+void launch_rhs_to_ext(const double2* rhs, int B, int n, int p, int W, double2* f_ext,
+                       const LayerDesc* layers_dev, int L, int* layer_active, hipStream_t st);
+void launch_ext_to_out(const double2* u_ext, int B, int n, int p, int W, double2* out,
+                       int physical, int conj, hipStream_t st);
+void launch_residual(const double2* u, const double2* f, double2* r, const double2* gdiag,
+                     const double2* gcx, const double2* gcz, int W, int B, int layout_bfast,
+                     hipStream_t st);
+void launch_misfit_grad(const double2* u, const double2* lam, int B, int W, int n, int p,
+                        const double2* wext, double omega, double* g, hipStream_t st);
+void launch_misfit(const double2* u_ext, const double2* d_obs, int rec_row, int B, int n, int p,
+                   int W, double2* adj, double* Jpart, hipStream_t st);
+void launch_conj_copy(double2* y, const double2* x, long long n, hipStream_t st);
+void launch_transpose_bfast(const double2* src, double2* dst, int B, long long n, int to_bfast,
+                            hipStream_t st);
+
+}  // namespace hz

@@ -1,0 +1,140 @@
+// Segmented batched complex GEMM:  out = add0 + c1 * add1 + alpha * A x
+// over a list of tasks.  Used for every dense operator application of the
+// interface factorisation (M_f, the inner block LU substitutions, and the
+// combined [M_u | D_loc] output operator), online and offline.
+//
+// x rows are gathered from up to NSEG contiguous segments (trace pairs, inner
+// traces), the output rows are scattered to up to NOSEG contiguous segments,
+// and every vector row holds B batch values contiguously (batch fastest).
+#include "hz_common.h"
+
+namespace hz {
+
+constexpr int GV_THREADS = 256;
+constexpr int GV_ROWS = 16;          // rows per workgroup (4 per wave)
+
+template <typename T>
+__device__ inline C2<T> shfl_down_c(C2<T> v, int d) {
+    C2<T> r;
+    r.x = __shfl_down(v.x, d, 64);
+    r.y = __shfl_down(v.y, d, 64);
+    return r;
+}
+
+template <typename T>
+__device__ inline void epilogue(const GemmTask<T>& t, int i, int b, C2<T> acc) {
+    for (int s = 0; s < t.noseg; ++s) {
+        const int rel = i - t.oseg_i0[s];
+        if (rel >= 0 && rel < t.oseg_len[s]) {
+            const long long off = (long long)rel * t.ldo + b;
+            C2<T> v = cscale(acc, t.alpha);
+            if (t.oseg_add0[s]) v = cadd(v, t.oseg_add0[s][off]);
+            if (t.oseg_add1[s]) v = cadd(v, cscale(t.oseg_add1[s][off], t.c1[s]));
+            t.oseg_ptr[s][off] = v;
+            return;
+        }
+    }
+}
+
+// B == 1: each wave reduces one row at a time, lanes run along k.
+template <typename T>
+__global__ void __launch_bounds__(GV_THREADS) k_gemv(const GemmTask<T>* __restrict__ tasks) {
+    const GemmTask<T> t = tasks[blockIdx.z];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    for (int rr = wave; rr < GV_ROWS; rr += GV_THREADS / 64) {
+        const int i = blockIdx.x * GV_ROWS + rr;
+        if (i >= t.m) break;
+        const C2<T>* Ar = t.A + (long long)i * t.lda;
+        C2<T> acc = mk<T>((T)0, (T)0);
+        for (int s = 0; s < t.nseg; ++s) {
+            const C2<T>* xp = t.seg_ptr[s];
+            if (!xp) continue;
+            const int k0 = t.seg_k0[s], len = t.seg_len[s];
+            for (int kk = lane; kk < len; kk += 64) acc = cfma(Ar[k0 + kk], xp[(long long)kk * t.ldx], acc);
+        }
+        for (int d = 32; d > 0; d >>= 1) {
+            C2<T> o = shfl_down_c<T>(acc, d);
+            acc.x += o.x; acc.y += o.y;
+        }
+        if (lane == 0) epilogue<T>(t, i, 0, acc);
+    }
+}
+
+constexpr int TM = 32, TB = 32, TK = 16;
+
+// B > 1: 32 x 32 output tile, 16-deep k chunks staged in LDS, 2 x 2 per thread.
+template <typename T>
+__global__ void __launch_bounds__(GV_THREADS)
+k_gemm_tiled(const GemmTask<T>* __restrict__ tasks, int B) {
+    const GemmTask<T> t = tasks[blockIdx.z];
+    const int i0 = blockIdx.x * TM;
+    if (i0 >= t.m) return;
+    const int b0 = blockIdx.y * TB;
+    if (t.ncol > 0) B = t.ncol;
+    if (b0 >= B) return;
+    __shared__ C2<T> As[TM][TK + 1];
+    __shared__ C2<T> Xs[TK][TB + 1];
+    const int tid = threadIdx.x;
+    const int tr = (tid / 16) * 2;      // 16 row pairs
+    const int tc = (tid % 16) * 2;      // 16 column pairs
+    C2<T> acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int c = 0; c < 2; ++c) acc[a][c] = mk<T>((T)0, (T)0);
+    for (int s = 0; s < t.nseg; ++s) {
+        const C2<T>* xp = t.seg_ptr[s];
+        if (!xp) continue;
+        const int k0 = t.seg_k0[s], len = t.seg_len[s];
+        for (int kc = 0; kc < len; kc += TK) {
+            __syncthreads();
+            for (int idx = tid; idx < TM * TK; idx += GV_THREADS) {
+                const int r = idx / TK, q = idx % TK;
+                const int i = i0 + r;
+                As[r][q] = (i < t.m && kc + q < len) ? t.A[(long long)i * t.lda + k0 + kc + q]
+                                                     : mk<T>((T)0, (T)0);
+            }
+            for (int idx = tid; idx < TK * TB; idx += GV_THREADS) {
+                const int q = idx / TB, c = idx % TB;
+                const int b = b0 + c;
+                Xs[q][c] = (kc + q < len && b < B) ? xp[(long long)(kc + q) * t.ldx + b]
+                                                   : mk<T>((T)0, (T)0);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < TK; ++q) {
+                const C2<T> a0 = As[tr][q], a1 = As[tr + 1][q];
+                const C2<T> x0 = Xs[q][tc], x1 = Xs[q][tc + 1];
+                acc[0][0] = cfma(a0, x0, acc[0][0]);
+                acc[0][1] = cfma(a0, x1, acc[0][1]);
+                acc[1][0] = cfma(a1, x0, acc[1][0]);
+                acc[1][1] = cfma(a1, x1, acc[1][1]);
+            }
+        }
+    }
+    for (int a = 0; a < 2; ++a) {
+        const int i = i0 + tr + a;
+        if (i >= t.m) continue;
+        for (int c = 0; c < 2; ++c) {
+            const int b = b0 + tc + c;
+            if (b < B) epilogue<T>(t, i, b, acc[a][c]);
+        }
+    }
+}
+
+template <typename T>
+void launch_gemm(const GemmTask<T>* tasks_dev, int ntasks, int max_m, int B, hipStream_t st) {
+    if (ntasks <= 0 || max_m <= 0) return;
+    if (B == 1) {
+        dim3 grid((max_m + GV_ROWS - 1) / GV_ROWS, 1, ntasks);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemv<T>), grid, dim3(GV_THREADS), 0, st, tasks_dev);
+    } else {
+        dim3 grid((max_m + TM - 1) / TM, (B + TB - 1) / TB, ntasks);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_tiled<T>), grid, dim3(GV_THREADS), 0, st,
+                           tasks_dev, B);
+    }
+}
+
+template void launch_gemm<double>(const GemmTask<double>*, int, int, int, hipStream_t);
+template void launch_gemm<float>(const GemmTask<float>*, int, int, int, hipStream_t);
+
+}  // namespace hz

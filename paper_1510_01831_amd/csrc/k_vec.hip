@@ -1,0 +1,472 @@
+// Coefficient construction (App. A), layout conversions, the FP64 residual,
+// the misfit gradient and the reductions of the GMRES driver.
+#include "hz_common.h"
+
+namespace hz {
+
+__device__ inline double model_m(const double* model, int kind, int n, int zpos, int xpos) {
+    // m is extended beyond the physical square by copying the nearest value
+    zpos = zpos < 1 ? 1 : (zpos > n ? n : zpos);
+    xpos = xpos < 1 ? 1 : (xpos > n ? n : xpos);
+    const double v = model[(long long)(zpos - 1) * n + (xpos - 1)];
+    return kind == 0 ? 1.0 / (v * v) : v;
+}
+
+__global__ void k_check_model(const double* model, long long count, int* bad) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
+         i += (long long)gridDim.x * blockDim.x) {
+        const double v = model[i];
+        if (!(v > 0.0) || !isfinite(v)) atomicOr(bad, 1);
+    }
+}
+
+// Symmetric-form 5-point coefficients of every cell grid, stored per grid
+// column: diag, the depth coupling between rows j and j+1, and the coupling
+// e_k between columns k-1 and k.
+__global__ void k_cell_coef(const double* model, int kind, Dims d, const CellDesc* cells,
+                            const LayerDesc* layers, double2* diag, double2* cz, double2* e,
+                            double2* ax_pool, double2* az_pool) {
+    const CellDesc cd = cells[blockIdx.y];
+    const LayerDesc ld = layers[cd.layer];
+    const int p = d.p;
+    const double ih2 = 1.0 / (d.h * d.h);
+    const double w2 = d.omega * d.omega;
+    const long long total = (long long)cd.Wc * cd.HL;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int k = (int)(q / cd.HL), j = (int)(q % cd.HL);
+        const double xp = k - p + 1, zp = j - p + 1;           // local positions
+        const double2 ax = pml_alpha(xp, cd.nc, p, d.beta);
+        const double2 axm = pml_alpha(xp - 0.5, cd.nc, p, d.beta);
+        const double2 axp = pml_alpha(xp + 0.5, cd.nc, p, d.beta);
+        const double2 az = pml_alpha(zp, ld.nl, p, d.beta);
+        const double2 azm = pml_alpha(zp - 0.5, ld.nl, p, d.beta);
+        const double2 azp = pml_alpha(zp + 0.5, ld.nl, p, d.beta);
+        const double2 iax = cinv(ax), iaz = cinv(az);
+        const double m = model_m(model, kind, d.n, ld.first - p + j, cd.first - p + k);
+        double2 t1 = cmul(cadd(axm, axp), iaz);
+        double2 t2 = cmul(cadd(azm, azp), iax);
+        double2 t3 = cmul(iax, iaz);
+        double2 dg;
+        dg.x = (t1.x + t2.x) * ih2 - w2 * m * t3.x;
+        dg.y = (t1.y + t2.y) * ih2 - w2 * m * t3.y;
+        const long long o = cd.off_coef + q;
+        diag[o] = dg;
+        double2 c = cmul(azp, iax);
+        c.x *= -ih2; c.y *= -ih2;
+        cz[o] = c;
+        double2 ev = cmul(axm, iaz);
+        ev.x *= -ih2; ev.y *= -ih2;
+        e[o] = ev;
+        if (j == 0) ax_pool[(long long)cd.gidx * d.Wcmax + k] = ax;
+        if (k == 0 && cd.cell == 0) az_pool[(long long)cd.layer * d.HLmax + j] = az;
+    }
+}
+
+// Global operator (residual of the refinement, Sec. 5 footnote) and the
+// gradient weight w = 1/(alpha_x alpha_z).
+__global__ void k_global_coef(const double* model, int kind, Dims d, double2* gdiag,
+                              double2* gcx, double2* gcz, double2* wext) {
+    const int W = d.W, p = d.p;
+    const double ih2 = 1.0 / (d.h * d.h);
+    const double w2 = d.omega * d.omega;
+    const long long total = (long long)W * W;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int Z = (int)(q / W), X = (int)(q % W);
+        const double xp = X - p + 1, zp = Z - p + 1;
+        const double2 ax = pml_alpha(xp, d.n, p, d.beta);
+        const double2 axm = pml_alpha(xp - 0.5, d.n, p, d.beta);
+        const double2 axp = pml_alpha(xp + 0.5, d.n, p, d.beta);
+        const double2 az = pml_alpha(zp, d.n, p, d.beta);
+        const double2 azm = pml_alpha(zp - 0.5, d.n, p, d.beta);
+        const double2 azp = pml_alpha(zp + 0.5, d.n, p, d.beta);
+        const double2 iax = cinv(ax), iaz = cinv(az);
+        const double m = model_m(model, kind, d.n, (int)zp, (int)xp);
+        double2 t1 = cmul(cadd(axm, axp), iaz);
+        double2 t2 = cmul(cadd(azm, azp), iax);
+        double2 t3 = cmul(iax, iaz);
+        double2 dg;
+        dg.x = (t1.x + t2.x) * ih2 - w2 * m * t3.x;
+        dg.y = (t1.y + t2.y) * ih2 - w2 * m * t3.y;
+        gdiag[q] = dg;
+        double2 cx = cmul(axp, iaz); cx.x *= -ih2; cx.y *= -ih2;
+        double2 c2 = cmul(azp, iax); c2.x *= -ih2; c2.y *= -ih2;
+        gcx[q] = cx;
+        gcz[q] = c2;
+        wext[q] = t3;
+    }
+}
+
+void launch_build_coef(const double* model, int model_kind, const Dims& d,
+                       const CellDesc* cells_dev, const LayerDesc* layers_dev, int ncells,
+                       const CellDesc* cells_host, double2* diag, double2* cz, double2* e,
+                       double2* ax_pool, double2* az_pool, double2* gdiag, double2* gcx,
+                       double2* gcz, double2* wext, int* bad_flag, hipStream_t st) {
+    (void)cells_host;
+    hipLaunchKernelGGL(k_check_model, dim3(256), dim3(256), 0, st, model, (long long)d.n * d.n,
+                       bad_flag);
+    hipLaunchKernelGGL(k_cell_coef, dim3(64, ncells), dim3(256), 0, st, model, model_kind, d,
+                       cells_dev, layers_dev, diag, cz, e, ax_pool, az_pool);
+    hipLaunchKernelGGL(k_global_coef, dim3(1024), dim3(256), 0, st, model, model_kind, d, gdiag,
+                       gcx, gcz, wext);
+}
+
+// ---------------------------------------------------------------------------
+// elementwise helpers
+
+template <typename T>
+__global__ void k_axpby(C2<T>* y, const C2<T>* x, double2 a, double2 b, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        C2<T> xv = x ? x[i] : mk<T>((T)0, (T)0);
+        C2<T> yv = y[i];
+        C2<T> ta = mk<T>((T)a.x, (T)a.y), tb = mk<T>((T)b.x, (T)b.y);
+        y[i] = cadd(cmul(ta, xv), cmul(tb, yv));
+    }
+}
+
+template <typename T>
+void launch_axpby(C2<T>* y, const C2<T>* x, double2 a, double2 b, long long n, hipStream_t st) {
+    if (n <= 0) return;
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_axpby<T>), dim3(blocks), dim3(256), 0, st, y, x, a, b, n);
+}
+template void launch_axpby<double>(double2*, const double2*, double2, double2, long long, hipStream_t);
+template void launch_axpby<float>(float2*, const float2*, double2, double2, long long, hipStream_t);
+
+__global__ void k_cast_d2f(float2* y, const double2* x, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        double2 v = x[i];
+        y[i] = make_float2((float)v.x, (float)v.y);
+    }
+}
+__global__ void k_cast_f2d(double2* y, const float2* x, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        float2 v = x[i];
+        y[i] = make_double2((double)v.x, (double)v.y);
+    }
+}
+void launch_cast_d2f(float2* y, const double2* x, long long n, hipStream_t st) {
+    if (n <= 0) return;
+    int blocks = (int)std::min<long long>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_cast_d2f, dim3(blocks), dim3(256), 0, st, y, x, n);
+}
+void launch_cast_f2d(double2* y, const float2* x, long long n, hipStream_t st) {
+    if (n <= 0) return;
+    int blocks = (int)std::min<long long>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_cast_f2d, dim3(blocks), dim3(256), 0, st, y, x, n);
+}
+
+__global__ void k_conj_copy(double2* y, const double2* x, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        double2 v = x[i];
+        y[i] = make_double2(v.x, -v.y);
+    }
+}
+void launch_conj_copy(double2* y, const double2* x, long long n, hipStream_t st) {
+    if (n <= 0) return;
+    int blocks = (int)std::min<long long>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_conj_copy, dim3(blocks), dim3(256), 0, st, y, x, n);
+}
+
+// ---------------------------------------------------------------------------
+// GMRES reductions on batch-fastest vectors: element (i, b) at i * B + b.
+
+constexpr int RD_THREADS = 256;
+
+// partial[(chunk * nv + v) * B + b] = sum_{i in chunk} conj(V_v[i,b]) w[i,b]
+__global__ void __launch_bounds__(RD_THREADS)
+k_dots(const double2* V, long long vstride, const double2* w, long long n, int B,
+       double2* partial, int nchunks) {
+    __shared__ double2 red[RD_THREADS];
+    const int v = blockIdx.y;
+    const int tid = threadIdx.x;
+    const int per = RD_THREADS / B > 0 ? RD_THREADS / B : 1;     // threads per column
+    const int bcols = B < RD_THREADS ? B : RD_THREADS;
+    const double2* Vv = V ? V + v * vstride : w;
+    const long long chunk = (n + nchunks - 1) / nchunks;
+    const long long i0 = blockIdx.x * chunk;
+    const long long i1 = (i0 + chunk < n) ? i0 + chunk : n;
+    for (int bb = 0; bb < B; bb += bcols) {
+        double2 acc = make_double2(0.0, 0.0);
+        const int b = bb + tid % bcols;
+        const int sub = tid / bcols;
+        if (sub < per && b < B) {
+            for (long long i = i0 + sub; i < i1; i += per) {
+                const double2 a = Vv[i * B + b];
+                const double2 c = w[i * B + b];
+                acc.x += a.x * c.x + a.y * c.y;
+                acc.y += a.x * c.y - a.y * c.x;
+            }
+        }
+        red[tid] = acc;
+        __syncthreads();
+        if (tid < bcols && bb + tid < B) {
+            double2 s = make_double2(0.0, 0.0);
+            for (int q = 0; q < per; ++q) {
+                double2 r = red[q * bcols + tid];
+                s.x += r.x; s.y += r.y;
+            }
+            partial[((long long)blockIdx.x * gridDim.y + v) * B + bb + tid] = s;
+        }
+        __syncthreads();
+    }
+}
+
+void launch_dots(const double2* V, long long vstride, int nv, const double2* w, long long n,
+                 int B, double2* partial, int nchunks, hipStream_t st) {
+    hipLaunchKernelGGL(k_dots, dim3(nchunks, nv), dim3(RD_THREADS), 0, st, V, vstride, w, n, B,
+                       partial, nchunks);
+}
+
+void launch_norms(const double2* w, long long n, int B, double2* partial, int nchunks,
+                  hipStream_t st) {
+    hipLaunchKernelGGL(k_dots, dim3(nchunks, 1), dim3(RD_THREADS), 0, st, nullptr, 0LL, w, n, B,
+                       partial, nchunks);
+}
+
+__global__ void k_reduce_partials(const double2* partial, int nchunks, int count, double2* out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= count) return;
+    double2 s = make_double2(0.0, 0.0);
+    for (int c = 0; c < nchunks; ++c) {
+        double2 v = partial[(long long)c * count + q];
+        s.x += v.x; s.y += v.y;
+    }
+    out[q] = s;
+}
+void launch_reduce_partials(const double2* partial, int nchunks, int count, double2* out,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_partials, dim3((count + 255) / 256), dim3(256), 0, st, partial,
+                       nchunks, count, out);
+}
+
+// w[i,b] += sum_v coef[v,b] V_v[i,b]
+__global__ void k_update_basis(double2* w, const double2* V, long long vstride, int nv,
+                               const double2* coef, long long n, int B) {
+    const long long total = n * B;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int b = (int)(q % B);
+        double2 acc = w[q];
+        for (int v = 0; v < nv; ++v) {
+            const double2 c = coef[(long long)v * B + b];
+            const double2 x = V[v * vstride + q];
+            acc.x += c.x * x.x - c.y * x.y;
+            acc.y += c.x * x.y + c.y * x.x;
+        }
+        w[q] = acc;
+    }
+}
+void launch_update_basis(double2* w, const double2* V, long long vstride, int nv,
+                         const double2* coef, long long n, int B, hipStream_t st) {
+    const long long total = n * B;
+    int blocks = (int)std::min<long long>((total + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_update_basis, dim3(blocks), dim3(256), 0, st, w, V, vstride, nv, coef,
+                       n, B);
+}
+
+__global__ void k_scale_cols(double2* y, const double2* x, const double2* s, long long n, int B) {
+    const long long total = n * B;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
+         q += (long long)gridDim.x * blockDim.x) {
+        const double2 c = s[q % B];
+        const double2 v = x[q];
+        y[q] = make_double2(c.x * v.x - c.y * v.y, c.x * v.y + c.y * v.x);
+    }
+}
+void launch_scale_cols(double2* y, const double2* x, const double2* s, long long n, int B,
+                       hipStream_t st) {
+    const long long total = n * B;
+    int blocks = (int)std::min<long long>((total + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_scale_cols, dim3(blocks), dim3(256), 0, st, y, x, s, n, B);
+}
+
+// ---------------------------------------------------------------------------
+// layout conversions
+
+// rhs[b][z][x] (physical) -> f_ext[Z][X][b] (extended, batch fastest), and
+// flag the layers whose owned rows carry a nonzero source.
+__global__ void k_rhs_to_ext(const double2* rhs, int B, int n, int p, int W, double2* f_ext,
+                             const LayerDesc* layers, int L, int* active, int conj) {
+    const long long total = (long long)W * W * B;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int b = (int)(q % B);
+        const long long node = q / B;
+        const int Z = (int)(node / W), X = (int)(node % W);
+        double2 v = make_double2(0.0, 0.0);
+        if (Z >= p && Z < p + n && X >= p && X < p + n) {
+            v = rhs[((long long)b * n + (Z - p)) * n + (X - p)];
+            if (conj) v.y = -v.y;
+            if (active && (v.x != 0.0 || v.y != 0.0)) {
+                // layer of extended row Z: owned rows are [row0 + own_r0, row0 + own_r1]
+                for (int l = 0; l < L; ++l) {
+                    const int lo = layers[l].row0 + layers[l].own_r0;
+                    const int hi = layers[l].row0 + layers[l].own_r1;
+                    if (Z >= lo && Z <= hi) { atomicOr(&active[l], 1); break; }
+                }
+            }
+        }
+        f_ext[q] = v;
+    }
+}
+void launch_rhs_to_ext(const double2* rhs, int B, int n, int p, int W, double2* f_ext,
+                       const LayerDesc* layers_dev, int L, int* layer_active, hipStream_t st) {
+    const long long total = (long long)W * W * B;
+    int blocks = (int)std::min<long long>((total + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_rhs_to_ext, dim3(blocks), dim3(256), 0, st, rhs, B, n, p, W, f_ext,
+                       layers_dev, L, layer_active, 0);
+}
+
+// u_ext[Z][X][b] -> out[b][z][x] (physical) or out[b][Z][X] (extended)
+__global__ void k_ext_to_out(const double2* u, int B, int n, int p, int W, double2* out,
+                             int physical, int conj) {
+    const int side = physical ? n : W;
+    const long long total = (long long)side * side * B;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int b = (int)(q / ((long long)side * side));
+        const long long r = q % ((long long)side * side);
+        const int z = (int)(r / side), x = (int)(r % side);
+        const int Z = physical ? z + p : z, X = physical ? x + p : x;
+        double2 v = u[((long long)Z * W + X) * B + b];
+        if (conj) v.y = -v.y;
+        out[q] = v;
+    }
+}
+void launch_ext_to_out(const double2* u_ext, int B, int n, int p, int W, double2* out,
+                       int physical, int conj, hipStream_t st) {
+    const int side = physical ? n : W;
+    const long long total = (long long)side * side * B;
+    int blocks = (int)std::min<long long>((total + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_ext_to_out, dim3(blocks), dim3(256), 0, st, u_ext, B, n, p, W, out,
+                       physical, conj);
+}
+
+__global__ void k_transpose_bfast(const double2* src, double2* dst, int B, long long n, int to_bfast) {
+    const long long total = n * B;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
+         q += (long long)gridDim.x * blockDim.x) {
+        // q indexes the destination
+        if (to_bfast) {
+            const long long i = q / B; const int b = (int)(q % B);
+            dst[q] = src[(long long)b * n + i];
+        } else {
+            const int b = (int)(q / n); const long long i = q % n;
+            dst[q] = src[i * B + b];
+        }
+    }
+}
+void launch_transpose_bfast(const double2* src, double2* dst, int B, long long n, int to_bfast,
+                            hipStream_t st) {
+    const long long total = n * B;
+    int blocks = (int)std::min<long long>((total + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_transpose_bfast, dim3(blocks), dim3(256), 0, st, src, dst, B, n, to_bfast);
+}
+
+// ---------------------------------------------------------------------------
+// r = f - H u on the extended grid (FP64)
+__global__ void k_residual(const double2* u, const double2* f, double2* r, const double2* gd,
+                           const double2* gcx, const double2* gcz, int W, int B, int bfast) {
+    const long long total = (long long)W * W * B;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
+         q += (long long)gridDim.x * blockDim.x) {
+        int b, Z, X;
+        if (bfast) { b = (int)(q % B); long long node = q / B; Z = (int)(node / W); X = (int)(node % W); }
+        else { b = (int)(q / ((long long)W * W)); long long node = q % ((long long)W * W); Z = (int)(node / W); X = (int)(node % W); }
+        auto idx = [&](int z, int x) -> long long {
+            return bfast ? (((long long)z * W + x) * B + b) : ((long long)b * W * W + (long long)z * W + x);
+        };
+        const long long g = (long long)Z * W + X;
+        double2 acc = cmul(gd[g], u[q]);
+        if (X + 1 < W) acc = cfma(gcx[g], u[idx(Z, X + 1)], acc);
+        if (X > 0) acc = cfma(gcx[g - 1], u[idx(Z, X - 1)], acc);
+        if (Z + 1 < W) acc = cfma(gcz[g], u[idx(Z + 1, X)], acc);
+        if (Z > 0) acc = cfma(gcz[g - W], u[idx(Z - 1, X)], acc);
+        const double2 fv = f ? f[q] : make_double2(0.0, 0.0);
+        r[q] = make_double2(fv.x - acc.x, fv.y - acc.y);
+    }
+}
+void launch_residual(const double2* u, const double2* f, double2* r, const double2* gdiag,
+                     const double2* gcx, const double2* gcz, int W, int B, int layout_bfast,
+                     hipStream_t st) {
+    const long long total = (long long)W * W * B;
+    int blocks = (int)std::min<long long>((total + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_residual, dim3(blocks), dim3(256), 0, st, u, f, r, gdiag, gcx, gcz, W, B,
+                       layout_bfast);
+}
+
+// r = P u - d on the receiver row; adjoint source P^T r; partial sums of |r|^2
+__global__ void k_misfit(const double2* u, const double2* d, int rec_row, int B, int n, int p,
+                         int W, double2* adj, double* Jpart) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    const long long total = (long long)B * n * n;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int b = (int)(q / ((long long)n * n));
+        const long long rr = q % ((long long)n * n);
+        const int z = (int)(rr / n), x = (int)(rr % n);
+        double2 v = make_double2(0.0, 0.0);
+        if (z == rec_row - 1) {
+            const double2 uv = u[(long long)b * W * W + (long long)(z + p) * W + (x + p)];
+            const double2 dv = d[(long long)b * n + x];
+            v = make_double2(uv.x - dv.x, uv.y - dv.y);
+            acc += v.x * v.x + v.y * v.y;
+        }
+        adj[q] = v;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) Jpart[blockIdx.x] = red[0];
+}
+void launch_misfit(const double2* u_ext, const double2* d_obs, int rec_row, int B, int n, int p,
+                   int W, double2* adj, double* Jpart, hipStream_t st) {
+    hipLaunchKernelGGL(k_misfit, dim3(256), dim3(256), 0, st, u_ext, d_obs, rec_row, B, n, p, W,
+                       adj, Jpart);
+}
+
+// g[k] = omega^2 Re sum_b sum_{e -> k} w_e u_b[e] conj(lam_b[e]); u, lam: [b][Z][X]
+__global__ void k_misfit_grad(const double2* u, const double2* lam, int B, int W, int n, int p,
+                              const double2* wext, double omega, double* g) {
+    const long long total = (long long)n * n;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int z = (int)(q / n), x = (int)(q % n);     // physical, 0-based
+        const int Z0 = (z == 0) ? 0 : z + p, Z1 = (z == n - 1) ? W - 1 : z + p;
+        const int X0 = (x == 0) ? 0 : x + p, X1 = (x == n - 1) ? W - 1 : x + p;
+        double acc = 0.0;
+        for (int Z = Z0; Z <= Z1; ++Z)
+            for (int X = X0; X <= X1; ++X) {
+                const long long e = (long long)Z * W + X;
+                const double2 w = wext[e];
+                for (int b = 0; b < B; ++b) {
+                    const double2 a = u[(long long)b * W * W + e];
+                    const double2 l = lam[(long long)b * W * W + e];
+                    // u * conj(lam)
+                    const double2 t = make_double2(a.x * l.x + a.y * l.y, a.y * l.x - a.x * l.y);
+                    acc += w.x * t.x - w.y * t.y;
+                }
+            }
+        g[q] = omega * omega * acc;
+    }
+}
+void launch_misfit_grad(const double2* u, const double2* lam, int B, int W, int n, int p,
+                        const double2* wext, double omega, double* g, hipStream_t st) {
+    const long long total = (long long)n * n;
+    int blocks = (int)std::min<long long>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_misfit_grad, dim3(blocks), dim3(256), 0, st, u, lam, B, W, n, p, wext,
+                       omega, g);
+}
+
+}  // namespace hz
