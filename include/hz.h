@@ -59,8 +59,16 @@ typedef enum {
 
 typedef enum {
     HZ_FP64 = 0,        /* everything in complex128 */
-    HZ_MIXED = 1        /* complex64 local operators as an approximate inverse,
-                           complex128 GMRES, residual and refinement */
+    HZ_MIXED = 1,       /* the Gauss-Seidel preconditioner (the sequential
+                           sweeps) applies complex64 copies of the interface
+                           operators with FP32 accumulation; the SIE matrix,
+                           the volume solves and the flexible GMRES stay in
+                           complex128 (Sec. 5: a low-accuracy operator for the
+                           preconditioner, a high-accuracy one for M) */
+    HZ_MIXED_REFINE = 2 /* every local operator (cell factors, interface
+                           operators, sweeps) in complex64 as an approximate
+                           inverse, wrapped in FP64 iterative refinement on
+                           the volume: u += Hhat^{-1}(f - H u) */
 } hz_precision;
 
 typedef enum {
@@ -85,7 +93,9 @@ typedef struct {
     int iters;               /* outer GMRES iterations (summed over refinement steps) */
     double rel_resid;        /* final preconditioned relative residual of the SIE */
     double vol_resid;        /* ||f - H u|| / ||f|| on the extended grid (FP64) */
-    int refine_steps;        /* HZ_MIXED: refinement steps; HZ_FP64: 0 */
+    int refine_steps;        /* HZ_MIXED_REFINE: refinement steps; otherwise 0 */
+    double err_est;          /* HZ_MIXED_REFINE: estimated relative error of u from the
+                                observed contraction of the updates; otherwise 0 */
 } hz_rhs_stats;
 
 typedef struct {
@@ -122,8 +132,10 @@ hz_status hz_factor(hz_ctx* ctx);
 /* Online stage (Alg. 6): solve H u = f for B right-hand sides.
  * rhs_dev: B x n_z x n_x complex128 (physical grid, zero-extended into the
  * PML); u_dev: B x n_z x n_x complex128 output (may not alias rhs_dev).
- * tol: relative tolerance of the preconditioned SIE residual per RHS
- * (HZ_FP64), or target of the relative refinement update (HZ_MIXED).
+ * tol: per RHS, relative tolerance of the preconditioned SIE residual
+ * (HZ_FP64, left-preconditioned GMRES), of the unpreconditioned SIE residual
+ * (HZ_MIXED, flexible right-preconditioned GMRES), or of the estimated
+ * relative error of the refined volume solution (HZ_MIXED_REFINE).
  * max_iter: GMRES iterations per solve (also the Krylov dimension).
  * stats_host: B entries or NULL.  timing: or NULL.
  * HZ_ENOCONV: u_dev holds the last iterate; stats say which RHS failed. */
@@ -172,6 +184,22 @@ hz_status hz_update_model(hz_ctx* ctx, const double* model_dev);
 /* Enqueue all further work of ctx on `hip_stream` (a hipStream_t, or NULL for
  * the null stream). */
 hz_status hz_set_stream(hz_ctx* ctx, void* hip_stream);
+
+/* Kernel timing for roofline measurements.  While profiling is on, every
+ * launch of the solver's dense kernels is bracketed by HIP events on the
+ * context's stream, and its algorithmic traffic (each operator entry and
+ * vector element the method must read or write, counted once per launch)
+ * and flops are accumulated per kernel family.  hz_profile(ctx, 1) clears
+ * the counters; hz_profile_read fills up to `max` records. */
+typedef struct {
+    char name[32];           /* kernel family */
+    int launches;
+    double ms;               /* summed launch durations (event to event) */
+    double bytes;            /* summed algorithmic bytes */
+    double flops;            /* summed algorithmic flops */
+} hz_kstat;
+hz_status hz_profile(hz_ctx* ctx, int on);
+hz_status hz_profile_read(hz_ctx* ctx, hz_kstat* out, int max, int* count);
 
 hz_status hz_get_info(const hz_ctx* ctx, hz_info_t* info);
 hz_status hz_get_timing(const hz_ctx* ctx, hz_timing* timing);

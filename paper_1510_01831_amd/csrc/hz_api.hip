@@ -7,8 +7,10 @@
 //                (Sec. 4.2.2)
 //  hz_solve   -- Alg. 6: RHS formation (Alg. 7 volume mode in the layers that
 //                hold sources), GMRES on P^GS M (Sec. 3.1), reconstruction
-//                (Alg. 7 volume mode in every layer); HZ_MIXED wraps it in an
-//                FP64 iterative refinement on the volume.
+//                (Alg. 7 volume mode in every layer).  HZ_MIXED applies the
+//                preconditioner with complex64 operators inside flexible
+//                GMRES; HZ_MIXED_REFINE runs the whole solve in complex64
+//                inside an FP64 iterative refinement on the volume.
 //
 // Every dense operator application is a list of GemmTask records executed by
 // the segmented GEMM kernels; the lists of the GMRES operators (M and P^GS)
@@ -20,6 +22,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -101,6 +104,7 @@ struct LaunchRec {
     long long off;        // first task
     int ntasks, max_m;
     C2<T>* y; const C2<T>* x; double2 a, b; long long n;   // vector ops
+    double bytes, flops;  // algorithmic traffic / work of a GEMM launch
 };
 
 template <typename T>
@@ -150,6 +154,15 @@ struct Work {
     std::map<int, std::unique_ptr<Plan<T>>> sie, pre;
 };
 
+struct Prof {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t next = 0;
+    struct Pending { std::string fam; size_t e0, e1; double bytes, flops; };
+    std::vector<Pending> pend;
+    std::map<std::string, hz_kstat> acc;
+};
+
 }  // namespace
 
 struct hz_ctx {
@@ -176,11 +189,13 @@ struct hz_ctx {
     Work<float> w32;
     // FP64 GMRES / refinement workspace
     int g_cap_B = 0, g_cap_m = 0;
+    double2 *Z = nullptr;          // flexible GMRES: preconditioned basis
     double2 *V = nullptr, *gw = nullptr, *gb = nullptr, *gx = nullptr, *gpart = nullptr,
             *gsmall = nullptr, *gcoef = nullptr;
     int gpart_chunks = 0;
     double2 *u64 = nullptr, *f64 = nullptr, *r64 = nullptr;   // refinement [W][W][B]
     hz_timing timing{};
+    Prof prof;
 };
 
 namespace {
@@ -305,6 +320,44 @@ void upload(hz_ctx* c, void* dst, const void* src, size_t bytes) {
 }
 
 // ---------------------------------------------------------------------------
+// profiling (events on the context stream around each dense launch)
+
+size_t prof_event(hz_ctx* c) {
+    Prof& P = c->prof;
+    if (P.next == P.pool.size()) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        P.pool.push_back(e);
+    }
+    const size_t i = P.next++;
+    HIPCHK(hipEventRecord(P.pool[i], c->st));
+    return i;
+}
+
+void prof_flush(hz_ctx* c) {
+    Prof& P = c->prof;
+    if (P.pend.empty()) { P.next = 0; return; }
+    sync(c);
+    for (const auto& q : P.pend) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, P.pool[q.e0], P.pool[q.e1]));
+        hz_kstat& k = P.acc[q.fam];
+        std::snprintf(k.name, sizeof(k.name), "%s", q.fam.c_str());
+        k.launches += 1;
+        k.ms += ms;
+        k.bytes += q.bytes;
+        k.flops += q.flops;
+    }
+    P.pend.clear();
+    P.next = 0;
+}
+
+template <typename T>
+std::string fam_name(const char* base) {
+    return std::string(base) + (sizeof(T) == sizeof(double) ? "_c128" : "_c64");
+}
+
+// ---------------------------------------------------------------------------
 // GEMM plans for layer jobs (design: phases M_f -> inner LU -> [M_u | D_loc])
 
 template <typename T>
@@ -321,12 +374,29 @@ const C2<T>* pair_row(const C2<T>* pair, int row, int col, int W, int B) {
 }
 
 template <typename T>
-void add_launch(Plan<T>& pl, long long first, int maxm) {
+void add_launch(Plan<T>& pl, long long first, int maxm, int B) {
     LaunchRec<T> r{};
     r.kind = L_GEMM;
     r.off = first;
     r.ntasks = (int)(pl.tasks.size() - first);
     r.max_m = maxm;
+    // algorithmic traffic: every operator entry that meets a nonzero input
+    // segment, every input and output vector element, every addend
+    double bytes = 0, flops = 0;
+    const double cs = sizeof(C2<T>);
+    for (size_t q = first; q < pl.tasks.size(); ++q) {
+        const GemmTask<T>& t = pl.tasks[q];
+        long long kk = 0;
+        for (int s = 0; s < t.nseg; ++s)
+            if (t.seg_ptr[s]) kk += t.seg_len[s];
+        int adds = 0;
+        for (int s = 0; s < t.noseg; ++s) adds += (t.oseg_add0[s] != nullptr) + (t.oseg_add1[s] != nullptr);
+        const int nb = t.ncol > 0 ? t.ncol : B;
+        bytes += cs * ((double)t.m * kk + (double)kk * nb + (double)t.m * nb * (1.0 + (t.noseg ? (double)adds / t.noseg : 0.0)));
+        flops += 8.0 * t.m * kk * nb;
+    }
+    r.bytes = bytes;
+    r.flops = flops;
     if (r.ntasks > 0) pl.launches.push_back(r);
 }
 
@@ -391,7 +461,7 @@ void plan_jobs(hz_ctx* c, Plan<T>& pl, const std::vector<LayerJob<T>>& jobs, int
                 pl.tasks.push_back(t);
             }
         }
-        add_launch(pl, first, maxm);
+        add_launch(pl, first, maxm, B);
         // ---- phase 2: block LU substitutions across the cells (inner sweeps)
         for (int j = 1; j < J; ++j) {                       // forward
             long long f2 = pl.tasks.size();
@@ -415,7 +485,7 @@ void plan_jobs(hz_ctx* c, Plan<T>& pl, const std::vector<LayerJob<T>>& jobs, int
                 mm = std::max(mm, t.m);
                 pl.tasks.push_back(t);
             }
-            add_launch(pl, f2, mm);
+            add_launch(pl, f2, mm, B);
         }
         for (int j = J - 1; j >= 0; --j) {                  // backward
             if (j < J - 1) {
@@ -443,7 +513,7 @@ void plan_jobs(hz_ctx* c, Plan<T>& pl, const std::vector<LayerJob<T>>& jobs, int
                     mm = std::max(mm, t.m);
                     pl.tasks.push_back(t);
                 }
-                add_launch(pl, f2, mm);
+                add_launch(pl, f2, mm, B);
             }
             long long f2 = pl.tasks.size();
             int mm = 0;
@@ -464,7 +534,7 @@ void plan_jobs(hz_ctx* c, Plan<T>& pl, const std::vector<LayerJob<T>>& jobs, int
                 mm = std::max(mm, t.m);
                 pl.tasks.push_back(t);
             }
-            add_launch(pl, f2, mm);
+            add_launch(pl, f2, mm, B);
         }
     }
     // ---- phase 3: samples on the requested interface rows
@@ -522,7 +592,7 @@ void plan_jobs(hz_ctx* c, Plan<T>& pl, const std::vector<LayerJob<T>>& jobs, int
             pl.tasks.push_back(t);
         }
     }
-    add_launch(pl, first, maxm);
+    add_launch(pl, first, maxm, B);
 }
 
 template <typename T>
@@ -539,9 +609,16 @@ void plan_upload(hz_ctx* c, Plan<T>& pl) {
 
 template <typename T>
 void plan_run(hz_ctx* c, const Plan<T>& pl, int B) {
+    const bool prof = c->prof.on;
+    const std::string fam = fam_name<T>(B == 1 ? "layer_gemv" : "layer_gemm");
     for (const auto& r : pl.launches) {
         if (r.kind == L_GEMM) {
+            size_t e0 = prof ? prof_event(c) : 0;
             launch_gemm<T>(pl.dev + r.off, r.ntasks, r.max_m, B, c->st);
+            if (prof) {
+                size_t e1 = prof_event(c);
+                c->prof.pend.push_back({fam, e0, e1, r.bytes, r.flops});
+            }
         } else if (r.kind == L_AXPBY) {
             launch_axpby<T>(r.y, r.x, r.a, r.b, r.n, c->st);
         } else if (r.kind == L_COPY) {
@@ -685,20 +762,32 @@ Plan<T>& get_plan(hz_ctx* c, bool sie, int B) {
 // ---------------------------------------------------------------------------
 // workspaces
 
+// Workspaces for batches up to max_batch.  `volume` adds the volume-solve
+// buffers (sources, solutions, cell-solve scratch); the vectors of the
+// interface operators are always allocated.
 template <typename T>
-void ensure_work(hz_ctx* c, int B) {
+void ensure_work(hz_ctx* c, int B, bool volume = true) {
     Work<T>& w = work<T>(c);
-    if (w.Bcap >= B) return;
-    if (w.Bcap > 0) raise(HZ_EINVAL, "batch larger than max_batch");
     const Dims& d = c->d;
     const long long W = d.W;
+    if (B > std::max(c->prm.max_batch, 1)) raise(HZ_EINVAL, "batch larger than max_batch");
     B = std::max(B, c->prm.max_batch);
+    if (volume && !w.f_ext) {
+        w.f_ext = alloc_c<T>(c, W * W * B);
+        w.u_ext = alloc_c<T>(c, W * W * B);
+        w.rows_out = alloc_c<T>(c, (long long)d.L * MAXSLOT * W * B);
+        const long long inner = std::max<long long>((long long)d.L * c->inner_per_layer * B, 1);
+        w.gf = alloc_c<T>(c, inner);
+        // cell-solve scratch: one region per workgroup of a volume solve
+        const int nb = cs_nb(B);
+        const int chunks = (B + nb - 1) / nb;
+        w.y_stride = (long long)d.Wcmax * d.HLmax * nb;
+        w.y_wgs = (int)c->cells.size() * chunks;
+        w.Y = alloc_c<T>(c, w.y_stride * w.y_wgs);
+    }
+    if (w.Bcap >= B) return;
     w.Bcap = B;
-    w.f_ext = alloc_c<T>(c, W * W * B);
-    w.u_ext = alloc_c<T>(c, W * W * B);
-    w.rows_out = alloc_c<T>(c, (long long)d.L * MAXSLOT * W * B);
     const long long inner = std::max<long long>((long long)d.L * c->inner_per_layer * B, 1);
-    w.gf = alloc_c<T>(c, inner);
     for (int s = 0; s < 2; ++s) {
         w.iy[s] = alloc_c<T>(c, inner);
         w.ix[s] = alloc_c<T>(c, inner);
@@ -708,12 +797,6 @@ void ensure_work(hz_ctx* c, int B) {
     w.pB = alloc_c<T>(c, pol);
     w.pC = alloc_c<T>(c, pol);
     w.sv = alloc_c<T>(c, std::max<long long>(2LL * d.K * W * B, 1));
-    // cell-solve scratch: one region per workgroup of a volume solve
-    const int nb = cs_nb(B);
-    const int chunks = (B + nb - 1) / nb;
-    w.y_stride = (long long)d.Wcmax * d.HLmax * nb;
-    w.y_wgs = (int)c->cells.size() * chunks;
-    w.Y = alloc_c<T>(c, w.y_stride * w.y_wgs);
     w.pair_tab = (const C2<T>**)c->arena.alloc(sizeof(C2<T>*) * 2 * d.L);
 }
 
@@ -749,6 +832,10 @@ void ensure_gmres(hz_ctx* c, int B, int m) {
     c->g_cap_m = m;
     const long long nb = std::max<long long>(n * B, 1);
     c->V = (double2*)c->arena.alloc(sizeof(double2) * nb * (m + 1));
+    if (c->prm.precision == HZ_MIXED) {
+        if (c->Z) c->arena.release(c->Z, 0);
+        c->Z = (double2*)c->arena.alloc(sizeof(double2) * nb * m);
+    }
     c->gw = (double2*)c->arena.alloc(sizeof(double2) * nb);
     c->gb = (double2*)c->arena.alloc(sizeof(double2) * nb);
     c->gx = (double2*)c->arena.alloc(sizeof(double2) * nb);
@@ -770,14 +857,29 @@ void cell_solve_launch(hz_ctx* c, CellSolveArgs<T> a, const std::vector<int>& li
     const int per = std::max(1, w.y_wgs / chunks);
     int* d_list = (int*)c->arena.alloc(sizeof(int) * list.size());
     upload(c, d_list, list.data(), sizeof(int) * list.size());
+    const bool prof = c->prof.on;
     for (size_t g = 0; g < list.size(); g += per) {
         const int cnt = (int)std::min<size_t>(per, list.size() - g);
         a.cell_list = d_list + g;
         a.B = Bcols;
         a.Y = w.Y;
         a.y_stride = (long long)c->d.Wcmax * c->d.HLmax * nb;
+        size_t e0 = prof ? prof_event(c) : 0;
         launch_cell_solve<T>(a, cnt, chunks, c->st);
         HIPCHK(hipGetLastError());
+        if (prof) {
+            size_t e1 = prof_event(c);
+            double bytes = 0, flops = 0;
+            for (int q = 0; q < cnt; ++q) {
+                const CellDesc& cd = c->cells[list[g + q]];
+                const double blk = (double)cd.Wc * cd.HL * cd.HL;
+                // factors read in both sweeps, forward iterates written and
+                // read back, one source and one result per grid node
+                bytes += sizeof(C2<T>) * (2.0 * blk + 4.0 * (double)cd.Wc * cd.HL * Bcols);
+                flops += 16.0 * blk * Bcols;
+            }
+            c->prof.pend.push_back({fam_name<T>("cell_solve"), e0, e1, bytes, flops});
+        }
     }
     sync(c);
     c->arena.release(d_list, sizeof(int) * list.size());
@@ -982,8 +1084,8 @@ void factor_impl(hz_ctx* c) {
         c->arena.release(ns, sizeof(int) * L);
         c->arena.release(tdev, sizeof(GemmTask<double>) * 2 * L);
     }
-    // 4. mixed precision: keep complex64 copies of every operator
-    if (c->prm.precision == HZ_MIXED) {
+    // 4. mixed precision: complex64 copies of every operator
+    if (c->prm.precision != HZ_FP64) {
         Ops<float>& f = c->o32;
         auto cast = [&](float2*& dst, const double2* src, long long n) {
             if (!dst) dst = alloc_c<float>(c, std::max<long long>(n, 1));
@@ -999,6 +1101,8 @@ void factor_impl(hz_ctx* c) {
         cast(f.Lfac, o.Lfac, c->Lfac_elems);
         HIPCHK(hipGetLastError());
         sync(c);
+    }
+    if (c->prm.precision == HZ_MIXED_REFINE) {      // the FP64 operators are not used
         c->arena.release(o.X, sizeof(double2) * c->X_elems);
         c->arena.release(o.Q, sizeof(double2) * std::max<long long>(c->Q_elems, 1));
         c->arena.release(o.CS, sizeof(double2) * std::max<long long>(c->CS_elems, 1));
@@ -1177,17 +1281,37 @@ void norms(hz_ctx* c, const double2* w, long long n, int B, std::vector<double>&
     for (int b = 0; b < B; ++b) out[b] = std::sqrt(std::max(0.0, t[b].real()));
 }
 
-// Left-preconditioned GMRES (Alg. 6) on FP64 vectors, x0 = 0, no restart,
-// classical Gram-Schmidt with one re-orthogonalisation, Givens rotations.
+// M on FP64 vectors with the FP64 operators
+void apply_M64(hz_ctx* c, const double2* x, double2* y, int B) {
+    Work<double>& w = c->w64;
+    const long long n = 4LL * c->d.K * c->d.W * B;
+    Plan<double>& ps = get_plan<double>(c, true, B);
+    HIPCHK(hipMemcpyAsync(w.pA, x, sizeof(double2) * n, hipMemcpyDeviceToDevice, c->st));
+    plan_run<double>(c, ps, B);
+    HIPCHK(hipMemcpyAsync(y, w.pB, sizeof(double2) * n, hipMemcpyDeviceToDevice, c->st));
+}
+
+// GMRES (Alg. 6) on FP64 vectors, x0 = 0, no restart, classical Gram-Schmidt
+// with one re-orthogonalisation, Givens rotations.
+//  flex = false: left preconditioning, P M x = P b, both in precision T;
+//  flex = true : flexible right preconditioning, M P y = b, x = P y, with M
+//                in FP64 and P in complex64 (the preconditioned basis Z is
+//                stored, so the inexact P only affects the convergence rate).
 template <typename T>
 void gmres(hz_ctx* c, const double2* b, double2* x, int B, double tol, int maxit,
-           std::vector<int>& iters, std::vector<double>& relres) {
+           std::vector<int>& iters, std::vector<double>& relres, bool flex = false) {
     const long long n = 4LL * c->d.K * c->d.W;
     const long long nB = n * B;
     ensure_gmres(c, B, maxit);
     double2* V = c->V;
+    double2* Z = c->Z;
     const long long vs = nB;
-    apply_P<T>(c, b, V, B);
+    if (flex) {
+        if (!Z) raise(HZ_ESTATE, "flexible GMRES basis missing");
+        HIPCHK(hipMemcpyAsync(V, b, sizeof(double2) * nB, hipMemcpyDeviceToDevice, c->st));
+    } else {
+        apply_P<T>(c, b, V, B);
+    }
     std::vector<double> beta;
     norms(c, V, n, B, beta);
     std::vector<std::vector<std::complex<double>>> Hm(B, std::vector<std::complex<double>>((size_t)(maxit + 1) * maxit));
@@ -1213,7 +1337,12 @@ void gmres(hz_ctx* c, const double2* b, double2* x, int B, double tol, int maxit
         if (std::all_of(done.begin(), done.end(), [](int v) { return v != 0; })) break;
         double2* Vj = V + (long long)j * vs;
         double2* Vn = V + (long long)(j + 1) * vs;
-        apply_PM<T>(c, Vj, c->gw, B);
+        if (flex) {
+            apply_P<float>(c, Vj, Z + (long long)j * vs, B);
+            apply_M64(c, Z + (long long)j * vs, c->gw, B);
+        } else {
+            apply_PM<T>(c, Vj, c->gw, B);
+        }
         // two passes of classical Gram-Schmidt
         std::vector<std::complex<double>> hsum((size_t)(j + 1) * B, 0.0);
         for (int pass = 0; pass < 2; ++pass) {
@@ -1271,7 +1400,7 @@ void gmres(hz_ctx* c, const double2* b, double2* x, int B, double tol, int maxit
     HIPCHK(hipMemsetAsync(x, 0, sizeof(double2) * nB, c->st));
     if (kmax > 0) {
         upload(c, c->gcoef, coef.data(), sizeof(double2) * (size_t)kmax * B);
-        launch_update_basis(x, V, vs, kmax, c->gcoef, n, B, c->st);
+        launch_update_basis(x, flex ? Z : V, vs, kmax, c->gcoef, n, B, c->st);
     }
     sync(c);
 }
@@ -1280,7 +1409,7 @@ void gmres(hz_ctx* c, const double2* b, double2* x, int B, double tol, int maxit
 template <typename T>
 void dd_solve(hz_ctx* c, int B, double tol, int maxit, const std::vector<int>& active,
               std::vector<int>& iters, std::vector<double>& relres, double* t_rhs,
-              double* t_gm, double* t_rec) {
+              double* t_gm, double* t_rec, bool flex = false) {
     Work<T>& w = work<T>(c);
     const Dims& d = c->d;
     double t0 = now_s();
@@ -1305,7 +1434,7 @@ void dd_solve(hz_ctx* c, int B, double tol, int maxit, const std::vector<int>& a
     sync(c);
     double t1 = now_s();
     *t_rhs += t1 - t0;
-    gmres<T>(c, c->gb, c->gx, B, tol, maxit, iters, relres);
+    gmres<T>(c, c->gb, c->gx, B, tol, maxit, iters, relres, flex);
     double t2 = now_s();
     *t_gm += t2 - t1;
     // s = d + q  (in T)
@@ -1377,11 +1506,14 @@ hz_status solve_impl(hz_ctx* c, const void* rhs_dev, int B, void* out_dev, doubl
     std::vector<double> relres(B, 0.0), vres;
     int refine_steps = 0;
     bool conv = true;
-    if (c->prm.precision == HZ_FP64) {
+    std::vector<double> err_est(B, 0.0);
+    if (c->prm.precision == HZ_FP64 || c->prm.precision == HZ_MIXED) {
+        const bool flex = c->prm.precision == HZ_MIXED;
         ensure_work<double>(c, B);
+        if (flex) ensure_work<float>(c, B, false);
         Work<double>& w = c->w64;
         HIPCHK(hipMemcpyAsync(w.f_ext, c->f64, sizeof(double2) * N * B, hipMemcpyDeviceToDevice, c->st));
-        dd_solve<double>(c, B, tol, max_iter, active, iters, relres, &t_rhs, &t_gm, &t_rec);
+        dd_solve<double>(c, B, tol, max_iter, active, iters, relres, &t_rhs, &t_gm, &t_rec, flex);
         for (int b = 0; b < B; ++b) if (!(relres[b] <= tol)) conv = false;
         HIPCHK(hipMemcpyAsync(c->u64, w.u_ext, sizeof(double2) * N * B, hipMemcpyDeviceToDevice, c->st));
     } else {
@@ -1392,7 +1524,7 @@ hz_status solve_impl(hz_ctx* c, const void* rhs_dev, int B, void* out_dev, doubl
         std::vector<int> all(d.L, 1);
         const double inner_tol = std::max(1e-6, tol);
         const int max_refine = 30;
-        std::vector<double> un, dn;
+        std::vector<double> un, dn, dprev(B, 0.0);
         for (int step = 0; step < max_refine; ++step) {
             launch_residual(c->u64, c->f64, c->r64, c->gdiag, c->gcx, c->gcz, d.W, B, 1, c->st);
             launch_cast_d2f(w.f_ext, c->r64, N * B, c->st);
@@ -1404,14 +1536,27 @@ hz_status solve_impl(hz_ctx* c, const void* rhs_dev, int B, void* out_dev, doubl
             norms(c, c->r64, N, B, dn);
             norms(c, c->u64, N, B, un);
             refine_steps = step + 1;
+            // error of u after this step ~ rho/(1 - rho) ||delta|| with the
+            // observed contraction rho = ||delta_k|| / ||delta_{k-1}||
             bool ok = true;
-            for (int b = 0; b < B; ++b)
-                if (un[b] > 0 && dn[b] > tol * un[b]) ok = false;
+            for (int b = 0; b < B; ++b) {
+                const double rel = un[b] > 0 ? dn[b] / un[b] : 0.0;
+                double est = 1.0;
+                if (step > 0 && dprev[b] > 0) {
+                    const double rho = dn[b] / dprev[b];
+                    est = rho < 1.0 ? rho / (1.0 - rho) * rel : 1.0;
+                }
+                if (rel == 0.0) est = 0.0;
+                err_est[b] = est;
+                dprev[b] = dn[b];
+                if (est > tol) ok = false;
+            }
             if (ok) break;
             if (step == max_refine - 1) conv = false;
         }
     }
     if (stats) vol_resid(c, c->u64, c->f64, B, vres);
+    if (c->prof.on) prof_flush(c);
     launch_ext_to_out(c->u64, B, d.n, d.p, d.W, (double2*)out_dev, ext_out ? 0 : 1, adjoint, c->st);
     HIPCHK(hipGetLastError());
     sync(c);
@@ -1428,6 +1573,7 @@ hz_status solve_impl(hz_ctx* c, const void* rhs_dev, int B, void* out_dev, doubl
             stats[b].rel_resid = relres[b];
             stats[b].vol_resid = vres.empty() ? -1.0 : vres[b];
             stats[b].refine_steps = refine_steps;
+            stats[b].err_est = err_est[b];
         }
     }
     return conv ? HZ_OK : HZ_ENOCONV;
@@ -1498,7 +1644,9 @@ hz_status hz_setup(const double* model_dev, const hz_params* prm, hz_ctx** out) 
     if (prm->n_pml < 0) raise(HZ_EINVAL, "n_pml must be >= 0");
     if (prm->layers < 1 || prm->layers > n / 2) raise(HZ_EINVAL, "layers must be in 1..n/2 (>= 2 rows each)");
     if (prm->cells < 1 || prm->cells > n / 2) raise(HZ_EINVAL, "cells must be in 1..n/2 (>= 2 columns each)");
-    if (prm->precision != HZ_FP64 && prm->precision != HZ_MIXED) raise(HZ_EINVAL, "bad precision");
+    if (prm->precision != HZ_FP64 && prm->precision != HZ_MIXED &&
+        prm->precision != HZ_MIXED_REFINE)
+        raise(HZ_EINVAL, "bad precision");
     if (prm->model_kind != HZ_MODEL_VELOCITY && prm->model_kind != HZ_MODEL_SLOWNESS2)
         raise(HZ_EINVAL, "bad model kind");
     c = new hz_ctx();
@@ -1647,6 +1795,30 @@ hz_status hz_set_stream(hz_ctx* c, void* s) {
     API_END
 }
 
+hz_status hz_profile(hz_ctx* c, int on) {
+    API_BEGIN
+    if (!c) raise(HZ_EINVAL, "null context");
+    prof_flush(c);
+    c->prof.acc.clear();
+    c->prof.on = on != 0;
+    return HZ_OK;
+    API_END
+}
+
+hz_status hz_profile_read(hz_ctx* c, hz_kstat* out, int max, int* count) {
+    API_BEGIN
+    if (!c || !count) raise(HZ_EINVAL, "null argument");
+    prof_flush(c);
+    int i = 0;
+    for (const auto& kv : c->prof.acc) {
+        if (out && i < max) out[i] = kv.second;
+        ++i;
+    }
+    *count = i;
+    return HZ_OK;
+    API_END
+}
+
 hz_status hz_get_info(const hz_ctx* c, hz_info_t* info) {
     if (!c || !info) return HZ_EINVAL;
     info->n = c->d.n;
@@ -1669,6 +1841,7 @@ hz_status hz_get_timing(const hz_ctx* c, hz_timing* t) {
 void hz_destroy(hz_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->st);
+    for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
     c->arena.free_all();
     delete c;
 }
@@ -1679,7 +1852,7 @@ hz_status hz_apply_layer(hz_ctx* c, int layer, const void* top, const void* bot,
                          void* out, int B) {
     API_BEGIN
     check_state(c, 2);
-    if (c->prm.precision != HZ_FP64) raise(HZ_EINVAL, "building blocks need HZ_FP64");
+    if (c->prm.precision == HZ_MIXED_REFINE) raise(HZ_EINVAL, "building blocks need FP64 operators");
     if (layer < 0 || layer >= c->d.L || !out || B < 1 || B > c->prm.max_batch) raise(HZ_EINVAL, "bad arguments");
     const LayerDesc& ld = c->layers[layer];
     if ((side == 0 && !ld.has_top) || (side == 1 && !ld.has_bot) || side < 0 || side > 1)
@@ -1703,7 +1876,7 @@ hz_status hz_apply_layer(hz_ctx* c, int layer, const void* top, const void* bot,
 hz_status hz_apply_sie(hz_ctx* c, const void* x, void* y, int B) {
     API_BEGIN
     check_state(c, 2);
-    if (c->prm.precision != HZ_FP64) raise(HZ_EINVAL, "building blocks need HZ_FP64");
+    if (c->prm.precision == HZ_MIXED_REFINE) raise(HZ_EINVAL, "building blocks need FP64 operators");
     if (!x || !y || B < 1 || B > c->prm.max_batch || c->d.K == 0) raise(HZ_EINVAL, "bad arguments");
     ensure_work<double>(c, B);
     Work<double>& w = c->w64;
@@ -1719,7 +1892,7 @@ hz_status hz_apply_sie(hz_ctx* c, const void* x, void* y, int B) {
 hz_status hz_apply_precond(hz_ctx* c, const void* x, void* y, int B) {
     API_BEGIN
     check_state(c, 2);
-    if (c->prm.precision != HZ_FP64) raise(HZ_EINVAL, "building blocks need HZ_FP64");
+    if (c->prm.precision == HZ_MIXED_REFINE) raise(HZ_EINVAL, "building blocks need FP64 operators");
     if (!x || !y || B < 1 || B > c->prm.max_batch || c->d.K == 0) raise(HZ_EINVAL, "bad arguments");
     ensure_work<double>(c, B);
     Work<double>& w = c->w64;
@@ -1735,7 +1908,7 @@ hz_status hz_apply_precond(hz_ctx* c, const void* x, void* y, int B) {
 hz_status hz_sie_rhs(hz_ctx* c, const void* rhs, void* y, int B) {
     API_BEGIN
     check_state(c, 2);
-    if (c->prm.precision != HZ_FP64) raise(HZ_EINVAL, "building blocks need HZ_FP64");
+    if (c->prm.precision == HZ_MIXED_REFINE) raise(HZ_EINVAL, "building blocks need FP64 operators");
     if (!rhs || !y || B < 1 || B > c->prm.max_batch || c->d.K == 0) raise(HZ_EINVAL, "bad arguments");
     ensure_work<double>(c, B);
     ensure_refine(c);
@@ -1764,7 +1937,7 @@ hz_status hz_cell_shape(const hz_ctx* c, int layer, int cell, int* HL, int* Wc) 
 hz_status hz_cell_solve(hz_ctx* c, int layer, int cell, const void* g, void* x, int B) {
     API_BEGIN
     check_state(c, 2);
-    if (c->prm.precision != HZ_FP64) raise(HZ_EINVAL, "building blocks need HZ_FP64");
+    if (c->prm.precision == HZ_MIXED_REFINE) raise(HZ_EINVAL, "building blocks need FP64 operators");
     if (layer < 0 || layer >= c->d.L || cell < 0 || cell >= c->d.Lc || !g || !x || B < 1 ||
         B > c->prm.max_batch)
         raise(HZ_EINVAL, "bad arguments");

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhz.so")
 
 HZ_OK, HZ_EINVAL, HZ_ENOMEM, HZ_ESTATE, HZ_ENOCONV, HZ_ESINGULAR, HZ_EDEVICE = 0, -1, -2, -3, -4, -5, -6
-HZ_FP64, HZ_MIXED = 0, 1
+HZ_FP64, HZ_MIXED, HZ_MIXED_REFINE = 0, 1, 2
 HZ_MODEL_VELOCITY, HZ_MODEL_SLOWNESS2 = 0, 1
 
 EXPORTED = [
@@ -22,6 +22,7 @@ EXPORTED = [
     "hz_misfit_gradient", "hz_misfit", "hz_update_model", "hz_set_stream", "hz_get_info", "hz_get_timing",
     "hz_destroy", "hz_strerror", "hz_last_error", "hz_apply_layer", "hz_apply_sie",
     "hz_apply_precond", "hz_sie_rhs", "hz_cell_solve", "hz_cell_shape", "hz_residual",
+    "hz_profile", "hz_profile_read",
 ]
 
 
@@ -35,7 +36,8 @@ class Params(ctypes.Structure):
 
 class RhsStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("rel_resid", ctypes.c_double),
-                ("vol_resid", ctypes.c_double), ("refine_steps", ctypes.c_int)]
+                ("vol_resid", ctypes.c_double), ("refine_steps", ctypes.c_int),
+                ("err_est", ctypes.c_double)]
 
 
 class Timing(ctypes.Structure):
@@ -43,6 +45,12 @@ class Timing(ctypes.Structure):
                 ("t_rhs", ctypes.c_double), ("t_gmres", ctypes.c_double),
                 ("t_recon", ctypes.c_double), ("t_solve", ctypes.c_double),
                 ("gmres_iters", ctypes.c_int)]
+
+
+class KStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int),
+                ("ms", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("flops", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -90,6 +98,8 @@ def lib() -> ctypes.CDLL:
         L.hz_cell_solve.argtypes = [vp, i, i, vp, vp, i]
         L.hz_cell_shape.argtypes = [vp, i, i, ctypes.POINTER(i), ctypes.POINTER(i)]
         L.hz_residual.argtypes = [vp, vp, vp, vp, i]
+        L.hz_profile.argtypes = [vp, i]
+        L.hz_profile_read.argtypes = [vp, ctypes.POINTER(KStat), i, ctypes.POINTER(i)]
         for name in EXPORTED:
             if name not in ("hz_destroy", "hz_strerror", "hz_last_error"):
                 getattr(L, name).restype = ctypes.c_int
@@ -171,7 +181,8 @@ class Solver:
         _check(st, fn, allow=(HZ_ENOCONV,) if allow_noconv else ())
         self.last_status = st
         self.last_stats = [dict(iters=s.iters, rel_resid=s.rel_resid, vol_resid=s.vol_resid,
-                                refine_steps=s.refine_steps) for s in stats]
+                                refine_steps=s.refine_steps, err_est=s.err_est)
+                           for s in stats]
         return u
 
     def solve(self, f, tol=1e-10, max_iter=100, ext=False, allow_noconv=False):
@@ -200,6 +211,16 @@ class Solver:
                                _ptr(d_obs.to(device="cuda", dtype=torch.complex128).contiguous()),
                                int(rec_row), B, _ptr(adj), ctypes.byref(J)), "hz_misfit")
         return J.value, adj
+
+    def profile(self, on: bool):
+        _check(lib().hz_profile(self.ctx, int(bool(on))), "hz_profile")
+
+    def profile_read(self) -> list:
+        arr = (KStat * 32)()
+        cnt = ctypes.c_int()
+        _check(lib().hz_profile_read(self.ctx, arr, 32, ctypes.byref(cnt)), "hz_profile_read")
+        return [dict(name=k.name.decode(), launches=k.launches, ms=k.ms, bytes=k.bytes,
+                     flops=k.flops) for k in arr[:min(cnt.value, 32)]]
 
     def timing(self) -> dict:
         t = Timing()

@@ -151,15 +151,17 @@ def test_residual_kernel(setup):
     assert _rel(r, ref) < 1e-13
 
 
-def test_mixed_precision_solve():
+@pytest.mark.parametrize("prec,tol", [("mixed", 1e-11), ("refine", 1e-10)])
+def test_mixed_precision_solve(prec, tol):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     c, omega = media.small_problem(N, P, L, LC, seed=5)
     prob = Problem(c, omega, P)
     f = media.point_sources(N, (24, 7), 12)
-    _log("[solve mixed] B=2")
-    s = hz.Solver(torch.from_numpy(c), omega, P, L, LC, precision=hz.HZ_MIXED, max_batch=2)
-    u = s.solve(torch.from_numpy(f), tol=1e-11).cpu().numpy()
+    _log(f"[solve {prec}] B=2")
+    code = hz.HZ_MIXED if prec == "mixed" else hz.HZ_MIXED_REFINE
+    s = hz.Solver(torch.from_numpy(c), omega, P, L, LC, precision=code, max_batch=2)
+    u = s.solve(torch.from_numpy(f), tol=tol).cpu().numpy()
     lu = spla.splu(prob.H.tocsc())
     for bb in range(2):
         ref = prob.restrict(lu.solve(prob.extend(f[bb]).ravel()).reshape(prob.W, prob.W))
