@@ -878,7 +878,9 @@ void cell_solve_launch(hz_ctx* c, CellSolveArgs<T> a, const std::vector<int>& li
                 bytes += sizeof(C2<T>) * (2.0 * blk + 4.0 * (double)cd.Wc * cd.HL * Bcols);
                 flops += 16.0 * blk * Bcols;
             }
-            c->prof.pend.push_back({fam_name<T>("cell_solve"), e0, e1, bytes, flops});
+            const char* fam = a.mode == SOLVE_VOLUME ? "cell_solve_volume"
+                              : a.mode == SOLVE_SAMPLE ? "cell_solve_sample" : "cell_solve_other";
+            c->prof.pend.push_back({fam_name<T>(fam), e0, e1, bytes, flops});
         }
     }
     sync(c);
