@@ -207,7 +207,7 @@ def main():
                    "form": chosen, "batch": B, "tol": 1e-10,
                    "max_rel_err_vs_fp64": err, "gmres_iters": its},
         "vs_plain_fp64_single": (B * n * n / dt) / forms["fp64_single"]["dof_solves_per_s"],
-        "forms": {k: {kk: vv for kk, vv in v.items() if kk != "kernels"} for k, v in forms.items()},
+        "forms": forms,
         "kernels": prof,
         "roofline": roof,
         "cpu_baseline": cpu,

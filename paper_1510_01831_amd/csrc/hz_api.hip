@@ -23,6 +23,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -113,6 +114,13 @@ struct Plan {
     size_t dev_bytes = 0;
     std::vector<GemmTask<T>> tasks;
     std::vector<LaunchRec<T>> launches;
+    hipGraph_t graph = nullptr;          // the launches captured once, replayed after
+    hipGraphExec_t exec = nullptr;
+    std::string name;                    // profiling family of the whole replay
+    ~Plan() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
 };
 
 template <typename T>
@@ -170,6 +178,8 @@ struct hz_ctx {
     Dims d{};
     int state = 0;                 // 1 set up, 2 factored
     hipStream_t st = nullptr;
+    hipStream_t own_st = nullptr;  // stream created by the context (blocking, default priority)
+    bool use_graphs = true;
     Arena arena;
     std::vector<LayerDesc> layers;
     std::vector<CellDesc> cells;
@@ -241,6 +251,7 @@ void build_descriptors(hz_ctx* c) {
     for (auto& cp : cparts) Wcmax = std::max(Wcmax, cp.second - cp.first + 1 + 2 * p);
     c->d.HLmax = HLmax;
     c->d.Wcmax = Wcmax;
+    c->d.HLpmax = (HLmax + 15) / 16 * 16;
     const int J = d.Lc - 1;
     c->inner_per_layer = (long long)J * 2 * HLmax;
     long long off_coef = 0, off_X = 0, off_Q = 0, off_CS = 0, off_Sinv = 0, off_Lfac = 0;
@@ -280,6 +291,7 @@ void build_descriptors(hz_ctx* c) {
             cd.cell = k;
             cd.gidx = l * d.Lc + k;
             cd.HL = ld.HL;
+            cd.HLp = (ld.HL + 15) / 16 * 16;
             cd.first = cparts[k].first;
             cd.nc = cparts[k].second - cparts[k].first + 1;
             cd.Wc = cd.nc + 2 * p;
@@ -296,7 +308,7 @@ void build_descriptors(hz_ctx* c) {
             cd.off_coef = off_coef;
             off_coef += (long long)cd.Wc * cd.HL;
             cd.off_X = off_X;
-            off_X += (long long)cd.Wc * cd.HL * cd.HL;
+            off_X += (long long)cd.Wc * cd.HLp * cd.HLp;
             cd.off_Q = off_Q;
             off_Q += (long long)cd.nslot * cd.s * cd.R;
             cd.off_CS = off_CS;
@@ -608,7 +620,40 @@ void plan_upload(hz_ctx* c, Plan<T>& pl) {
 }
 
 template <typename T>
-void plan_run(hz_ctx* c, const Plan<T>& pl, int B) {
+void plan_launches(hz_ctx* c, const Plan<T>& pl, int B);
+
+// Replay a plan: through its captured HIP graph when the context owns a
+// capturable stream and profiling is off, launch by launch otherwise.
+template <typename T>
+void plan_run(hz_ctx* c, Plan<T>& pl, int B) {
+    if (c->use_graphs && c->st && !pl.name.empty()) {
+        if (!pl.exec) {
+            const bool prof = c->prof.on;
+            c->prof.on = false;                       // no event records inside the capture
+            HIPCHK(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+            plan_launches<T>(c, pl, B);
+            hipGraph_t g = nullptr;
+            HIPCHK(hipStreamEndCapture(c->st, &g));
+            c->prof.on = prof;
+            pl.graph = g;
+            HIPCHK(hipGraphInstantiate(&pl.exec, g, nullptr, nullptr, 0));
+        }
+        const bool prof = c->prof.on;
+        size_t e0 = prof ? prof_event(c) : 0;
+        HIPCHK(hipGraphLaunch(pl.exec, c->st));
+        if (prof) {
+            size_t e1 = prof_event(c);
+            double bytes = 0, flops = 0;
+            for (const auto& r : pl.launches) { bytes += r.bytes; flops += r.flops; }
+            c->prof.pend.push_back({pl.name, e0, e1, bytes, flops});
+        }
+        return;
+    }
+    plan_launches<T>(c, pl, B);
+}
+
+template <typename T>
+void plan_launches(hz_ctx* c, const Plan<T>& pl, int B) {
     const bool prof = c->prof.on;
     const std::string fam = fam_name<T>(B == 1 ? "layer_gemv" : "layer_gemm");
     for (const auto& r : pl.launches) {
@@ -622,7 +667,7 @@ void plan_run(hz_ctx* c, const Plan<T>& pl, int B) {
         } else if (r.kind == L_AXPBY) {
             launch_axpby<T>(r.y, r.x, r.a, r.b, r.n, c->st);
         } else if (r.kind == L_COPY) {
-            HIPCHK(hipMemcpyAsync(r.y, r.x, (size_t)r.n * sizeof(C2<T>), hipMemcpyDeviceToDevice, c->st));
+            launch_copy<T>(r.y, r.x, r.n, c->st);
         }
     }
     HIPCHK(hipGetLastError());
@@ -751,6 +796,7 @@ Plan<T>& get_plan(hz_ctx* c, bool sie, int B) {
     auto it = mp.find(B);
     if (it != mp.end()) return *it->second;
     auto pl = std::make_unique<Plan<T>>();
+    pl->name = fam_name<T>(sie ? "sie_graph" : "precond_graph");
     if (sie) build_sie_plan<T>(c, *pl, B);
     else build_pre_plan<T>(c, *pl, B);
     plan_upload<T>(c, *pl);
@@ -781,7 +827,7 @@ void ensure_work(hz_ctx* c, int B, bool volume = true) {
         // cell-solve scratch: one region per workgroup of a volume solve
         const int nb = cs_nb(B);
         const int chunks = (B + nb - 1) / nb;
-        w.y_stride = (long long)d.Wcmax * d.HLmax * nb;
+        w.y_stride = (long long)d.Wcmax * d.HLpmax * nb;
         w.y_wgs = (int)c->cells.size() * chunks;
         w.Y = alloc_c<T>(c, w.y_stride * w.y_wgs);
     }
@@ -852,9 +898,11 @@ template <typename T>
 void cell_solve_launch(hz_ctx* c, CellSolveArgs<T> a, const std::vector<int>& list, int Bcols) {
     // groups limited by the scratch available
     Work<T>& w = work<T>(c);
-    const int nb = cs_nb(Bcols);
+    const int nb = cs_nb(Bcols, (int)list.size());
     const int chunks = (Bcols + nb - 1) / nb;
-    const int per = std::max(1, w.y_wgs / chunks);
+    const long long wg_elems = (long long)c->d.Wcmax * c->d.HLpmax * nb;
+    const int per = (int)std::max<long long>(1, (w.y_stride * w.y_wgs / wg_elems) / chunks);
+    a.nb = nb;
     int* d_list = (int*)c->arena.alloc(sizeof(int) * list.size());
     upload(c, d_list, list.data(), sizeof(int) * list.size());
     const bool prof = c->prof.on;
@@ -863,7 +911,7 @@ void cell_solve_launch(hz_ctx* c, CellSolveArgs<T> a, const std::vector<int>& li
         a.cell_list = d_list + g;
         a.B = Bcols;
         a.Y = w.Y;
-        a.y_stride = (long long)c->d.Wcmax * c->d.HLmax * nb;
+        a.y_stride = wg_elems;
         size_t e0 = prof ? prof_event(c) : 0;
         launch_cell_solve<T>(a, cnt, chunks, c->st);
         HIPCHK(hipGetLastError());
@@ -955,7 +1003,7 @@ void factor_impl(hz_ctx* c) {
     HIPCHK(hipMemsetAsync(c->flags, 0, 2 * sizeof(int), c->st));
     // 1. cell Schur factors
     {
-        const long long ws = (long long)d.HLmax * d.HLmax;
+        const long long ws = (long long)d.HLpmax * d.HLpmax;
         const int batch = std::min(ncells, 1024);
         double2* workbuf = alloc_c<double>(c, ws * batch);
         for (int c0 = 0; c0 < ncells; c0 += batch) {
@@ -976,7 +1024,7 @@ void factor_impl(hz_ctx* c) {
     if (Rmax > 0) {
         const int nb = cs_nb(Rmax);
         const int chunks = (Rmax + nb - 1) / nb;
-        const long long ystride = (long long)d.Wcmax * d.HLmax * nb;
+        const long long ystride = (long long)d.Wcmax * d.HLpmax * nb;
         // scratch budget ~ 4 GiB
         long long budget_wgs = std::max<long long>(chunks, (4LL << 30) / (ystride * (long long)sizeof(double2)));
         const int per = (int)std::max<long long>(1, budget_wgs / chunks);
@@ -991,6 +1039,7 @@ void factor_impl(hz_ctx* c) {
         a.CSpool = o.CS;
         a.probe0 = 0;
         a.B = Rmax;
+        a.nb = nb;
         a.Y = Y;
         a.y_stride = ystride;
         for (int g = 0; g < ncells; g += per) {
@@ -1122,7 +1171,7 @@ void run_jobs(hz_ctx* c, const std::vector<LayerJob<T>>& jobs, int B) {
     Plan<T> pl;
     plan_jobs<T>(c, pl, jobs, B);
     plan_upload<T>(c, pl);
-    plan_run<T>(c, pl, B);
+    plan_launches<T>(c, pl, B);
     sync(c);
     if (pl.dev) c->arena.release(pl.dev, pl.dev_bytes);
 }
@@ -1653,6 +1702,7 @@ hz_status hz_setup(const double* model_dev, const hz_params* prm, hz_ctx** out) 
         raise(HZ_EINVAL, "bad model kind");
     c = new hz_ctx();
     c->prm = *prm;
+    if (const char* g = std::getenv("HZ_GRAPHS")) c->use_graphs = std::atoi(g) != 0;
     if (c->prm.pml_beta <= 0.0) c->prm.pml_beta = 2.0;
     if (c->prm.max_batch <= 0) c->prm.max_batch = 1;
     Dims& d = c->d;
@@ -1669,6 +1719,10 @@ hz_status hz_setup(const double* model_dev, const hz_params* prm, hz_ctx** out) 
     if (d.HLmax > 224) raise(HZ_EINVAL, "layer grid taller than 224 rows: use more layers");
     if (2 * d.HLmax > 448) raise(HZ_EINVAL, "inner block too large");
     double t0 = now_s();
+    // a blocking stream of default priority: ordered after work on the null
+    // stream, and capturable into graphs
+    HIPCHK(hipStreamCreate(&c->own_st));
+    c->st = c->own_st;
     c->d_layers = (LayerDesc*)c->arena.alloc(sizeof(LayerDesc) * d.L);
     c->d_cells = (CellDesc*)c->arena.alloc(sizeof(CellDesc) * c->cells.size());
     upload(c, c->d_layers, c->layers.data(), sizeof(LayerDesc) * d.L);
@@ -1792,7 +1846,11 @@ hz_status hz_misfit(hz_ctx* c, const void* u_ext, const void* d_obs, int rec_row
 hz_status hz_set_stream(hz_ctx* c, void* s) {
     API_BEGIN
     if (!c) raise(HZ_EINVAL, "null context");
-    c->st = (hipStream_t)s;
+    sync(c);
+    c->st = s ? (hipStream_t)s : c->own_st;
+    // graphs were captured on the previous stream; rebuild lazily
+    c->w64.sie.clear(); c->w64.pre.clear();
+    c->w32.sie.clear(); c->w32.pre.clear();
     return HZ_OK;
     API_END
 }
@@ -1844,7 +1902,10 @@ void hz_destroy(hz_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->st);
     for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
+    c->w64.sie.clear(); c->w64.pre.clear();
+    c->w32.sie.clear(); c->w32.pre.clear();
     c->arena.free_all();
+    if (c->own_st) (void)hipStreamDestroy(c->own_st);
     delete c;
 }
 

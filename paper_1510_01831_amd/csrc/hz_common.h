@@ -80,6 +80,7 @@ struct LayerDesc {
 struct CellDesc {
     int layer, cell, gidx;   // layer index, cell index in the layer, global cell index
     int HL, Wc, nc;          // grid rows, grid columns, owned physical columns
+    int HLp;                 // HL rounded up to a multiple of 16 (padded factor blocks)
     int first;               // first owned physical column (1-based, global)
     int col0;                // extended-grid array column of cell-local array column 0
     int own_c0, own_c1, s;   // owned cell-local array columns (inclusive), count
@@ -88,7 +89,7 @@ struct CellDesc {
     int ncol;                // column probes = adj * 2 HL
     int R;                   // probes = ncol + nslot * s
     long long off_coef;      // diag/cz/e: [Wc][HL] each
-    long long off_X;         // X_k = S_k^{-1}: [Wc][HL][HL]
+    long long off_X;         // X_k = S_k^{-1}: [Wc][HLp x HLp in 16x4 MFMA tiles, see xt_index]
     long long off_Q;         // Q = [M_u | D_loc]: [nslot * s][R]
     long long off_CS;        // column samples: [adj * HL][R] (left side first)
 };
@@ -96,8 +97,15 @@ struct CellDesc {
 struct Dims {
     int n, p, W, L, Lc, K;   // K = L - 1 interfaces
     double h, omega, beta;
-    int HLmax, Wcmax;
+    int HLmax, Wcmax, HLpmax;
 };
+
+// Position of entry (i, j) of an HLp x HLp Schur inverse stored as 16x4 tiles
+// in MFMA operand order: tile (i/16, j/4), lane (i%16) + 16 (j%4).  A wave
+// reads one tile as 1 KB of contiguous complex values.
+__host__ __device__ inline long long xt_index(int i, int j, int HLp) {
+    return (((long long)(i >> 4) * (HLp >> 2) + (j >> 2)) << 6) + (i & 15) + ((j & 3) << 4);
+}
 
 // ---------------------------------------------------------------------------
 // generic segmented GEMM:  out[i] = add0[i] + c1 * add1[i] + alpha * sum_k A[i][k] x[k]
@@ -138,6 +146,7 @@ template <typename T>
 struct CellSolveArgs {
     int mode;
     int B;               // batch columns handled in total (per cell)
+    int nb;              // batch columns per workgroup (cs_nb)
     const CellDesc* cells;
     const LayerDesc* layers;
     const int* cell_list;        // cells handled by this launch (grid.x index -> global cell)
@@ -145,7 +154,7 @@ struct CellSolveArgs {
     const C2<T>* coef_e;         // e pool (same layout as coef, complex)
     const double2* alpha_x;      // per cell: alpha_x at own nodes [Wcmax] (cell profile), FP64
     const double2* alpha_z;      // per layer: alpha_z at nodes [HLmax], FP64
-    C2<T>* Y;                    // scratch for the forward sweep: per launch-cell [Wc][HL][B]
+    C2<T>* Y;                    // scratch for the forward sweep: per workgroup [Wc][HLp][NB]
     long long y_stride;          // complex elements per launch-cell in Y
     // SOLVE_GRID: g/x on the cell grid [HL][Wc][B] (row-major grid) for one cell
     const C2<T>* g_grid; C2<T>* x_grid;
@@ -196,8 +205,19 @@ void launch_cell_solve(const CellSolveArgs<T>& a, int ncells_launch, int nb_chun
 template <typename T>
 void launch_gemm(const GemmTask<T>* tasks_dev, int ntasks, int max_m, int B, hipStream_t st);
 
+template <typename T>
+void launch_copy(C2<T>* y, const C2<T>* x, long long n, hipStream_t st);
+
 // number of right-hand sides one cell-solve workgroup handles for a batch B
-inline int cs_nb(int B) { return B <= 1 ? 1 : (B <= 4 ? 4 : 16); }
+// When a launch has few cells, a narrower batch per workgroup (16 instead of
+// 32 columns) doubles the workgroups and halves each one's sequential work.
+inline int cs_nb(int B, int ncells = 1 << 20) {
+    if (B <= 1) return 1;
+    if (B <= 2) return 2;
+    if (B <= 4) return 4;
+    if (B <= 16) return 16;
+    return (long long)ncells * ((B + 31) / 32) < 512 ? 16 : 32;
+}
 
 // vector / reduction kernels (FP64 unless templated)
 template <typename T>

@@ -6,35 +6,40 @@
 //   backward:  x_{W-1} = X_{W-1} y_{W-1},  x_k = X_k (y_k - e_{k+1} o x_{k+1})
 // where o is the elementwise product over the rows of a column.
 //
-// One workgroup handles one cell and NB right-hand sides; the current column
-// vector lives in LDS, the factor blocks stream through LDS tiles, the
-// forward iterates are kept in a global scratch for the backward sweep.
-// Sources are assembled on the fly (volume source, App. C equivalent sources
-// on the layer interface rows, column equivalent sources of the inner traces,
-// or unit probes) and the results are sampled as they are produced.
+// One workgroup handles one cell and NB right-hand sides.  The current
+// column block lives in LDS; the X_k blocks stream from HBM/L2 in their 16x4
+// MFMA tile order (each wave load is 1 KB contiguous); the forward iterates go
+// to a global scratch for the backward sweep.  NB >= 16 runs the block
+// products on the matrix cores (four real MFMAs per complex tile product);
+// NB <= 4 is a matrix-vector product reduced across the four lanes that share
+// a row.  Sources are assembled on the fly (volume source, App. C equivalent
+// sources on the layer interface rows, column equivalent sources of the inner
+// traces, or unit probes) and results are sampled as they are produced.
+// The solve mode is a template parameter so each mode is its own kernel.
 #include "hz_common.h"
+#include "hz_mfma.h"
 
 namespace hz {
 
 constexpr int CS_THREADS = 256;
-constexpr int CS_HLMAX = 224;
-constexpr int CS_KC = 16;
+constexpr int CS_HLPMAX = 224;
 
 template <typename T>
 __device__ inline C2<T> to_t(double2 v) { return mk<T>((T)v.x, (T)v.y); }
 
-template <typename T, int NB>
+template <typename T, int MODE>
 __device__ inline C2<T> cell_source(const CellSolveArgs<T>& a, const CellDesc& cd,
                                     const LayerDesc& ld, int k, int j, int b) {
     const int p = a.p;
     const double ih2 = 1.0 / (a.h * a.h);
     C2<T> z = mk<T>((T)0, (T)0);
     const int B = a.B;
-    if (a.mode == SOLVE_GRID) {
+    if (j >= cd.HL) return z;
+    if constexpr (MODE == SOLVE_GRID) {
         return a.g_grid[((long long)j * cd.Wc + k) * B + b];
     }
     const bool own_col = (k >= cd.own_c0 && k <= cd.own_c1);
-    if (a.mode == SOLVE_PROBE) {
+    if constexpr (MODE == SOLVE_PROBE) {
         const int probe = a.probe0 + b;
         if (probe < cd.ncol) {
             int q = probe;
@@ -71,7 +76,7 @@ __device__ inline C2<T> cell_source(const CellSolveArgs<T>& a, const CellDesc& c
     if (a.f_ext && own_col && own_row && (!a.layer_active || a.layer_active[cd.layer])) {
         v = a.f_ext[(((long long)(ld.row0 + j)) * W + cd.col0 + k) * B + b];
     }
-    if (a.mode == SOLVE_VOLUME) {
+    if constexpr (MODE == SOLVE_VOLUME) {
         if (own_col) {
             const C2<T>* top = a.top_pair ? a.top_pair[cd.layer] : nullptr;
             const C2<T>* bot = a.bot_pair ? a.bot_pair[cd.layer] : nullptr;
@@ -113,18 +118,17 @@ __device__ inline C2<T> cell_source(const CellSolveArgs<T>& a, const CellDesc& c
     return v;
 }
 
-template <typename T, int NB>
+template <typename T, int MODE>
 __device__ inline void cell_emit(const CellSolveArgs<T>& a, const CellDesc& cd,
                                  const LayerDesc& ld, int k, int j, int b, C2<T> x) {
     const int p = a.p;
     const int B = a.B;
     const long long W = a.W;
+    if (j >= cd.HL) return;
     const bool own_col = (k >= cd.own_c0 && k <= cd.own_c1);
-    switch (a.mode) {
-    case SOLVE_GRID:
+    if constexpr (MODE == SOLVE_GRID) {
         a.x_grid[((long long)j * cd.Wc + k) * B + b] = x;
-        break;
-    case SOLVE_PROBE: {
+    } else if constexpr (MODE == SOLVE_PROBE) {
         const long long probe = a.probe0 + b;
         C2<T>* CS = a.CSpool + cd.off_CS;
         C2<T>* Q = a.Qpool + cd.off_Q;
@@ -136,8 +140,7 @@ __device__ inline void cell_emit(const CellSolveArgs<T>& a, const CellDesc& cd,
                 if (ld.slot_row[si] == j)
                     Q[((long long)si * cd.s + (k - cd.own_c0)) * cd.R + probe] = x;
         }
-    } break;
-    case SOLVE_SAMPLE: {
+    } else if constexpr (MODE == SOLVE_SAMPLE) {
         C2<T>* ir = a.inner_rhs + ld.off_inner * B;
         const int HL = cd.HL;
         if (cd.has_left && k == p)
@@ -149,117 +152,249 @@ __device__ inline void cell_emit(const CellSolveArgs<T>& a, const CellDesc& cd,
                 if (ld.slot_row[si] == j)
                     a.rows_out[(((long long)cd.layer * MAXSLOT + si) * W + cd.col0 + k) * B + b] = x;
         }
-    } break;
-    case SOLVE_VOLUME:
+    } else {
         if (own_col && j >= ld.own_r0 && j <= ld.own_r1)
             a.u_ext[(((long long)(ld.row0 + j)) * W + cd.col0 + k) * B + b] = x;
-        break;
-    default:
-        break;
     }
 }
 
-// t = X * v for an HL x HL block X (row-major, global) and v [HL][NB] in LDS;
-// thread owns column c = tid % NB and rows j = tid / NB + m * (CS_THREADS/NB).
-template <typename T, int NB, int MR>
-__device__ inline void block_matvec(const C2<T>* __restrict__ X, int HL, const C2<T>* vs,
-                                    C2<T> (*Xs)[CS_KC + 1], C2<T> acc[MR]) {
-    const int tid = threadIdx.x;
-    constexpr int RG = CS_THREADS / NB;
-    const int c = tid % NB;
-    const int j0 = tid / NB;
-#pragma unroll
-    for (int m = 0; m < MR; ++m) acc[m] = mk<T>((T)0, (T)0);
-    for (int i0 = 0; i0 < HL; i0 += CS_KC) {
-        const int kc = min(CS_KC, HL - i0);
-        __syncthreads();
-        for (int idx = tid; idx < HL * CS_KC; idx += CS_THREADS) {
-            const int r = idx / CS_KC, ii = idx - r * CS_KC;
-            Xs[r][ii] = (ii < kc) ? X[(long long)r * HL + i0 + ii] : mk<T>((T)0, (T)0);
-        }
-        __syncthreads();
-        for (int ii = 0; ii < kc; ++ii) {
-            const C2<T> vv = vs[(i0 + ii) * NB + c];
-#pragma unroll
-            for (int m = 0; m < MR; ++m) {
-                const int j = j0 + m * RG;
-                if (j < HL) acc[m] = cfma(Xs[j][ii], vv, acc[m]);
-            }
-        }
-    }
+template <typename T>
+__device__ inline C2<T> e_coef(const C2<T>* ee, int k, int j, int HL) {
+    return j < HL ? ee[(long long)k * HL + j] : mk<T>((T)0, (T)0);
 }
 
-template <typename T, int NB>
-__global__ void __launch_bounds__(CS_THREADS) k_cell_solve(CellSolveArgs<T> a) {
-    constexpr int RG = CS_THREADS / NB;
-    constexpr int MR = (CS_HLMAX + RG - 1) / RG;
-    __shared__ C2<T> vs[CS_HLMAX * NB];
-    __shared__ C2<T> Xs[CS_HLMAX][CS_KC + 1];
+// ===========================================================================
+// NB <= 4: lanes run along the tile's 4 columns, each lane owning one row of
+// a 16-row tile; the 4 partial sums of a row are combined with two shuffles.
+template <typename T, int NB, int MODE>
+__global__ void __launch_bounds__(CS_THREADS) k_cs_gemv(CellSolveArgs<T> a) {
+    constexpr int MRT = (CS_HLPMAX / 16 + 3) / 4;   // row tiles per wave (4 for 224 rows)
+    __shared__ C2<T> vs[CS_HLPMAX * NB];
 
     const int gc = a.cell_list[blockIdx.x];
     const CellDesc cd = a.cells[gc];
     const LayerDesc ld = a.layers[cd.layer];
-    const int HL = cd.HL, Wc = cd.Wc;
+    const int HL = cd.HL, HLp = cd.HLp, Wc = cd.Wc;
+    const int RT = HLp >> 4, KS = HLp >> 2;
     const int b0 = blockIdx.y * NB;
-    if (a.mode == SOLVE_PROBE && a.probe0 + b0 >= cd.R) return;   // uniform per workgroup
-    const int tid = threadIdx.x;
-    const int c = tid % NB;
-    const int j0 = tid / NB;
-    const int b = b0 + c;
-    const bool bvalid = b < a.B && (a.mode != SOLVE_PROBE || a.probe0 + b < cd.R);
-    const long long nn = (long long)HL * HL;
+    if (MODE == SOLVE_PROBE && a.probe0 + b0 >= cd.R) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const long long np2 = (long long)HLp * HLp;
     const C2<T>* Xf = a.X + cd.off_X;
     const C2<T>* ee = a.coef_e + cd.off_coef;
     C2<T>* Y = a.Y + ((long long)blockIdx.x * gridDim.y + blockIdx.y) * a.y_stride;
-    C2<T> acc[MR];
+    auto bval = [&](int c) {
+        const int b = b0 + c;
+        return b < a.B && (MODE != SOLVE_PROBE || a.probe0 + b < cd.R);
+    };
+    for (int q = tid; q < HLp * NB; q += CS_THREADS) vs[q] = mk<T>((T)0, (T)0);
+    __syncthreads();
+
+    C2<T> acc[MRT][NB];
+    auto matvec = [&](const C2<T>* Xk) {
+#pragma unroll
+        for (int m = 0; m < MRT; ++m)
+#pragma unroll
+            for (int c = 0; c < NB; ++c) acc[m][c] = mk<T>((T)0, (T)0);
+#pragma unroll
+        for (int m = 0; m < MRT; ++m) {
+            const int R = w + 4 * m;
+            if (R < RT) {
+                const C2<T>* base = Xk + ((long long)R * KS << 6) + lane;
+#pragma unroll 8
+                for (int s = 0; s < KS; ++s) {
+                    const C2<T> x = base[(long long)s << 6];
+                    const int cc = 4 * s + (lane >> 4);
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) acc[m][c] = cfma(x, vs[cc * NB + c], acc[m][c]);
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < MRT; ++m)
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                C2<T> v = acc[m][c];
+                v.x += __shfl_xor(v.x, 16, 64); v.y += __shfl_xor(v.y, 16, 64);
+                v.x += __shfl_xor(v.x, 32, 64); v.y += __shfl_xor(v.y, 32, 64);
+                acc[m][c] = v;
+            }
+    };
 
     // ---- forward sweep
     for (int k = 0; k < Wc; ++k) {
-        if (k > 0) block_matvec<T, NB, MR>(Xf + (long long)(k - 1) * nn, HL, vs, Xs, acc);
-        C2<T> yv[MR];
-#pragma unroll
-        for (int m = 0; m < MR; ++m) {
-            const int j = j0 + m * RG;
-            if (j < HL) {
-                C2<T> s = bvalid ? cell_source<T, NB>(a, cd, ld, k, j, b) : mk<T>((T)0, (T)0);
-                if (k > 0) s = csub(s, cmul(ee[(long long)k * HL + j], acc[m]));
-                yv[m] = s;
-                Y[((long long)k * HL + j) * NB + c] = s;
-            }
-        }
+        if (k > 0) matvec(Xf + (long long)(k - 1) * np2);
         __syncthreads();
+        if (lane < 16) {
 #pragma unroll
-        for (int m = 0; m < MR; ++m) {
-            const int j = j0 + m * RG;
-            if (j < HL) vs[j * NB + c] = yv[m];
+            for (int m = 0; m < MRT; ++m) {
+                const int R = w + 4 * m;
+                if (R < RT) {
+                    const int j = R * 16 + lane;
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) {
+                        C2<T> s = bval(c) ? cell_source<T, MODE>(a, cd, ld, k, j, b0 + c)
+                                          : mk<T>((T)0, (T)0);
+                        if (k > 0) s = csub(s, cmul(e_coef<T>(ee, k, j, HL), acc[m][c]));
+                        vs[j * NB + c] = s;
+                        Y[((long long)k * HLp + j) * NB + c] = s;
+                    }
+                }
+            }
         }
         __syncthreads();
     }
     // ---- backward sweep
     for (int k = Wc - 1; k >= 0; --k) {
         if (k < Wc - 1) {
-            // v <- y_k - e_{k+1} o x_{k+1}   (elementwise, own entries)
+            for (int q = tid; q < HLp * NB; q += CS_THREADS) {
+                const int j = q / NB;
+                vs[q] = csub(Y[(long long)k * HLp * NB + q], cmul(e_coef<T>(ee, k + 1, j, HL), vs[q]));
+            }
+            __syncthreads();
+        }
+        matvec(Xf + (long long)k * np2);
+        __syncthreads();
+        if (lane < 16) {
 #pragma unroll
-            for (int m = 0; m < MR; ++m) {
-                const int j = j0 + m * RG;
-                if (j < HL) {
-                    C2<T> xv = vs[j * NB + c];
-                    vs[j * NB + c] = csub(Y[((long long)k * HL + j) * NB + c],
-                                          cmul(ee[(long long)(k + 1) * HL + j], xv));
+            for (int m = 0; m < MRT; ++m) {
+                const int R = w + 4 * m;
+                if (R < RT) {
+                    const int j = R * 16 + lane;
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) {
+                        vs[j * NB + c] = acc[m][c];
+                        if (bval(c)) cell_emit<T, MODE>(a, cd, ld, k, j, b0 + c, acc[m][c]);
+                    }
                 }
             }
         }
-        block_matvec<T, NB, MR>(Xf + (long long)k * nn, HL, vs, Xs, acc);
         __syncthreads();
+    }
+}
+
+// ===========================================================================
+// NB in {16, 32}: block products on the matrix cores.  Wave w owns row tiles
+// w, w+4, ...; the B operand (column block) is read from LDS, the A operand
+// (factor tile) straight from global memory in MFMA order.
+template <typename T, int NB, int MODE>
+__global__ void __launch_bounds__(CS_THREADS) k_cs_mfma(CellSolveArgs<T> a) {
+    constexpr int MRT = (CS_HLPMAX / 16 + 3) / 4;
+    constexpr int NCT = NB / 16;
+    using acc_t = typename Mf<T>::acc;
+    __shared__ C2<T> vs[CS_HLPMAX * NB];
+
+    const int gc = a.cell_list[blockIdx.x];
+    const CellDesc cd = a.cells[gc];
+    const LayerDesc ld = a.layers[cd.layer];
+    const int HL = cd.HL, HLp = cd.HLp, Wc = cd.Wc;
+    const int RT = HLp >> 4, KS = HLp >> 2;
+    const int b0 = blockIdx.y * NB;
+    if (MODE == SOLVE_PROBE && a.probe0 + b0 >= cd.R) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int lc = lane & 15, lk = lane >> 4;
+    const long long np2 = (long long)HLp * HLp;
+    const C2<T>* Xf = a.X + cd.off_X;
+    const C2<T>* ee = a.coef_e + cd.off_coef;
+    C2<T>* Y = a.Y + ((long long)blockIdx.x * gridDim.y + blockIdx.y) * a.y_stride;
+    auto bval = [&](int c) {
+        const int b = b0 + c;
+        return b < a.B && (MODE != SOLVE_PROBE || a.probe0 + b < cd.R);
+    };
+    for (int q = tid; q < HLp * NB; q += CS_THREADS) vs[q] = mk<T>((T)0, (T)0);
+    __syncthreads();
+
+    acc_t cr[MRT][NCT], ci[MRT][NCT];
+    auto matmul = [&](const C2<T>* Xk) {
 #pragma unroll
-        for (int m = 0; m < MR; ++m) {
-            const int j = j0 + m * RG;
-            if (j < HL) {
-                vs[j * NB + c] = acc[m];
-                if (bvalid) cell_emit<T, NB>(a, cd, ld, k, j, b, acc[m]);
+        for (int m = 0; m < MRT; ++m)
+#pragma unroll
+            for (int t = 0; t < NCT; ++t) { cr[m][t] = mf_zero<T>(); ci[m][t] = mf_zero<T>(); }
+#pragma unroll 2
+        for (int s = 0; s < KS; ++s) {
+            C2<T> bv[NCT];
+#pragma unroll
+            for (int t = 0; t < NCT; ++t) bv[t] = vs[(4 * s + lk) * NB + t * 16 + lc];
+#pragma unroll
+            for (int m = 0; m < MRT; ++m) {
+                const int R = w + 4 * m;
+                if (R < RT) {
+                    const C2<T> x = Xk[(((long long)R * KS + s) << 6) + lane];
+#pragma unroll
+                    for (int t = 0; t < NCT; ++t) cmma<T>(x.x, x.y, bv[t].x, bv[t].y, cr[m][t], ci[m][t]);
+                }
             }
         }
+    };
+
+    // accumulators -> LDS (each lane its own entries)
+    auto store_acc = [&]() {
+#pragma unroll
+        for (int m = 0; m < MRT; ++m) {
+            const int R = w + 4 * m;
+            if (R < RT) {
+#pragma unroll
+                for (int t = 0; t < NCT; ++t)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int j = R * 16 + Mf<T>::row(lane, v);
+                        vs[j * NB + t * 16 + lc] = mk<T>(cr[m][t][v], ci[m][t][v]);
+                    }
+            }
+        }
+    };
+    const int nq = HLp * NB;
+
+    // ---- forward sweep
+    for (int k = 0; k < Wc; ++k) {
+        if (k > 0) {
+            matmul(Xf + (long long)(k - 1) * np2);
+            __syncthreads();
+            store_acc();
+            __syncthreads();
+        }
+        // y_k = b_k - e_k o t, thread-strided over (row, column) with the
+        // batch column fastest (coalesced sources and scratch)
+        for (int q = tid; q < nq; q += CS_THREADS) {
+            const int j = q / NB, c = q - j * NB;
+            C2<T> yv = bval(c) ? cell_source<T, MODE>(a, cd, ld, k, j, b0 + c) : mk<T>((T)0, (T)0);
+            if (k > 0) yv = csub(yv, cmul(e_coef<T>(ee, k, j, HL), vs[q]));
+            vs[q] = yv;
+            Y[(long long)k * nq + q] = yv;
+        }
         __syncthreads();
+    }
+    // ---- backward sweep
+    for (int k = Wc - 1; k >= 0; --k) {
+        if (k < Wc - 1) {
+            for (int q = tid; q < nq; q += CS_THREADS) {
+                const int j = q / NB;
+                vs[q] = csub(Y[(long long)k * nq + q], cmul(e_coef<T>(ee, k + 1, j, HL), vs[q]));
+            }
+            __syncthreads();
+        }
+        matmul(Xf + (long long)k * np2);
+        __syncthreads();
+        store_acc();
+        __syncthreads();
+        for (int q = tid; q < nq; q += CS_THREADS) {
+            const int j = q / NB, c = q - j * NB;
+            if (bval(c)) cell_emit<T, MODE>(a, cd, ld, k, j, b0 + c, vs[q]);
+        }
+    }
+}
+
+template <typename T, int MODE>
+void launch_mode(const CellSolveArgs<T>& a, int ncells, hipStream_t st) {
+    const int nb = a.nb > 0 ? a.nb : cs_nb(a.B);
+    const int chunks = (a.B + nb - 1) / nb;
+    dim3 grid(ncells, chunks), blk(CS_THREADS);
+    switch (nb) {
+    case 1: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cs_gemv<T, 1, MODE>), grid, blk, 0, st, a); break;
+    case 2: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cs_gemv<T, 2, MODE>), grid, blk, 0, st, a); break;
+    case 4: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cs_gemv<T, 4, MODE>), grid, blk, 0, st, a); break;
+    case 16: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cs_mfma<T, 16, MODE>), grid, blk, 0, st, a); break;
+    default: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cs_mfma<T, 32, MODE>), grid, blk, 0, st, a); break;
     }
 }
 
@@ -267,13 +402,11 @@ template <typename T>
 void launch_cell_solve(const CellSolveArgs<T>& a, int ncells_launch, int nb_chunks,
                        hipStream_t st) {
     (void)nb_chunks;
-    if (a.B <= 1) {
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cell_solve<T, 1>), dim3(ncells_launch, 1), dim3(CS_THREADS), 0, st, a);
-    } else if (a.B <= 4) {
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cell_solve<T, 4>), dim3(ncells_launch, 1), dim3(CS_THREADS), 0, st, a);
-    } else {
-        const int chunks = (a.B + 15) / 16;
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cell_solve<T, 16>), dim3(ncells_launch, chunks), dim3(CS_THREADS), 0, st, a);
+    switch (a.mode) {
+    case SOLVE_GRID: launch_mode<T, SOLVE_GRID>(a, ncells_launch, st); break;
+    case SOLVE_PROBE: launch_mode<T, SOLVE_PROBE>(a, ncells_launch, st); break;
+    case SOLVE_SAMPLE: launch_mode<T, SOLVE_SAMPLE>(a, ncells_launch, st); break;
+    default: launch_mode<T, SOLVE_VOLUME>(a, ncells_launch, st); break;
     }
 }
 

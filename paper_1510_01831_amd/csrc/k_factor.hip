@@ -27,8 +27,11 @@ __device__ inline T cabs2(C2<T> a) { return a.x * a.x + a.y * a.y; }
 // entries: entry e = r*n + j is only ever touched by thread e % blockDim.x)
 // and write the inverse to `out` (row stride ldo).  `work` is destroyed.
 // LDS: colbuf[2][GJ_NMAX], prow[GJ_NMAX], pivrow/pivstep/used, reduction.
+// out_tiled > 0: write the inverse in the 16x4 MFMA tile layout of order
+// out_tiled (padded entries untouched); otherwise row-major with stride ldo.
 template <typename T>
-__device__ void gj_invert(C2<T>* work, C2<T>* out, int n, long long ldo, int* sing_flag) {
+__device__ void gj_invert(C2<T>* work, C2<T>* out, int n, long long ldo, int* sing_flag,
+                          int out_tiled = 0) {
     __shared__ C2<T> colbuf[2][GJ_NMAX];
     __shared__ C2<T> prow[GJ_NMAX];
     __shared__ int pivrow[GJ_NMAX];
@@ -127,7 +130,9 @@ __device__ void gj_invert(C2<T>* work, C2<T>* out, int n, long long ldo, int* si
     for (long long e = tid; e < nn; e += nt) {
         int r = (int)(e / n);
         int j = (int)(e % n);
-        out[(long long)pivstep[r] * ldo + pivrow[j]] = work[e];
+        const int oi = pivstep[r], oj = pivrow[j];
+        if (out_tiled) out[xt_index(oi, oj, out_tiled)] = work[e];
+        else out[(long long)oi * ldo + oj] = work[e];
     }
     __syncthreads();
 }
@@ -140,8 +145,9 @@ k_cell_factor(const CellDesc* __restrict__ cells, const double2* __restrict__ di
               C2<T>* __restrict__ Xpool, C2<T>* __restrict__ workpool, long long work_stride,
               int* sing_flag) {
     const CellDesc cd = cells[blockIdx.x];
-    const int HL = cd.HL, Wc = cd.Wc;
+    const int HL = cd.HL, Wc = cd.Wc, HLp = cd.HLp;
     const long long nn = (long long)HL * HL;
+    const long long np2 = (long long)HLp * HLp;
     C2<T>* work = workpool + (long long)blockIdx.x * work_stride;
     C2<T>* X = Xpool + cd.off_X;
     const double2* dg = diag + cd.off_coef;
@@ -151,7 +157,7 @@ k_cell_factor(const CellDesc* __restrict__ cells, const double2* __restrict__ di
     for (int k = 0; k < Wc; ++k) {
         // S_k = A_k - diag(e_k) X_{k-1} diag(e_k), written with the ownership
         // pattern of gj_invert (entry e owned by thread e % nt).
-        const C2<T>* Xp = X + (long long)(k - 1) * nn;
+        const C2<T>* Xp = X + (long long)(k - 1) * np2;
         for (long long q = tid; q < nn; q += nt) {
             int r = (int)(q / HL), j = (int)(q % HL);
             double2 a; a.x = 0.0; a.y = 0.0;
@@ -162,14 +168,23 @@ k_cell_factor(const CellDesc* __restrict__ cells, const double2* __restrict__ di
             if (k > 0) {
                 double2 er = ee[(long long)k * HL + r];
                 double2 ej = ee[(long long)k * HL + j];
-                C2<T> x = Xp[q];
+                C2<T> x = Xp[xt_index(r, j, HLp)];
                 C2<T> t = cmul(cmul(mk<T>((T)er.x, (T)er.y), x), mk<T>((T)ej.x, (T)ej.y));
                 v = csub(v, t);
             }
             work[q] = v;
         }
+        if (HLp != HL) {       // zero the padding of the tiled block
+            C2<T>* Xk = X + (long long)k * np2;
+            for (long long q = tid; q < np2; q += nt) {
+                const int tile = (int)(q >> 6), ln = (int)(q & 63);
+                const int i = (tile / (HLp >> 2)) * 16 + (ln & 15);
+                const int j = (tile % (HLp >> 2)) * 4 + (ln >> 4);
+                if (i >= HL || j >= HL) Xk[q] = mk<T>((T)0, (T)0);
+            }
+        }
         __syncthreads();
-        gj_invert<T>(work, X + (long long)k * nn, HL, HL, sing_flag);
+        gj_invert<T>(work, X + (long long)k * np2, HL, HL, sing_flag, HLp);
     }
 }
 

@@ -6,7 +6,10 @@
 // x rows are gathered from up to NSEG contiguous segments (trace pairs, inner
 // traces), the output rows are scattered to up to NOSEG contiguous segments,
 // and every vector row holds B batch values contiguously (batch fastest).
+#include <algorithm>
+
 #include "hz_common.h"
+#include "hz_mfma.h"
 
 namespace hz {
 
@@ -121,12 +124,124 @@ k_gemm_tiled(const GemmTask<T>* __restrict__ tasks, int B) {
     }
 }
 
+// Batched: MT x TBM output tile per workgroup on the matrix cores.  A (MT rows
+// x 16 k) and x (16 k x TBM batch columns) are staged in padded LDS tiles;
+// the 4 waves form a 2 x 2 grid, each computing (MT/2) x (TBM/2) as 16x16
+// complex tiles (four real MFMAs each per 4-deep k step).
+constexpr int MTK = 16;
+
+template <typename T, int MT, int TBM>
+__global__ void __launch_bounds__(GV_THREADS)
+k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B) {
+    constexpr int RTW = MT / 32;                 // row tiles per wave
+    constexpr int CTW = TBM / 32;                // column tiles per wave
+    using acc_t = typename Mf<T>::acc;
+    const GemmTask<T> t = tasks[blockIdx.z];
+    const int i0 = blockIdx.x * MT;
+    if (i0 >= t.m) return;
+    if (t.ncol > 0) B = t.ncol;
+    const int b0 = blockIdx.y * TBM;
+    if (b0 >= B) return;
+    __shared__ C2<T> As[MT][MTK + 1];
+    __shared__ C2<T> Xs[MTK][TBM + 1];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int lc = lane & 15, lk = lane >> 4;
+    const int wr = (w >> 1) * (MT / 2), wc = (w & 1) * (TBM / 2);
+    acc_t cr[RTW][CTW], ci[RTW][CTW];
+#pragma unroll
+    for (int a = 0; a < RTW; ++a)
+#pragma unroll
+        for (int c = 0; c < CTW; ++c) { cr[a][c] = mf_zero<T>(); ci[a][c] = mf_zero<T>(); }
+    for (int sg = 0; sg < t.nseg; ++sg) {
+        const C2<T>* xp = t.seg_ptr[sg];
+        if (!xp) continue;
+        const int k0 = t.seg_k0[sg], len = t.seg_len[sg];
+        for (int kc = 0; kc < len; kc += MTK) {
+            __syncthreads();
+            for (int idx = tid; idx < MT * MTK / 4; idx += GV_THREADS) {   // A: 4 k per thread
+                const int r = idx >> 2, q0 = (idx & 3) * 4;
+                const int i = i0 + r;
+                const C2<T>* src = t.A + (long long)i * t.lda + k0 + kc + q0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    As[r][q0 + q] = (i < t.m && kc + q0 + q < len) ? src[q] : mk<T>((T)0, (T)0);
+            }
+            for (int idx = tid; idx < MTK * TBM / 4; idx += GV_THREADS) {  // x: 4 columns per thread
+                const int q = idx / (TBM / 4), c0 = (idx % (TBM / 4)) * 4;
+                const C2<T>* src = xp + (long long)(kc + q) * t.ldx + b0 + c0;
+                const bool ok = kc + q < len;
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    Xs[q][c0 + c] = (ok && b0 + c0 + c < B) ? src[c] : mk<T>((T)0, (T)0);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int s4 = 0; s4 < MTK / 4; ++s4) {
+                C2<T> av[RTW], bv[CTW];
+#pragma unroll
+                for (int a = 0; a < RTW; ++a) av[a] = As[wr + a * 16 + lc][s4 * 4 + lk];
+#pragma unroll
+                for (int c = 0; c < CTW; ++c) bv[c] = Xs[s4 * 4 + lk][wc + c * 16 + lc];
+#pragma unroll
+                for (int a = 0; a < RTW; ++a)
+#pragma unroll
+                    for (int c = 0; c < CTW; ++c)
+                        cmma<T>(av[a].x, av[a].y, bv[c].x, bv[c].y, cr[a][c], ci[a][c]);
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < RTW; ++a)
+#pragma unroll
+        for (int c = 0; c < CTW; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = i0 + wr + a * 16 + Mf<T>::row(lane, v);
+                const int b = b0 + wc + c * 16 + lc;
+                if (i < t.m && b < B) epilogue<T>(t, i, b, mk<T>(cr[a][c][v], ci[a][c][v]));
+            }
+}
+
+template <typename T>
+__global__ void k_copy(C2<T>* __restrict__ y, const C2<T>* __restrict__ x, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        y[i] = x[i];
+}
+
+template <typename T>
+void launch_copy(C2<T>* y, const C2<T>* x, long long n, hipStream_t st) {
+    if (n <= 0) return;
+    const int blocks = (int)std::min<long long>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_copy<T>), dim3(blocks), dim3(256), 0, st, y, x, n);
+}
+template void launch_copy<double>(double2*, const double2*, long long, hipStream_t);
+template void launch_copy<float>(float2*, const float2*, long long, hipStream_t);
+
 template <typename T>
 void launch_gemm(const GemmTask<T>* tasks_dev, int ntasks, int max_m, int B, hipStream_t st) {
     if (ntasks <= 0 || max_m <= 0) return;
     if (B == 1) {
         dim3 grid((max_m + GV_ROWS - 1) / GV_ROWS, 1, ntasks);
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemv<T>), grid, dim3(GV_THREADS), 0, st, tasks_dev);
+    } else if (B >= 16) {
+        // largest tile that still gives every CU work (>= 512 workgroups)
+        auto count = [&](int mt, int tb) {
+            return (long long)ntasks * ((max_m + mt - 1) / mt) * ((B + tb - 1) / tb);
+        };
+        if (B >= 64 && count(64, 64) >= 512) {
+            dim3 grid((max_m + 63) / 64, (B + 63) / 64, ntasks);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 64, 64>), grid, dim3(GV_THREADS), 0,
+                               st, tasks_dev, B);
+        } else if (count(64, 32) >= 512) {
+            dim3 grid((max_m + 63) / 64, (B + 31) / 32, ntasks);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 64, 32>), grid, dim3(GV_THREADS), 0,
+                               st, tasks_dev, B);
+        } else {
+            dim3 grid((max_m + 31) / 32, (B + 31) / 32, ntasks);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32>), grid, dim3(GV_THREADS), 0,
+                               st, tasks_dev, B);
+        }
     } else {
         dim3 grid((max_m + TM - 1) / TM, (B + TB - 1) / TB, ntasks);
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_tiled<T>), grid, dim3(GV_THREADS), 0, st,

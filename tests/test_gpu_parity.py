@@ -210,3 +210,45 @@ def test_misfit_gradient_vs_oracle():
     s.close()
     assert abs(J - J_ref) <= 1e-9 * J_ref
     assert _rel(g, g_ref) < 1e-8
+
+
+def test_batched_paths_match_oracle():
+    """Batches that select the matrix-core kernels (16 <= B < 64 and B >= 64)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c, omega = media.small_problem(N, P, L, LC, seed=5)
+    prob = Problem(c, omega, P)
+    oracle = LayeredSolver(prob, L)
+    s = hz.Solver(torch.from_numpy(c), omega, P, L, LC, max_batch=70)
+    rng = np.random.default_rng(12)
+    # cell solve with 20 and 40 right-hand sides
+    for B in (20, 40):
+        _log(f"[batched cell_solve] B={B}")
+        HL, Wc = s.cell_shape(2, 1)
+        C = CellGrid(oracle.grids[2], 17, 32, 1, LC)
+        g = rng.standard_normal((HL, Wc, B)) + 1j * rng.standard_normal((HL, Wc, B))
+        x = s.cell_solve(2, 1, torch.from_numpy(g).cuda()).cpu().numpy()
+        lu = spla.splu(C.H.tocsc())
+        ref = lu.solve(g.reshape(HL * Wc, B)).reshape(HL, Wc, B)
+        assert _rel(x, ref) < 1e-11
+    # M and P^GS on 20 vectors
+    K, W = L - 1, prob.W
+    x = _rand_pol(K, W, 20, 4)
+    _log("[batched apply_sie / precond] B=20")
+    y = s.apply_sie(torch.from_numpy(x).cuda()).cpu().numpy()
+    z = s.apply_precond(torch.from_numpy(x).cuda()).cpu().numpy()
+    for bb in (0, 7, 19):
+        assert _rel(y[:, bb], oracle.pack(*oracle.apply_M(*oracle.unpack(x[:, bb])))) < 1e-11
+        assert _rel(z[:, bb], oracle.pack(*oracle.precond_gs(*oracle.unpack(x[:, bb])))) < 1e-11
+    # full solves with 70 sources (a row of sources and a few scattered ones)
+    _log("[batched solve] B=70")
+    xs = tuple(int(v) for v in np.linspace(1, N, 64).round())
+    f = np.concatenate([media.point_sources(N, xs, 9),
+                        media.point_sources(N, (3, 11, 19, 27, 35, 43), 40)])
+    u = s.solve(torch.from_numpy(f), tol=1e-12).cpu().numpy()
+    F = np.stack([prob.extend(fi).ravel() for fi in f], axis=1)
+    U = spla.splu(prob.H.tocsc()).solve(F).T.reshape(-1, prob.W, prob.W)
+    errs = [_rel(u[b], prob.restrict(U[b])) for b in range(len(f))]
+    _log(f"  max err {max(errs):.2e}")
+    assert max(errs) < 1e-9
+    s.close()
