@@ -825,7 +825,7 @@ void ensure_work(hz_ctx* c, int B, bool volume = true) {
         const long long inner = std::max<long long>((long long)d.L * c->inner_per_layer * B, 1);
         w.gf = alloc_c<T>(c, inner);
         // cell-solve scratch: one region per workgroup of a volume solve
-        const int nb = cs_nb(B);
+        const int nb = cs_nb_cap(B);
         const int chunks = (B + nb - 1) / nb;
         w.y_stride = (long long)d.Wcmax * d.HLpmax * nb;
         w.y_wgs = (int)c->cells.size() * chunks;
@@ -898,7 +898,7 @@ template <typename T>
 void cell_solve_launch(hz_ctx* c, CellSolveArgs<T> a, const std::vector<int>& list, int Bcols) {
     // groups limited by the scratch available
     Work<T>& w = work<T>(c);
-    const int nb = cs_nb(Bcols, (int)list.size());
+    const int nb = cs_nb(Bcols, (int)list.size(), c->d.HLpmax);
     const int chunks = (Bcols + nb - 1) / nb;
     const long long wg_elems = (long long)c->d.Wcmax * c->d.HLpmax * nb;
     const int per = (int)std::max<long long>(1, (w.y_stride * w.y_wgs / wg_elems) / chunks);
@@ -1022,7 +1022,7 @@ void factor_impl(hz_ctx* c) {
     int Rmax = 0;
     for (auto& cd : c->cells) Rmax = std::max(Rmax, cd.R);
     if (Rmax > 0) {
-        const int nb = cs_nb(Rmax);
+        const int nb = cs_nb(Rmax, ncells, d.HLpmax);
         const int chunks = (Rmax + nb - 1) / nb;
         const long long ystride = (long long)d.Wcmax * d.HLpmax * nb;
         // scratch budget ~ 4 GiB

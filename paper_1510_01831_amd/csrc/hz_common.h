@@ -8,6 +8,8 @@
 //    at [k * HL + j], because the cell factorisation eliminates whole columns;
 //  * dense operators are row-major.
 #pragma once
+#include <algorithm>
+#include <cstdlib>
 
 #include <hip/hip_runtime.h>
 #include <cstddef>
@@ -208,15 +210,28 @@ void launch_gemm(const GemmTask<T>* tasks_dev, int ntasks, int max_m, int B, hip
 template <typename T>
 void launch_copy(C2<T>* y, const C2<T>* x, long long n, hipStream_t st);
 
-// number of right-hand sides one cell-solve workgroup handles for a batch B
-// When a launch has few cells, a narrower batch per workgroup (16 instead of
-// 32 columns) doubles the workgroups and halves each one's sequential work.
-inline int cs_nb(int B, int ncells = 1 << 20) {
+// number of right-hand sides one cell-solve workgroup handles for a batch B:
+// the largest value, used to size the per-workgroup scratch
+inline int cs_nb_cap(int B) {
     if (B <= 1) return 1;
     if (B <= 2) return 2;
     if (B <= 4) return 4;
-    if (B <= 16) return 16;
-    return (long long)ncells * ((B + 31) / 32) < 512 ? 16 : 32;
+    return B <= 16 ? 16 : 32;
+}
+
+// and the value used for a launch of `ncells` cells whose largest padded
+// height is `hlp`.  With few cells, 16 columns instead of 32 doubles the
+// workgroups and halves each one's sequential work; cells taller than 128
+// rows keep 16 columns (two row tiles per wave leave no registers for 32).
+// HZ_CELL_NB overrides the choice (1, 2, 4, 16 or 32; clamped to the cap).
+inline int cs_nb(int B, int ncells, int hlp) {
+    int nb = cs_nb_cap(B);
+    if (nb == 32 && ((long long)ncells * ((B + 31) / 32) < 512 || hlp > 128)) nb = 16;
+    if (const char* e = std::getenv("HZ_CELL_NB")) {
+        const int o = std::atoi(e);
+        if (o == 1 || o == 2 || o == 4 || o == 16 || o == 32) nb = std::min(o, cs_nb_cap(B));
+    }
+    return nb;
 }
 
 // vector / reduction kernels (FP64 unless templated)

@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(CS_THREADS) k_cs_gemv(CellSolveArgs<T> a) {
 
     const int gc = a.cell_list[blockIdx.x];
     const CellDesc cd = a.cells[gc];
-    const LayerDesc ld = a.layers[cd.layer];
+    const LayerDesc& ld = a.layers[cd.layer];
     const int HL = cd.HL, HLp = cd.HLp, Wc = cd.Wc;
     const int RT = HLp >> 4, KS = HLp >> 2;
     const int b0 = blockIdx.y * NB;
@@ -274,127 +274,222 @@ __global__ void __launch_bounds__(CS_THREADS) k_cs_gemv(CellSolveArgs<T> a) {
 }
 
 // ===========================================================================
-// NB in {16, 32}: block products on the matrix cores.  Wave w owns row tiles
-// w, w+4, ...; the B operand (column block) is read from LDS, the A operand
-// (factor tile) straight from global memory in MFMA order.
-template <typename T, int NB, int MODE>
-__global__ void __launch_bounds__(CS_THREADS) k_cs_mfma(CellSolveArgs<T> a) {
-    constexpr int MRT = (CS_HLPMAX / 16 + 3) / 4;
-    constexpr int NCT = NB / 16;
-    using acc_t = typename Mf<T>::acc;
-    __shared__ C2<T> vs[CS_HLPMAX * NB];
+// NB in {16, 32}: block products on the matrix cores, 8 waves per workgroup.
+// Wave w owns the 16-row tiles w and w + 8 (MC of them, a per-wave constant
+// chosen once by a wave-uniform switch).  The A operand (factor tile) streams
+// from global memory in MFMA order with a two-group register double buffer;
+// the B operand (current column block) is read from LDS.  The elementwise
+// updates y = b - e o t run on the accumulators in registers: each lane keeps
+// its own entries, so the forward iterates go to a lane-private, coalesced
+// scratch and the sources and scratch reads of the next step are issued
+// before the block product that they wait for.
+constexpr int CS_MF_THREADS = 512;
+constexpr int CS_MF_WAVES = CS_MF_THREADS / 64;
+#ifndef CS_U1
+#define CS_U1 4
+#endif
+#ifndef CS_U2
+#define CS_U2 2
+#endif
 
-    const int gc = a.cell_list[blockIdx.x];
-    const CellDesc cd = a.cells[gc];
-    const LayerDesc ld = a.layers[cd.layer];
+template <typename T, int NB, int MODE, int MC>
+__device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const CellDesc& cd,
+                                             const LayerDesc& ld, C2<T>* vs, int b0) {
+    constexpr int NCT = NB / 16;
+    constexpr int MCA = MC > 0 ? MC : 1;
+    constexpr int U = MC > 1 ? CS_U2 : CS_U1; // k steps per register group
+    using acc_t = typename Mf<T>::acc;
     const int HL = cd.HL, HLp = cd.HLp, Wc = cd.Wc;
-    const int RT = HLp >> 4, KS = HLp >> 2;
-    const int b0 = blockIdx.y * NB;
-    if (MODE == SOLVE_PROBE && a.probe0 + b0 >= cd.R) return;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int KS = HLp >> 2;                  // multiple of 4
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int lc = lane & 15, lk = lane >> 4;
     const long long np2 = (long long)HLp * HLp;
-    const C2<T>* Xf = a.X + cd.off_X;
-    const C2<T>* ee = a.coef_e + cd.off_coef;
-    C2<T>* Y = a.Y + ((long long)blockIdx.x * gridDim.y + blockIdx.y) * a.y_stride;
+    const long long nq = (long long)HLp * NB;
+    const C2<T>* __restrict__ Xf = a.X + cd.off_X;
+    const C2<T>* __restrict__ ee = a.coef_e + cd.off_coef;
+    C2<T>* __restrict__ Y = a.Y + ((long long)blockIdx.x * gridDim.y + blockIdx.y) * a.y_stride;
+    const C2<T> z = mk<T>((T)0, (T)0);
+
+    auto row_of = [&](int m, int v) { return (w + CS_MF_WAVES * m) * 16 + Mf<T>::row(lane, v); };
+    auto yidx = [&](int m, int t, int v) {
+        return ((long long)((w + CS_MF_WAVES * m) * NCT + t) * 4 + v) * 64 + lane;
+    };
     auto bval = [&](int c) {
         const int b = b0 + c;
         return b < a.B && (MODE != SOLVE_PROBE || a.probe0 + b < cd.R);
     };
-    for (int q = tid; q < HLp * NB; q += CS_THREADS) vs[q] = mk<T>((T)0, (T)0);
-    __syncthreads();
 
-    acc_t cr[MRT][NCT], ci[MRT][NCT];
-    auto matmul = [&](const C2<T>* Xk) {
+    acc_t cr[MCA][NCT], ci[MCA][NCT];
+    auto matmul = [&](const C2<T>* __restrict__ Xk) {
 #pragma unroll
-        for (int m = 0; m < MRT; ++m)
+        for (int m = 0; m < MCA; ++m)
 #pragma unroll
             for (int t = 0; t < NCT; ++t) { cr[m][t] = mf_zero<T>(); ci[m][t] = mf_zero<T>(); }
-#pragma unroll 2
-        for (int s = 0; s < KS; ++s) {
-            C2<T> bv[NCT];
+        if constexpr (MC > 0) {
+            const C2<T>* xp[MC];
 #pragma unroll
-            for (int t = 0; t < NCT; ++t) bv[t] = vs[(4 * s + lk) * NB + t * 16 + lc];
+            for (int m = 0; m < MC; ++m)
+                xp[m] = Xk + (((long long)(w + CS_MF_WAVES * m) * KS) << 6) + lane;
+            C2<T> xa[U][MC], xb[U][MC];
+            auto load = [&](C2<T> (&dst)[U][MC], int s0) {
 #pragma unroll
-            for (int m = 0; m < MRT; ++m) {
-                const int R = w + 4 * m;
-                if (R < RT) {
-                    const C2<T> x = Xk[(((long long)R * KS + s) << 6) + lane];
+                for (int u = 0; u < U; ++u)
 #pragma unroll
-                    for (int t = 0; t < NCT; ++t) cmma<T>(x.x, x.y, bv[t].x, bv[t].y, cr[m][t], ci[m][t]);
+                    for (int m = 0; m < MC; ++m) dst[u][m] = xp[m][(long long)(s0 + u) << 6];
+            };
+            auto mult = [&](const C2<T> (&src)[U][MC], int s0) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    C2<T> bv[NCT];
+#pragma unroll
+                    for (int t = 0; t < NCT; ++t) bv[t] = vs[(4 * (s0 + u) + lk) * NB + t * 16 + lc];
+#pragma unroll
+                    for (int m = 0; m < MC; ++m)
+#pragma unroll
+                        for (int t = 0; t < NCT; ++t)
+                            cmma<T>(src[u][m].x, src[u][m].y, bv[t].x, bv[t].y, cr[m][t], ci[m][t]);
                 }
+            };
+            load(xa, 0);
+            for (int s = 0; s < KS; s += 2 * U) {
+                if (s + U < KS) load(xb, s + U);
+                mult(xa, s);
+                if (s + U >= KS) break;
+                if (s + 2 * U < KS) load(xa, s + 2 * U);
+                mult(xb, s + U);
             }
         }
     };
 
-    // accumulators -> LDS (each lane its own entries)
-    auto store_acc = [&]() {
+    C2<T> pv[MCA][NCT][4];   // prefetched sources (forward) / iterates (backward)
+    C2<T> pe[MCA][4];        // prefetched coupling coefficients
+
+    // ---- forward sweep: y_0 = b_0, y_k = b_k - e_k o (X_{k-1} y_{k-1})
+    for (int k = 0; k < Wc; ++k) {
 #pragma unroll
-        for (int m = 0; m < MRT; ++m) {
-            const int R = w + 4 * m;
-            if (R < RT) {
+        for (int m = 0; m < MC; ++m)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int j = row_of(m, v);
+                pe[m][v] = k > 0 ? e_coef<T>(ee, k, j, HL) : z;
+#pragma unroll
+                for (int t = 0; t < NCT; ++t) {
+                    const int c = t * 16 + lc;
+                    pv[m][t][v] = bval(c) ? cell_source<T, MODE>(a, cd, ld, k, j, b0 + c) : z;
+                }
+            }
+        if (k > 0) matmul(Xf + (long long)(k - 1) * np2);
+#pragma unroll
+        for (int m = 0; m < MC; ++m)
+#pragma unroll
+            for (int t = 0; t < NCT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    C2<T> y = pv[m][t][v];
+                    if (k > 0) y = csub(y, cmul(pe[m][v], mk<T>(cr[m][t][v], ci[m][t][v])));
+                    pv[m][t][v] = y;
+                    Y[(long long)k * nq + yidx(m, t, v)] = y;
+                }
+        __syncthreads();                      // all block products of this step done
+#pragma unroll
+        for (int m = 0; m < MC; ++m)
+#pragma unroll
+            for (int t = 0; t < NCT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) vs[row_of(m, v) * NB + t * 16 + lc] = pv[m][t][v];
+        __syncthreads();
+    }
+    // ---- backward sweep: x_{W-1} = X_{W-1} y_{W-1}, x_k = X_k (y_k - e_{k+1} o x_{k+1})
+    for (int k = Wc - 1; k >= 0; --k) {
+        if (k > 0) {
+#pragma unroll
+            for (int m = 0; m < MC; ++m)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    pe[m][v] = e_coef<T>(ee, k, row_of(m, v), HL);
+#pragma unroll
+                    for (int t = 0; t < NCT; ++t)
+                        pv[m][t][v] = Y[(long long)(k - 1) * nq + yidx(m, t, v)];
+                }
+        }
+        matmul(Xf + (long long)k * np2);
+#pragma unroll
+        for (int m = 0; m < MC; ++m)
+#pragma unroll
+            for (int t = 0; t < NCT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int c = t * 16 + lc;
+                    const C2<T> x = mk<T>(cr[m][t][v], ci[m][t][v]);
+                    if (bval(c)) cell_emit<T, MODE>(a, cd, ld, k, row_of(m, v), b0 + c, x);
+                    pv[m][t][v] = csub(pv[m][t][v], cmul(pe[m][v], x));
+                }
+        if (k > 0) {
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < MC; ++m)
 #pragma unroll
                 for (int t = 0; t < NCT; ++t)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int j = R * 16 + Mf<T>::row(lane, v);
-                        vs[j * NB + t * 16 + lc] = mk<T>(cr[m][t][v], ci[m][t][v]);
-                    }
-            }
-        }
-    };
-    const int nq = HLp * NB;
-
-    // ---- forward sweep
-    for (int k = 0; k < Wc; ++k) {
-        if (k > 0) {
-            matmul(Xf + (long long)(k - 1) * np2);
+                    for (int v = 0; v < 4; ++v) vs[row_of(m, v) * NB + t * 16 + lc] = pv[m][t][v];
             __syncthreads();
-            store_acc();
-            __syncthreads();
-        }
-        // y_k = b_k - e_k o t, thread-strided over (row, column) with the
-        // batch column fastest (coalesced sources and scratch)
-        for (int q = tid; q < nq; q += CS_THREADS) {
-            const int j = q / NB, c = q - j * NB;
-            C2<T> yv = bval(c) ? cell_source<T, MODE>(a, cd, ld, k, j, b0 + c) : mk<T>((T)0, (T)0);
-            if (k > 0) yv = csub(yv, cmul(e_coef<T>(ee, k, j, HL), vs[q]));
-            vs[q] = yv;
-            Y[(long long)k * nq + q] = yv;
-        }
-        __syncthreads();
-    }
-    // ---- backward sweep
-    for (int k = Wc - 1; k >= 0; --k) {
-        if (k < Wc - 1) {
-            for (int q = tid; q < nq; q += CS_THREADS) {
-                const int j = q / NB;
-                vs[q] = csub(Y[(long long)k * nq + q], cmul(e_coef<T>(ee, k + 1, j, HL), vs[q]));
-            }
-            __syncthreads();
-        }
-        matmul(Xf + (long long)k * np2);
-        __syncthreads();
-        store_acc();
-        __syncthreads();
-        for (int q = tid; q < nq; q += CS_THREADS) {
-            const int j = q / NB, c = q - j * NB;
-            if (bval(c)) cell_emit<T, MODE>(a, cd, ld, k, j, b0 + c, vs[q]);
         }
     }
 }
 
+// MCMAX = 1 serves cells of up to 8 row tiles (HLp <= 128) with fewer
+// registers; MCMAX = 2 serves up to 16.
+template <typename T, int NB, int MODE, int MCMAX>
+__global__ void __launch_bounds__(CS_MF_THREADS) k_cs_mfma(CellSolveArgs<T> a) {
+    extern __shared__ __align__(16) unsigned char cs_lds[];
+    C2<T>* vs = reinterpret_cast<C2<T>*>(cs_lds);
+    const int gc = a.cell_list[blockIdx.x];
+    const CellDesc cd = a.cells[gc];
+    const LayerDesc& ld = a.layers[cd.layer];
+    const int b0 = blockIdx.y * NB;
+    if (MODE == SOLVE_PROBE && a.probe0 + b0 >= cd.R) return;   // whole workgroup
+    const int RT = cd.HLp >> 4;
+    const int w = threadIdx.x >> 6;
+    // tiles w and w + 8 (HLp <= 224 gives at most 14 tiles)
+    const int mc = RT > w ? (RT - w + CS_MF_WAVES - 1) / CS_MF_WAVES : 0;
+    // every branch passes the same sequence of barriers
+    if (mc == 0) cs_mfma_body<T, NB, MODE, 0>(a, cd, ld, vs, b0);
+    else if (MCMAX == 1 || mc == 1) cs_mfma_body<T, NB, MODE, 1>(a, cd, ld, vs, b0);
+    else cs_mfma_body<T, NB, MODE, MCMAX>(a, cd, ld, vs, b0);
+}
+
+template <typename T, int NB, int MODE, int MCMAX>
+void launch_cs_mfma_mc(const CellSolveArgs<T>& a, dim3 grid, size_t lds, hipStream_t st) {
+    static bool attr = false;
+    if (!attr) {
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cs_mfma<T, NB, MODE, MCMAX>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(CS_HLPMAX * NB * sizeof(C2<T>)));
+        attr = true;
+    }
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cs_mfma<T, NB, MODE, MCMAX>), grid, dim3(CS_MF_THREADS),
+                       lds, st, a);
+}
+
+template <typename T, int NB, int MODE>
+void launch_cs_mfma(const CellSolveArgs<T>& a, dim3 grid, hipStream_t st) {
+    const int hlp = (a.HLmax + 15) / 16 * 16;     // largest HLp of any cell
+    const size_t lds = (size_t)hlp * NB * sizeof(C2<T>);
+    if (hlp <= 16 * CS_MF_WAVES) launch_cs_mfma_mc<T, NB, MODE, 1>(a, grid, lds, st);
+    else launch_cs_mfma_mc<T, NB, MODE, 2>(a, grid, lds, st);
+}
+
 template <typename T, int MODE>
 void launch_mode(const CellSolveArgs<T>& a, int ncells, hipStream_t st) {
-    const int nb = a.nb > 0 ? a.nb : cs_nb(a.B);
+    const int nb = a.nb > 0 ? a.nb : cs_nb_cap(a.B);
     const int chunks = (a.B + nb - 1) / nb;
     dim3 grid(ncells, chunks), blk(CS_THREADS);
     switch (nb) {
     case 1: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cs_gemv<T, 1, MODE>), grid, blk, 0, st, a); break;
     case 2: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cs_gemv<T, 2, MODE>), grid, blk, 0, st, a); break;
     case 4: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cs_gemv<T, 4, MODE>), grid, blk, 0, st, a); break;
-    case 16: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cs_mfma<T, 16, MODE>), grid, blk, 0, st, a); break;
-    default: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cs_mfma<T, 32, MODE>), grid, blk, 0, st, a); break;
+    case 16: launch_cs_mfma<T, 16, MODE>(a, grid, st); break;
+    default: launch_cs_mfma<T, 32, MODE>(a, grid, st); break;
     }
 }
 

@@ -42,7 +42,7 @@ __device__ inline void epilogue(const GemmTask<T>& t, int i, int b, C2<T> acc) {
 // B == 1: each wave reduces one row at a time, lanes run along k.
 template <typename T>
 __global__ void __launch_bounds__(GV_THREADS) k_gemv(const GemmTask<T>* __restrict__ tasks) {
-    const GemmTask<T> t = tasks[blockIdx.z];
+    const GemmTask<T>& t = tasks[blockIdx.z];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     for (int rr = wave; rr < GV_ROWS; rr += GV_THREADS / 64) {
@@ -70,7 +70,7 @@ constexpr int TM = 32, TB = 32, TK = 16;
 template <typename T>
 __global__ void __launch_bounds__(GV_THREADS)
 k_gemm_tiled(const GemmTask<T>* __restrict__ tasks, int B) {
-    const GemmTask<T> t = tasks[blockIdx.z];
+    const GemmTask<T>& t = tasks[blockIdx.z];
     const int i0 = blockIdx.x * TM;
     if (i0 >= t.m) return;
     const int b0 = blockIdx.y * TB;
@@ -136,7 +136,7 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B) {
     constexpr int RTW = MT / 32;                 // row tiles per wave
     constexpr int CTW = TBM / 32;                // column tiles per wave
     using acc_t = typename Mf<T>::acc;
-    const GemmTask<T> t = tasks[blockIdx.z];
+    const GemmTask<T>& t = tasks[blockIdx.z];
     const int i0 = blockIdx.x * MT;
     if (i0 >= t.m) return;
     if (t.ncol > 0) B = t.ncol;
