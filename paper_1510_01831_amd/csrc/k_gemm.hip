@@ -124,13 +124,57 @@ k_gemm_tiled(const GemmTask<T>* __restrict__ tasks, int B) {
     }
 }
 
-// Batched: MT x TBM output tile per workgroup on the matrix cores.  A (MT rows
-// x 16 k) and x (16 k x TBM batch columns) are staged in padded LDS tiles;
-// the 4 waves form a 2 x 2 grid, each computing (MT/2) x (TBM/2) as 16x16
-// complex tiles (four real MFMAs each per 4-deep k step).
-constexpr int MTK = 16;
+// Batched: MT x TBM output tile per workgroup on the matrix cores.  The k
+// range (all segments) is walked in KC-deep chunks; chunk c+1 is fetched into
+// registers while chunk c is multiplied out of one of two LDS buffers, so one
+// barrier per chunk separates the loads from the products.  The 4 waves form
+// a 2 x 2 grid, each computing (MT/2) x (TBM/2) as 16x16 complex tiles (four
+// real MFMAs per 4-deep k step).
+template <typename T, int MT, int TBM, int KC>
+struct GemmStage {
+    static constexpr int NA = MT * KC / GV_THREADS;    // A entries per thread
+    static constexpr int NX = KC * TBM / GV_THREADS;   // x entries per thread
+    C2<T> a[NA], x[NX];
 
-template <typename T, int MT, int TBM>
+    __device__ __forceinline__ void load(const GemmTask<T>& t, int sg, int kc, int i0, int b0,
+                                         int B, int tid) {
+        const C2<T>* xp = t.seg_ptr[sg];
+        const int k0 = t.seg_k0[sg], len = t.seg_len[sg];
+#pragma unroll
+        for (int e = 0; e < NA; ++e) {
+            const int idx = tid + e * GV_THREADS, r = idx / KC, q = idx % KC, i = i0 + r;
+            a[e] = (i < t.m && kc + q < len) ? t.A[(long long)i * t.lda + k0 + kc + q]
+                                             : mk<T>((T)0, (T)0);
+        }
+#pragma unroll
+        for (int e = 0; e < NX; ++e) {
+            const int idx = tid + e * GV_THREADS, q = idx / TBM, c = idx % TBM;
+            x[e] = (kc + q < len && b0 + c < B) ? xp[(long long)(kc + q) * t.ldx + b0 + c]
+                                                : mk<T>((T)0, (T)0);
+        }
+    }
+    __device__ __forceinline__ void stash(C2<T> (*As)[KC + 1], C2<T> (*Xs)[TBM + 1], int tid) const {
+#pragma unroll
+        for (int e = 0; e < NA; ++e) {
+            const int idx = tid + e * GV_THREADS;
+            As[idx / KC][idx % KC] = a[e];
+        }
+#pragma unroll
+        for (int e = 0; e < NX; ++e) {
+            const int idx = tid + e * GV_THREADS;
+            Xs[idx / TBM][idx % TBM] = x[e];
+        }
+    }
+};
+
+// next non-empty chunk after (sg, kc); sg == nseg when none is left
+template <typename T, int KC>
+__device__ __forceinline__ void next_chunk(const GemmTask<T>& t, int& sg, int& kc) {
+    kc += KC;
+    while (sg < t.nseg && (!t.seg_ptr[sg] || kc >= t.seg_len[sg])) { ++sg; kc = 0; }
+}
+
+template <typename T, int MT, int TBM, int KC>
 __global__ void __launch_bounds__(GV_THREADS)
 k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B) {
     constexpr int RTW = MT / 32;                 // row tiles per wave
@@ -142,8 +186,8 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B) {
     if (t.ncol > 0) B = t.ncol;
     const int b0 = blockIdx.y * TBM;
     if (b0 >= B) return;
-    __shared__ C2<T> As[MT][MTK + 1];
-    __shared__ C2<T> Xs[MTK][TBM + 1];
+    __shared__ C2<T> As[2][MT][KC + 1];
+    __shared__ C2<T> Xs[2][KC][TBM + 1];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int lc = lane & 15, lk = lane >> 4;
     const int wr = (w >> 1) * (MT / 2), wc = (w & 1) * (TBM / 2);
@@ -152,42 +196,38 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B) {
     for (int a = 0; a < RTW; ++a)
 #pragma unroll
         for (int c = 0; c < CTW; ++c) { cr[a][c] = mf_zero<T>(); ci[a][c] = mf_zero<T>(); }
-    for (int sg = 0; sg < t.nseg; ++sg) {
-        const C2<T>* xp = t.seg_ptr[sg];
-        if (!xp) continue;
-        const int k0 = t.seg_k0[sg], len = t.seg_len[sg];
-        for (int kc = 0; kc < len; kc += MTK) {
-            __syncthreads();
-            for (int idx = tid; idx < MT * MTK / 4; idx += GV_THREADS) {   // A: 4 k per thread
-                const int r = idx >> 2, q0 = (idx & 3) * 4;
-                const int i = i0 + r;
-                const C2<T>* src = t.A + (long long)i * t.lda + k0 + kc + q0;
+    int sg = 0, kc = -KC;
+    next_chunk<T, KC>(t, sg, kc);
+    if (sg < t.nseg) {
+        GemmStage<T, MT, TBM, KC> stage;
+        stage.load(t, sg, kc, i0, b0, B, tid);
+        stage.stash(As[0], Xs[0], tid);
+        __syncthreads();
+        int buf = 0;
+        while (true) {
+            int ns = sg, nk = kc;
+            next_chunk<T, KC>(t, ns, nk);
+            const bool more = ns < t.nseg;
+            if (more) stage.load(t, ns, nk, i0, b0, B, tid);
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    As[r][q0 + q] = (i < t.m && kc + q0 + q < len) ? src[q] : mk<T>((T)0, (T)0);
-            }
-            for (int idx = tid; idx < MTK * TBM / 4; idx += GV_THREADS) {  // x: 4 columns per thread
-                const int q = idx / (TBM / 4), c0 = (idx % (TBM / 4)) * 4;
-                const C2<T>* src = xp + (long long)(kc + q) * t.ldx + b0 + c0;
-                const bool ok = kc + q < len;
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    Xs[q][c0 + c] = (ok && b0 + c0 + c < B) ? src[c] : mk<T>((T)0, (T)0);
-            }
-            __syncthreads();
-#pragma unroll
-            for (int s4 = 0; s4 < MTK / 4; ++s4) {
+            for (int s4 = 0; s4 < KC / 4; ++s4) {
                 C2<T> av[RTW], bv[CTW];
 #pragma unroll
-                for (int a = 0; a < RTW; ++a) av[a] = As[wr + a * 16 + lc][s4 * 4 + lk];
+                for (int a = 0; a < RTW; ++a) av[a] = As[buf][wr + a * 16 + lc][s4 * 4 + lk];
 #pragma unroll
-                for (int c = 0; c < CTW; ++c) bv[c] = Xs[s4 * 4 + lk][wc + c * 16 + lc];
+                for (int c = 0; c < CTW; ++c) bv[c] = Xs[buf][s4 * 4 + lk][wc + c * 16 + lc];
 #pragma unroll
                 for (int a = 0; a < RTW; ++a)
 #pragma unroll
                     for (int c = 0; c < CTW; ++c)
                         cmma<T>(av[a].x, av[a].y, bv[c].x, bv[c].y, cr[a][c], ci[a][c]);
             }
+            if (!more) break;
+            stage.stash(As[buf ^ 1], Xs[buf ^ 1], tid);   // last read two barriers ago
+            __syncthreads();
+            buf ^= 1;
+            sg = ns;
+            kc = nk;
         }
     }
 #pragma unroll
@@ -225,22 +265,17 @@ void launch_gemm(const GemmTask<T>* tasks_dev, int ntasks, int max_m, int B, hip
         dim3 grid((max_m + GV_ROWS - 1) / GV_ROWS, 1, ntasks);
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemv<T>), grid, dim3(GV_THREADS), 0, st, tasks_dev);
     } else if (B >= 16) {
-        // largest tile that still gives every CU work (>= 512 workgroups)
-        auto count = [&](int mt, int tb) {
-            return (long long)ntasks * ((max_m + mt - 1) / mt) * ((B + tb - 1) / tb);
-        };
-        if (B >= 64 && count(64, 64) >= 512) {
+        // big launches: 64 x 64 tiles; otherwise 32 x 32 tiles with deeper
+        // chunks, which keep more workgroups busy and fewer chunks in flight
+        const long long big = (long long)ntasks * ((max_m + 63) / 64) * ((B + 63) / 64);
+        if (B >= 64 && big >= 512) {
             dim3 grid((max_m + 63) / 64, (B + 63) / 64, ntasks);
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 64, 64>), grid, dim3(GV_THREADS), 0,
-                               st, tasks_dev, B);
-        } else if (count(64, 32) >= 512) {
-            dim3 grid((max_m + 63) / 64, (B + 31) / 32, ntasks);
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 64, 32>), grid, dim3(GV_THREADS), 0,
-                               st, tasks_dev, B);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 64, 64, 16>), grid, dim3(GV_THREADS),
+                               0, st, tasks_dev, B);
         } else {
             dim3 grid((max_m + 31) / 32, (B + 31) / 32, ntasks);
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32>), grid, dim3(GV_THREADS), 0,
-                               st, tasks_dev, B);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 32>), grid, dim3(GV_THREADS),
+                               0, st, tasks_dev, B);
         }
     } else {
         dim3 grid((max_m + TM - 1) / TM, (B + TB - 1) / TB, ntasks);
