@@ -95,6 +95,7 @@ struct Ops {                       // factors and interface operators in precisi
     C2<T>* CS = nullptr;
     C2<T>* Sinv = nullptr;
     C2<T>* Lfac = nullptr;
+    C2<T>* Qc = nullptr;           // composed output operators [Q_x S^{-1} | Q_u] per side and cell
 };
 
 enum LaunchKind { L_GEMM = 0, L_AXPBY = 1, L_COPY = 2 };
@@ -180,6 +181,7 @@ struct hz_ctx {
     hipStream_t st = nullptr;
     hipStream_t own_st = nullptr;  // stream created by the context (blocking, default priority)
     bool use_graphs = true;
+    bool compose = true;           // output operators composed with the inner SIE inverse
     Arena arena;
     std::vector<LayerDesc> layers;
     std::vector<CellDesc> cells;
@@ -193,6 +195,9 @@ struct hz_ctx {
     int* layer_active = nullptr;   // [L]
     long long coef_elems = 0, X_elems = 0, Q_elems = 0, CS_elems = 0, Sinv_elems = 0, Lfac_elems = 0;
     long long inner_per_layer = 0; // J * 2 * HLmax
+    long long Qc_elems = 0;
+    std::vector<long long> qc_off; // [(layer * 2 + side) * Lc + cell] -> offset in Qc, -1 if none
+    std::vector<int> qc_ld;        // row length of that block (J 2 HL + nslot s)
     Ops<double> o64;
     Ops<float> o32;
     Work<double> w64;
@@ -427,6 +432,12 @@ void plan_jobs(hz_ctx* c, Plan<T>& pl, const std::vector<LayerJob<T>>& jobs, int
     const int W = d.W;
     const int J = d.Lc - 1;
     Ops<T>& o = ops<T>(c);
+    // with the composed output operators, only jobs that need the inner
+    // traces themselves (no phase 3) run the block LU substitutions
+    const bool comp = c->compose && J > 0 && o.Qc != nullptr;
+    std::vector<LayerJob<T>> p2;
+    for (const auto& jb : jobs)
+        if (!(comp && jb.phase3)) p2.push_back(jb);
     // ---- phase 1: inner right-hand sides from the interface-row sources
     if (J > 0) {
         long long first = pl.tasks.size();
@@ -475,78 +486,80 @@ void plan_jobs(hz_ctx* c, Plan<T>& pl, const std::vector<LayerJob<T>>& jobs, int
         }
         add_launch(pl, first, maxm, B);
         // ---- phase 2: block LU substitutions across the cells (inner sweeps)
-        for (int j = 1; j < J; ++j) {                       // forward
-            long long f2 = pl.tasks.size();
-            int mm = 0;
-            for (const auto& jb : jobs) {
-                const LayerDesc& ld = c->layers[jb.layer];
-                const int HL = ld.HL;
-                const long long blk = 2LL * HL * B;
-                GemmTask<T> t = blank_task<T>();
-                t.A = o.Lfac + ld.off_Lfac + (long long)(j - 1) * HL * 2 * HL;
-                t.lda = 2 * HL;
-                t.m = HL;
-                t.k = 2 * HL;
-                t.ldx = B; t.ldo = B;
-                t.nseg = 1;
-                t.seg_k0[0] = 0; t.seg_len[0] = 2 * HL; t.seg_ptr[0] = jb.iy + (j - 1) * blk;
-                t.noseg = 1;
-                t.oseg_i0[0] = 0; t.oseg_len[0] = HL; t.oseg_ptr[0] = jb.iy + j * blk;
-                t.oseg_add0[0] = jb.iy + j * blk;
-                t.alpha = (T)-1;
-                mm = std::max(mm, t.m);
-                pl.tasks.push_back(t);
-            }
-            add_launch(pl, f2, mm, B);
-        }
-        for (int j = J - 1; j >= 0; --j) {                  // backward
-            if (j < J - 1) {
+        if (!p2.empty()) {
+            for (int j = 1; j < J; ++j) {                       // forward
                 long long f2 = pl.tasks.size();
                 int mm = 0;
-                for (const auto& jb : jobs) {
+                for (const auto& jb : p2) {
                     const LayerDesc& ld = c->layers[jb.layer];
                     const int HL = ld.HL;
                     const long long blk = 2LL * HL * B;
-                    const CellDesc& cn = c->cells[ld.cell_begin + j + 1];   // cell right of iface j
                     GemmTask<T> t = blank_task<T>();
-                    // y_j.b - C_j x_{j+1},  C_j = -(left-column samples of cell j+1, right probes)
-                    t.A = o.CS + cn.off_CS + 2LL * HL;      // left rows, right probes
-                    t.lda = cn.R;
+                    t.A = o.Lfac + ld.off_Lfac + (long long)(j - 1) * HL * 2 * HL;
+                    t.lda = 2 * HL;
                     t.m = HL;
                     t.k = 2 * HL;
                     t.ldx = B; t.ldo = B;
                     t.nseg = 1;
-                    t.seg_k0[0] = 0; t.seg_len[0] = 2 * HL; t.seg_ptr[0] = jb.ix + (j + 1) * blk;
+                    t.seg_k0[0] = 0; t.seg_len[0] = 2 * HL; t.seg_ptr[0] = jb.iy + (j - 1) * blk;
                     t.noseg = 1;
-                    t.oseg_i0[0] = 0; t.oseg_len[0] = HL;
-                    t.oseg_ptr[0] = jb.iy + j * blk + (long long)HL * B;
-                    t.oseg_add0[0] = jb.iy + j * blk + (long long)HL * B;
-                    t.alpha = (T)1;
+                    t.oseg_i0[0] = 0; t.oseg_len[0] = HL; t.oseg_ptr[0] = jb.iy + j * blk;
+                    t.oseg_add0[0] = jb.iy + j * blk;
+                    t.alpha = (T)-1;
                     mm = std::max(mm, t.m);
                     pl.tasks.push_back(t);
                 }
                 add_launch(pl, f2, mm, B);
             }
-            long long f2 = pl.tasks.size();
-            int mm = 0;
-            for (const auto& jb : jobs) {
-                const LayerDesc& ld = c->layers[jb.layer];
-                const int HL = ld.HL;
-                const long long blk = 2LL * HL * B;
-                GemmTask<T> t = blank_task<T>();
-                t.A = o.Sinv + ld.off_Sinv + (long long)j * 4 * HL * HL;
-                t.lda = 2 * HL;
-                t.m = 2 * HL;
-                t.k = 2 * HL;
-                t.ldx = B; t.ldo = B;
-                t.nseg = 1;
-                t.seg_k0[0] = 0; t.seg_len[0] = 2 * HL; t.seg_ptr[0] = jb.iy + j * blk;
-                t.noseg = 1;
-                t.oseg_i0[0] = 0; t.oseg_len[0] = 2 * HL; t.oseg_ptr[0] = jb.ix + j * blk;
-                mm = std::max(mm, t.m);
-                pl.tasks.push_back(t);
+            for (int j = J - 1; j >= 0; --j) {                  // backward
+                if (j < J - 1) {
+                    long long f2 = pl.tasks.size();
+                    int mm = 0;
+                    for (const auto& jb : p2) {
+                        const LayerDesc& ld = c->layers[jb.layer];
+                        const int HL = ld.HL;
+                        const long long blk = 2LL * HL * B;
+                        const CellDesc& cn = c->cells[ld.cell_begin + j + 1];   // cell right of iface j
+                        GemmTask<T> t = blank_task<T>();
+                        // y_j.b - C_j x_{j+1},  C_j = -(left-column samples of cell j+1, right probes)
+                        t.A = o.CS + cn.off_CS + 2LL * HL;      // left rows, right probes
+                        t.lda = cn.R;
+                        t.m = HL;
+                        t.k = 2 * HL;
+                        t.ldx = B; t.ldo = B;
+                        t.nseg = 1;
+                        t.seg_k0[0] = 0; t.seg_len[0] = 2 * HL; t.seg_ptr[0] = jb.ix + (j + 1) * blk;
+                        t.noseg = 1;
+                        t.oseg_i0[0] = 0; t.oseg_len[0] = HL;
+                        t.oseg_ptr[0] = jb.iy + j * blk + (long long)HL * B;
+                        t.oseg_add0[0] = jb.iy + j * blk + (long long)HL * B;
+                        t.alpha = (T)1;
+                        mm = std::max(mm, t.m);
+                        pl.tasks.push_back(t);
+                    }
+                    add_launch(pl, f2, mm, B);
+                }
+                long long f2 = pl.tasks.size();
+                int mm = 0;
+                for (const auto& jb : p2) {
+                    const LayerDesc& ld = c->layers[jb.layer];
+                    const int HL = ld.HL;
+                    const long long blk = 2LL * HL * B;
+                    GemmTask<T> t = blank_task<T>();
+                    t.A = o.Sinv + ld.off_Sinv + (long long)j * 4 * HL * HL;
+                    t.lda = 2 * HL;
+                    t.m = 2 * HL;
+                    t.k = 2 * HL;
+                    t.ldx = B; t.ldo = B;
+                    t.nseg = 1;
+                    t.seg_k0[0] = 0; t.seg_len[0] = 2 * HL; t.seg_ptr[0] = jb.iy + j * blk;
+                    t.noseg = 1;
+                    t.oseg_i0[0] = 0; t.oseg_len[0] = 2 * HL; t.oseg_ptr[0] = jb.ix + j * blk;
+                    mm = std::max(mm, t.m);
+                    pl.tasks.push_back(t);
+                }
+                add_launch(pl, f2, mm, B);
             }
-            add_launch(pl, f2, mm, B);
         }
     }
     // ---- phase 3: samples on the requested interface rows
@@ -567,23 +580,36 @@ void plan_jobs(hz_ctx* c, Plan<T>& pl, const std::vector<LayerJob<T>>& jobs, int
             t.ldx = B; t.ldo = B;
             t.nseg = 0;
             const long long HLB = (long long)cd.HL * B;
-            if (cd.has_left) {
-                t.seg_k0[t.nseg] = 0;
-                t.seg_len[t.nseg] = 2 * cd.HL;
-                t.seg_ptr[t.nseg] = jb.ix + (long long)(k - 1) * 2 * HLB;
-                t.nseg++;
-            }
-            if (cd.has_right) {
-                t.seg_k0[t.nseg] = cd.has_left ? 2 * cd.HL : 0;
-                t.seg_len[t.nseg] = 2 * cd.HL;
-                t.seg_ptr[t.nseg] = jb.ix + (long long)k * 2 * HLB;
-                t.nseg++;
+            int x0 = cd.ncol;                    // first column of the interface-row sources
+            if (comp) {                          // [Q_x S^{-1} | Q_u] applied to [iy; pair]
+                const long long q = ((long long)jb.layer * 2 + jb.side) * d.Lc + k;
+                t.A = o.Qc + c->qc_off[q];
+                t.lda = c->qc_ld[q];
+                t.k = c->qc_ld[q];
+                t.seg_k0[0] = 0;
+                t.seg_len[0] = J * 2 * cd.HL;
+                t.seg_ptr[0] = jb.iy;
+                t.nseg = 1;
+                x0 = J * 2 * cd.HL;
+            } else {
+                if (cd.has_left) {
+                    t.seg_k0[t.nseg] = 0;
+                    t.seg_len[t.nseg] = 2 * cd.HL;
+                    t.seg_ptr[t.nseg] = jb.ix + (long long)(k - 1) * 2 * HLB;
+                    t.nseg++;
+                }
+                if (cd.has_right) {
+                    t.seg_k0[t.nseg] = cd.has_left ? 2 * cd.HL : 0;
+                    t.seg_len[t.nseg] = 2 * cd.HL;
+                    t.seg_ptr[t.nseg] = jb.ix + (long long)k * 2 * HLB;
+                    t.nseg++;
+                }
             }
             if (jb.use_x) {
                 for (int si = 0; si < ld.nslot; ++si) {
                     const int lid = ld.slot_id[si];
                     const C2<T>* pr = lid < 2 ? jb.top : jb.bot;
-                    t.seg_k0[t.nseg] = cd.ncol + si * cd.s;
+                    t.seg_k0[t.nseg] = x0 + si * cd.s;
                     t.seg_len[t.nseg] = cd.s;
                     t.seg_ptr[t.nseg] = pair_row<T>(pr, lid % 2, cd.col0 + cd.own_c0, W, B);
                     t.nseg++;
@@ -980,6 +1006,122 @@ __global__ void k_inner_diag(const LayerDesc* layers, const CellDesc* cells, con
     }
 }
 
+__global__ void k_eye(double2* a, int n) {
+    const long long nn = (long long)n * n;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nn;
+         i += (long long)gridDim.x * blockDim.x)
+        a[i] = make_double2(i / n == i % n ? 1.0 : 0.0, 0.0);
+}
+
+template <typename T>
+void run_jobs(hz_ctx* c, const std::vector<LayerJob<T>>& jobs, int B);
+
+// Composed output operators (offline): for every layer side and cell,
+//   Qc = [ Q_x S^{-1} | Q_u ],
+// Q_x the row samples of the cell's Green's function driven by the inner
+// traces of its two interfaces, S the inner SIE matrix of the layer and Q_u
+// the row samples driven by the interface-row sources.  Applying Qc to
+// [inner rhs; pair] gives the same samples as solving the inner SIE and then
+// applying [Q_x | Q_u]; the inner solve is taken out of the sequential path.
+// S^{-1} itself is the inner block LU applied to the identity.
+void build_composed(hz_ctx* c) {
+    const Dims& d = c->d;
+    const int J = d.Lc - 1;
+    Ops<double>& o = c->o64;
+    c->qc_off.assign((size_t)d.L * 2 * d.Lc, -1);
+    c->qc_ld.assign((size_t)d.L * 2 * d.Lc, 0);
+    long long tot = 0;
+    for (int l = 0; l < d.L; ++l) {
+        const LayerDesc& ld = c->layers[l];
+        const int NI = J * 2 * ld.HL;
+        for (int side = 0; side < 2; ++side) {
+            if (ld.slot_of[side == 0 ? 0 : 2] < 0) continue;
+            for (int k = 0; k < d.Lc; ++k) {
+                const CellDesc& cd = c->cells[ld.cell_begin + k];
+                const size_t q = ((size_t)l * 2 + side) * d.Lc + k;
+                c->qc_off[q] = tot;
+                c->qc_ld[q] = NI + ld.nslot * cd.s;
+                tot += 2LL * cd.s * c->qc_ld[q];
+            }
+        }
+    }
+    c->Qc_elems = tot;
+    if (!o.Qc) o.Qc = alloc_c<double>(c, std::max<long long>(tot, 1));
+    const int NImax = J * 2 * d.HLmax;
+    const long long nn = (long long)NImax * NImax;
+    double2* E = alloc_c<double>(c, nn);
+    double2* IY = alloc_c<double>(c, nn);
+    double2* IX = alloc_c<double>(c, nn);
+    GemmTask<double>* tdev = (GemmTask<double>*)c->arena.alloc(sizeof(GemmTask<double>) * 2 * d.Lc);
+    for (int l = 0; l < d.L; ++l) {
+        const LayerDesc& ld = c->layers[l];
+        const int NI = J * 2 * ld.HL;
+        hipLaunchKernelGGL(k_eye, dim3(1024), dim3(256), 0, c->st, E, NI);
+        HIPCHK(hipGetLastError());
+        LayerJob<double> jb;
+        jb.layer = l;
+        jb.inner_add = E;                 // phase 1 without sources: iy = I
+        jb.iy = IY;
+        jb.ix = IX;                       // -> S^{-1}, [NI][NI]
+        jb.phase3 = false;
+        run_jobs<double>(c, {jb}, NI);
+        std::vector<GemmTask<double>> tasks;
+        int maxm = 0;
+        for (int side = 0; side < 2; ++side) {
+            const int so_a = ld.slot_of[side == 0 ? 0 : 2];
+            if (so_a < 0) continue;
+            for (int k = 0; k < d.Lc; ++k) {
+                const CellDesc& cd = c->cells[ld.cell_begin + k];
+                const size_t q = ((size_t)l * 2 + side) * d.Lc + k;
+                const int NC = c->qc_ld[q];
+                double2* dst = o.Qc + c->qc_off[q];
+                const double2* src = o.Q + cd.off_Q + (long long)so_a * cd.s * cd.R;
+                GemmTask<double> t = blank_task<double>();
+                t.A = src;
+                t.lda = cd.R;
+                t.m = 2 * cd.s;
+                t.k = cd.ncol;
+                t.ldx = NI;
+                t.ldo = NC;
+                t.nseg = 0;
+                if (cd.has_left) {
+                    t.seg_k0[t.nseg] = 0;
+                    t.seg_len[t.nseg] = 2 * ld.HL;
+                    t.seg_ptr[t.nseg] = IX + (long long)(k - 1) * 2 * ld.HL * NI;
+                    t.nseg++;
+                }
+                if (cd.has_right) {
+                    t.seg_k0[t.nseg] = cd.has_left ? 2 * ld.HL : 0;
+                    t.seg_len[t.nseg] = 2 * ld.HL;
+                    t.seg_ptr[t.nseg] = IX + (long long)k * 2 * ld.HL * NI;
+                    t.nseg++;
+                }
+                t.noseg = 1;
+                t.oseg_i0[0] = 0;
+                t.oseg_len[0] = 2 * cd.s;
+                t.oseg_ptr[0] = dst;
+                t.alpha = 1.0;
+                tasks.push_back(t);
+                maxm = std::max(maxm, t.m);
+                // Q_u: the interface-row-source columns, copied
+                HIPCHK(hipMemcpy2DAsync(dst + NI, sizeof(double2) * NC, src + cd.ncol,
+                                        sizeof(double2) * cd.R, sizeof(double2) * ld.nslot * cd.s,
+                                        2 * cd.s, hipMemcpyDeviceToDevice, c->st));
+            }
+        }
+        if (!tasks.empty()) {
+            upload(c, tdev, tasks.data(), sizeof(GemmTask<double>) * tasks.size());
+            launch_gemm<double>(tdev, (int)tasks.size(), maxm, NI, c->st);
+            HIPCHK(hipGetLastError());
+        }
+        sync(c);
+    }
+    c->arena.release(E, sizeof(double2) * nn);
+    c->arena.release(IY, sizeof(double2) * nn);
+    c->arena.release(IX, sizeof(double2) * nn);
+    c->arena.release(tdev, sizeof(GemmTask<double>) * 2 * d.Lc);
+}
+
 template <typename T>
 __global__ void k_cast_pool(C2<T>* y, const double2* x, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
@@ -1135,7 +1277,9 @@ void factor_impl(hz_ctx* c) {
         c->arena.release(ns, sizeof(int) * L);
         c->arena.release(tdev, sizeof(GemmTask<double>) * 2 * L);
     }
-    // 4. mixed precision: complex64 copies of every operator
+    // 4. composed output operators
+    if (J > 0 && c->compose) build_composed(c);
+    // 5. mixed precision: complex64 copies of every operator
     if (c->prm.precision != HZ_FP64) {
         Ops<float>& f = c->o32;
         auto cast = [&](float2*& dst, const double2* src, long long n) {
@@ -1150,6 +1294,7 @@ void factor_impl(hz_ctx* c) {
         cast(f.CS, o.CS, c->CS_elems);
         cast(f.Sinv, o.Sinv, c->Sinv_elems);
         cast(f.Lfac, o.Lfac, c->Lfac_elems);
+        if (o.Qc) cast(f.Qc, o.Qc, c->Qc_elems);
         HIPCHK(hipGetLastError());
         sync(c);
     }
@@ -1159,6 +1304,7 @@ void factor_impl(hz_ctx* c) {
         c->arena.release(o.CS, sizeof(double2) * std::max<long long>(c->CS_elems, 1));
         c->arena.release(o.Sinv, sizeof(double2) * std::max<long long>(c->Sinv_elems, 1));
         c->arena.release(o.Lfac, sizeof(double2) * std::max<long long>(c->Lfac_elems, 1));
+        if (o.Qc) c->arena.release(o.Qc, sizeof(double2) * std::max<long long>(c->Qc_elems, 1));
         o = Ops<double>();
     }
 }
@@ -1703,6 +1849,7 @@ hz_status hz_setup(const double* model_dev, const hz_params* prm, hz_ctx** out) 
     c = new hz_ctx();
     c->prm = *prm;
     if (const char* g = std::getenv("HZ_GRAPHS")) c->use_graphs = std::atoi(g) != 0;
+    if (const char* g = std::getenv("HZ_COMPOSE")) c->compose = std::atoi(g) != 0;
     if (c->prm.pml_beta <= 0.0) c->prm.pml_beta = 2.0;
     if (c->prm.max_batch <= 0) c->prm.max_batch = 1;
     Dims& d = c->d;

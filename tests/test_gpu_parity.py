@@ -123,6 +123,35 @@ def test_full_solve_fp64(setup):
         assert err < 1e-9
 
 
+def test_uncomposed_inner_solve(monkeypatch):
+    """The same operators with the inner SIE solved by block LU substitutions
+    at every application (HZ_COMPOSE=0) instead of through the composed
+    output operators: both match the oracle."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c, omega = media.small_problem(N, P, L, LC, seed=5)
+    prob = Problem(c, omega, P)
+    oracle = LayeredSolver(prob, L)
+    K, W = L - 1, prob.W
+    x = _rand_pol(K, W, 2, 3)
+    f = media.point_sources(N, (24, 7), 12)
+    lu = spla.splu(prob.H.tocsc())
+    for flag in ("0", "1"):
+        monkeypatch.setenv("HZ_COMPOSE", flag)
+        _log(f"[compose={flag}] apply_sie / apply_precond / solve")
+        s = hz.Solver(torch.from_numpy(c), omega, P, L, LC, max_batch=2)
+        y = s.apply_sie(torch.from_numpy(x).cuda()).cpu().numpy()
+        z = s.apply_precond(torch.from_numpy(x).cuda()).cpu().numpy()
+        u = s.solve(torch.from_numpy(f), tol=1e-12).cpu().numpy()
+        s.close()
+        for bb in range(2):
+            xs = oracle.unpack(x[:, bb])
+            assert _rel(y[:, bb], oracle.pack(*oracle.apply_M(*xs))) < 1e-11
+            assert _rel(z[:, bb], oracle.pack(*oracle.precond_gs(*xs))) < 1e-11
+            ref = prob.restrict(lu.solve(prob.extend(f[bb]).ravel()).reshape(W, W))
+            assert _rel(u[bb], ref) < 1e-9
+
+
 def test_single_layer_and_cell_counts():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
