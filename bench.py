@@ -21,6 +21,7 @@ is the oracle's global sparse direct solve on the same system.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -30,7 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "DOF-solves/sec at rel. err 1e-8: chosen form vs plain FP64, one MI355X"
-PEAK = {"c128": 78.6e12, "c64": 157.3e12}          # dense FP64 / FP32 vector (= MFMA) peak
+PEAK = {"c128": 78.6e12, "c64": 157.3e12}          # dense FP64 / FP32 MFMA peak
 HBM_PEAK = 8.0e12
 
 
@@ -38,7 +39,19 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def timed_solves(solver, f, tol, steps, warmup, max_iter, profile=False):
+_ROCTX = None
+
+
+def roctx_region(on):
+    """Resume / pause an external profiler started with --selected-regions
+    (ROCTx profiler control), so that it records exactly one timed region."""
+    global _ROCTX
+    if _ROCTX is None:
+        _ROCTX = ctypes.CDLL("librocprofiler-sdk-roctx.so")
+    (_ROCTX.roctxProfilerResume if on else _ROCTX.roctxProfilerPause)(ctypes.c_uint64(0))
+
+
+def timed_solves(solver, f, tol, steps, warmup, max_iter, profile=False, region=False):
     import torch
 
     for _ in range(warmup):
@@ -46,15 +59,52 @@ def timed_solves(solver, f, tol, steps, warmup, max_iter, profile=False):
     torch.cuda.synchronize()
     if profile:
         solver.profile(True)
+    if region:
+        roctx_region(True)
     t0 = time.perf_counter()
     for _ in range(steps):
         u = solver.solve(f, tol=tol, max_iter=max_iter)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
+    if region:
+        roctx_region(False)
     prof = solver.profile_read() if profile else None
     if profile:
         solver.profile(False)
     return u, dt, prof
+
+
+def roofline(k, B):
+    """Roofline record of one kernel family from the solver's event profile:
+    matrix-core kernels against the dense MFMA peak of their precision,
+    single-column kernels (matrix-vector products) against HBM bandwidth."""
+    prec = "c64" if k["name"].endswith("_c64") else "c128"
+    avg_ms = k["ms"] / k["launches"]
+    rec = {"kernel": k["name"], "launches": k["launches"], "avg_launch_ms": avg_ms,
+           "flops_per_launch": k["flops"] / k["launches"],
+           "bytes_per_launch": k["bytes"] / k["launches"], "traffic": None}
+    if B > 1:
+        achieved = k["flops"] / (k["ms"] * 1e-3)
+        rec.update({"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12,
+                    "unit": "TFLOP/s", "frac": achieved / PEAK[prec]})
+    else:
+        achieved = k["bytes"] / (k["ms"] * 1e-3)
+        rec.update({"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
+                    "unit": "GB/s", "frac": achieved / HBM_PEAK})
+    return rec
+
+
+def copy_calibration(nbytes):
+    """One plain device-to-device copy of nbytes (reference dispatch for the
+    HBM traffic counters: FETCH_SIZE / WRITE_SIZE of a known-size copy)."""
+    import torch
+
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes}), flush=True)
 
 
 def cpu_baseline(c, omega, n_pml, src_x, src_z, nsample=8):
@@ -97,7 +147,15 @@ def main():
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="fp64,mixed")
+    ap.add_argument("--roctx-form", default="",
+                    help="mark this form's timed steps as the profiled region "
+                         "(fp64_single, fp64_batched or mixed_batched)")
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="only run one plain copy of this many bytes (counter reference)")
     args = ap.parse_args()
+    if args.copy_calib:
+        copy_calibration(args.copy_calib)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU layout is described in DESIGN.md, not run.", file=sys.stderr)
@@ -124,7 +182,8 @@ def main():
     t_fac64 = time.perf_counter() - t0
     log(f"[bench] fp64 setup+factor {t_fac64:.2f} s")
     f1 = f_all[B // 2: B // 2 + 1].contiguous()
-    u1, dt1, prof1 = timed_solves(s64, f1, 1e-10, args.steps, args.warmup, max_iter, profile=True)
+    u1, dt1, prof1 = timed_solves(s64, f1, 1e-10, args.steps, args.warmup, max_iter, profile=True,
+                                  region=args.roctx_form == "fp64_single")
     it1 = s64.last_stats[0]["iters"]
     log(f"[bench] fp64 single RHS: {dt1 * 1e3:.1f} ms/solve, {it1} GMRES iterations")
     forms = {"fp64_single": {"dof_solves_per_s": n * n / dt1, "ms_per_solve": dt1 * 1e3,
@@ -135,7 +194,8 @@ def main():
         refs[k] = s64.solve(f_all[k:k + 1].contiguous(), tol=1e-12, max_iter=max_iter)[0]
     results = {}
     if "fp64" in args.forms:
-        u, dt, prof = timed_solves(s64, f_all, 1e-10, args.steps, args.warmup, max_iter, True)
+        u, dt, prof = timed_solves(s64, f_all, 1e-10, args.steps, args.warmup, max_iter, True,
+                                   region=args.roctx_form == "fp64_batched")
         err = max(float(torch.linalg.norm(u[k] - refs[k]) / torch.linalg.norm(refs[k]))
                   for k in ref_idx)
         its = max(x["iters"] for x in s64.last_stats)
@@ -150,7 +210,8 @@ def main():
                         precision=hz.HZ_MIXED, max_batch=B)
         torch.cuda.synchronize()
         log(f"[bench] mixed setup+factor {time.perf_counter() - t0:.2f} s")
-        u, dt, prof = timed_solves(smx, f_all, 1e-10, args.steps, args.warmup, max_iter, True)
+        u, dt, prof = timed_solves(smx, f_all, 1e-10, args.steps, args.warmup, max_iter, True,
+                                   region=args.roctx_form == "mixed_batched")
         err = max(float(torch.linalg.norm(u[k] - refs[k]) / torch.linalg.norm(refs[k]))
                   for k in ref_idx)
         its = max(x["iters"] for x in smx.last_stats)
@@ -165,22 +226,11 @@ def main():
     chosen = min(ok, key=lambda k: ok[k][0]) if ok else min(results, key=lambda k: results[k][0])
     dt, prof, err, its, dty = results[chosen]
 
-    # ---- roofline of the dominant kernel family of the chosen form
+    # ---- roofline of the dominant kernel of the chosen form (most time in
+    # the timed steps; every family is one kernel, timed launch by launch
+    # with HIP events on the solver's stream)
     dom = max(prof, key=lambda k: k["ms"])
-    prec = "c64" if dom["name"].endswith("_c64") else "c128"
-    batched = B > 1
-    if batched:
-        achieved = dom["flops"] / (dom["ms"] * 1e-3)
-        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK[prec], "traffic": None,
-                "kernel": dom["name"], "launches": dom["launches"],
-                "avg_launch_ms": dom["ms"] / dom["launches"]}
-    else:
-        achieved = dom["bytes"] / (dom["ms"] * 1e-3)
-        roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None,
-                "kernel": dom["name"]}
-
+    roof = roofline(dom, B)
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle direct solve) ...")

@@ -182,6 +182,7 @@ struct hz_ctx {
     hipStream_t own_st = nullptr;  // stream created by the context (blocking, default priority)
     bool use_graphs = true;
     bool compose = true;           // output operators composed with the inner SIE inverse
+    bool offline = false;          // inside the factorisation stage
     Arena arena;
     std::vector<LayerDesc> layers;
     std::vector<CellDesc> cells;
@@ -648,31 +649,20 @@ void plan_upload(hz_ctx* c, Plan<T>& pl) {
 template <typename T>
 void plan_launches(hz_ctx* c, const Plan<T>& pl, int B);
 
-// Replay a plan: through its captured HIP graph when the context owns a
-// capturable stream and profiling is off, launch by launch otherwise.
+// Replay a plan: through its captured HIP graph when graphs are enabled and
+// profiling is off, launch by launch (one event pair per kernel) otherwise.
 template <typename T>
 void plan_run(hz_ctx* c, Plan<T>& pl, int B) {
-    if (c->use_graphs && c->st && !pl.name.empty()) {
+    if (c->use_graphs && c->st && !pl.name.empty() && !c->prof.on) {
         if (!pl.exec) {
-            const bool prof = c->prof.on;
-            c->prof.on = false;                       // no event records inside the capture
             HIPCHK(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
             plan_launches<T>(c, pl, B);
             hipGraph_t g = nullptr;
             HIPCHK(hipStreamEndCapture(c->st, &g));
-            c->prof.on = prof;
             pl.graph = g;
             HIPCHK(hipGraphInstantiate(&pl.exec, g, nullptr, nullptr, 0));
         }
-        const bool prof = c->prof.on;
-        size_t e0 = prof ? prof_event(c) : 0;
         HIPCHK(hipGraphLaunch(pl.exec, c->st));
-        if (prof) {
-            size_t e1 = prof_event(c);
-            double bytes = 0, flops = 0;
-            for (const auto& r : pl.launches) { bytes += r.bytes; flops += r.flops; }
-            c->prof.pend.push_back({pl.name, e0, e1, bytes, flops});
-        }
         return;
     }
     plan_launches<T>(c, pl, B);
@@ -681,14 +671,14 @@ void plan_run(hz_ctx* c, Plan<T>& pl, int B) {
 template <typename T>
 void plan_launches(hz_ctx* c, const Plan<T>& pl, int B) {
     const bool prof = c->prof.on;
-    const std::string fam = fam_name<T>(B == 1 ? "layer_gemv" : "layer_gemm");
     for (const auto& r : pl.launches) {
         if (r.kind == L_GEMM) {
             size_t e0 = prof ? prof_event(c) : 0;
-            launch_gemm<T>(pl.dev + r.off, r.ntasks, r.max_m, B, c->st);
+            launch_gemm<T>(pl.dev + r.off, r.ntasks, r.max_m, B, c->st, c->offline);
             if (prof) {
                 size_t e1 = prof_event(c);
-                c->prof.pend.push_back({fam, e0, e1, r.bytes, r.flops});
+                const char* k = gemm_kernel_name(gemm_kernel(r.ntasks, r.max_m, B));
+                c->prof.pend.push_back({fam_name<T>(k), e0, e1, r.bytes, r.flops});
             }
         } else if (r.kind == L_AXPBY) {
             launch_axpby<T>(r.y, r.x, r.a, r.b, r.n, c->st);
@@ -950,7 +940,7 @@ void cell_solve_launch(hz_ctx* c, CellSolveArgs<T> a, const std::vector<int>& li
                 // factors read in both sweeps, forward iterates written and
                 // read back, one source and one result per grid node
                 bytes += sizeof(C2<T>) * (2.0 * blk + 4.0 * (double)cd.Wc * cd.HL * Bcols);
-                flops += 16.0 * blk * Bcols;
+                flops += 8.0 * (2.0 * cd.Wc - 1.0) * cd.HL * cd.HL * Bcols;
             }
             const char* fam = a.mode == SOLVE_VOLUME ? "cell_solve_volume"
                               : a.mode == SOLVE_SAMPLE ? "cell_solve_sample" : "cell_solve_other";
@@ -1111,7 +1101,7 @@ void build_composed(hz_ctx* c) {
         }
         if (!tasks.empty()) {
             upload(c, tdev, tasks.data(), sizeof(GemmTask<double>) * tasks.size());
-            launch_gemm<double>(tdev, (int)tasks.size(), maxm, NI, c->st);
+            launch_gemm<double>(tdev, (int)tasks.size(), maxm, NI, c->st, true);
             HIPCHK(hipGetLastError());
         }
         sync(c);
@@ -1130,7 +1120,14 @@ __global__ void k_cast_pool(C2<T>* y, const double2* x, long long n) {
     }
 }
 
+struct OfflineScope {              // marks launches as factorisation-stage launches
+    hz_ctx* c;
+    explicit OfflineScope(hz_ctx* ctx) : c(ctx) { c->offline = true; }
+    ~OfflineScope() { c->offline = false; }
+};
+
 void factor_impl(hz_ctx* c) {
+    OfflineScope scope(c);
     const Dims& d = c->d;
     const int ncells = (int)c->cells.size();
     Ops<double>& o = c->o64;
@@ -1252,11 +1249,11 @@ void factor_impl(hz_ctx* c) {
                     mm = std::max(mm, 2 * HL);
                 }
                 upload(c, tdev, t1.data(), sizeof(GemmTask<double>) * L);
-                launch_gemm<double>(tdev, L, mm, 2 * d.HLmax, c->st);
+                launch_gemm<double>(tdev, L, mm, 2 * d.HLmax, c->st, true);
                 HIPCHK(hipGetLastError());
                 sync(c);
                 upload(c, tdev + L, t2.data(), sizeof(GemmTask<double>) * L);
-                launch_gemm<double>(tdev + L, L, mm, 2 * d.HLmax, c->st);
+                launch_gemm<double>(tdev + L, L, mm, 2 * d.HLmax, c->st, true);
                 HIPCHK(hipGetLastError());
                 sync(c);
             }

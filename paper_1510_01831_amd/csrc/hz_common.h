@@ -204,8 +204,15 @@ void launch_cell_solve(const CellSolveArgs<T>& a, int ncells_launch, int nb_chun
                        hipStream_t st);
 
 // B = number of batch columns; ldx/ldo come from the tasks.
+// offline = launch from the factorisation stage (separate kernel instance)
 template <typename T>
-void launch_gemm(const GemmTask<T>* tasks_dev, int ntasks, int max_m, int B, hipStream_t st);
+void launch_gemm(const GemmTask<T>* tasks_dev, int ntasks, int max_m, int B, hipStream_t st,
+                 bool offline = false);
+
+// the GEMM kernel launch_gemm selects for a shape (for per-kernel profiles)
+enum GemmKernel { GEMM_GEMV = 0, GEMM_TILED = 1, GEMM_MFMA32 = 2, GEMM_MFMA64 = 3 };
+GemmKernel gemm_kernel(int ntasks, int max_m, int B);
+const char* gemm_kernel_name(GemmKernel k);
 
 template <typename T>
 void launch_copy(C2<T>* y, const C2<T>* x, long long n, hipStream_t st);

@@ -174,7 +174,9 @@ __device__ __forceinline__ void next_chunk(const GemmTask<T>& t, int& sg, int& k
     while (sg < t.nseg && (!t.seg_ptr[sg] || kc >= t.seg_len[sg])) { ++sg; kc = 0; }
 }
 
-template <typename T, int MT, int TBM, int KC>
+// OFFLINE selects a separate instantiation (same code) for the factorisation
+// stage, so per-kernel profiles of the solve phase hold only solve launches.
+template <typename T, int MT, int TBM, int KC, bool OFFLINE>
 __global__ void __launch_bounds__(GV_THREADS)
 k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B) {
     constexpr int RTW = MT / 32;                 // row tiles per wave
@@ -258,33 +260,59 @@ void launch_copy(C2<T>* y, const C2<T>* x, long long n, hipStream_t st) {
 template void launch_copy<double>(double2*, const double2*, long long, hipStream_t);
 template void launch_copy<float>(float2*, const float2*, long long, hipStream_t);
 
-template <typename T>
-void launch_gemm(const GemmTask<T>* tasks_dev, int ntasks, int max_m, int B, hipStream_t st) {
-    if (ntasks <= 0 || max_m <= 0) return;
-    if (B == 1) {
-        dim3 grid((max_m + GV_ROWS - 1) / GV_ROWS, 1, ntasks);
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemv<T>), grid, dim3(GV_THREADS), 0, st, tasks_dev);
-    } else if (B >= 16) {
-        // big launches: 64 x 64 tiles; otherwise 32 x 32 tiles with deeper
-        // chunks, which keep more workgroups busy and fewer chunks in flight
-        const long long big = (long long)ntasks * ((max_m + 63) / 64) * ((B + 63) / 64);
-        if (B >= 64 && big >= 512) {
-            dim3 grid((max_m + 63) / 64, (B + 63) / 64, ntasks);
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 64, 64, 16>), grid, dim3(GV_THREADS),
-                               0, st, tasks_dev, B);
-        } else {
-            dim3 grid((max_m + 31) / 32, (B + 31) / 32, ntasks);
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 32>), grid, dim3(GV_THREADS),
-                               0, st, tasks_dev, B);
-        }
-    } else {
-        dim3 grid((max_m + TM - 1) / TM, (B + TB - 1) / TB, ntasks);
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_tiled<T>), grid, dim3(GV_THREADS), 0, st,
-                           tasks_dev, B);
+// which kernel launch_gemm runs for a launch of this shape
+GemmKernel gemm_kernel(int ntasks, int max_m, int B) {
+    if (B == 1) return GEMM_GEMV;
+    if (B < 16) return GEMM_TILED;
+    const long long big = (long long)ntasks * ((max_m + 63) / 64) * ((B + 63) / 64);
+    return (B >= 64 && big >= 512) ? GEMM_MFMA64 : GEMM_MFMA32;
+}
+
+const char* gemm_kernel_name(GemmKernel k) {
+    switch (k) {
+    case GEMM_GEMV: return "gemv";
+    case GEMM_TILED: return "gemm_tiled";
+    case GEMM_MFMA64: return "gemm_mfma64";
+    default: return "gemm_mfma32";
     }
 }
 
-template void launch_gemm<double>(const GemmTask<double>*, int, int, int, hipStream_t);
-template void launch_gemm<float>(const GemmTask<float>*, int, int, int, hipStream_t);
+template <typename T, bool OFFLINE>
+void launch_gemm_mfma(GemmKernel kind, const GemmTask<T>* tasks_dev, int ntasks, int max_m, int B,
+                      hipStream_t st) {
+    // big launches: 64 x 64 tiles; otherwise 32 x 32 tiles with deeper
+    // chunks, which keep more workgroups busy and fewer chunks in flight
+    if (kind == GEMM_MFMA64) {
+        dim3 grid((max_m + 63) / 64, (B + 63) / 64, ntasks);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 64, 64, 16, OFFLINE>), grid,
+                           dim3(GV_THREADS), 0, st, tasks_dev, B);
+    } else {
+        dim3 grid((max_m + 31) / 32, (B + 31) / 32, ntasks);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 32, OFFLINE>), grid,
+                           dim3(GV_THREADS), 0, st, tasks_dev, B);
+    }
+}
+
+template <typename T>
+void launch_gemm(const GemmTask<T>* tasks_dev, int ntasks, int max_m, int B, hipStream_t st,
+                 bool offline) {
+    if (ntasks <= 0 || max_m <= 0) return;
+    const GemmKernel kind = gemm_kernel(ntasks, max_m, B);
+    if (kind == GEMM_GEMV) {
+        dim3 grid((max_m + GV_ROWS - 1) / GV_ROWS, 1, ntasks);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemv<T>), grid, dim3(GV_THREADS), 0, st, tasks_dev);
+    } else if (kind == GEMM_TILED) {
+        dim3 grid((max_m + TM - 1) / TM, (B + TB - 1) / TB, ntasks);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_tiled<T>), grid, dim3(GV_THREADS), 0, st,
+                           tasks_dev, B);
+    } else if (offline) {
+        launch_gemm_mfma<T, true>(kind, tasks_dev, ntasks, max_m, B, st);
+    } else {
+        launch_gemm_mfma<T, false>(kind, tasks_dev, ntasks, max_m, B, st);
+    }
+}
+
+template void launch_gemm<double>(const GemmTask<double>*, int, int, int, hipStream_t, bool);
+template void launch_gemm<float>(const GemmTask<float>*, int, int, int, hipStream_t, bool);
 
 }  // namespace hz

@@ -1,6 +1,7 @@
 """Form (c) at the n = 511 workload: the adjoint-state gradient of the
 least-squares misfit behind torch.autograd, against the oracle's gradient and
-central finite differences of the GPU misfit (16 seeded directions)."""
+fourth-order central finite differences of the GPU misfit (16 seeded
+directions, relative step 1e-6)."""
 import sys
 
 import numpy as np
@@ -43,10 +44,17 @@ def test_autograd_gradient_matches_oracle(c5):
                         w.src_z, w.omega, w.n_pml, w.layers, w.cells, tol=1e-13)
     J.backward()
     g = m.grad.cpu().numpy()
-    _log(f"[C5] J={J.item():.6e} J_ref={J_ref:.6e} grad rel err="
-         f"{np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref):.2e}")
+    # The adjoint source r = P u - d is a difference of nearly equal data
+    # (|P u| / |r| ~ 1.7e5 at the starting model), so a relative solve error
+    # e_u appears in r, and in g = w u conj(lam) through lam, amplified by
+    # |d| / |r|.  Bound: 10 * (solve tolerance) * |d| / |r|, |r| = sqrt(2 J).
+    amp = np.linalg.norm(d_obs) / np.sqrt(2.0 * J_ref)
+    tol_g = 10 * 1e-13 * amp
+    err = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    _log(f"[C5] J={J.item():.6e} J_ref={J_ref:.6e} |d|/|r|={amp:.3e} grad rel err={err:.2e} "
+         f"(bound {tol_g:.2e})")
     assert abs(J.item() - J_ref) <= 1e-9 * J_ref
-    assert np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref) < 1e-8
+    assert err < tol_g
 
 
 def test_gradient_central_differences(c5):
@@ -58,13 +66,20 @@ def test_gradient_central_differences(c5):
     g = m.grad.double().cpu().numpy()
     dirs = media.random_directions(w.n, 16, seed=0)
     worst = 0.0
+    # Five-point (fourth-order) central differences at relative step 1e-6:
+    # at this step the model change moves the data far more than the current
+    # residual, and the second-order stencil's truncation error is ~1e-5
+    # (the oracle's own direct-solve misfit shows the same), while the
+    # fourth-order stencil's is ~1e-8.
+    def J_at(dmod):
+        return autograd.misfit(torch.from_numpy(m0 + dmod).cuda(), ft, dt, w.src_z, w.omega,
+                               w.n_pml, w.layers, w.cells, tol=1e-13).item()
+
     for i, dm in enumerate(dirs):
         eps = 1e-6 * np.linalg.norm(m0) / np.linalg.norm(dm)
-        Jp = autograd.misfit(torch.from_numpy(m0 + eps * dm).cuda(), ft, dt, w.src_z, w.omega,
-                             w.n_pml, w.layers, w.cells, tol=1e-13).item()
-        Jm = autograd.misfit(torch.from_numpy(m0 - eps * dm).cuda(), ft, dt, w.src_z, w.omega,
-                             w.n_pml, w.layers, w.cells, tol=1e-13).item()
-        fd = (Jp - Jm) / (2 * eps)
+        Jp1, Jm1 = J_at(eps * dm), J_at(-eps * dm)
+        Jp2, Jm2 = J_at(2 * eps * dm), J_at(-2 * eps * dm)
+        fd = (-Jp2 + 8 * Jp1 - 8 * Jm1 + Jm2) / (12 * eps)
         an = float(np.sum(g * dm))
         rel = abs(fd - an) / abs(an)
         worst = max(worst, rel)
