@@ -74,6 +74,44 @@ def timed_solves(solver, f, tol, steps, warmup, max_iter, profile=False, region=
     return u, dt, prof
 
 
+KERNEL_SOURCES = {"gemm": ["k_gemm.hip", "hz_mfma.h", "hz_common.h"],
+                  "cell_solve": ["k_cellsolve.hip", "hz_mfma.h", "hz_common.h"]}
+
+
+def kernel_src_hash(family):
+    """Hash of the sources of one kernel family (traffic figures recorded in
+    profiles/ are used only while the kernel is unchanged)."""
+    import hashlib
+
+    group = "gemm" if family.startswith("gemm") else "cell_solve"
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[group]:
+        with open(os.path.join(ROOT, "paper_1510_01831_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(family):
+    """HBM bytes per launch measured with the FETCH_SIZE / WRITE_SIZE
+    counters for this kernel, from the summaries in profiles/; None when no
+    summary covers the kernel as it is now."""
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    want = kernel_src_hash(family)
+    for name in sorted(os.listdir(pdir)):
+        if not name.endswith(".md"):
+            continue
+        with open(os.path.join(pdir, name)) as fh:
+            for line in fh:
+                if not line.startswith("traffic: "):
+                    continue
+                kv = dict(x.split("=", 1) for x in line.split()[1:])
+                if kv.get("kernel") == family and kv.get("src") == want:
+                    return float(kv["bytes_per_launch"])
+    return None
+
+
 def roofline(k, B):
     """Roofline record of one kernel family from the solver's event profile:
     matrix-core kernels against the dense MFMA peak of their precision,
@@ -82,7 +120,7 @@ def roofline(k, B):
     avg_ms = k["ms"] / k["launches"]
     rec = {"kernel": k["name"], "launches": k["launches"], "avg_launch_ms": avg_ms,
            "flops_per_launch": k["flops"] / k["launches"],
-           "bytes_per_launch": k["bytes"] / k["launches"], "traffic": None}
+           "bytes_per_launch": k["bytes"] / k["launches"], "traffic": recorded_traffic(k["name"])}
     if B > 1:
         achieved = k["flops"] / (k["ms"] * 1e-3)
         rec.update({"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12,
