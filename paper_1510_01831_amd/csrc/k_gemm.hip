@@ -176,17 +176,31 @@ __device__ __forceinline__ void next_chunk(const GemmTask<T>& t, int& sg, int& k
 
 // OFFLINE selects a separate instantiation (same code) for the factorisation
 // stage, so per-kernel profiles of the solve phase hold only solve launches.
+// Tile order: workgroup slot L runs on XCD L mod 8 (round-robin dispatch), so
+// each XCD is given one contiguous run of the (task, row tile, column tile)
+// sequence, column tiles fastest: the workgroups that share a row block of A
+// and a task's x run together and read them once into that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int L, int total) {
+    const int xcd = L & 7, local = L >> 3;
+    const int q = total >> 3, r = total & 7;
+    return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + local;
+}
+
 template <typename T, int MT, int TBM, int KC, bool OFFLINE>
 __global__ void __launch_bounds__(GV_THREADS)
-k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B) {
+k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col_tiles) {
     constexpr int RTW = MT / 32;                 // row tiles per wave
     constexpr int CTW = TBM / 32;                // column tiles per wave
     using acc_t = typename Mf<T>::acc;
-    const GemmTask<T>& t = tasks[blockIdx.z];
-    const int i0 = blockIdx.x * MT;
+    const int per_task = row_tiles * col_tiles;
+    const int tile = xcd_tile(blockIdx.x, (int)gridDim.x);
+    const int task = tile / per_task, rem = tile - task * per_task;
+    const int rt = rem / col_tiles, ct = rem - rt * col_tiles;
+    const GemmTask<T>& t = tasks[task];
+    const int i0 = rt * MT;
     if (i0 >= t.m) return;
     if (t.ncol > 0) B = t.ncol;
-    const int b0 = blockIdx.y * TBM;
+    const int b0 = ct * TBM;
     if (b0 >= B) return;
     __shared__ C2<T> As[2][MT][KC + 1];
     __shared__ C2<T> Xs[2][KC][TBM + 1];
@@ -283,13 +297,13 @@ void launch_gemm_mfma(GemmKernel kind, const GemmTask<T>* tasks_dev, int ntasks,
     // big launches: 64 x 64 tiles; otherwise 32 x 32 tiles with deeper
     // chunks, which keep more workgroups busy and fewer chunks in flight
     if (kind == GEMM_MFMA64) {
-        dim3 grid((max_m + 63) / 64, (B + 63) / 64, ntasks);
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 64, 64, 16, OFFLINE>), grid,
-                           dim3(GV_THREADS), 0, st, tasks_dev, B);
+        const int rt = (max_m + 63) / 64, ct = (B + 63) / 64;
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 64, 64, 16, OFFLINE>),
+                           dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct);
     } else {
-        dim3 grid((max_m + 31) / 32, (B + 31) / 32, ntasks);
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 32, OFFLINE>), grid,
-                           dim3(GV_THREADS), 0, st, tasks_dev, B);
+        const int rt = (max_m + 31) / 32, ct = (B + 31) / 32;
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 32, OFFLINE>),
+                           dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct);
     }
 }
 
