@@ -28,6 +28,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 using namespace hz;
@@ -57,7 +58,7 @@ double now_s() {
 
 // device allocations owned by a context
 struct Arena {
-    std::vector<void*> ptrs;
+    std::unordered_map<void*, size_t> sizes;
     long long bytes = 0;
     void* alloc(size_t n) {
         if (n == 0) n = 16;
@@ -67,22 +68,22 @@ struct Arena {
             (void)hipGetLastError();
             raise(HZ_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
         }
-        ptrs.push_back(p);
+        sizes[p] = n;
         bytes += (long long)n;
         return p;
     }
-    void release(void* p, size_t n) {
+    void release(void* p, size_t /*n: recorded at allocation*/) {
         if (!p) return;
-        auto it = std::find(ptrs.begin(), ptrs.end(), p);
-        if (it != ptrs.end()) {
-            ptrs.erase(it);
+        auto it = sizes.find(p);
+        if (it != sizes.end()) {
+            bytes -= (long long)it->second;
+            sizes.erase(it);
             (void)hipFree(p);
-            bytes -= (long long)n;
         }
     }
     void free_all() {
-        for (void* p : ptrs) (void)hipFree(p);
-        ptrs.clear();
+        for (auto& kv : sizes) (void)hipFree(kv.first);
+        sizes.clear();
         bytes = 0;
     }
 };
@@ -827,6 +828,8 @@ Plan<T>& get_plan(hz_ctx* c, bool sie, int B) {
 // Workspaces for batches up to max_batch.  `volume` adds the volume-solve
 // buffers (sources, solutions, cell-solve scratch); the vectors of the
 // interface operators are always allocated.
+void ensure_refine(hz_ctx* c);
+
 template <typename T>
 void ensure_work(hz_ctx* c, int B, bool volume = true) {
     Work<T>& w = work<T>(c);
@@ -835,8 +838,16 @@ void ensure_work(hz_ctx* c, int B, bool volume = true) {
     if (B > std::max(c->prm.max_batch, 1)) raise(HZ_EINVAL, "batch larger than max_batch");
     B = std::max(B, c->prm.max_batch);
     if (volume && !w.f_ext) {
-        w.f_ext = alloc_c<T>(c, W * W * B);
-        w.u_ext = alloc_c<T>(c, W * W * B);
+        if constexpr (sizeof(T) == sizeof(double)) {
+            // the FP64 volume buffers are the context's f64 / u64 (same size
+            // and layout): solves copy nothing in or out
+            ensure_refine(c);
+            w.f_ext = c->f64;
+            w.u_ext = c->u64;
+        } else {
+            w.f_ext = alloc_c<T>(c, W * W * B);
+            w.u_ext = alloc_c<T>(c, W * W * B);
+        }
         w.rows_out = alloc_c<T>(c, (long long)d.L * MAXSLOT * W * B);
         const long long inner = std::max<long long>((long long)d.L * c->inner_per_layer * B, 1);
         w.gf = alloc_c<T>(c, inner);
@@ -1653,12 +1664,22 @@ void check_state(hz_ctx* c, int need) {
 // volume residual norms ||f - H u|| / ||f|| per RHS, fields [W][W][B] FP64
 void vol_resid(hz_ctx* c, const double2* u, const double2* f, int B, std::vector<double>& out) {
     const long long N = (long long)c->d.W * c->d.W;
+    out.resize(B);
+    if (B <= 4096) {                        // one pass: norms without storing f - H u
+        const int nb = (int)std::min<long long>(c->gpart_chunks, std::max<long long>(1, N / 64));
+        launch_residual_norms(u, f, c->gdiag, c->gcx, c->gcz, c->d.W, B, c->gpart, nb, c->st);
+        launch_reduce_partials(c->gpart, nb, B, c->gsmall, c->st);
+        std::vector<double2> h(B);
+        HIPCHK(hipMemcpyAsync(h.data(), c->gsmall, sizeof(double2) * B, hipMemcpyDeviceToHost, c->st));
+        sync(c);
+        for (int b = 0; b < B; ++b) out[b] = h[b].y > 0 ? std::sqrt(h[b].x / h[b].y) : 0.0;
+        return;
+    }
     double2* r = c->r64;
     launch_residual(u, f, r, c->gdiag, c->gcx, c->gcz, c->d.W, B, 1, c->st);
     std::vector<double> nr, nf;
     norms(c, r, N, B, nr);
     norms(c, f, N, B, nf);
-    out.resize(B);
     for (int b = 0; b < B; ++b) out[b] = nf[b] > 0 ? nr[b] / nf[b] : 0.0;
 }
 
@@ -1705,11 +1726,8 @@ hz_status solve_impl(hz_ctx* c, const void* rhs_dev, int B, void* out_dev, doubl
         const bool flex = c->prm.precision == HZ_MIXED;
         ensure_work<double>(c, B);
         if (flex) ensure_work<float>(c, B, false);
-        Work<double>& w = c->w64;
-        HIPCHK(hipMemcpyAsync(w.f_ext, c->f64, sizeof(double2) * N * B, hipMemcpyDeviceToDevice, c->st));
         dd_solve<double>(c, B, tol, max_iter, active, iters, relres, &t_rhs, &t_gm, &t_rec, flex);
         for (int b = 0; b < B; ++b) if (!(relres[b] <= tol)) conv = false;
-        HIPCHK(hipMemcpyAsync(c->u64, w.u_ext, sizeof(double2) * N * B, hipMemcpyDeviceToDevice, c->st));
     } else {
         // FP64 iterative refinement around the complex64 nested solver
         ensure_work<float>(c, B);

@@ -260,6 +260,11 @@ void launch_rhs_to_ext(const double2* rhs, int B, int n, int p, int W, double2* 
                        const LayerDesc* layers_dev, int L, int* layer_active, hipStream_t st);
 void launch_ext_to_out(const double2* u_ext, int B, int n, int p, int W, double2* out,
                        int physical, int conj, hipStream_t st);
+// (sum |f - H u|^2, sum |f|^2) per column over node ranges -> partial[nblocks][B]
+// (needs 16 B bytes of LDS)
+void launch_residual_norms(const double2* u, const double2* f, const double2* gdiag,
+                           const double2* gcx, const double2* gcz, int W, int B, double2* partial,
+                           int nblocks, hipStream_t st);
 void launch_residual(const double2* u, const double2* f, double2* r, const double2* gdiag,
                      const double2* gcx, const double2* gcz, int W, int B, int layout_bfast,
                      hipStream_t st);

@@ -45,4 +45,41 @@ __device__ inline void cmma(T ar, T ai, T br, T bi, typename Mf<T>::acc& cr,
     ci = Mf<T>::mma(ai, br, ci);
 }
 
+// Complex accumulator of one 16x16 output tile.  G3 selects Gauss's
+// three-multiplication form: P1 += Ar Br, P2 += Ai Bi, P3 += (Ar + Ai)(Br + Bi),
+// then Re = P1 - P2 and Im = P3 - P1 - P2 -- three real MFMAs per complex tile
+// step instead of four (normwise error of the same order as the four-product
+// form), at the cost of a third accumulator.  Kernels choose per tile shape:
+// where the extra accumulator costs a wave of occupancy the four-product form
+// is faster.  HZ_GAUSS3=0 turns the three-product form off everywhere.
+#ifndef HZ_GAUSS3
+#define HZ_GAUSS3 1
+#endif
+template <typename T, bool G3>
+struct CAcc;
+
+template <typename T>
+struct CAcc<T, true> {
+    using acc = typename Mf<T>::acc;
+    acc p1, p2, p3;
+    __device__ inline void zero() { p1 = mf_zero<T>(); p2 = mf_zero<T>(); p3 = mf_zero<T>(); }
+    __device__ inline void add(T ar, T ai, T br, T bi) {
+        p1 = Mf<T>::mma(ar, br, p1);
+        p2 = Mf<T>::mma(ai, bi, p2);
+        p3 = Mf<T>::mma(ar + ai, br + bi, p3);
+    }
+    __device__ inline T re(int v) const { return p1[v] - p2[v]; }
+    __device__ inline T im(int v) const { return p3[v] - p1[v] - p2[v]; }
+};
+
+template <typename T>
+struct CAcc<T, false> {
+    using acc = typename Mf<T>::acc;
+    acc r, i;
+    __device__ inline void zero() { r = mf_zero<T>(); i = mf_zero<T>(); }
+    __device__ inline void add(T ar, T ai, T br, T bi) { cmma<T>(ar, ai, br, bi, r, i); }
+    __device__ inline T re(int v) const { return r[v]; }
+    __device__ inline T im(int v) const { return i[v]; }
+};
+
 }  // namespace hz

@@ -298,7 +298,6 @@ __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const Ce
     constexpr int NCT = NB / 16;
     constexpr int MCA = MC > 0 ? MC : 1;
     constexpr int U = MC > 1 ? CS_U2 : CS_U1; // k steps per register group
-    using acc_t = typename Mf<T>::acc;
     const int HL = cd.HL, HLp = cd.HLp, Wc = cd.Wc;
     const int KS = HLp >> 2;                  // multiple of 4
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -319,12 +318,12 @@ __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const Ce
         return b < a.B && (MODE != SOLVE_PROBE || a.probe0 + b < cd.R);
     };
 
-    acc_t cr[MCA][NCT], ci[MCA][NCT];
+    CAcc<T, HZ_GAUSS3 != 0> ac[MCA][NCT];
     auto matmul = [&](const C2<T>* __restrict__ Xk) {
 #pragma unroll
         for (int m = 0; m < MCA; ++m)
 #pragma unroll
-            for (int t = 0; t < NCT; ++t) { cr[m][t] = mf_zero<T>(); ci[m][t] = mf_zero<T>(); }
+            for (int t = 0; t < NCT; ++t) ac[m][t].zero();
         if constexpr (MC > 0) {
             const C2<T>* xp[MC];
 #pragma unroll
@@ -347,7 +346,7 @@ __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const Ce
                     for (int m = 0; m < MC; ++m)
 #pragma unroll
                         for (int t = 0; t < NCT; ++t)
-                            cmma<T>(src[u][m].x, src[u][m].y, bv[t].x, bv[t].y, cr[m][t], ci[m][t]);
+                            ac[m][t].add(src[u][m].x, src[u][m].y, bv[t].x, bv[t].y);
                 }
             };
             load(xa, 0);
@@ -386,7 +385,7 @@ __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const Ce
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     C2<T> y = pv[m][t][v];
-                    if (k > 0) y = csub(y, cmul(pe[m][v], mk<T>(cr[m][t][v], ci[m][t][v])));
+                    if (k > 0) y = csub(y, cmul(pe[m][v], mk<T>(ac[m][t].re(v), ac[m][t].im(v))));
                     pv[m][t][v] = y;
                     Y[(long long)k * nq + yidx(m, t, v)] = y;
                 }
@@ -420,7 +419,7 @@ __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const Ce
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int c = t * 16 + lc;
-                    const C2<T> x = mk<T>(cr[m][t][v], ci[m][t][v]);
+                    const C2<T> x = mk<T>(ac[m][t].re(v), ac[m][t].im(v));
                     if (bval(c)) cell_emit<T, MODE>(a, cd, ld, k, row_of(m, v), b0 + c, x);
                     pv[m][t][v] = csub(pv[m][t][v], cmul(pe[m][v], x));
                 }

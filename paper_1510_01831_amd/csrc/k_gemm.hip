@@ -191,7 +191,6 @@ __global__ void __launch_bounds__(GV_THREADS)
 k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col_tiles) {
     constexpr int RTW = MT / 32;                 // row tiles per wave
     constexpr int CTW = TBM / 32;                // column tiles per wave
-    using acc_t = typename Mf<T>::acc;
     const int per_task = row_tiles * col_tiles;
     const int tile = xcd_tile(blockIdx.x, (int)gridDim.x);
     const int task = tile / per_task, rem = tile - task * per_task;
@@ -207,11 +206,14 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int lc = lane & 15, lk = lane >> 4;
     const int wr = (w >> 1) * (MT / 2), wc = (w & 1) * (TBM / 2);
-    acc_t cr[RTW][CTW], ci[RTW][CTW];
+    // FP64 64 x 64 tiles keep the four-product form (a third accumulator set
+    // would cost them a wave of occupancy)
+    constexpr bool G3 = HZ_GAUSS3 && !(sizeof(T) == sizeof(double) && MT == 64 && TBM == 64);
+    CAcc<T, G3> acc[RTW][CTW];
 #pragma unroll
     for (int a = 0; a < RTW; ++a)
 #pragma unroll
-        for (int c = 0; c < CTW; ++c) { cr[a][c] = mf_zero<T>(); ci[a][c] = mf_zero<T>(); }
+        for (int c = 0; c < CTW; ++c) acc[a][c].zero();
     int sg = 0, kc = -KC;
     next_chunk<T, KC>(t, sg, kc);
     if (sg < t.nseg) {
@@ -236,7 +238,7 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
                 for (int a = 0; a < RTW; ++a)
 #pragma unroll
                     for (int c = 0; c < CTW; ++c)
-                        cmma<T>(av[a].x, av[a].y, bv[c].x, bv[c].y, cr[a][c], ci[a][c]);
+                        acc[a][c].add(av[a].x, av[a].y, bv[c].x, bv[c].y);
             }
             if (!more) break;
             stage.stash(As[buf ^ 1], Xs[buf ^ 1], tid);   // last read two barriers ago
@@ -254,7 +256,7 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
             for (int v = 0; v < 4; ++v) {
                 const int i = i0 + wr + a * 16 + Mf<T>::row(lane, v);
                 const int b = b0 + wc + c * 16 + lc;
-                if (i < t.m && b < B) epilogue<T>(t, i, b, mk<T>(cr[a][c][v], ci[a][c][v]));
+                if (i < t.m && b < B) epilogue<T>(t, i, b, mk<T>(acc[a][c].re(v), acc[a][c].im(v)));
             }
 }
 

@@ -180,54 +180,67 @@ void launch_conj_copy(double2* y, const double2* x, long long n, hipStream_t st)
 constexpr int RD_THREADS = 256;
 
 // partial[(chunk * nv + v) * B + b] = sum_{i in chunk} conj(V_v[i,b]) w[i,b]
+// Up to DV basis vectors per workgroup, so w is read once per DV of them.
+constexpr int DV = 8;
+
 __global__ void __launch_bounds__(RD_THREADS)
-k_dots(const double2* V, long long vstride, const double2* w, long long n, int B,
+k_dots(const double2* V, long long vstride, int nv, const double2* w, long long n, int B,
        double2* partial, int nchunks) {
     __shared__ double2 red[RD_THREADS];
-    const int v = blockIdx.y;
+    const int v0 = blockIdx.y * DV;
+    const int nvb = nv - v0 < DV ? nv - v0 : DV;
     const int tid = threadIdx.x;
     const int per = RD_THREADS / B > 0 ? RD_THREADS / B : 1;     // threads per column
     const int bcols = B < RD_THREADS ? B : RD_THREADS;
-    const double2* Vv = V ? V + v * vstride : w;
     const long long chunk = (n + nchunks - 1) / nchunks;
     const long long i0 = blockIdx.x * chunk;
     const long long i1 = (i0 + chunk < n) ? i0 + chunk : n;
     for (int bb = 0; bb < B; bb += bcols) {
-        double2 acc = make_double2(0.0, 0.0);
+        double2 acc[DV];
+#pragma unroll
+        for (int v = 0; v < DV; ++v) acc[v] = make_double2(0.0, 0.0);
         const int b = bb + tid % bcols;
         const int sub = tid / bcols;
         if (sub < per && b < B) {
             for (long long i = i0 + sub; i < i1; i += per) {
-                const double2 a = Vv[i * B + b];
-                const double2 c = w[i * B + b];
-                acc.x += a.x * c.x + a.y * c.y;
-                acc.y += a.x * c.y - a.y * c.x;
+                const long long q = i * B + b;
+                const double2 c = w[q];
+#pragma unroll
+                for (int v = 0; v < DV; ++v) {
+                    if (v < nvb) {
+                        const double2 a = V ? V[(v0 + v) * vstride + q] : c;
+                        acc[v].x += a.x * c.x + a.y * c.y;
+                        acc[v].y += a.x * c.y - a.y * c.x;
+                    }
+                }
             }
         }
-        red[tid] = acc;
-        __syncthreads();
-        if (tid < bcols && bb + tid < B) {
-            double2 s = make_double2(0.0, 0.0);
-            for (int q = 0; q < per; ++q) {
-                double2 r = red[q * bcols + tid];
-                s.x += r.x; s.y += r.y;
+        for (int v = 0; v < nvb; ++v) {
+            red[tid] = acc[v];
+            __syncthreads();
+            if (tid < bcols && bb + tid < B) {
+                double2 s = make_double2(0.0, 0.0);
+                for (int q = 0; q < per; ++q) {
+                    double2 r = red[q * bcols + tid];
+                    s.x += r.x; s.y += r.y;
+                }
+                partial[((long long)blockIdx.x * nv + v0 + v) * B + bb + tid] = s;
             }
-            partial[((long long)blockIdx.x * gridDim.y + v) * B + bb + tid] = s;
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
 void launch_dots(const double2* V, long long vstride, int nv, const double2* w, long long n,
                  int B, double2* partial, int nchunks, hipStream_t st) {
-    hipLaunchKernelGGL(k_dots, dim3(nchunks, nv), dim3(RD_THREADS), 0, st, V, vstride, w, n, B,
-                       partial, nchunks);
+    hipLaunchKernelGGL(k_dots, dim3(nchunks, (nv + DV - 1) / DV), dim3(RD_THREADS), 0, st, V,
+                       vstride, nv, w, n, B, partial, nchunks);
 }
 
 void launch_norms(const double2* w, long long n, int B, double2* partial, int nchunks,
                   hipStream_t st) {
-    hipLaunchKernelGGL(k_dots, dim3(nchunks, 1), dim3(RD_THREADS), 0, st, nullptr, 0LL, w, n, B,
-                       partial, nchunks);
+    hipLaunchKernelGGL(k_dots, dim3(nchunks, 1), dim3(RD_THREADS), 0, st, nullptr, 0LL, 1, w, n,
+                       B, partial, nchunks);
 }
 
 __global__ void k_reduce_partials(const double2* partial, int nchunks, int count, double2* out) {
@@ -290,62 +303,86 @@ void launch_scale_cols(double2* y, const double2* x, const double2* s, long long
 // ---------------------------------------------------------------------------
 // layout conversions
 
-// rhs[b][z][x] (physical) -> f_ext[Z][X][b] (extended, batch fastest), and
-// flag the layers whose owned rows carry a nonzero source.
-__global__ void k_rhs_to_ext(const double2* rhs, int B, int n, int p, int W, double2* f_ext,
-                             const LayerDesc* layers, int L, int* active, int conj) {
-    const long long total = (long long)W * W * B;
-    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
-         q += (long long)gridDim.x * blockDim.x) {
-        const int b = (int)(q % B);
-        const long long node = q / B;
-        const int Z = (int)(node / W), X = (int)(node % W);
+// Both conversions go through LDS: a workgroup moves a TT x TT block of
+// (batch column, grid column) pairs of one grid row, reading along the grid
+// row and writing along the batch (or the reverse), both coalesced.
+constexpr int TT = 32;
+
+// rhs[b][z][x] (physical) -> f_ext[Z][X][b] (extended, batch fastest), zero in
+// the PML, and flag the layer whose owned rows hold extended row Z when the
+// block carries a nonzero source.  Grid: (column tiles x batch tiles, W).
+__global__ void __launch_bounds__(256)
+k_rhs_to_ext(const double2* __restrict__ rhs, int B, int n, int p, int W,
+             double2* __restrict__ f_ext, const LayerDesc* layers, int L, int* active) {
+    __shared__ double2 tile[TT][TT + 1];
+    __shared__ int any;
+    const int xt = (W + TT - 1) / TT;
+    const int X0 = (blockIdx.x % xt) * TT, b0 = (blockIdx.x / xt) * TT;
+    const int Z = blockIdx.y, z = Z - p;
+    const bool row_in = z >= 0 && z < n;
+    const int tx = threadIdx.x % TT, ty = threadIdx.x / TT;      // 8 rows of 32 lanes
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    bool nz = false;
+    for (int r = ty; r < TT; r += 256 / TT) {                    // r: batch column
+        const int b = b0 + r, x = X0 + tx - p;
         double2 v = make_double2(0.0, 0.0);
-        if (Z >= p && Z < p + n && X >= p && X < p + n) {
-            v = rhs[((long long)b * n + (Z - p)) * n + (X - p)];
-            if (conj) v.y = -v.y;
-            if (active && (v.x != 0.0 || v.y != 0.0)) {
-                // layer of extended row Z: owned rows are [row0 + own_r0, row0 + own_r1]
-                for (int l = 0; l < L; ++l) {
-                    const int lo = layers[l].row0 + layers[l].own_r0;
-                    const int hi = layers[l].row0 + layers[l].own_r1;
-                    if (Z >= lo && Z <= hi) { atomicOr(&active[l], 1); break; }
-                }
-            }
+        if (row_in && b < B && x >= 0 && x < n) v = rhs[((long long)b * n + z) * n + x];
+        nz = nz || v.x != 0.0 || v.y != 0.0;
+        tile[r][tx] = v;
+    }
+    if (nz) any = 1;
+    __syncthreads();
+    for (int r = ty; r < TT; r += 256 / TT) {                    // r: grid column
+        const int X = X0 + r, b = b0 + tx;
+        if (X < W && b < B) f_ext[((long long)Z * W + X) * B + b] = tile[tx][r];
+    }
+    if (active && threadIdx.x == 0 && any) {
+        for (int l = 0; l < L; ++l) {
+            const int lo = layers[l].row0 + layers[l].own_r0;
+            const int hi = layers[l].row0 + layers[l].own_r1;
+            if (Z >= lo && Z <= hi) { atomicOr(&active[l], 1); break; }
         }
-        f_ext[q] = v;
     }
 }
 void launch_rhs_to_ext(const double2* rhs, int B, int n, int p, int W, double2* f_ext,
                        const LayerDesc* layers_dev, int L, int* layer_active, hipStream_t st) {
-    const long long total = (long long)W * W * B;
-    int blocks = (int)std::min<long long>((total + 255) / 256, 16384);
-    hipLaunchKernelGGL(k_rhs_to_ext, dim3(blocks), dim3(256), 0, st, rhs, B, n, p, W, f_ext,
-                       layers_dev, L, layer_active, 0);
+    const int xt = (W + TT - 1) / TT, bt = (B + TT - 1) / TT;
+    hipLaunchKernelGGL(k_rhs_to_ext, dim3(xt * bt, W), dim3(256), 0, st, rhs, B, n, p, W, f_ext,
+                       layers_dev, L, layer_active);
 }
 
-// u_ext[Z][X][b] -> out[b][z][x] (physical) or out[b][Z][X] (extended)
-__global__ void k_ext_to_out(const double2* u, int B, int n, int p, int W, double2* out,
-                             int physical, int conj) {
+// u[Z][X][b] (extended, batch fastest) -> out[b][z][x] on the physical grid
+// (physical = 1) or out[b][Z][X] on the extended grid, conjugated if asked.
+// Grid: (column tiles x batch tiles, side).
+__global__ void __launch_bounds__(256)
+k_ext_to_out(const double2* __restrict__ u, int B, int n, int p, int W, double2* __restrict__ out,
+             int physical, int conj) {
+    __shared__ double2 tile[TT][TT + 1];
     const int side = physical ? n : W;
-    const long long total = (long long)side * side * B;
-    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
-         q += (long long)gridDim.x * blockDim.x) {
-        const int b = (int)(q / ((long long)side * side));
-        const long long r = q % ((long long)side * side);
-        const int z = (int)(r / side), x = (int)(r % side);
-        const int Z = physical ? z + p : z, X = physical ? x + p : x;
-        double2 v = u[((long long)Z * W + X) * B + b];
+    const int off = physical ? p : 0;
+    const int xt = (side + TT - 1) / TT;
+    const int x0 = (blockIdx.x % xt) * TT, b0 = (blockIdx.x / xt) * TT;
+    const int z = blockIdx.y;
+    const int tx = threadIdx.x % TT, ty = threadIdx.x / TT;
+    for (int r = ty; r < TT; r += 256 / TT) {                    // r: grid column
+        const int x = x0 + r, b = b0 + tx;
+        double2 v = make_double2(0.0, 0.0);
+        if (x < side && b < B) v = u[((long long)(z + off) * W + x + off) * B + b];
         if (conj) v.y = -v.y;
-        out[q] = v;
+        tile[r][tx] = v;
+    }
+    __syncthreads();
+    for (int r = ty; r < TT; r += 256 / TT) {                    // r: batch column
+        const int b = b0 + r, x = x0 + tx;
+        if (b < B && x < side) out[((long long)b * side + z) * side + x] = tile[tx][r];
     }
 }
 void launch_ext_to_out(const double2* u_ext, int B, int n, int p, int W, double2* out,
                        int physical, int conj, hipStream_t st) {
     const int side = physical ? n : W;
-    const long long total = (long long)side * side * B;
-    int blocks = (int)std::min<long long>((total + 255) / 256, 16384);
-    hipLaunchKernelGGL(k_ext_to_out, dim3(blocks), dim3(256), 0, st, u_ext, B, n, p, W, out,
+    const int xt = (side + TT - 1) / TT, bt = (B + TT - 1) / TT;
+    hipLaunchKernelGGL(k_ext_to_out, dim3(xt * bt, side), dim3(256), 0, st, u_ext, B, n, p, W, out,
                        physical, conj);
 }
 
@@ -368,6 +405,63 @@ void launch_transpose_bfast(const double2* src, double2* dst, int B, long long n
     const long long total = n * B;
     int blocks = (int)std::min<long long>((total + 255) / 256, 16384);
     hipLaunchKernelGGL(k_transpose_bfast, dim3(blocks), dim3(256), 0, st, src, dst, B, n, to_bfast);
+}
+
+// ---------------------------------------------------------------------------
+// Per right-hand side, over the extended grid (batch fastest), without
+// storing the residual: partial[blk * B + b] = (sum |f - H u|^2, sum |f|^2)
+// over the workgroup's node range.  Sums are collected in LDS (dynamic,
+// 2 B doubles); when B divides the workgroup size every thread keeps one
+// column and adds once at the end.
+__global__ void __launch_bounds__(256)
+k_residual_norms(const double2* __restrict__ u, const double2* __restrict__ f,
+                 const double2* __restrict__ gd, const double2* __restrict__ gcx,
+                 const double2* __restrict__ gcz, int W, int B, long long nodes_per_block,
+                 double2* __restrict__ partial) {
+    extern __shared__ double rn_sh[];
+    for (int i = threadIdx.x; i < 2 * B; i += blockDim.x) rn_sh[i] = 0.0;
+    __syncthreads();
+    const long long nodes = (long long)W * W;
+    const long long n0 = blockIdx.x * nodes_per_block;
+    const long long n1 = n0 + nodes_per_block < nodes ? n0 + nodes_per_block : nodes;
+    const bool fixed = (blockDim.x % B) == 0;
+    double sr = 0.0, sf = 0.0;
+    for (long long q = n0 * B + threadIdx.x; q < n1 * B; q += blockDim.x) {
+        const int b = (int)(q % B);
+        const long long g = q / B;
+        const int Z = (int)(g / W), X = (int)(g % W);
+        double2 acc = cmul(gd[g], u[q]);
+        if (X + 1 < W) acc = cfma(gcx[g], u[q + B], acc);
+        if (X > 0) acc = cfma(gcx[g - 1], u[q - B], acc);
+        if (Z + 1 < W) acc = cfma(gcz[g], u[q + (long long)W * B], acc);
+        if (Z > 0) acc = cfma(gcz[g - W], u[q - (long long)W * B], acc);
+        const double2 fv = f[q];
+        const double rx = fv.x - acc.x, ry = fv.y - acc.y;
+        const double r2 = rx * rx + ry * ry, f2 = fv.x * fv.x + fv.y * fv.y;
+        if (fixed) {
+            sr += r2;
+            sf += f2;
+        } else {
+            atomicAdd(&rn_sh[2 * b], r2);
+            atomicAdd(&rn_sh[2 * b + 1], f2);
+        }
+    }
+    if (fixed) {                                  // this thread's column throughout
+        const int b = (int)((n0 * B + threadIdx.x) % B);
+        atomicAdd(&rn_sh[2 * b], sr);
+        atomicAdd(&rn_sh[2 * b + 1], sf);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < B; b += blockDim.x)
+        partial[(long long)blockIdx.x * B + b] = make_double2(rn_sh[2 * b], rn_sh[2 * b + 1]);
+}
+void launch_residual_norms(const double2* u, const double2* f, const double2* gdiag,
+                           const double2* gcx, const double2* gcz, int W, int B, double2* partial,
+                           int nblocks, hipStream_t st) {
+    const long long nodes = (long long)W * W;
+    const long long per = (nodes + nblocks - 1) / nblocks;
+    hipLaunchKernelGGL(k_residual_norms, dim3(nblocks), dim3(256), sizeof(double) * 2 * B, st, u,
+                       f, gdiag, gcx, gcz, W, B, per, partial);
 }
 
 // ---------------------------------------------------------------------------

@@ -152,6 +152,22 @@ def test_uncomposed_inner_solve(monkeypatch):
             assert _rel(u[bb], ref) < 1e-9
 
 
+def test_volume_residual_statistic(setup):
+    """The per-RHS residual reported by the solve, |f - H u| / |f| over the
+    extended grid, against the same norm computed on the CPU from the GPU's
+    extended solution and the oracle's matrix."""
+    c, omega, prob, solver, oracle = setup
+    f = media.point_sources(N, (5, 33, 41), 30)
+    _log("[vol_resid] B=3")
+    u = solver.solve(torch.from_numpy(f), tol=1e-11, ext=True).cpu().numpy()
+    for bb in range(3):
+        fe = prob.extend(f[bb]).ravel()
+        ref = np.linalg.norm(fe - prob.H @ u[bb].ravel()) / np.linalg.norm(fe)
+        got = solver.last_stats[bb]["vol_resid"]
+        _log(f"  rhs {bb}: gpu {got:.6e} cpu {ref:.6e}")
+        assert abs(got - ref) <= 1e-2 * ref + 1e-15
+
+
 def test_single_layer_and_cell_counts():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
