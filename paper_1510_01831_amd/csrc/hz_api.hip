@@ -162,6 +162,7 @@ struct Work {
     int y_wgs = 0;
     const C2<T>** pair_tab = nullptr;   // device [2L]: top pairs then bottom pairs
     std::map<int, std::unique_ptr<Plan<T>>> sie, pre;
+    std::map<std::string, std::unique_ptr<Plan<T>>> jobs;   // RHS formation / reconstruction
 };
 
 struct Prof {
@@ -189,6 +190,8 @@ struct hz_ctx {
     std::vector<CellDesc> cells;
     LayerDesc* d_layers = nullptr;
     CellDesc* d_cells = nullptr;
+    int* d_all_cells = nullptr;    // 0 .. ncells-1 (contiguous cell lists point into it)
+    int* d_cell_list = nullptr;    // [ncells] other cell lists
     double* model = nullptr;
     double2 *diag = nullptr, *cz = nullptr, *e = nullptr;
     double2 *ax_pool = nullptr, *az_pool = nullptr;
@@ -210,6 +213,7 @@ struct hz_ctx {
     double2 *V = nullptr, *gw = nullptr, *gb = nullptr, *gx = nullptr, *gpart = nullptr,
             *gsmall = nullptr, *gcoef = nullptr;
     int gpart_chunks = 0;
+    double2* gh = nullptr;         // GMRES projections of both passes and |w|^2, on the device
     double2 *u64 = nullptr, *f64 = nullptr, *r64 = nullptr;   // refinement [W][W][B]
     hz_timing timing{};
     Prof prof;
@@ -898,6 +902,7 @@ void ensure_gmres(hz_ctx* c, int B, int m) {
         c->arena.release(c->gpart, 0);
         c->arena.release(c->gsmall, 0);
         c->arena.release(c->gcoef, 0);
+        c->arena.release(c->gh, 0);
     }
     B = std::max(B, c->g_cap_B);
     m = std::max(m, c->g_cap_m);
@@ -916,6 +921,7 @@ void ensure_gmres(hz_ctx* c, int B, int m) {
     c->gpart = (double2*)c->arena.alloc(sizeof(double2) * c->gpart_chunks * (m + 2) * B);
     c->gsmall = (double2*)c->arena.alloc(sizeof(double2) * (m + 2) * B);
     c->gcoef = (double2*)c->arena.alloc(sizeof(double2) * (m + 2) * B);
+    c->gh = (double2*)c->arena.alloc(sizeof(double2) * (2 * (m + 1) + 1) * B);
 }
 
 // ---------------------------------------------------------------------------
@@ -930,8 +936,15 @@ void cell_solve_launch(hz_ctx* c, CellSolveArgs<T> a, const std::vector<int>& li
     const long long wg_elems = (long long)c->d.Wcmax * c->d.HLpmax * nb;
     const int per = (int)std::max<long long>(1, (w.y_stride * w.y_wgs / wg_elems) / chunks);
     a.nb = nb;
-    int* d_list = (int*)c->arena.alloc(sizeof(int) * list.size());
-    upload(c, d_list, list.data(), sizeof(int) * list.size());
+    // a contiguous run of cells is a slice of the all-cells table; other
+    // lists go to the persistent list buffer (no allocation per solve)
+    bool contiguous = true;
+    for (size_t i = 1; i < list.size(); ++i) contiguous = contiguous && list[i] == list[0] + (int)i;
+    const int* d_list = c->d_all_cells + (list.empty() ? 0 : list[0]);
+    if (!contiguous) {
+        upload(c, c->d_cell_list, list.data(), sizeof(int) * list.size());
+        d_list = c->d_cell_list;
+    }
     const bool prof = c->prof.on;
     for (size_t g = 0; g < list.size(); g += per) {
         const int cnt = (int)std::min<size_t>(per, list.size() - g);
@@ -958,8 +971,6 @@ void cell_solve_launch(hz_ctx* c, CellSolveArgs<T> a, const std::vector<int>& li
             c->prof.pend.push_back({fam_name<T>(fam), e0, e1, bytes, flops});
         }
     }
-    sync(c);
-    c->arena.release(d_list, sizeof(int) * list.size());
 }
 
 template <typename T>
@@ -1320,6 +1331,12 @@ void factor_impl(hz_ctx* c) {
 // ---------------------------------------------------------------------------
 // online stage, precision T for the local operators
 
+// drop every cached plan (operators, stream or buffers changed)
+void clear_plans(hz_ctx* c) {
+    c->w64.sie.clear(); c->w64.pre.clear(); c->w64.jobs.clear();
+    c->w32.sie.clear(); c->w32.pre.clear(); c->w32.jobs.clear();
+}
+
 template <typename T>
 void run_jobs(hz_ctx* c, const std::vector<LayerJob<T>>& jobs, int B) {
     Plan<T> pl;
@@ -1328,6 +1345,30 @@ void run_jobs(hz_ctx* c, const std::vector<LayerJob<T>>& jobs, int B) {
     plan_launches<T>(c, pl, B);
     sync(c);
     if (pl.dev) c->arena.release(pl.dev, pl.dev_bytes);
+}
+
+// The same, with the plan kept under `key` (the jobs must be a function of
+// the key) and replayed like the operator plans.
+template <typename T>
+void run_jobs_cached(hz_ctx* c, const std::string& key, const std::vector<LayerJob<T>>& jobs,
+                     int B) {
+    Work<T>& w = work<T>(c);
+    auto it = w.jobs.find(key);
+    if (it == w.jobs.end()) {
+        auto pl = std::make_unique<Plan<T>>();
+        pl->name = fam_name<T>("jobs_graph");
+        plan_jobs<T>(c, *pl, jobs, B);
+        plan_upload<T>(c, *pl);
+        it = w.jobs.emplace(key, std::move(pl)).first;
+    }
+    plan_run<T>(c, *it->second, B);
+}
+
+std::string jobs_key(const char* kind, int B, const int* active, int L, const void* out) {
+    std::string k = std::string(kind) + "|" + std::to_string(B) + "|" +
+                    std::to_string((unsigned long long)(uintptr_t)out) + "|";
+    for (int l = 0; l < L; ++l) k += active[l] ? '1' : '0';
+    return k;
 }
 
 // Cell Newton potentials of the volume source in the layers that hold one
@@ -1381,7 +1422,7 @@ void sie_rhs_impl(hz_ctx* c, int B, C2<T>* out, const int* active_host) {
             jobs.push_back(jb);
         }
     }
-    run_jobs<T>(c, jobs, B);
+    run_jobs_cached<T>(c, jobs_key("rhs", B, active_host, d.L, out), jobs, B);
 }
 
 // volume reconstruction from traces in w.sv (s = d + q) into w.u_ext
@@ -1404,7 +1445,7 @@ void reconstruct_impl(hz_ctx* c, int B, const int* active_host) {
             jb.phase3 = false;
             jobs.push_back(jb);
         }
-        run_jobs<T>(c, jobs, B);
+        run_jobs_cached<T>(c, jobs_key("rec", B, active_host, d.L, nullptr), jobs, B);
     }
     std::vector<int> list(c->cells.size());
     for (size_t i = 0; i < list.size(); ++i) list[i] = (int)i;
@@ -1479,6 +1520,14 @@ void dots(hz_ctx* c, const double2* V, long long vstride, int nv, const double2*
     sync(c);
 }
 
+// the same reductions left on the device: out_dev[v * B + b]
+void dots_dev(hz_ctx* c, const double2* V, long long vstride, int nv, const double2* w,
+              long long n, int B, double2* out_dev) {
+    const int chunks = (int)std::min<long long>(c->gpart_chunks, std::max<long long>(1, n / 256));
+    launch_dots(V, vstride, nv, w, n, B, c->gpart, chunks, c->st);
+    launch_reduce_partials(c->gpart, chunks, nv * B, out_dev, c->st);
+}
+
 void norms(hz_ctx* c, const double2* w, long long n, int B, std::vector<double>& out) {
     std::vector<std::complex<double>> t;
     dots(c, nullptr, 0, 1, w, n, B, t);
@@ -1534,7 +1583,6 @@ void gmres(hz_ctx* c, const double2* b, double2* x, int B, double tol, int maxit
     }
     upload(c, c->gcoef, sc.data(), sizeof(double2) * B);
     launch_scale_cols(V, V, c->gcoef, n, B, c->st);
-    std::vector<std::complex<double>> h1, h2;
     std::vector<double> nrm;
     std::vector<double2> coef;
     int j = 0;
@@ -1548,19 +1596,26 @@ void gmres(hz_ctx* c, const double2* b, double2* x, int B, double tol, int maxit
         } else {
             apply_PM<T>(c, Vj, c->gw, B);
         }
-        // two passes of classical Gram-Schmidt
-        std::vector<std::complex<double>> hsum((size_t)(j + 1) * B, 0.0);
-        for (int pass = 0; pass < 2; ++pass) {
-            dots(c, V, vs, j + 1, c->gw, n, B, h1);
-            coef.assign((size_t)(j + 1) * B, make_double2(0, 0));
-            for (size_t q = 0; q < h1.size(); ++q) {
-                hsum[q] += h1[q];
-                coef[q] = make_double2(-h1[q].real(), -h1[q].imag());
-            }
-            upload(c, c->gcoef, coef.data(), sizeof(double2) * coef.size());
-            launch_update_basis(c->gw, V, vs, j + 1, c->gcoef, n, B, c->st);
-        }
-        norms(c, c->gw, n, B, nrm);
+        // two passes of classical Gram-Schmidt; the projections stay on the
+        // device and the host reads both passes and |w|^2 once per iteration
+        const size_t nh = (size_t)(j + 1) * B;
+        double2* hA = c->gh;
+        double2* hB = c->gh + nh;
+        double2* hN = c->gh + 2 * nh;
+        dots_dev(c, V, vs, j + 1, c->gw, n, B, hA);
+        launch_update_basis(c->gw, V, vs, j + 1, hA, n, B, c->st, -1.0);
+        dots_dev(c, V, vs, j + 1, c->gw, n, B, hB);
+        launch_update_basis(c->gw, V, vs, j + 1, hB, n, B, c->st, -1.0);
+        dots_dev(c, nullptr, 0, 1, c->gw, n, B, hN);
+        std::vector<double2> hh(2 * nh + B);
+        HIPCHK(hipMemcpyAsync(hh.data(), c->gh, sizeof(double2) * hh.size(), hipMemcpyDeviceToHost,
+                              c->st));
+        sync(c);
+        std::vector<std::complex<double>> hsum(nh);
+        for (size_t q = 0; q < nh; ++q)
+            hsum[q] = std::complex<double>(hh[q].x + hh[nh + q].x, hh[q].y + hh[nh + q].y);
+        nrm.resize(B);
+        for (int bb = 0; bb < B; ++bb) nrm[bb] = std::sqrt(std::max(0.0, hh[2 * nh + bb].x));
         for (int bb = 0; bb < B; ++bb) {
             sc[bb] = make_double2(0.0, 0.0);
             if (done[bb]) continue;
@@ -1666,7 +1721,10 @@ void vol_resid(hz_ctx* c, const double2* u, const double2* f, int B, std::vector
     const long long N = (long long)c->d.W * c->d.W;
     out.resize(B);
     if (B <= 4096) {                        // one pass: norms without storing f - H u
-        const int nb = (int)std::min<long long>(c->gpart_chunks, std::max<long long>(1, N / 64));
+        // gpart holds gpart_chunks * (m + 2) * B entries (m >= 1)
+        const long long cap = (long long)c->gpart_chunks * (c->g_cap_m + 2);
+        const int nb = (int)std::min<long long>(std::min<long long>(cap, 2048),
+                                                std::max<long long>(1, N / 64));
         launch_residual_norms(u, f, c->gdiag, c->gcx, c->gcz, c->d.W, B, c->gpart, nb, c->st);
         launch_reduce_partials(c->gpart, nb, B, c->gsmall, c->st);
         std::vector<double2> h(B);
@@ -1889,6 +1947,13 @@ hz_status hz_setup(const double* model_dev, const hz_params* prm, hz_ctx** out) 
     c->d_cells = (CellDesc*)c->arena.alloc(sizeof(CellDesc) * c->cells.size());
     upload(c, c->d_layers, c->layers.data(), sizeof(LayerDesc) * d.L);
     upload(c, c->d_cells, c->cells.data(), sizeof(CellDesc) * c->cells.size());
+    {
+        std::vector<int> all(c->cells.size());
+        for (size_t i = 0; i < all.size(); ++i) all[i] = (int)i;
+        c->d_all_cells = (int*)c->arena.alloc(sizeof(int) * all.size());
+        c->d_cell_list = (int*)c->arena.alloc(sizeof(int) * all.size());
+        upload(c, c->d_all_cells, all.data(), sizeof(int) * all.size());
+    }
     c->model = (double*)c->arena.alloc(sizeof(double) * n * n);
     c->diag = alloc_c<double>(c, c->coef_elems);
     c->cz = alloc_c<double>(c, c->coef_elems);
@@ -1936,8 +2001,7 @@ hz_status hz_factor(hz_ctx* c) {
     double t0 = now_s();
     c->state = 1;
     factor_impl(c);
-    c->w64.sie.clear(); c->w64.pre.clear();
-    c->w32.sie.clear(); c->w32.pre.clear();
+    clear_plans(c);
     c->state = 2;
     c->timing.t_factor = now_s() - t0;
     return HZ_OK;
@@ -2011,8 +2075,7 @@ hz_status hz_set_stream(hz_ctx* c, void* s) {
     sync(c);
     c->st = s ? (hipStream_t)s : c->own_st;
     // graphs were captured on the previous stream; rebuild lazily
-    c->w64.sie.clear(); c->w64.pre.clear();
-    c->w32.sie.clear(); c->w32.pre.clear();
+    clear_plans(c);
     return HZ_OK;
     API_END
 }
@@ -2064,8 +2127,7 @@ void hz_destroy(hz_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->st);
     for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
-    c->w64.sie.clear(); c->w64.pre.clear();
-    c->w32.sie.clear(); c->w32.pre.clear();
+    clear_plans(c);
     c->arena.free_all();
     if (c->own_st) (void)hipStreamDestroy(c->own_st);
     delete c;

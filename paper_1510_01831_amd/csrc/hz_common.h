@@ -251,7 +251,8 @@ void launch_dots(const double2* V, long long vstride, int nv, const double2* w, 
 void launch_reduce_partials(const double2* partial, int nchunks, int count, double2* out,
                             hipStream_t st);
 void launch_update_basis(double2* w, const double2* V, long long vstride, int nv,
-                         const double2* coef, long long n, int B, hipStream_t st);
+                         const double2* coef, long long n, int B, hipStream_t st,
+                         double sgn = 1.0);
 void launch_scale_cols(double2* y, const double2* x, const double2* s, long long n, int B,
                        hipStream_t st);
 void launch_norms(const double2* w, long long n, int B, double2* partial, int nchunks,

@@ -259,29 +259,30 @@ void launch_reduce_partials(const double2* partial, int nchunks, int count, doub
                        nchunks, count, out);
 }
 
-// w[i,b] += sum_v coef[v,b] V_v[i,b]
+// w[i,b] += sgn * sum_v coef[v,b] V_v[i,b]
 __global__ void k_update_basis(double2* w, const double2* V, long long vstride, int nv,
-                               const double2* coef, long long n, int B) {
+                               const double2* coef, long long n, int B, double sgn) {
     const long long total = n * B;
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
          q += (long long)gridDim.x * blockDim.x) {
         const int b = (int)(q % B);
-        double2 acc = w[q];
+        double2 acc = make_double2(0.0, 0.0);
         for (int v = 0; v < nv; ++v) {
             const double2 c = coef[(long long)v * B + b];
             const double2 x = V[v * vstride + q];
             acc.x += c.x * x.x - c.y * x.y;
             acc.y += c.x * x.y + c.y * x.x;
         }
-        w[q] = acc;
+        const double2 w0 = w[q];
+        w[q] = make_double2(w0.x + sgn * acc.x, w0.y + sgn * acc.y);
     }
 }
 void launch_update_basis(double2* w, const double2* V, long long vstride, int nv,
-                         const double2* coef, long long n, int B, hipStream_t st) {
+                         const double2* coef, long long n, int B, hipStream_t st, double sgn) {
     const long long total = n * B;
     int blocks = (int)std::min<long long>((total + 255) / 256, 16384);
     hipLaunchKernelGGL(k_update_basis, dim3(blocks), dim3(256), 0, st, w, V, vstride, nv, coef,
-                       n, B);
+                       n, B, sgn);
 }
 
 __global__ void k_scale_cols(double2* y, const double2* x, const double2* s, long long n, int B) {
