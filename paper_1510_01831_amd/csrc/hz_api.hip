@@ -917,7 +917,7 @@ void ensure_gmres(hz_ctx* c, int B, int m) {
     c->gw = (double2*)c->arena.alloc(sizeof(double2) * nb);
     c->gb = (double2*)c->arena.alloc(sizeof(double2) * nb);
     c->gx = (double2*)c->arena.alloc(sizeof(double2) * nb);
-    c->gpart_chunks = 256;
+    c->gpart_chunks = 1024;
     c->gpart = (double2*)c->arena.alloc(sizeof(double2) * c->gpart_chunks * (m + 2) * B);
     c->gsmall = (double2*)c->arena.alloc(sizeof(double2) * (m + 2) * B);
     c->gcoef = (double2*)c->arena.alloc(sizeof(double2) * (m + 2) * B);

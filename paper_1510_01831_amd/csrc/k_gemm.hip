@@ -187,7 +187,7 @@ __device__ __forceinline__ int xcd_tile(int L, int total) {
 }
 
 template <typename T, int MT, int TBM, int KC, bool OFFLINE>
-__global__ void __launch_bounds__(GV_THREADS)
+__global__ void __launch_bounds__(GV_THREADS, 2)
 k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col_tiles) {
     constexpr int RTW = MT / 32;                 // row tiles per wave
     constexpr int CTW = TBM / 32;                // column tiles per wave
@@ -206,10 +206,9 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int lc = lane & 15, lk = lane >> 4;
     const int wr = (w >> 1) * (MT / 2), wc = (w & 1) * (TBM / 2);
-    // FP64 64 x 64 tiles keep the four-product form (a third accumulator set
-    // would cost them a wave of occupancy)
-    constexpr bool G3 = HZ_GAUSS3 && !(sizeof(T) == sizeof(double) && MT == 64 && TBM == 64);
-    CAcc<T, G3> acc[RTW][CTW];
+    // (two workgroups per CU are requested: the FP64 64 x 64 tile with three
+    // accumulator sets then fits in 256 registers per lane without spilling)
+    CAcc<T, HZ_GAUSS3 != 0> acc[RTW][CTW];
 #pragma unroll
     for (int a = 0; a < RTW; ++a)
 #pragma unroll
