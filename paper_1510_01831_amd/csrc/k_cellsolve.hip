@@ -118,6 +118,104 @@ __device__ inline C2<T> cell_source(const CellSolveArgs<T>& a, const CellDesc& c
     return v;
 }
 
+// Per-workgroup constants of the source assembly, fetched once: whether the
+// volume source is read in this layer, the interface pair and inner-trace
+// pointers, and (in LDS) the scaled PML factors 1/(alpha_z h^2) per row and
+// 1/(alpha_x h^2) per column of the cell.
+template <typename T>
+struct SrcCtx {
+    bool act;
+    const C2<T>* top;
+    const C2<T>* bot;
+    const C2<T>* iv;
+    const double2* izs;     // [HLp] (LDS)
+    const double2* ixs;     // [Wc]  (LDS)
+};
+
+template <typename T, int MODE>
+__device__ inline C2<T> cell_source_ctx(const CellSolveArgs<T>& a, const CellDesc& cd,
+                                        const LayerDesc& ld, const SrcCtx<T>& sc, int k, int j,
+                                        int b) {
+    const int p = a.p;
+    const C2<T> z = mk<T>((T)0, (T)0);
+    const int B = a.B;
+    if (j >= cd.HL) return z;
+    if constexpr (MODE == SOLVE_GRID) {
+        return a.g_grid[((long long)j * cd.Wc + k) * B + b];
+    }
+    const bool own_col = (k >= cd.own_c0 && k <= cd.own_c1);
+    if constexpr (MODE == SOLVE_PROBE) {
+        const int probe = a.probe0 + b;
+        if (probe < cd.ncol) {
+            int q = probe;
+            int right = 0;
+            if (!cd.has_left) right = 1;
+            else if (q >= 2 * cd.HL) { right = 1; q -= 2 * cd.HL; }
+            const int ab = q / cd.HL, jj = q - ab * cd.HL;
+            if (j != jj) return z;
+            int kk; double sg;
+            if (!right) { kk = ab == 0 ? p : p - 1; sg = ab == 0 ? 1.0 : -1.0; }
+            else { kk = ab == 0 ? p + cd.nc : p + cd.nc - 1; sg = ab == 0 ? -1.0 : 1.0; }
+            if (k != kk) return z;
+            const double2 iz = sc.izs[j];
+            return mk<T>((T)(sg * iz.x), (T)(sg * iz.y));
+        } else {
+            const int t = probe - cd.ncol;
+            const int si = t / cd.s, ci = t - si * cd.s;
+            if (k != cd.own_c0 + ci) return z;
+            const int lid = ld.slot_id[si];
+            int rr; double sg;
+            if (lid == 0) { rr = p; sg = 1.0; }
+            else if (lid == 1) { rr = p - 1; sg = -1.0; }
+            else if (lid == 2) { rr = p + ld.nl; sg = -1.0; }
+            else { rr = p + ld.nl - 1; sg = 1.0; }
+            if (j != rr) return z;
+            const double2 ix = sc.ixs[k];
+            return mk<T>((T)(sg * ix.x), (T)(sg * ix.y));
+        }
+    }
+    // SOLVE_SAMPLE / SOLVE_VOLUME
+    C2<T> v = z;
+    const long long W = a.W;
+    const bool own_row = (j >= ld.own_r0 && j <= ld.own_r1);
+    if (sc.act && own_col && own_row)
+        v = a.f_ext[(((long long)(ld.row0 + j)) * W + cd.col0 + k) * B + b];
+    if constexpr (MODE == SOLVE_VOLUME) {
+        if (own_col) {
+            const long long col = cd.col0 + k;
+            if (sc.top && (j == p || j == p - 1)) {
+                const C2<T> s = to_t<T>(sc.ixs[k]);
+                if (j == p) v = cfma(s, sc.top[(0 * W + col) * B + b], v);
+                else v = csub(v, cmul(s, sc.top[(1 * W + col) * B + b]));
+            }
+            if (sc.bot && (j == p + ld.nl - 1 || j == p + ld.nl)) {
+                const C2<T> s = to_t<T>(sc.ixs[k]);
+                if (j == p + ld.nl - 1) v = cfma(s, sc.bot[(1 * W + col) * B + b], v);
+                else v = csub(v, cmul(s, sc.bot[(0 * W + col) * B + b]));
+            }
+        }
+        if (sc.iv) {
+            const int HL = cd.HL;
+            const bool kl = cd.has_left && (k == p || k == p - 1);
+            const bool kr = cd.has_right && (k == p + cd.nc || k == p + cd.nc - 1);
+            if (kl || kr) {
+                const C2<T> s = to_t<T>(sc.izs[j]);
+                if (kl) {
+                    const int jf = cd.cell - 1;
+                    if (k == p) v = cfma(s, sc.iv[(((long long)jf * 2 + 0) * HL + j) * B + b], v);
+                    else v = csub(v, cmul(s, sc.iv[(((long long)jf * 2 + 1) * HL + j) * B + b]));
+                }
+                if (kr) {
+                    const int jf = cd.cell;
+                    if (k == p + cd.nc) v = csub(v, cmul(s, sc.iv[(((long long)jf * 2 + 0) * HL + j) * B + b]));
+                    else v = cfma(s, sc.iv[(((long long)jf * 2 + 1) * HL + j) * B + b], v);
+                }
+            }
+        }
+    }
+    return v;
+}
+
 template <typename T, int MODE>
 __device__ inline void cell_emit(const CellSolveArgs<T>& a, const CellDesc& cd,
                                  const LayerDesc& ld, int k, int j, int b, C2<T> x) {
@@ -294,7 +392,8 @@ constexpr int CS_MF_WAVES = CS_MF_THREADS / 64;
 
 template <typename T, int NB, int MODE, int MC>
 __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const CellDesc& cd,
-                                             const LayerDesc& ld, C2<T>* vs, int b0) {
+                                             const LayerDesc& ld, C2<T>* vs, double2* izs,
+                                             double2* ixs, int b0) {
     constexpr int NCT = NB / 16;
     constexpr int MCA = MC > 0 ? MC : 1;
     constexpr int U = MC > 1 ? CS_U2 : CS_U1; // k steps per register group
@@ -360,6 +459,32 @@ __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const Ce
         }
     };
 
+    // per-workgroup source constants
+    {
+        const double ih2 = 1.0 / (a.h * a.h);
+        for (int j = threadIdx.x; j < HLp; j += CS_MF_THREADS) {
+            double2 v = make_double2(0.0, 0.0);
+            if (j < HL) {
+                const double2 iz = cinv(a.alpha_z[(long long)cd.layer * a.HLmax + j]);
+                v = make_double2(iz.x * ih2, iz.y * ih2);
+            }
+            izs[j] = v;
+        }
+        for (int k = threadIdx.x; k < Wc; k += CS_MF_THREADS) {
+            const double2 ix = cinv(a.alpha_x[(long long)cd.gidx * a.Wcmax + k]);
+            ixs[k] = make_double2(ix.x * ih2, ix.y * ih2);
+        }
+    }
+    SrcCtx<T> sc;
+    sc.act = a.f_ext && (!a.layer_active || a.layer_active[cd.layer]);
+    sc.top = (MODE == SOLVE_VOLUME && a.top_pair) ? a.top_pair[cd.layer] : nullptr;
+    sc.bot = (MODE == SOLVE_VOLUME && a.bot_pair) ? a.bot_pair[cd.layer] : nullptr;
+    sc.iv = (MODE == SOLVE_VOLUME && a.inner_v && ld.J > 0) ? a.inner_v + ld.off_inner * a.B
+                                                             : nullptr;
+    sc.izs = izs;
+    sc.ixs = ixs;
+    __syncthreads();
+
     C2<T> pv[MCA][NCT][4];   // prefetched sources (forward) / iterates (backward)
     C2<T> pe[MCA][4];        // prefetched coupling coefficients
 
@@ -374,7 +499,7 @@ __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const Ce
 #pragma unroll
                 for (int t = 0; t < NCT; ++t) {
                     const int c = t * 16 + lc;
-                    pv[m][t][v] = bval(c) ? cell_source<T, MODE>(a, cd, ld, k, j, b0 + c) : z;
+                    pv[m][t][v] = bval(c) ? cell_source_ctx<T, MODE>(a, cd, ld, sc, k, j, b0 + c) : z;
                 }
             }
         if (k > 0) matmul(Xf + (long long)(k - 1) * np2);
@@ -442,6 +567,9 @@ template <typename T, int NB, int MODE, int MCMAX>
 __global__ void __launch_bounds__(CS_MF_THREADS) k_cs_mfma(CellSolveArgs<T> a) {
     extern __shared__ __align__(16) unsigned char cs_lds[];
     C2<T>* vs = reinterpret_cast<C2<T>*>(cs_lds);
+    const int hlp_max = (a.HLmax + 15) / 16 * 16;
+    double2* izs = reinterpret_cast<double2*>(cs_lds + (size_t)hlp_max * NB * sizeof(C2<T>));
+    double2* ixs = izs + hlp_max;
     const int gc = a.cell_list[blockIdx.x];
     const CellDesc cd = a.cells[gc];
     const LayerDesc& ld = a.layers[cd.layer];
@@ -452,9 +580,9 @@ __global__ void __launch_bounds__(CS_MF_THREADS) k_cs_mfma(CellSolveArgs<T> a) {
     // tiles w and w + 8 (HLp <= 224 gives at most 14 tiles)
     const int mc = RT > w ? (RT - w + CS_MF_WAVES - 1) / CS_MF_WAVES : 0;
     // every branch passes the same sequence of barriers
-    if (mc == 0) cs_mfma_body<T, NB, MODE, 0>(a, cd, ld, vs, b0);
-    else if (MCMAX == 1 || mc == 1) cs_mfma_body<T, NB, MODE, 1>(a, cd, ld, vs, b0);
-    else cs_mfma_body<T, NB, MODE, MCMAX>(a, cd, ld, vs, b0);
+    if (mc == 0) cs_mfma_body<T, NB, MODE, 0>(a, cd, ld, vs, izs, ixs, b0);
+    else if (MCMAX == 1 || mc == 1) cs_mfma_body<T, NB, MODE, 1>(a, cd, ld, vs, izs, ixs, b0);
+    else cs_mfma_body<T, NB, MODE, MCMAX>(a, cd, ld, vs, izs, ixs, b0);
 }
 
 template <typename T, int NB, int MODE, int MCMAX>
@@ -462,8 +590,7 @@ void launch_cs_mfma_mc(const CellSolveArgs<T>& a, dim3 grid, size_t lds, hipStre
     static bool attr = false;
     if (!attr) {
         hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cs_mfma<T, NB, MODE, MCMAX>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(CS_HLPMAX * NB * sizeof(C2<T>)));
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cs_mfma<T, NB, MODE, MCMAX>), grid, dim3(CS_MF_THREADS),
@@ -473,7 +600,8 @@ void launch_cs_mfma_mc(const CellSolveArgs<T>& a, dim3 grid, size_t lds, hipStre
 template <typename T, int NB, int MODE>
 void launch_cs_mfma(const CellSolveArgs<T>& a, dim3 grid, hipStream_t st) {
     const int hlp = (a.HLmax + 15) / 16 * 16;     // largest HLp of any cell
-    const size_t lds = (size_t)hlp * NB * sizeof(C2<T>);
+    // column block, then the row and column PML scalings
+    const size_t lds = (size_t)hlp * NB * sizeof(C2<T>) + (size_t)(hlp + a.Wcmax) * sizeof(double2);
     if (hlp <= 16 * CS_MF_WAVES) launch_cs_mfma_mc<T, NB, MODE, 1>(a, grid, lds, st);
     else launch_cs_mfma_mc<T, NB, MODE, 2>(a, grid, lds, st);
 }
