@@ -159,6 +159,9 @@ class Solver:
     # ------------------------------------------------------------------
     def factor(self):
         _check(lib().hz_factor(self.ctx), "hz_factor")
+        info = Info()
+        _check(lib().hz_get_info(self.ctx, ctypes.byref(info)), "hz_get_info")
+        self.info = info
 
     def update_model(self, model):
         self.model = model.to(device="cuda", dtype=self.torch.float64).contiguous()
