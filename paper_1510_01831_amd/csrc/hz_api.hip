@@ -108,6 +108,7 @@ struct LaunchRec {
     int ntasks, max_m;
     C2<T>* y; const C2<T>* x; double2 a, b; long long n;   // vector ops
     double bytes, flops;  // algorithmic traffic / work of a GEMM launch
+    int choice = -1;      // GEMM kernel picked by the autotuner (-1: default)
 };
 
 template <typename T>
@@ -185,6 +186,8 @@ struct hz_ctx {
     bool use_graphs = true;
     bool compose = true;           // output operators composed with the inner SIE inverse
     bool offline = false;          // inside the factorisation stage
+    bool tune = true;              // autotune GEMM kernels and cell-solve widths (HZ_TUNE=0: off)
+    std::map<std::string, int> cs_tuned;   // (mode, B, cells) -> cell-solve batch width
     Arena arena;
     std::vector<LayerDesc> layers;
     std::vector<CellDesc> cells;
@@ -654,6 +657,66 @@ void plan_upload(hz_ctx* c, Plan<T>& pl) {
 template <typename T>
 void plan_launches(hz_ctx* c, const Plan<T>& pl, int B);
 
+// Autotuner for the matrix-core GEMM launches of a solve plan.  Each launch is
+// timed with every candidate kernel on its own operator blocks, with the
+// input segments and outputs redirected to scratch buffers (plans that update
+// vectors in place are not disturbed), and the fastest kernel is kept in the
+// launch record.  Runs once, when the plan is built for a batch size.
+template <typename T>
+void tune_plan(hz_ctx* c, Plan<T>& pl, int B) {
+    if (!c->tune || B < 16 || pl.launches.empty()) return;
+    long long in_elems = 1, out_elems = 1;
+    int max_tasks = 1;
+    for (const auto& r : pl.launches) max_tasks = std::max(max_tasks, r.ntasks);
+    for (const auto& t : pl.tasks) {
+        for (int q = 0; q < t.nseg; ++q)
+            if (t.seg_ptr[q]) in_elems = std::max(in_elems, (long long)t.seg_len[q] * t.ldx);
+        for (int q = 0; q < t.noseg; ++q)
+            out_elems = std::max(out_elems, (long long)t.oseg_len[q] * t.ldo);
+    }
+    C2<T>* sin = alloc_c<T>(c, in_elems);
+    C2<T>* sout = alloc_c<T>(c, out_elems);
+    GemmTask<T>* dt = (GemmTask<T>*)c->arena.alloc(sizeof(GemmTask<T>) * max_tasks);
+    HIPCHK(hipMemsetAsync(sin, 0, sizeof(C2<T>) * in_elems, c->st));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    for (auto& r : pl.launches) {
+        if (r.kind != L_GEMM) continue;
+        if (gemm_kernel(r.ntasks, r.max_m, B) < GEMM_MFMA32) continue;
+        std::vector<GemmTask<T>> tt(pl.tasks.begin() + r.off, pl.tasks.begin() + r.off + r.ntasks);
+        for (auto& t : tt) {
+            for (int q = 0; q < t.nseg; ++q)
+                if (t.seg_ptr[q]) t.seg_ptr[q] = sin;
+            for (int q = 0; q < t.noseg; ++q) {
+                t.oseg_ptr[q] = sout;
+                t.oseg_add0[q] = nullptr;
+                t.oseg_add1[q] = nullptr;
+            }
+        }
+        upload(c, dt, tt.data(), sizeof(GemmTask<T>) * tt.size());
+        float best = 1e30f;
+        for (int cand : {(int)GEMM_MFMA64, (int)GEMM_MFMA32, (int)GEMM_MFMA32K16}) {
+            if (cand == GEMM_MFMA64 && B < 64) continue;
+            launch_gemm<T>(dt, r.ntasks, r.max_m, B, c->st, false, cand);     // warm-up
+            HIPCHK(hipEventRecord(e0, c->st));
+            for (int rep = 0; rep < 3; ++rep)
+                launch_gemm<T>(dt, r.ntasks, r.max_m, B, c->st, false, cand);
+            HIPCHK(hipEventRecord(e1, c->st));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) { best = ms; r.choice = cand; }
+        }
+    }
+    HIPCHK(hipGetLastError());
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->arena.release(sin, 0);
+    c->arena.release(sout, 0);
+    c->arena.release(dt, 0);
+}
+
 // Replay a plan: through its captured HIP graph when graphs are enabled and
 // profiling is off, launch by launch (one event pair per kernel) otherwise.
 template <typename T>
@@ -679,10 +742,12 @@ void plan_launches(hz_ctx* c, const Plan<T>& pl, int B) {
     for (const auto& r : pl.launches) {
         if (r.kind == L_GEMM) {
             size_t e0 = prof ? prof_event(c) : 0;
-            launch_gemm<T>(pl.dev + r.off, r.ntasks, r.max_m, B, c->st, c->offline);
+            launch_gemm<T>(pl.dev + r.off, r.ntasks, r.max_m, B, c->st, c->offline, r.choice);
             if (prof) {
                 size_t e1 = prof_event(c);
-                const char* k = gemm_kernel_name(gemm_kernel(r.ntasks, r.max_m, B));
+                const GemmKernel kk = gemm_kernel(r.ntasks, r.max_m, B);
+                const char* k = gemm_kernel_name(r.choice >= 0 && kk >= GEMM_MFMA32
+                                                     ? (GemmKernel)r.choice : kk);
                 c->prof.pend.push_back({fam_name<T>(k), e0, e1, r.bytes, r.flops});
             }
         } else if (r.kind == L_AXPBY) {
@@ -820,6 +885,7 @@ Plan<T>& get_plan(hz_ctx* c, bool sie, int B) {
     pl->name = fam_name<T>(sie ? "sie_graph" : "precond_graph");
     if (sie) build_sie_plan<T>(c, *pl, B);
     else build_pre_plan<T>(c, *pl, B);
+    tune_plan<T>(c, *pl, B);
     plan_upload<T>(c, *pl);
     Plan<T>& ref = *pl;
     mp[B] = std::move(pl);
@@ -929,13 +995,7 @@ void ensure_gmres(hz_ctx* c, int B, int m) {
 
 template <typename T>
 void cell_solve_launch(hz_ctx* c, CellSolveArgs<T> a, const std::vector<int>& list, int Bcols) {
-    // groups limited by the scratch available
     Work<T>& w = work<T>(c);
-    const int nb = cs_nb(Bcols, (int)list.size(), c->d.HLpmax);
-    const int chunks = (Bcols + nb - 1) / nb;
-    const long long wg_elems = (long long)c->d.Wcmax * c->d.HLpmax * nb;
-    const int per = (int)std::max<long long>(1, (w.y_stride * w.y_wgs / wg_elems) / chunks);
-    a.nb = nb;
     // a contiguous run of cells is a slice of the all-cells table; other
     // lists go to the persistent list buffer (no allocation per solve)
     bool contiguous = true;
@@ -945,32 +1005,74 @@ void cell_solve_launch(hz_ctx* c, CellSolveArgs<T> a, const std::vector<int>& li
         upload(c, c->d_cell_list, list.data(), sizeof(int) * list.size());
         d_list = c->d_cell_list;
     }
-    const bool prof = c->prof.on;
-    for (size_t g = 0; g < list.size(); g += per) {
-        const int cnt = (int)std::min<size_t>(per, list.size() - g);
-        a.cell_list = d_list + g;
-        a.B = Bcols;
-        a.Y = w.Y;
-        a.y_stride = wg_elems;
-        size_t e0 = prof ? prof_event(c) : 0;
-        launch_cell_solve<T>(a, cnt, chunks, c->st);
-        HIPCHK(hipGetLastError());
-        if (prof) {
-            size_t e1 = prof_event(c);
-            double bytes = 0, flops = 0;
-            for (int q = 0; q < cnt; ++q) {
-                const CellDesc& cd = c->cells[list[g + q]];
-                const double blk = (double)cd.Wc * cd.HL * cd.HL;
-                // factors read in both sweeps, forward iterates written and
-                // read back, one source and one result per grid node
-                bytes += sizeof(C2<T>) * (2.0 * blk + 4.0 * (double)cd.Wc * cd.HL * Bcols);
-                flops += 8.0 * (2.0 * cd.Wc - 1.0) * cd.HL * cd.HL * Bcols;
+    // all cells of the list with nb batch columns per workgroup, in groups
+    // limited by the scratch available
+    auto run = [&](int nb, bool prof) {
+        const int chunks = (Bcols + nb - 1) / nb;
+        const long long wg_elems = (long long)c->d.Wcmax * c->d.HLpmax * nb;
+        const int per = (int)std::max<long long>(1, (w.y_stride * w.y_wgs / wg_elems) / chunks);
+        a.nb = nb;
+        for (size_t g = 0; g < list.size(); g += per) {
+            const int cnt = (int)std::min<size_t>(per, list.size() - g);
+            a.cell_list = d_list + g;
+            a.B = Bcols;
+            a.Y = w.Y;
+            a.y_stride = wg_elems;
+            size_t e0 = prof ? prof_event(c) : 0;
+            launch_cell_solve<T>(a, cnt, chunks, c->st);
+            HIPCHK(hipGetLastError());
+            if (prof) {
+                size_t e1 = prof_event(c);
+                double bytes = 0, flops = 0;
+                for (int q = 0; q < cnt; ++q) {
+                    const CellDesc& cd = c->cells[list[g + q]];
+                    const double blk = (double)cd.Wc * cd.HL * cd.HL;
+                    // factors read in both sweeps, forward iterates written and
+                    // read back, one source and one result per grid node
+                    bytes += sizeof(C2<T>) * (2.0 * blk + 4.0 * (double)cd.Wc * cd.HL * Bcols);
+                    flops += 8.0 * (2.0 * cd.Wc - 1.0) * cd.HL * cd.HL * Bcols;
+                }
+                const char* fam = a.mode == SOLVE_VOLUME ? "cell_solve_volume"
+                                  : a.mode == SOLVE_SAMPLE ? "cell_solve_sample" : "cell_solve_other";
+                c->prof.pend.push_back({fam_name<T>(fam), e0, e1, bytes, flops});
             }
-            const char* fam = a.mode == SOLVE_VOLUME ? "cell_solve_volume"
-                              : a.mode == SOLVE_SAMPLE ? "cell_solve_sample" : "cell_solve_other";
-            c->prof.pend.push_back({fam_name<T>(fam), e0, e1, bytes, flops});
+        }
+    };
+    int nb = cs_nb(Bcols, (int)list.size(), c->d.HLpmax);
+    // Autotune the batch width once per (mode, batch, cells): both widths give
+    // the same results column by column, so the solve itself is timed with
+    // each and the last run's output is kept.
+    const bool tunable = c->tune && Bcols > 16 && c->d.HLpmax <= 128 && !std::getenv("HZ_CELL_NB") &&
+                         (a.mode == SOLVE_SAMPLE || a.mode == SOLVE_VOLUME);
+    if (tunable) {
+        const std::string key = std::to_string(a.mode) + "|" + std::to_string(Bcols) + "|" +
+                                std::to_string(list.size()) + "|" + std::to_string(sizeof(T));
+        auto it = c->cs_tuned.find(key);
+        if (it != c->cs_tuned.end()) {
+            nb = it->second;
+        } else {
+            hipEvent_t e0, e1;
+            HIPCHK(hipEventCreate(&e0));
+            HIPCHK(hipEventCreate(&e1));
+            float best = 1e30f;
+            int best_nb = nb;
+            for (int cand : {32, 16}) {
+                HIPCHK(hipEventRecord(e0, c->st));
+                run(cand, false);
+                HIPCHK(hipEventRecord(e1, c->st));
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) { best = ms; best_nb = cand; }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            c->cs_tuned[key] = best_nb;
+            if (best_nb == 16) return;           // the last run already wrote the result
+            nb = best_nb;
         }
     }
+    run(nb, c->prof.on);
 }
 
 template <typename T>
@@ -1359,6 +1461,7 @@ void run_jobs_cached(hz_ctx* c, const std::string& key, const std::vector<LayerJ
         pl->name = fam_name<T>("jobs_graph");
         plan_jobs<T>(c, *pl, jobs, B);
         plan_upload<T>(c, *pl);
+        tune_plan<T>(c, *pl, B);
         it = w.jobs.emplace(key, std::move(pl)).first;
     }
     plan_run<T>(c, *it->second, B);
@@ -1923,6 +2026,7 @@ hz_status hz_setup(const double* model_dev, const hz_params* prm, hz_ctx** out) 
     c->prm = *prm;
     if (const char* g = std::getenv("HZ_GRAPHS")) c->use_graphs = std::atoi(g) != 0;
     if (const char* g = std::getenv("HZ_COMPOSE")) c->compose = std::atoi(g) != 0;
+    if (const char* g = std::getenv("HZ_TUNE")) c->tune = std::atoi(g) != 0;
     if (c->prm.pml_beta <= 0.0) c->prm.pml_beta = 2.0;
     if (c->prm.max_batch <= 0) c->prm.max_batch = 1;
     Dims& d = c->d;

@@ -204,13 +204,17 @@ void launch_cell_solve(const CellSolveArgs<T>& a, int ncells_launch, int nb_chun
                        hipStream_t st);
 
 // B = number of batch columns; ldx/ldo come from the tasks.
-// offline = launch from the factorisation stage (separate kernel instance)
+// offline = launch from the factorisation stage (separate kernel instance);
+// kind_choice = a matrix-core variant picked by the autotuner (-1: default)
 template <typename T>
 void launch_gemm(const GemmTask<T>* tasks_dev, int ntasks, int max_m, int B, hipStream_t st,
-                 bool offline = false);
+                 bool offline = false, int kind_choice = -1);
 
-// the GEMM kernel launch_gemm selects for a shape (for per-kernel profiles)
-enum GemmKernel { GEMM_GEMV = 0, GEMM_TILED = 1, GEMM_MFMA32 = 2, GEMM_MFMA64 = 3 };
+// the GEMM kernel launch_gemm selects for a shape (for per-kernel profiles);
+// the matrix-core variants are 64x64 tiles / 16-deep chunks, 32x32 / 32-deep
+// and 32x32 / 16-deep
+enum GemmKernel { GEMM_GEMV = 0, GEMM_TILED = 1, GEMM_MFMA32 = 2, GEMM_MFMA64 = 3,
+                  GEMM_MFMA32K16 = 4 };
 GemmKernel gemm_kernel(int ntasks, int max_m, int B);
 const char* gemm_kernel_name(GemmKernel k);
 

@@ -288,6 +288,7 @@ const char* gemm_kernel_name(GemmKernel k) {
     case GEMM_GEMV: return "gemv";
     case GEMM_TILED: return "gemm_tiled";
     case GEMM_MFMA64: return "gemm_mfma64";
+    case GEMM_MFMA32K16: return "gemm_mfma32k16";
     default: return "gemm_mfma32";
     }
 }
@@ -301,6 +302,10 @@ void launch_gemm_mfma(GemmKernel kind, const GemmTask<T>* tasks_dev, int ntasks,
         const int rt = (max_m + 63) / 64, ct = (B + 63) / 64;
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 64, 64, 16, OFFLINE>),
                            dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct);
+    } else if (kind == GEMM_MFMA32K16) {
+        const int rt = (max_m + 31) / 32, ct = (B + 31) / 32;
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 16, OFFLINE>),
+                           dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct);
     } else {
         const int rt = (max_m + 31) / 32, ct = (B + 31) / 32;
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 32, OFFLINE>),
@@ -310,9 +315,10 @@ void launch_gemm_mfma(GemmKernel kind, const GemmTask<T>* tasks_dev, int ntasks,
 
 template <typename T>
 void launch_gemm(const GemmTask<T>* tasks_dev, int ntasks, int max_m, int B, hipStream_t st,
-                 bool offline) {
+                 bool offline, int kind_choice) {
     if (ntasks <= 0 || max_m <= 0) return;
-    const GemmKernel kind = gemm_kernel(ntasks, max_m, B);
+    GemmKernel kind = gemm_kernel(ntasks, max_m, B);
+    if (kind_choice >= GEMM_MFMA32 && kind >= GEMM_MFMA32) kind = (GemmKernel)kind_choice;
     if (kind == GEMM_GEMV) {
         dim3 grid((max_m + GV_ROWS - 1) / GV_ROWS, 1, ntasks);
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemv<T>), grid, dim3(GV_THREADS), 0, st, tasks_dev);
@@ -327,7 +333,7 @@ void launch_gemm(const GemmTask<T>* tasks_dev, int ntasks, int max_m, int B, hip
     }
 }
 
-template void launch_gemm<double>(const GemmTask<double>*, int, int, int, hipStream_t, bool);
-template void launch_gemm<float>(const GemmTask<float>*, int, int, int, hipStream_t, bool);
+template void launch_gemm<double>(const GemmTask<double>*, int, int, int, hipStream_t, bool, int);
+template void launch_gemm<float>(const GemmTask<float>*, int, int, int, hipStream_t, bool, int);
 
 }  // namespace hz

@@ -168,6 +168,32 @@ def test_volume_residual_statistic(setup):
         assert abs(got - ref) <= 1e-2 * ref + 1e-15
 
 
+def test_autotuned_kernels_same_solution(monkeypatch):
+    """Solves with the autotuner on (GEMM kernels and cell-solve widths timed
+    and picked per launch) and off (fixed heuristic) agree to rounding, and
+    both match the oracle."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c, omega = media.small_problem(N, P, L, LC, seed=5)
+    prob = Problem(c, omega, P)
+    xs = tuple(range(2, 42, 2))                       # 20 sources: matrix-core paths
+    f = media.point_sources(N, xs, 17)
+    out = {}
+    for flag in ("0", "1"):
+        monkeypatch.setenv("HZ_TUNE", flag)
+        _log(f"[tune={flag}] B={len(xs)}")
+        s = hz.Solver(torch.from_numpy(c), omega, P, L, LC, max_batch=len(xs))
+        out[flag] = s.solve(torch.from_numpy(f), tol=1e-12).cpu().numpy()
+        out[flag + "b"] = s.solve(torch.from_numpy(f), tol=1e-12).cpu().numpy()   # tuned plans reused
+        s.close()
+    assert _rel(out["1"], out["0"]) < 1e-11
+    assert _rel(out["1b"], out["1"]) < 1e-13
+    lu = spla.splu(prob.H.tocsc())
+    for bb in (0, 9, 19):
+        ref = prob.restrict(lu.solve(prob.extend(f[bb]).ravel()).reshape(prob.W, prob.W))
+        assert _rel(out["1"][bb], ref) < 1e-9
+
+
 def test_single_layer_and_cell_counts():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
