@@ -1615,7 +1615,7 @@ void givens(std::complex<double> a, std::complex<double> b, double& cs, std::com
 // dots h[v][b] = V_v^H w for v < nv (device -> host)
 void dots(hz_ctx* c, const double2* V, long long vstride, int nv, const double2* w, long long n,
           int B, std::vector<std::complex<double>>& out) {
-    const int chunks = (int)std::min<long long>(c->gpart_chunks, std::max<long long>(1, n / 256));
+    const int chunks = (int)std::min<long long>(c->gpart_chunks, std::max<long long>(1, n / 32));
     launch_dots(V, vstride, nv, w, n, B, c->gpart, chunks, c->st);
     launch_reduce_partials(c->gpart, chunks, nv * B, c->gsmall, c->st);
     out.resize((size_t)nv * B);
@@ -1626,7 +1626,7 @@ void dots(hz_ctx* c, const double2* V, long long vstride, int nv, const double2*
 // the same reductions left on the device: out_dev[v * B + b]
 void dots_dev(hz_ctx* c, const double2* V, long long vstride, int nv, const double2* w,
               long long n, int B, double2* out_dev) {
-    const int chunks = (int)std::min<long long>(c->gpart_chunks, std::max<long long>(1, n / 256));
+    const int chunks = (int)std::min<long long>(c->gpart_chunks, std::max<long long>(1, n / 32));
     launch_dots(V, vstride, nv, w, n, B, c->gpart, chunks, c->st);
     launch_reduce_partials(c->gpart, chunks, nv * B, out_dev, c->st);
 }

@@ -243,20 +243,33 @@ void launch_norms(const double2* w, long long n, int B, double2* partial, int nc
                        B, partial, nchunks);
 }
 
-__global__ void k_reduce_partials(const double2* partial, int nchunks, int count, double2* out) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= count) return;
+// out[q] = sum_c partial[c * count + q]: one workgroup per output entry, a
+// strided pass over the chunks and a tree in LDS (fixed order: deterministic)
+__global__ void __launch_bounds__(RD_THREADS)
+k_reduce_partials(const double2* partial, int nchunks, int count, double2* out) {
+    __shared__ double2 red[RD_THREADS];
+    const int q = blockIdx.x;
     double2 s = make_double2(0.0, 0.0);
-    for (int c = 0; c < nchunks; ++c) {
-        double2 v = partial[(long long)c * count + q];
+    for (int c = threadIdx.x; c < nchunks; c += RD_THREADS) {
+        const double2 v = partial[(long long)c * count + q];
         s.x += v.x; s.y += v.y;
     }
-    out[q] = s;
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = RD_THREADS / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            red[threadIdx.x].x += red[threadIdx.x + h].x;
+            red[threadIdx.x].y += red[threadIdx.x + h].y;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[q] = red[0];
 }
 void launch_reduce_partials(const double2* partial, int nchunks, int count, double2* out,
                             hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_partials, dim3((count + 255) / 256), dim3(256), 0, st, partial,
-                       nchunks, count, out);
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_reduce_partials, dim3(count), dim3(RD_THREADS), 0, st, partial, nchunks,
+                       count, out);
 }
 
 // w[i,b] += sgn * sum_v coef[v,b] V_v[i,b]
