@@ -1710,6 +1710,10 @@ void gmres(hz_ctx* c, const double2* b, double2* x, int B, double tol, int maxit
         dots_dev(c, V, vs, j + 1, c->gw, n, B, hB);
         launch_update_basis(c->gw, V, vs, j + 1, hB, n, B, c->st, -1.0);
         dots_dev(c, nullptr, 0, 1, c->gw, n, B, hN);
+        // next basis vector scaled on the device (columns that have converged
+        // keep being normalised; their coefficients beyond convergence are 0)
+        launch_inv_norms(hN, c->gcoef, B, c->st);
+        launch_scale_cols(Vn, c->gw, c->gcoef, n, B, c->st);
         std::vector<double2> hh(2 * nh + B);
         HIPCHK(hipMemcpyAsync(hh.data(), c->gh, sizeof(double2) * hh.size(), hipMemcpyDeviceToHost,
                               c->st));
@@ -1720,7 +1724,6 @@ void gmres(hz_ctx* c, const double2* b, double2* x, int B, double tol, int maxit
         nrm.resize(B);
         for (int bb = 0; bb < B; ++bb) nrm[bb] = std::sqrt(std::max(0.0, hh[2 * nh + bb].x));
         for (int bb = 0; bb < B; ++bb) {
-            sc[bb] = make_double2(0.0, 0.0);
             if (done[bb]) continue;
             auto& H = Hm[bb];
             auto Hat = [&](int r, int col) -> std::complex<double>& { return H[(size_t)r * maxit + col]; };
@@ -1740,10 +1743,7 @@ void gmres(hz_ctx* c, const double2* b, double2* x, int B, double tol, int maxit
             kfin[bb] = j + 1;
             relres[bb] = std::abs(g[bb][j + 1]) / beta[bb];
             if (relres[bb] <= tol || nrm[bb] == 0.0) done[bb] = 1;
-            else sc[bb] = make_double2(1.0 / nrm[bb], 0.0);
         }
-        upload(c, c->gcoef, sc.data(), sizeof(double2) * B);
-        launch_scale_cols(Vn, c->gw, c->gcoef, n, B, c->st);
     }
     // x = V y
     const int kmax = *std::max_element(kfin.begin(), kfin.end());

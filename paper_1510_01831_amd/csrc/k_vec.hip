@@ -272,6 +272,16 @@ void launch_reduce_partials(const double2* partial, int nchunks, int count, doub
                        count, out);
 }
 
+// s[b] = 1 / sqrt(n2[b].x) (0 for a zero norm): column scales for GMRES from
+// the squared norms left on the device
+__global__ void k_inv_norms(const double2* n2, double2* s, int B) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B) s[b] = make_double2(n2[b].x > 0.0 ? 1.0 / sqrt(n2[b].x) : 0.0, 0.0);
+}
+void launch_inv_norms(const double2* n2, double2* s, int B, hipStream_t st) {
+    hipLaunchKernelGGL(k_inv_norms, dim3((B + 255) / 256), dim3(256), 0, st, n2, s, B);
+}
+
 // w[i,b] += sgn * sum_v coef[v,b] V_v[i,b]
 __global__ void k_update_basis(double2* w, const double2* V, long long vstride, int nv,
                                const double2* coef, long long n, int B, double sgn) {
