@@ -32,11 +32,23 @@
  *    tensors); *_host are host pointers.  The caller owns every pointer it
  *    passes; the library copies what it keeps.  The context owns all device
  *    memory it allocates and frees it in hz_destroy.
- *  - All device work is enqueued on the context's stream (default: the null
- *    stream, see hz_set_stream).  Every call returns only after its work has
+ *  - All device work is enqueued on the context's stream (default: a stream
+ *    of default priority that hz_setup creates, blocking with respect to the
+ *    null stream; see hz_set_stream).  Every call returns only after its work has
  *    completed on that stream, unless stated otherwise.
  *  - No call throws across the ABI.  Errors are returned as hz_status; the
  *    text of the last error of the calling thread is in hz_last_error().
+ *  - Environment (read by hz_setup / per launch; for experiments, results do
+ *    not depend on them beyond rounding):
+ *      HZ_TUNE=0     fixed kernel heuristics instead of the autotuner (which
+ *                    times the GEMM kernels of every solve plan and the
+ *                    cell-solve batch width once per batch size);
+ *      HZ_COMPOSE=0  inner SIE solved by block LU substitutions at every layer
+ *                    application instead of the composed output operators;
+ *      HZ_GRAPHS=0   plans launched kernel by kernel instead of replayed HIP
+ *                    graphs;
+ *      HZ_CELL_NB=w  force w right-hand sides per cell-solve workgroup
+ *                    (1, 2, 4, 16 or 32).
  */
 #ifndef HZ_H
 #define HZ_H
@@ -182,7 +194,8 @@ hz_status hz_misfit(hz_ctx* ctx, const void* u_ext_dev, const void* d_obs_dev, i
 hz_status hz_update_model(hz_ctx* ctx, const double* model_dev);
 
 /* Enqueue all further work of ctx on `hip_stream` (a hipStream_t, or NULL for
- * the null stream). */
+ * the null stream).  Waits for the work already enqueued; captured plans are
+ * rebuilt for the new stream. */
 hz_status hz_set_stream(hz_ctx* ctx, void* hip_stream);
 
 /* Kernel timing for roofline measurements.  While profiling is on, every

@@ -589,8 +589,10 @@ template <typename T, int NB, int MODE, int MCMAX>
 void launch_cs_mfma_mc(const CellSolveArgs<T>& a, dim3 grid, size_t lds, hipStream_t st) {
     static bool attr = false;
     if (!attr) {
-        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cs_mfma<T, NB, MODE, MCMAX>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        // if the device refuses, a launch needing more LDS fails and is reported
+        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cs_mfma<T, NB, MODE, MCMAX>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
+            (void)hipGetLastError();
         attr = true;
     }
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cs_mfma<T, NB, MODE, MCMAX>), grid, dim3(CS_MF_THREADS),

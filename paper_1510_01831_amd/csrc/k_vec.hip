@@ -257,7 +257,7 @@ k_reduce_partials(const double2* partial, int nchunks, int count, double2* out) 
     red[threadIdx.x] = s;
     __syncthreads();
     for (int h = RD_THREADS / 2; h > 0; h >>= 1) {
-        if (threadIdx.x < h) {
+        if ((int)threadIdx.x < h) {
             red[threadIdx.x].x += red[threadIdx.x + h].x;
             red[threadIdx.x].y += red[threadIdx.x + h].y;
         }
@@ -543,7 +543,7 @@ __global__ void k_misfit(const double2* u, const double2* d, int rec_row, int B,
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
     if (threadIdx.x == 0) Jpart[blockIdx.x] = red[0];
