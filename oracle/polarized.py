@@ -35,6 +35,7 @@ import numpy as np
 import scipy.sparse.linalg as spla
 
 from .discretization import LayerGrid, Problem, partition
+from .bicgstab import bicgstab
 from .gmres import gmres
 
 
@@ -240,15 +241,20 @@ class LayeredSolver:
         return u
 
     def solve(self, f_ext: np.ndarray, tol: float = 1e-10, maxit: int = 200,
-              precond: str = "gs"):
-        """Alg. 6 for one right-hand side on the extended grid."""
+              precond: str = "gs", krylov: str = "gmres"):
+        """Alg. 6 for one right-hand side on the extended grid; the polarized
+        system is solved by left-preconditioned GMRES or right-preconditioned
+        Bi-CGstab with P^GS or P^Jac (the combinations of Table 3)."""
         if self.L == 1:
             return self.solvers[0].solve(self.restrict_source(0, f_ext)), {"iters": 0}
         fd, fq = self.rhs(f_ext)
         P = self.precond_gs if precond == "gs" else self.precond_jacobi
         A = lambda v: self.pack(*self.apply_M(*self.unpack(v)))
         Pv = lambda v: self.pack(*P(*self.unpack(v)))
-        x, info = gmres(A, self.pack(fd, fq), Pv, tol=tol, maxit=maxit)
+        if krylov == "bicgstab":
+            x, info = bicgstab(A, self.pack(fd, fq), Pv, tol=tol, maxit=maxit)
+        else:
+            x, info = gmres(A, self.pack(fd, fq), Pv, tol=tol, maxit=maxit)
         d, q = self.unpack(x)
         s = d + q
         info["traces"] = s

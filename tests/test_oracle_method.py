@@ -5,6 +5,7 @@ import pytest
 import scipy.sparse.linalg as spla
 
 from oracle.discretization import Problem
+from oracle.bicgstab import bicgstab
 from oracle.gmres import gmres
 from oracle.nested import NestedLayerSolver
 from oracle.polarized import DirectLayerSolver, LayeredSolver
@@ -166,6 +167,66 @@ def test_gmres_matches_dense_solve():
     # the recorded residual is the true preconditioned residual
     k = info["iters"]
     assert abs(np.linalg.norm(P @ (b - A @ x)) / np.linalg.norm(P @ b) - info["history"][k]) < 1e-10
+
+
+def test_jacobi_is_block_diagonal_inverse(dense_polarized):
+    """P^Jac = inverse of diag(D_down, D_up) (eq. preconditioner_Jac), against
+    the dense blocks of the assembled polarized matrix."""
+    prob, f, u, S, M = dense_polarized
+    K, W = S.L - 1, S.W
+    half = K * 2 * W
+    rng = np.random.default_rng(3)
+    vd = rng.standard_normal((K, 2, W)) + 1j * rng.standard_normal((K, 2, W))
+    vq = rng.standard_normal((K, 2, W)) + 1j * rng.standard_normal((K, 2, W))
+    Dd, Du = M[:half, :half], M[half:, half:]
+    xd, xq = S.precond_jacobi(vd, vq)
+    assert np.abs(xd.ravel() - np.linalg.solve(Dd, vd.ravel())).max() < 1e-10
+    assert np.abs(xq.ravel() - np.linalg.solve(Du, vq.ravel())).max() < 1e-10
+
+
+def test_bicgstab_matches_dense_solve():
+    """Right-preconditioned Bi-CGstab reaches the dense solution, and the
+    residual it reports is the true unpreconditioned one."""
+    rng = np.random.default_rng(8)
+    n = 40
+    A = np.eye(n) * 4 + rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    P = np.linalg.inv(A + 0.3 * rng.standard_normal((n, n)))
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    xr = np.linalg.solve(A, b)
+    for prec in (lambda v: P @ v, None):
+        x, info = bicgstab(lambda v: A @ v, b, prec, tol=1e-12, maxit=200)
+        assert info["converged"] and not info["breakdown"]
+        assert np.abs(x - xr).max() < 1e-9 * np.abs(xr).max()
+        true = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+        assert true <= 1e-11
+        assert abs(true - info["history"][-1]) < 1e-12
+
+
+def test_bicgstab_dd_matches_global_direct():
+    prob, f, u = _setup(n=47, p=8, L=4, src=((24,), 9))
+    S = LayeredSolver(prob, 4, 2)
+    for pre in ("gs", "jacobi"):
+        ud, info = S.solve(f, tol=1e-11, precond=pre, krylov="bicgstab")
+        assert info["converged"]
+        assert np.linalg.norm(ud - u) / np.linalg.norm(u) < 1e-9
+
+
+def test_table3_iteration_pattern():
+    """Soft check of Table 3's qualitative findings on a synthetic medium:
+    with either Krylov method P^GS needs fewer iterations than P^Jac, and
+    Bi-CGstab (two applications per iteration) needs fewer iterations than
+    GMRES."""
+    prob, f, u = _setup(n=63, p=10, L=6, src=((32,), 8))
+    S = LayeredSolver(prob, 6)
+    it = {}
+    for kr in ("gmres", "bicgstab"):
+        for pre in ("gs", "jacobi"):
+            _, info = S.solve(f, tol=1e-7, precond=pre, krylov=kr)
+            assert info["converged"]
+            it[kr, pre] = info["iters"]
+    assert it["gmres", "gs"] < it["gmres", "jacobi"]
+    assert it["bicgstab", "gs"] < it["bicgstab", "jacobi"]
+    assert it["bicgstab", "gs"] <= it["gmres", "gs"]
 
 
 @pytest.mark.parametrize("cells", [1, 2, 3])
