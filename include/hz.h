@@ -88,6 +88,21 @@ typedef enum {
     HZ_MODEL_SLOWNESS2 = 1   /* model array holds m = 1/c^2 */
 } hz_model_kind;
 
+typedef enum {
+    HZ_PRECOND_GS = 0,       /* block Gauss-Seidel, eq. preconditioner_GS: downward sweep,
+                                up-going reflections, upward sweep (Algs. 3-5) */
+    HZ_PRECOND_JACOBI = 1    /* block Jacobi, eq. preconditioner_Jac: the two sweeps
+                                without the reflections */
+} hz_precond;
+
+typedef enum {
+    HZ_KRYLOV_GMRES = 0,     /* GMRES (Alg. 6): left-preconditioned in HZ_FP64, flexible
+                                right-preconditioned in HZ_MIXED */
+    HZ_KRYLOV_BICGSTAB = 1   /* right-preconditioned Bi-CGstab (Sec. 5, Table 3): two
+                                applications of M and P per iteration, stopping on the
+                                unpreconditioned SIE residual */
+} hz_krylov;
+
 typedef struct {
     int n_x, n_z;            /* physical nodes per side (must be equal) */
     double h;                /* grid step; must equal 1/(n+1) (unit square) */
@@ -99,6 +114,8 @@ typedef struct {
     hz_precision precision;
     hz_model_kind model_kind;
     int max_batch;           /* largest B accepted by hz_solve; <= 0 -> 1 */
+    hz_precond precond;      /* preconditioner of the polarized SIE (0: Gauss-Seidel) */
+    hz_krylov krylov;        /* Krylov method for the polarized SIE (0: GMRES) */
 } hz_params;
 
 typedef struct {

@@ -839,7 +839,11 @@ void build_pre_plan(hz_ctx* c, Plan<T>& pl, int B) {
         jb.alpha = (T)1;
         plan_jobs<T>(c, pl, {jb}, B);
     }
-    {                                                   // t = v_up - L x_down (parallel)
+    if (c->prm.precond == HZ_PRECOND_JACOBI) {          // P^Jac: no reflections, t = v_up
+        const double2 zero2 = make_double2(0.0, 0.0);
+        add_vec<T>(pl, L_COPY, qvec<T>(c, w.pC, 0, B), qvec<T>(c, w.pB, 0, B), zero2, zero2,
+                   K * pairn);
+    } else {                                            // t = v_up - L x_down (parallel)
         std::vector<LayerJob<T>> jobs;
         for (int k = 0; k < K; ++k) {
             LayerJob<T> jb;
@@ -1638,6 +1642,25 @@ void norms(hz_ctx* c, const double2* w, long long n, int B, std::vector<double>&
     for (int b = 0; b < B; ++b) out[b] = std::sqrt(std::max(0.0, t[b].real()));
 }
 
+// M on FP64 vectors with the operators of precision T
+template <typename T>
+void apply_M(hz_ctx* c, const double2* x, double2* y, int B) {
+    Work<T>& w = work<T>(c);
+    const long long n = 4LL * c->d.K * c->d.W * B;
+    Plan<T>& ps = get_plan<T>(c, true, B);
+    if constexpr (sizeof(T) == sizeof(double)) {
+        HIPCHK(hipMemcpyAsync(w.pA, x, sizeof(double2) * n, hipMemcpyDeviceToDevice, c->st));
+    } else {
+        launch_cast_d2f((float2*)w.pA, x, n, c->st);
+    }
+    plan_run<T>(c, ps, B);
+    if constexpr (sizeof(T) == sizeof(double)) {
+        HIPCHK(hipMemcpyAsync(y, w.pB, sizeof(double2) * n, hipMemcpyDeviceToDevice, c->st));
+    } else {
+        launch_cast_f2d(y, (const float2*)w.pB, n, c->st);
+    }
+}
+
 // M on FP64 vectors with the FP64 operators
 void apply_M64(hz_ctx* c, const double2* x, double2* y, int B) {
     Work<double>& w = c->w64;
@@ -1769,6 +1792,160 @@ void gmres(hz_ctx* c, const double2* b, double2* x, int B, double tol, int maxit
 }
 
 // One DD solve of H u = f with f already in work<T>.f_ext; result in work<T>.u_ext.
+// Right-preconditioned Bi-CGstab (van der Vorst) on FP64 vectors, x0 = 0,
+// shadow residual r0 = b: per iteration two applications of P and of M and
+// three host reads of per-column scalars; stops per column on the
+// unpreconditioned residual ||b - M x|| <= tol ||b|| (at the half step s or
+// the full step r).  Columns that have stopped keep x and r fixed (zero
+// coefficients).  P is complex64 when flex (the mixed form) or T = float,
+// M is complex128 unless T = float.
+template <typename T>
+void bicgstab(hz_ctx* c, const double2* b, double2* x, int B, double tol, int maxit,
+              std::vector<int>& iters, std::vector<double>& relres, bool flex = false) {
+    const long long n = 4LL * c->d.K * c->d.W;
+    const long long nB = n * B;
+    ensure_gmres(c, B, std::max(maxit, 8));
+    // workspace in the Krylov basis buffer: rhat, r (adjacent), p, v, s, t (adjacent), y, z
+    double2* rhat = c->V;
+    double2* r = c->V + nB;
+    double2* p = c->V + 2 * nB;
+    double2* v = c->V + 3 * nB;
+    double2* sv = c->V + 4 * nB;
+    double2* t = c->V + 5 * nB;
+    double2* y = c->V + 6 * nB;
+    double2* z = c->V + 7 * nB;
+    auto P = [&](const double2* in, double2* out) {
+        if (flex || sizeof(T) == sizeof(float)) apply_P<float>(c, in, out, B);
+        else apply_P<double>(c, in, out, B);
+    };
+    auto M = [&](const double2* in, double2* out) {
+        if (sizeof(T) == sizeof(float)) apply_M<float>(c, in, out, B);
+        else apply_M<double>(c, in, out, B);
+    };
+    std::vector<double2> hv(3 * (size_t)B), cf(3 * (size_t)B);
+    auto read = [&](int count) {       // c->gh[0 .. count*B) -> hv
+        HIPCHK(hipMemcpyAsync(hv.data(), c->gh, sizeof(double2) * count * B,
+                              hipMemcpyDeviceToHost, c->st));
+        sync(c);
+    };
+    auto coefs = [&]() {               // cf -> c->gcoef (3 per column: [j][b])
+        HIPCHK(hipMemcpyAsync(c->gcoef, cf.data(), sizeof(double2) * 3 * B,
+                              hipMemcpyHostToDevice, c->st));
+    };
+    using cd = std::complex<double>;
+    auto cx = [](double2 a) { return cd(a.x, a.y); };
+    auto d2 = [](cd a) { return make_double2(a.real(), a.imag()); };
+    // r = rhat = b, x = p = v = 0
+    HIPCHK(hipMemcpyAsync(r, b, sizeof(double2) * nB, hipMemcpyDeviceToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(rhat, b, sizeof(double2) * nB, hipMemcpyDeviceToDevice, c->st));
+    launch_fill_zero(x, nB, c->st);
+    launch_fill_zero(p, nB, c->st);
+    launch_fill_zero(v, nB, c->st);
+    dots_dev(c, nullptr, 0, 1, b, n, B, c->gh);                 // |b|^2
+    read(1);
+    std::vector<double> nb(B);
+    std::vector<cd> rho_prev(B, 1.0), alpha(B, 1.0), omega(B, 1.0);
+    std::vector<int> done(B, 0);
+    iters.assign(B, 0);
+    relres.assign(B, 0.0);
+    for (int bb = 0; bb < B; ++bb) {
+        nb[bb] = std::sqrt(std::max(0.0, hv[bb].x));
+        if (nb[bb] == 0.0) done[bb] = 1;
+    }
+    for (int it = 1; it <= maxit; ++it) {
+        if (std::all_of(done.begin(), done.end(), [](int q) { return q != 0; })) break;
+        // rho = (rhat, r)
+        dots_dev(c, rhat, nB, 1, r, n, B, c->gh);
+        read(1);
+        std::vector<cd> rho(B), beta(B, 0.0);
+        for (int bb = 0; bb < B; ++bb) {
+            rho[bb] = cx(hv[bb]);
+            if (done[bb]) continue;
+            if (rho[bb] == 0.0) { done[bb] = 1; continue; }          // breakdown
+            beta[bb] = (rho[bb] / rho_prev[bb]) * (alpha[bb] / omega[bb]);
+        }
+        // p = r + beta (p - omega v)
+        for (int bb = 0; bb < B; ++bb) {
+            const bool a = !done[bb];
+            cf[bb] = make_double2(1.0, 0.0);
+            cf[B + bb] = d2(a ? beta[bb] : cd(0.0));
+            cf[2 * B + bb] = d2(a ? -beta[bb] * omega[bb] : cd(0.0));
+        }
+        coefs();
+        launch_lincomb3(p, r, p, v, c->gcoef, n, B, c->st);
+        P(p, y);
+        M(y, v);
+        // alpha = rho / (rhat, v)
+        dots_dev(c, rhat, nB, 1, v, n, B, c->gh);
+        read(1);
+        for (int bb = 0; bb < B; ++bb) {
+            const cd den = cx(hv[bb]);
+            if (done[bb] || den == 0.0) { alpha[bb] = 0.0; if (!done[bb]) done[bb] = 1; continue; }
+            alpha[bb] = rho[bb] / den;
+        }
+        // s = r - alpha v
+        for (int bb = 0; bb < B; ++bb) {
+            cf[bb] = make_double2(1.0, 0.0);
+            cf[B + bb] = d2(-alpha[bb]);
+            cf[2 * B + bb] = make_double2(0.0, 0.0);
+        }
+        coefs();
+        launch_lincomb3(sv, r, v, nullptr, c->gcoef, n, B, c->st);
+        P(sv, z);
+        M(z, t);
+        // (s, t), (t, t) with w = t and V = [s, t]; |s|^2
+        dots_dev(c, sv, nB, 2, t, n, B, c->gh);
+        dots_dev(c, nullptr, 0, 1, sv, n, B, c->gh + 2 * B);
+        read(3);
+        std::vector<int> half(B, 0);
+        for (int bb = 0; bb < B; ++bb) {
+            if (done[bb]) { omega[bb] = 1.0; continue; }
+            const double rs = std::sqrt(std::max(0.0, hv[2 * B + bb].x)) / nb[bb];
+            if (rs <= tol) {                                   // converged at the half step
+                half[bb] = 1;
+                relres[bb] = rs;
+                iters[bb] = it;
+                omega[bb] = 0.0;
+                continue;
+            }
+            const double tt = hv[B + bb].x;
+            if (tt == 0.0) { half[bb] = 1; omega[bb] = 0.0; continue; }     // breakdown
+            omega[bb] = std::conj(cx(hv[bb])) / tt;            // (t, s) / (t, t)
+        }
+        // x = x + alpha y + omega z ; r = s - omega t
+        for (int bb = 0; bb < B; ++bb) {
+            const bool a = !done[bb];
+            cf[bb] = make_double2(1.0, 0.0);
+            cf[B + bb] = d2(a ? alpha[bb] : cd(0.0));
+            cf[2 * B + bb] = d2(a && !half[bb] ? omega[bb] : cd(0.0));
+        }
+        coefs();
+        launch_lincomb3(x, x, y, z, c->gcoef, n, B, c->st);
+        for (int bb = 0; bb < B; ++bb) {
+            cf[bb] = make_double2(1.0, 0.0);
+            cf[B + bb] = d2(!done[bb] && !half[bb] ? -omega[bb] : cd(0.0));
+            cf[2 * B + bb] = make_double2(0.0, 0.0);
+        }
+        coefs();
+        // (for stopped or half-step columns the coefficient is 0 and r = s,
+        // which is their residual: s = r there since alpha = 0, or the
+        // half-step residual)
+        launch_lincomb3(r, sv, t, nullptr, c->gcoef, n, B, c->st);
+        dots_dev(c, nullptr, 0, 1, r, n, B, c->gh);
+        read(1);
+        for (int bb = 0; bb < B; ++bb) {
+            if (done[bb]) continue;
+            if (half[bb]) { done[bb] = 1; continue; }
+            const double rr = std::sqrt(std::max(0.0, hv[bb].x)) / nb[bb];
+            relres[bb] = rr;
+            iters[bb] = it;
+            if (rr <= tol || omega[bb] == 0.0) done[bb] = 1;
+            rho_prev[bb] = rho[bb];
+        }
+    }
+    sync(c);
+}
+
 template <typename T>
 void dd_solve(hz_ctx* c, int B, double tol, int maxit, const std::vector<int>& active,
               std::vector<int>& iters, std::vector<double>& relres, double* t_rhs,
@@ -1797,7 +1974,10 @@ void dd_solve(hz_ctx* c, int B, double tol, int maxit, const std::vector<int>& a
     sync(c);
     double t1 = now_s();
     *t_rhs += t1 - t0;
-    gmres<T>(c, c->gb, c->gx, B, tol, maxit, iters, relres, flex);
+    if (c->prm.krylov == HZ_KRYLOV_BICGSTAB)
+        bicgstab<T>(c, c->gb, c->gx, B, tol, maxit, iters, relres, flex);
+    else
+        gmres<T>(c, c->gb, c->gx, B, tol, maxit, iters, relres, flex);
     double t2 = now_s();
     *t_gm += t2 - t1;
     // s = d + q  (in T)
@@ -2022,6 +2202,10 @@ hz_status hz_setup(const double* model_dev, const hz_params* prm, hz_ctx** out) 
         raise(HZ_EINVAL, "bad precision");
     if (prm->model_kind != HZ_MODEL_VELOCITY && prm->model_kind != HZ_MODEL_SLOWNESS2)
         raise(HZ_EINVAL, "bad model kind");
+    if (prm->precond != HZ_PRECOND_GS && prm->precond != HZ_PRECOND_JACOBI)
+        raise(HZ_EINVAL, "bad preconditioner");
+    if (prm->krylov != HZ_KRYLOV_GMRES && prm->krylov != HZ_KRYLOV_BICGSTAB)
+        raise(HZ_EINVAL, "bad Krylov method");
     c = new hz_ctx();
     c->prm = *prm;
     if (const char* g = std::getenv("HZ_GRAPHS")) c->use_graphs = std::atoi(g) != 0;

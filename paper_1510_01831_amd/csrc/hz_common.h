@@ -254,6 +254,9 @@ void launch_dots(const double2* V, long long vstride, int nv, const double2* w, 
                  int B, double2* partial, int nchunks, hipStream_t st);
 void launch_reduce_partials(const double2* partial, int nchunks, int count, double2* out,
                             hipStream_t st);
+void launch_lincomb3(double2* out, const double2* x0, const double2* x1, const double2* x2,
+                     const double2* coef, long long n, int B, hipStream_t st);
+void launch_fill_zero(double2* y, long long n, hipStream_t st);
 void launch_inv_norms(const double2* n2, double2* s, int B, hipStream_t st);
 void launch_update_basis(double2* w, const double2* V, long long vstride, int nv,
                          const double2* coef, long long n, int B, hipStream_t st,

@@ -272,6 +272,43 @@ void launch_reduce_partials(const double2* partial, int nchunks, int count, doub
                        count, out);
 }
 
+// out[i,b] = c0[b] x0[i,b] + c1[b] x1[i,b] (+ c2[b] x2[i,b]), coef = [3][B]
+// (per-column complex coefficients; out may alias an input)
+__global__ void k_lincomb3(double2* out, const double2* x0, const double2* x1, const double2* x2,
+                           const double2* coef, long long n, int B) {
+    const long long total = n * B;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int b = (int)(q % B);
+        const double2 c0 = coef[b], c1 = coef[B + b];
+        const double2 a0 = x0[q], a1 = x1[q];
+        double2 r = make_double2(c0.x * a0.x - c0.y * a0.y + c1.x * a1.x - c1.y * a1.y,
+                                 c0.x * a0.y + c0.y * a0.x + c1.x * a1.y + c1.y * a1.x);
+        if (x2) {
+            const double2 c2 = coef[2 * B + b], a2 = x2[q];
+            r.x += c2.x * a2.x - c2.y * a2.y;
+            r.y += c2.x * a2.y + c2.y * a2.x;
+        }
+        out[q] = r;
+    }
+}
+void launch_lincomb3(double2* out, const double2* x0, const double2* x1, const double2* x2,
+                     const double2* coef, long long n, int B, hipStream_t st) {
+    const long long total = n * B;
+    const int blocks = (int)std::min<long long>((total + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_lincomb3, dim3(blocks), dim3(256), 0, st, out, x0, x1, x2, coef, n, B);
+}
+
+__global__ void k_fill_zero(double2* y, long long n) {
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x)
+        y[q] = make_double2(0.0, 0.0);
+}
+void launch_fill_zero(double2* y, long long n, hipStream_t st) {
+    const int blocks = (int)std::min<long long>((n + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_fill_zero, dim3(blocks), dim3(256), 0, st, y, n);
+}
+
 // s[b] = 1 / sqrt(n2[b].x) (0 for a zero norm): column scales for GMRES from
 // the squared norms left on the device
 __global__ void k_inv_norms(const double2* n2, double2* s, int B) {

@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(HERE, "libhz.so")
 HZ_OK, HZ_EINVAL, HZ_ENOMEM, HZ_ESTATE, HZ_ENOCONV, HZ_ESINGULAR, HZ_EDEVICE = 0, -1, -2, -3, -4, -5, -6
 HZ_FP64, HZ_MIXED, HZ_MIXED_REFINE = 0, 1, 2
 HZ_MODEL_VELOCITY, HZ_MODEL_SLOWNESS2 = 0, 1
+HZ_PRECOND_GS, HZ_PRECOND_JACOBI = 0, 1
+HZ_KRYLOV_GMRES, HZ_KRYLOV_BICGSTAB = 0, 1
 
 EXPORTED = [
     "hz_setup", "hz_factor", "hz_solve", "hz_adjoint", "hz_solve_ext", "hz_adjoint_ext",
@@ -31,7 +33,8 @@ class Params(ctypes.Structure):
                 ("omega", ctypes.c_double), ("n_pml", ctypes.c_int),
                 ("pml_beta", ctypes.c_double), ("layers", ctypes.c_int),
                 ("cells", ctypes.c_int), ("precision", ctypes.c_int),
-                ("model_kind", ctypes.c_int), ("max_batch", ctypes.c_int)]
+                ("model_kind", ctypes.c_int), ("max_batch", ctypes.c_int),
+                ("precond", ctypes.c_int), ("krylov", ctypes.c_int)]
 
 
 class RhsStats(ctypes.Structure):
@@ -136,7 +139,8 @@ class Solver:
 
     def __init__(self, model, omega: float, n_pml: int, layers: int, cells: int,
                  precision: int = HZ_FP64, model_kind: int = HZ_MODEL_VELOCITY,
-                 pml_beta: float = 2.0, max_batch: int = 1, factor: bool = True):
+                 pml_beta: float = 2.0, max_batch: int = 1, factor: bool = True,
+                 precond: int = HZ_PRECOND_GS, krylov: int = HZ_KRYLOV_GMRES):
         import torch
 
         self.torch = torch
@@ -145,7 +149,7 @@ class Solver:
         self.model = model.to(device="cuda", dtype=torch.float64).contiguous()
         self.prm = Params(n, n, 1.0 / (n + 1), float(omega), int(n_pml), float(pml_beta),
                           int(layers), int(cells), int(precision), int(model_kind),
-                          int(max_batch))
+                          int(max_batch), int(precond), int(krylov))
         self.ctx = ctypes.c_void_p()
         L = lib()
         _check(L.hz_setup(_ptr(self.model), ctypes.byref(self.prm), ctypes.byref(self.ctx)),
