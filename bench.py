@@ -188,7 +188,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="fp64,mixed")
+    ap.add_argument("--forms", default="fp64,mixed",
+                    help="comma list of fp64, mixed, table3 (Krylov x preconditioner comparison)")
     ap.add_argument("--roctx-form", default="",
                     help="mark this form's timed steps as the profiled region "
                          "(fp64_single, fp64_batched or mixed_batched)")
@@ -229,7 +230,7 @@ def main():
     it1 = s64.last_stats[0]["iters"]
     log(f"[bench] fp64 single RHS: {dt1 * 1e3:.1f} ms/solve, {it1} GMRES iterations")
     forms = {"fp64_single": {"dof_solves_per_s": n * n / dt1, "ms_per_solve": dt1 * 1e3,
-                             "gmres_iters": it1, "kernels": prof1}}
+                             "gmres_iters": it1, "setup_factor_s": t_fac64, "kernels": prof1}}
     ref_idx = [0, B // 2, B - 1]
     refs = {}
     for k in ref_idx:
@@ -241,7 +242,7 @@ def main():
         err = max(float(torch.linalg.norm(u[k] - refs[k]) / torch.linalg.norm(refs[k]))
                   for k in ref_idx)
         its = max(x["iters"] for x in s64.last_stats)
-        results["fp64_batched"] = (dt, prof, err, its, "c128")
+        results["fp64_batched"] = (dt, prof, err, its, "c128", t_fac64)
         log(f"[bench] fp64 batched: {dt * 1e3:.1f} ms/step, err {err:.2e}, iters {its}")
     s64.close()
     del s64
@@ -251,22 +252,47 @@ def main():
         smx = hz.Solver(torch.from_numpy(c), w.omega, w.n_pml, w.layers, w.cells,
                         precision=hz.HZ_MIXED, max_batch=B)
         torch.cuda.synchronize()
-        log(f"[bench] mixed setup+factor {time.perf_counter() - t0:.2f} s")
+        t_facmx = time.perf_counter() - t0
+        log(f"[bench] mixed setup+factor {t_facmx:.2f} s")
         u, dt, prof = timed_solves(smx, f_all, 1e-10, args.steps, args.warmup, max_iter, True,
                                    region=args.roctx_form == "mixed_batched")
         err = max(float(torch.linalg.norm(u[k] - refs[k]) / torch.linalg.norm(refs[k]))
                   for k in ref_idx)
         its = max(x["iters"] for x in smx.last_stats)
-        results["mixed_batched"] = (dt, prof, err, its, "c64+c128")
+        results["mixed_batched"] = (dt, prof, err, its, "c64+c128", t_facmx)
         log(f"[bench] mixed batched: {dt * 1e3:.1f} ms/step, err {err:.2e}, iters {its}")
         smx.close()
         del smx
-    for name, (dt, prof, err, its, dty) in results.items():
+    table3 = None
+    if "table3" in args.forms:
+        # the iteration-count comparison of the paper (Table 3: GMRES and
+        # Bi-CGstab with the Gauss-Seidel and Jacobi preconditioners, relative
+        # residual 1e-7) on this workload, FP64, whole batch per solve
+        table3 = {}
+        for pre, pname in ((hz.HZ_PRECOND_GS, "gs"), (hz.HZ_PRECOND_JACOBI, "jacobi")):
+            for kry, kname in ((hz.HZ_KRYLOV_GMRES, "gmres"), (hz.HZ_KRYLOV_BICGSTAB, "bicgstab")):
+                st = hz.Solver(torch.from_numpy(c), w.omega, w.n_pml, w.layers, w.cells,
+                               precision=hz.HZ_FP64, max_batch=B, precond=pre, krylov=kry)
+                u, dtt, _ = timed_solves(st, f_all, 1e-7, args.steps, args.warmup, max_iter)
+                itt = max(x["iters"] for x in st.last_stats)
+                errt = max(float(torch.linalg.norm(u[k] - refs[k]) / torch.linalg.norm(refs[k]))
+                           for k in ref_idx)
+                table3[f"{pname}_{kname}"] = {"iters": itt, "ms_per_step": dtt * 1e3,
+                                              "max_rel_err_vs_fp64": errt}
+                log(f"[bench] table3 {pname}/{kname}: {itt} iterations, {dtt * 1e3:.1f} ms/step, "
+                    f"err {errt:.1e}")
+                st.close()
+                del st
+                torch.cuda.empty_cache()
+    for name, (dt, prof, err, its, dty, tf) in results.items():
         forms[name] = {"dof_solves_per_s": B * n * n / dt, "ms_per_step": dt * 1e3,
-                       "max_rel_err_vs_fp64": err, "gmres_iters": its, "kernels": prof}
+                       "max_rel_err_vs_fp64": err, "gmres_iters": its,
+                       "setup_factor_s": tf,
+                       "amortized_dof_solves_per_s": B * n * n / (dt + tf),
+                       "kernels": prof}
     ok = {k: v for k, v in results.items() if v[2] <= 1e-8}
     chosen = min(ok, key=lambda k: ok[k][0]) if ok else min(results, key=lambda k: results[k][0])
-    dt, prof, err, its, dty = results[chosen]
+    dt, prof, err, its, dty, t_fac = results[chosen]
 
     # ---- roofline of the dominant kernel of the chosen form (most time in
     # the timed steps; every family is one kernel, timed launch by launch
@@ -297,12 +323,15 @@ def main():
                                 f"(10 ppw at c_min), {w.layers} layers x {w.cells} cells, "
                                 f"{B} point sources on depth row {w.src_z}"),
                    "form": chosen, "batch": B, "tol": 1e-10,
-                   "max_rel_err_vs_fp64": err, "gmres_iters": its},
+                   "max_rel_err_vs_fp64": err, "gmres_iters": its,
+                   "setup_factor_s": t_fac,
+                   "amortized_dof_solves_per_s": B * n * n / (dt + t_fac)},
         "vs_plain_fp64_single": (B * n * n / dt) / forms["fp64_single"]["dof_solves_per_s"],
         "forms": forms,
         "kernels": prof,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "table3": table3,
     }
     print(json.dumps(line), flush=True)
 
