@@ -20,6 +20,10 @@ namespace hz {
 constexpr int GJ_THREADS = 512;
 constexpr int GJ_NMAX = 448;    // largest matrix order handled (2 HL <= 448)
 
+#ifndef HZ_GJ_REG
+#define HZ_GJ_REG 1             // register-resident cell recursion for HL <= 128
+#endif
+
 template <typename T>
 __device__ inline T cabs2(C2<T> a) { return a.x * a.x + a.y * a.y; }
 
@@ -45,7 +49,7 @@ __device__ void gj_invert(C2<T>* work, C2<T>* out, int n, long long ldo, int* si
     const int tid = threadIdx.x;
     const int nt = blockDim.x;
     const long long nn = (long long)n * n;
-    for (int r = tid; r < n; r += nt) used[r] = 0;
+    for (int r = tid; r < n; r += nt) { used[r] = 0; pivrow[r] = r; pivstep[r] = r; }
     // publish column 0
     for (long long e = tid; e < nn; e += nt) {
         int j = (int)(e % n);
@@ -77,9 +81,10 @@ __device__ void gj_invert(C2<T>* work, C2<T>* out, int n, long long ldo, int* si
             __syncthreads();
         }
         if (tid == 0) {
-            int pr = redi[0];
+            // redi[0] == n only if no candidate compared (NaN input)
+            int pr = redi[0] < n ? redi[0] : 0;
             C2<T> pv = colbuf[cur][pr];
-            if (redv[0] <= (T)0) {
+            if (redv[0] <= (T)0 || redi[0] >= n) {
                 atomicOr(sing_flag, 1);
                 s_inv = mk<T>((T)0, (T)0);
             } else {
@@ -188,6 +193,248 @@ k_cell_factor(const CellDesc* __restrict__ cells, const double2* __restrict__ di
     }
 }
 
+// Register-resident variant of the cell recursion for HL <= NM (NM = 64 or
+// 128): the Schur complement of the current grid column stays in registers
+// for the whole Gauss-Jordan elimination, so an elimination step reads no
+// global memory.  Thread t owns rows rg + 32 i (i < NM/32) and columns
+// cg + 16 jj (jj < NM/16), rg = t / 16, cg = t % 16 (so one row's owners
+// are 16 lanes of one wave); entries outside the
+// HL x HL block are zero and stay zero.  Step k with pivot row p is the
+// rank-1 update
+//     a[r][j] <- a[r][j] - c_r P_j   (r != p),      a[p][j] <- P_j,
+// where c is column k before the step, P_j = a[p][j] / a[p][k] (j != k),
+// P_k = 1 / a[p][k], and column k is cleared first so that it ends as
+// -c_r / a[p][k].  Only the pivot column (published by its owners at the end
+// of the previous step) and the scaled pivot row pass through LDS; every wave
+// runs the pivot search itself (a DPP max over its lanes, then a ballot for
+// the smallest row attaining it), so a step costs two barriers.  The pivoting
+// rule and the unscrambled output are those of gj_invert.
+//
+// Register layout: a[jj] is a vector over the owned rows, element 2i the
+// real and 2i+1 the imaginary part of row rg + 32 i.  The pivot row's slot
+// i = p / 32 is wave-uniform but known only at run time; indexing the vector
+// with it compiles to register-relative moves (no scratch).  The column slot
+// k / 16 is made a compile-time constant by unrolling the step loop over it.
+// Maximum over the 64 lanes of a wave, returned to every lane: DPP steps
+// within each row of 16 lanes, row broadcasts across rows, then lane 63.
+template <int CTRL, int ROWMASK>
+__device__ inline double dpp_max_step(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xF, false);
+    const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xF, false);
+    return fmax(v, __hiloint2double(hi2, lo2));
+}
+template <int CTRL, int ROWMASK>
+__device__ inline float dpp_max_step(float v) {
+    const int b = __float_as_int(v);
+    return fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(b, b, CTRL, ROWMASK, 0xF, false)));
+}
+template <typename T>
+__device__ inline T wave_max(T v) {
+    v = dpp_max_step<0xB1, 0xF>(v);     // quad_perm [1,0,3,2]
+    v = dpp_max_step<0x4E, 0xF>(v);     // quad_perm [2,3,0,1]
+    v = dpp_max_step<0x124, 0xF>(v);    // row_ror:4
+    v = dpp_max_step<0x128, 0xF>(v);    // row_ror:8
+    v = dpp_max_step<0x142, 0xA>(v);    // row_bcast:15 into rows 1 and 3
+    v = dpp_max_step<0x143, 0xC>(v);    // row_bcast:31 into rows 2 and 3
+    if constexpr (sizeof(T) == 8) {
+        const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+        const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+        return __hiloint2double(hi, lo);
+    } else {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+    }
+}
+
+template <typename T, int N>
+using vecT = T __attribute__((ext_vector_type(N)));
+
+template <typename T, int NM>
+__global__ void __launch_bounds__(GJ_THREADS)
+k_cell_factor_reg(const CellDesc* __restrict__ cells, const double2* __restrict__ diag,
+                  const double2* __restrict__ cz, const double2* __restrict__ e,
+                  C2<T>* __restrict__ Xpool, int* sing_flag) {
+    constexpr int R = NM / 32, C = NM / 16, SR = NM / 64;
+    using V = vecT<T, 2 * R>;
+    __shared__ C2<T> colbuf[2][NM];
+    __shared__ C2<T> prow[NM];
+    __shared__ int pivrow[NM];
+    __shared__ int pivstep[NM];
+    const CellDesc cd = cells[blockIdx.x];
+    const int n = cd.HL, Wc = cd.Wc, HLp = cd.HLp;
+    const long long np2 = (long long)HLp * HLp;
+    C2<T>* X = Xpool + cd.off_X;
+    const double2* dg = diag + cd.off_coef;
+    const double2* zz = cz + cd.off_coef;
+    const double2* ee = e + cd.off_coef;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int rg = tid >> 4, cg = tid & 15;
+    const C2<T> zero = mk<T>((T)0, (T)0);
+    V a[C];
+    for (int col = 0; col < Wc; ++col) {
+        // S_col = A_col - diag(e_col) X_{col-1} diag(e_col); every load uses
+        // an in-range index and out-of-block entries are selected away
+        const C2<T>* Xp = X + (long long)(col - 1) * np2;
+        const long long cb = (long long)col * n;
+        C2<T> ej[C];
+#pragma unroll
+        for (int jj = 0; jj < C; ++jj) {
+            const int j = cg + 16 * jj;
+            const double2 v = ee[cb + (j < n ? j : 0)];
+            ej[jj] = mk<T>((T)v.x, (T)v.y);
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int r = rg + 32 * i;
+            const int rc = r < n ? r : 0;
+            const double2 dr = dg[cb + rc], zr = zz[cb + rc], zm = zz[cb + (rc > 0 ? rc - 1 : 0)];
+            const double2 ev = ee[cb + rc];
+            const C2<T> er = mk<T>((T)ev.x, (T)ev.y);
+#pragma unroll
+            for (int jj = 0; jj < C; ++jj) {
+                const int j = cg + 16 * jj;
+                const bool in = r < n && j < n;
+                const double2 av = (j == r) ? dr : (j == r + 1) ? zr : (j == r - 1) ? zm
+                                 : make_double2(0.0, 0.0);
+                C2<T> v = mk<T>((T)av.x, (T)av.y);
+                if (col > 0) {
+                    const C2<T> x = Xp[xt_index(in ? r : 0, in ? j : 0, HLp)];
+                    v = csub(v, cmul(cmul(er, x), ej[jj]));
+                }
+                a[jj][2 * i] = in ? v.x : (T)0;
+                a[jj][2 * i + 1] = in ? v.y : (T)0;
+            }
+        }
+        if (cg == 0) {
+#pragma unroll
+            for (int i = 0; i < R; ++i) colbuf[0][rg + 32 * i] = mk<T>(a[0][2 * i], a[0][2 * i + 1]);
+        }
+        bool used[SR];
+#pragma unroll
+        for (int s = 0; s < SR; ++s) used[s] = false;
+        for (int r = tid; r < NM; r += GJ_THREADS) { pivrow[r] = r; pivstep[r] = r; }
+        __syncthreads();
+        int cur = 0;
+#pragma unroll
+        for (int kj = 0; kj < C; ++kj) {
+            for (int kc = 0; kc < 16; ++kc) {
+                const int k = kj * 16 + kc;
+                if (k >= n) break;
+                // pivot search (every wave): largest |c_r|^2 over unused rows,
+                // ties to the smallest row; -1 marks a row out of the race
+                T v[SR];
+#pragma unroll
+                for (int s = 0; s < SR; ++s) {
+                    const int r = lane + 64 * s;
+                    v[s] = (T)-1;
+                    if (r < n && !used[s]) v[s] = cabs2<T>(colbuf[cur][r]);
+                }
+                T best = v[0];
+#pragma unroll
+                for (int s = 1; s < SR; ++s) best = fmax(best, v[s]);
+                best = wave_max(best);
+                int pr = -1;
+#pragma unroll
+                for (int s = SR - 1; s >= 0; --s) {
+                    const unsigned long long m = __ballot(v[s] >= (T)0 && v[s] == best);
+                    if (m) pr = 64 * s + __ffsll((long long)m) - 1;
+                }
+                // pr < 0 only if no candidate compared (NaN input): flag it
+                // and keep every index in range
+                if (pr < 0) { pr = 0; best = (T)0; }
+                pr = __builtin_amdgcn_readfirstlane(pr);
+                const C2<T> pv = colbuf[cur][pr];
+                C2<T> inv = zero;
+                if (best <= (T)0) {
+                    if (tid == 0) atomicOr(sing_flag, 1);
+                } else {
+                    const T den = (T)1 / (pv.x * pv.x + pv.y * pv.y);
+                    inv = mk<T>(pv.x * den, -pv.y * den);
+                }
+#pragma unroll
+                for (int s = 0; s < SR; ++s)
+                    if (pr == lane + 64 * s) used[s] = true;
+                const int pi = pr >> 5, prg = pr & 31;
+                // scaled pivot row, from its owners
+                if (rg == prg) {
+#pragma unroll
+                    for (int jj = 0; jj < C; ++jj) {
+                        const C2<T> v = mk<T>(a[jj][2 * pi], a[jj][2 * pi + 1]);
+                        prow[cg + 16 * jj] = (jj == kj && cg == kc) ? inv : cmul(v, inv);
+                    }
+                }
+                if (tid == 0) { pivrow[k] = pr; pivstep[pr] = k; }
+                __syncthreads();
+                C2<T> P[C], cc[R];
+#pragma unroll
+                for (int jj = 0; jj < C; ++jj) P[jj] = prow[cg + 16 * jj];
+#pragma unroll
+                for (int i = 0; i < R; ++i) cc[i] = colbuf[cur][rg + 32 * i];
+                if (cg == kc) a[kj] = (V)(T)0;
+#pragma unroll
+                for (int jj = 0; jj < C; ++jj) {
+#pragma unroll
+                    for (int i = 0; i < R; ++i) {
+                        T re = a[jj][2 * i], im = a[jj][2 * i + 1];
+                        re = re - cc[i].x * P[jj].x;
+                        im = im - cc[i].x * P[jj].y;
+                        re = re + cc[i].y * P[jj].y;
+                        im = im - cc[i].y * P[jj].x;
+                        a[jj][2 * i] = re;
+                        a[jj][2 * i + 1] = im;
+                    }
+                }
+                if (rg == prg) {
+#pragma unroll
+                    for (int jj = 0; jj < C; ++jj) {
+                        a[jj][2 * pi] = P[jj].x;
+                        a[jj][2 * pi + 1] = P[jj].y;
+                    }
+                }
+                // publish column k + 1 for the next search
+                if (k + 1 < n) {
+                    if (kc < 15) {
+                        if (cg == kc + 1) {
+#pragma unroll
+                            for (int i = 0; i < R; ++i)
+                                colbuf[cur ^ 1][rg + 32 * i] = mk<T>(a[kj][2 * i], a[kj][2 * i + 1]);
+                        }
+                    } else if (kj + 1 < C) {
+                        if (cg == 0) {
+#pragma unroll
+                            for (int i = 0; i < R; ++i)
+                                colbuf[cur ^ 1][rg + 32 * i] =
+                                    mk<T>(a[kj + 1][2 * i], a[kj + 1][2 * i + 1]);
+                        }
+                    }
+                }
+                cur ^= 1;
+                __syncthreads();
+            }
+        }
+        // unscramble: X_col[pivstep[r]][pivrow[j]] = a[r][j]; padding zero
+        C2<T>* Xk = X + (long long)col * np2;
+        int ps[R], pc[C];
+#pragma unroll
+        for (int i = 0; i < R; ++i) ps[i] = pivstep[rg + 32 * i];
+#pragma unroll
+        for (int jj = 0; jj < C; ++jj) pc[jj] = pivrow[cg + 16 * jj];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int r = rg + 32 * i;
+#pragma unroll
+            for (int jj = 0; jj < C; ++jj) {
+                const int j = cg + 16 * jj;
+                const bool in = r < n && j < n;
+                if (r < HLp && j < HLp)
+                    Xk[xt_index(in ? ps[i] : r, in ? pc[jj] : j, HLp)] =
+                        in ? mk<T>(a[jj][2 * i], a[jj][2 * i + 1]) : zero;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(GJ_THREADS)
 k_invert_batch(C2<T>* const* mats, C2<T>* const* outs, const int* ns, C2<T>* workpool,
@@ -206,7 +453,18 @@ void launch_cell_factor(const CellDesc* cells_dev, int ncells, const Dims& d,
                         const double2* diag, const double2* cz, const double2* e,
                         C2<T>* Xpool, C2<T>* work, long long work_stride, int* sing_flag,
                         hipStream_t st) {
-    (void)d;
+#if HZ_GJ_REG
+    if (d.HLmax <= 64) {
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cell_factor_reg<T, 64>), dim3(ncells),
+                           dim3(GJ_THREADS), 0, st, cells_dev, diag, cz, e, Xpool, sing_flag);
+        return;
+    }
+    if (d.HLmax <= 128) {
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cell_factor_reg<T, 128>), dim3(ncells),
+                           dim3(GJ_THREADS), 0, st, cells_dev, diag, cz, e, Xpool, sing_flag);
+        return;
+    }
+#endif
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cell_factor<T>), dim3(ncells), dim3(GJ_THREADS), 0, st,
                        cells_dev, diag, cz, e, Xpool, work, work_stride, sing_flag);
 }
