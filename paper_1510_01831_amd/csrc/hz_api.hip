@@ -1292,9 +1292,15 @@ void factor_impl(hz_ctx* c) {
         const int nb = cs_nb(Rmax, ncells, d.HLpmax);
         const int chunks = (Rmax + nb - 1) / nb;
         const long long ystride = (long long)d.Wcmax * d.HLpmax * nb;
-        // scratch budget ~ 4 GiB
-        long long budget_wgs = std::max<long long>(chunks, (4LL << 30) / (ystride * (long long)sizeof(double2)));
-        const int per = (int)std::max<long long>(1, budget_wgs / chunks);
+        // Forward-sweep scratch: a quarter of the free memory, between 4 and
+        // 24 GiB, so that a launch holds several waves of workgroups (probe
+        // batches differ in length: the forward sweep starts at the batch's
+        // first source column) and the dispatcher can balance them.
+        size_t mfree = 0, mtot = 0;
+        if (hipMemGetInfo(&mfree, &mtot) != hipSuccess) { (void)hipGetLastError(); mfree = 0; }
+        const long long budget = std::min<long long>(24LL << 30, std::max<long long>(4LL << 30, (long long)(mfree / 4)));
+        long long budget_wgs = std::max<long long>(chunks, budget / (ystride * (long long)sizeof(double2)));
+        const int per = (int)std::min<long long>(ncells, std::max<long long>(1, budget_wgs / chunks));
         double2* Y = alloc_c<double>(c, ystride * (long long)per * chunks);
         std::vector<int> list(ncells);
         for (int i = 0; i < ncells; ++i) list[i] = i;

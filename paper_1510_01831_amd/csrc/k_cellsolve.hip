@@ -390,6 +390,19 @@ constexpr int CS_MF_WAVES = CS_MF_THREADS / 64;
 #define CS_U2 2
 #endif
 
+// Grid column of the point source of probe `probe` (the columns used by the
+// SOLVE_PROBE branch of cell_source).
+__device__ inline int probe_col(const CellDesc& cd, int p, int probe) {
+    if (probe < cd.ncol) {
+        int q = probe, right = 0;
+        if (!cd.has_left) right = 1;
+        else if (q >= 2 * cd.HL) { right = 1; q -= 2 * cd.HL; }
+        const int ab = q / cd.HL;
+        return right ? (ab == 0 ? p + cd.nc : p + cd.nc - 1) : (ab == 0 ? p : p - 1);
+    }
+    return cd.own_c0 + (probe - cd.ncol) % cd.s;
+}
+
 template <typename T, int NB, int MODE, int MC>
 __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const CellDesc& cd,
                                              const LayerDesc& ld, C2<T>* vs, double2* izs,
@@ -488,21 +501,32 @@ __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const Ce
     C2<T> pv[MCA][NCT][4];   // prefetched sources (forward) / iterates (backward)
     C2<T> pe[MCA][4];        // prefetched coupling coefficients
 
+    // A probe batch's sources are point sources; y_k = 0 before the first
+    // column kmin that holds one, so the forward sweep starts there.
+    int kmin = 0;
+    if constexpr (MODE == SOLVE_PROBE) {
+        int c = Wc;
+        if (lane < NB && bval(lane)) c = probe_col(cd, a.p, a.probe0 + b0 + lane);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) c = min(c, __shfl_xor(c, off));
+        kmin = __builtin_amdgcn_readfirstlane(c);
+    }
+
     // ---- forward sweep: y_0 = b_0, y_k = b_k - e_k o (X_{k-1} y_{k-1})
-    for (int k = 0; k < Wc; ++k) {
+    for (int k = kmin; k < Wc; ++k) {
 #pragma unroll
         for (int m = 0; m < MC; ++m)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int j = row_of(m, v);
-                pe[m][v] = k > 0 ? e_coef<T>(ee, k, j, HL) : z;
+                pe[m][v] = k > kmin ? e_coef<T>(ee, k, j, HL) : z;
 #pragma unroll
                 for (int t = 0; t < NCT; ++t) {
                     const int c = t * 16 + lc;
                     pv[m][t][v] = bval(c) ? cell_source_ctx<T, MODE>(a, cd, ld, sc, k, j, b0 + c) : z;
                 }
             }
-        if (k > 0) matmul(Xf + (long long)(k - 1) * np2);
+        if (k > kmin) matmul(Xf + (long long)(k - 1) * np2);
 #pragma unroll
         for (int m = 0; m < MC; ++m)
 #pragma unroll
@@ -510,7 +534,7 @@ __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const Ce
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     C2<T> y = pv[m][t][v];
-                    if (k > 0) y = csub(y, cmul(pe[m][v], mk<T>(ac[m][t].re(v), ac[m][t].im(v))));
+                    if (k > kmin) y = csub(y, cmul(pe[m][v], mk<T>(ac[m][t].re(v), ac[m][t].im(v))));
                     pv[m][t][v] = y;
                     Y[(long long)k * nq + yidx(m, t, v)] = y;
                 }
@@ -533,7 +557,7 @@ __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const Ce
                     pe[m][v] = e_coef<T>(ee, k, row_of(m, v), HL);
 #pragma unroll
                     for (int t = 0; t < NCT; ++t)
-                        pv[m][t][v] = Y[(long long)(k - 1) * nq + yidx(m, t, v)];
+                        pv[m][t][v] = k - 1 >= kmin ? Y[(long long)(k - 1) * nq + yidx(m, t, v)] : z;
                 }
         }
         matmul(Xf + (long long)k * np2);

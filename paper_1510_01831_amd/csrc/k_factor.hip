@@ -249,17 +249,21 @@ __device__ inline T wave_max(T v) {
 template <typename T, int N>
 using vecT = T __attribute__((ext_vector_type(N)));
 
-template <typename T, int NM>
+template <typename T, int NM, int CR, int CL>
 __global__ void __launch_bounds__(GJ_THREADS)
 k_cell_factor_reg(const CellDesc* __restrict__ cells, const double2* __restrict__ diag,
                   const double2* __restrict__ cz, const double2* __restrict__ e,
                   C2<T>* __restrict__ Xpool, int* sing_flag) {
-    constexpr int R = NM / 32, C = NM / 16, SR = NM / 64;
+    constexpr int R = NM / 32, C = CR + CL, SR = (NM + 63) / 64, LW = 16 * CL;
+    static_assert(NM % 32 == 0 && 16 * C >= NM, "layout must cover the block");
     using V = vecT<T, 2 * R>;
     __shared__ C2<T> colbuf[2][NM];
-    __shared__ C2<T> prow[NM];
+    __shared__ C2<T> prow[16 * C];
     __shared__ int pivrow[NM];
     __shared__ int pivstep[NM];
+    // columns 16 CR .. 16 C - 1 live in LDS, row-major with row length LW
+    extern __shared__ __align__(16) unsigned char fac_dyn[];
+    C2<T>* lm = reinterpret_cast<C2<T>*>(fac_dyn);
     const CellDesc cd = cells[blockIdx.x];
     const int n = cd.HL, Wc = cd.Wc, HLp = cd.HLp;
     const long long np2 = (long long)HLp * HLp;
@@ -270,19 +274,12 @@ k_cell_factor_reg(const CellDesc* __restrict__ cells, const double2* __restrict_
     const int tid = threadIdx.x, lane = tid & 63;
     const int rg = tid >> 4, cg = tid & 15;
     const C2<T> zero = mk<T>((T)0, (T)0);
-    V a[C];
+    V a[CR];
     for (int col = 0; col < Wc; ++col) {
         // S_col = A_col - diag(e_col) X_{col-1} diag(e_col); every load uses
         // an in-range index and out-of-block entries are selected away
         const C2<T>* Xp = X + (long long)(col - 1) * np2;
         const long long cb = (long long)col * n;
-        C2<T> ej[C];
-#pragma unroll
-        for (int jj = 0; jj < C; ++jj) {
-            const int j = cg + 16 * jj;
-            const double2 v = ee[cb + (j < n ? j : 0)];
-            ej[jj] = mk<T>((T)v.x, (T)v.y);
-        }
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             const int r = rg + 32 * i;
@@ -298,11 +295,17 @@ k_cell_factor_reg(const CellDesc* __restrict__ cells, const double2* __restrict_
                                  : make_double2(0.0, 0.0);
                 C2<T> v = mk<T>((T)av.x, (T)av.y);
                 if (col > 0) {
+                    const double2 evj = ee[cb + (in ? j : 0)];
                     const C2<T> x = Xp[xt_index(in ? r : 0, in ? j : 0, HLp)];
-                    v = csub(v, cmul(cmul(er, x), ej[jj]));
+                    v = csub(v, cmul(cmul(er, x), mk<T>((T)evj.x, (T)evj.y)));
                 }
-                a[jj][2 * i] = in ? v.x : (T)0;
-                a[jj][2 * i + 1] = in ? v.y : (T)0;
+                v = in ? v : zero;
+                if (jj < CR) {
+                    a[jj < CR ? jj : 0][2 * i] = v.x;
+                    a[jj < CR ? jj : 0][2 * i + 1] = v.y;
+                } else {
+                    lm[r * LW + cg + 16 * (jj - CR)] = v;
+                }
             }
         }
         if (cg == 0) {
@@ -355,56 +358,77 @@ k_cell_factor_reg(const CellDesc* __restrict__ cells, const double2* __restrict_
                 for (int s = 0; s < SR; ++s)
                     if (pr == lane + 64 * s) used[s] = true;
                 const int pi = pr >> 5, prg = pr & 31;
-                // scaled pivot row, from its owners
+                // scaled pivot row, from its owners (16 lanes of one wave)
                 if (rg == prg) {
 #pragma unroll
                     for (int jj = 0; jj < C; ++jj) {
-                        const C2<T> v = mk<T>(a[jj][2 * pi], a[jj][2 * pi + 1]);
+                        C2<T> v;
+                        if (jj < CR) v = mk<T>(a[jj < CR ? jj : 0][2 * pi], a[jj < CR ? jj : 0][2 * pi + 1]);
+                        else v = lm[pr * LW + cg + 16 * (jj - CR)];
                         prow[cg + 16 * jj] = (jj == kj && cg == kc) ? inv : cmul(v, inv);
                     }
                 }
                 if (tid == 0) { pivrow[k] = pr; pivstep[pr] = k; }
                 __syncthreads();
-                C2<T> P[C], cc[R];
-#pragma unroll
-                for (int jj = 0; jj < C; ++jj) P[jj] = prow[cg + 16 * jj];
+                C2<T> cc[R];
 #pragma unroll
                 for (int i = 0; i < R; ++i) cc[i] = colbuf[cur][rg + 32 * i];
-                if (cg == kc) a[kj] = (V)(T)0;
+                if (kj < CR) {
+                    if (cg == kc) a[kj < CR ? kj : 0] = (V)(T)0;
+                }
 #pragma unroll
                 for (int jj = 0; jj < C; ++jj) {
+                    const C2<T> P = prow[cg + 16 * jj];
 #pragma unroll
                     for (int i = 0; i < R; ++i) {
-                        T re = a[jj][2 * i], im = a[jj][2 * i + 1];
-                        re = re - cc[i].x * P[jj].x;
-                        im = im - cc[i].x * P[jj].y;
-                        re = re + cc[i].y * P[jj].y;
-                        im = im - cc[i].y * P[jj].x;
-                        a[jj][2 * i] = re;
-                        a[jj][2 * i + 1] = im;
+                        T re, im;
+                        if (jj < CR) {
+                            re = a[jj < CR ? jj : 0][2 * i];
+                            im = a[jj < CR ? jj : 0][2 * i + 1];
+                        } else {
+                            const C2<T> w = lm[(rg + 32 * i) * LW + cg + 16 * (jj - CR)];
+                            const bool clr = jj == kj && cg == kc;
+                            re = clr ? (T)0 : w.x;
+                            im = clr ? (T)0 : w.y;
+                        }
+                        re = re - cc[i].x * P.x;
+                        im = im - cc[i].x * P.y;
+                        re = re + cc[i].y * P.y;
+                        im = im - cc[i].y * P.x;
+                        if (jj < CR) {
+                            a[jj < CR ? jj : 0][2 * i] = re;
+                            a[jj < CR ? jj : 0][2 * i + 1] = im;
+                        } else {
+                            lm[(rg + 32 * i) * LW + cg + 16 * (jj - CR)] = mk<T>(re, im);
+                        }
                     }
                 }
                 if (rg == prg) {
 #pragma unroll
                     for (int jj = 0; jj < C; ++jj) {
-                        a[jj][2 * pi] = P[jj].x;
-                        a[jj][2 * pi + 1] = P[jj].y;
+                        const C2<T> P = prow[cg + 16 * jj];
+                        if (jj < CR) {
+                            a[jj < CR ? jj : 0][2 * pi] = P.x;
+                            a[jj < CR ? jj : 0][2 * pi + 1] = P.y;
+                        } else {
+                            lm[pr * LW + cg + 16 * (jj - CR)] = P;
+                        }
                     }
                 }
                 // publish column k + 1 for the next search
-                if (k + 1 < n) {
-                    if (kc < 15) {
-                        if (cg == kc + 1) {
+                const int k1 = k + 1;
+                if (k1 < n) {
+                    const int kj1 = kc < 15 ? kj : kj + 1, kc1 = kc < 15 ? kc + 1 : 0;
 #pragma unroll
-                            for (int i = 0; i < R; ++i)
-                                colbuf[cur ^ 1][rg + 32 * i] = mk<T>(a[kj][2 * i], a[kj][2 * i + 1]);
-                        }
-                    } else if (kj + 1 < C) {
-                        if (cg == 0) {
+                    for (int jq = kj; jq <= kj + 1 && jq < C; ++jq) {
+                        if (jq == kj1 && cg == kc1) {
 #pragma unroll
-                            for (int i = 0; i < R; ++i)
-                                colbuf[cur ^ 1][rg + 32 * i] =
-                                    mk<T>(a[kj + 1][2 * i], a[kj + 1][2 * i + 1]);
+                            for (int i = 0; i < R; ++i) {
+                                C2<T> w;
+                                if (jq < CR) w = mk<T>(a[jq < CR ? jq : 0][2 * i], a[jq < CR ? jq : 0][2 * i + 1]);
+                                else w = lm[(rg + 32 * i) * LW + cg + 16 * (jq - CR)];
+                                colbuf[cur ^ 1][rg + 32 * i] = w;
+                            }
                         }
                     }
                 }
@@ -414,26 +438,31 @@ k_cell_factor_reg(const CellDesc* __restrict__ cells, const double2* __restrict_
         }
         // unscramble: X_col[pivstep[r]][pivrow[j]] = a[r][j]; padding zero
         C2<T>* Xk = X + (long long)col * np2;
-        int ps[R], pc[C];
+        int ps[R];
 #pragma unroll
         for (int i = 0; i < R; ++i) ps[i] = pivstep[rg + 32 * i];
 #pragma unroll
-        for (int jj = 0; jj < C; ++jj) pc[jj] = pivrow[cg + 16 * jj];
+        for (int jj = 0; jj < C; ++jj) {
+            const int j = cg + 16 * jj;
+            const int pcj = pivrow[j < NM ? j : 0];
 #pragma unroll
-        for (int i = 0; i < R; ++i) {
-            const int r = rg + 32 * i;
-#pragma unroll
-            for (int jj = 0; jj < C; ++jj) {
-                const int j = cg + 16 * jj;
+            for (int i = 0; i < R; ++i) {
+                const int r = rg + 32 * i;
                 const bool in = r < n && j < n;
+                C2<T> w;
+                if (jj < CR) w = mk<T>(a[jj < CR ? jj : 0][2 * i], a[jj < CR ? jj : 0][2 * i + 1]);
+                else w = lm[r * LW + cg + 16 * (jj - CR)];
                 if (r < HLp && j < HLp)
-                    Xk[xt_index(in ? ps[i] : r, in ? pc[jj] : j, HLp)] =
-                        in ? mk<T>(a[jj][2 * i], a[jj][2 * i + 1]) : zero;
+                    Xk[xt_index(in ? ps[i] : r, in ? pcj : j, HLp)] = in ? w : zero;
             }
         }
         __syncthreads();
     }
 }
+
+// LDS bytes of the LDS-resident columns of k_cell_factor_reg.
+template <typename T, int NM, int CL>
+constexpr size_t fac_lds_bytes() { return (size_t)NM * 16 * CL * sizeof(C2<T>); }
 
 template <typename T>
 __global__ void __launch_bounds__(GJ_THREADS)
@@ -455,13 +484,28 @@ void launch_cell_factor(const CellDesc* cells_dev, int ncells, const Dims& d,
                         hipStream_t st) {
 #if HZ_GJ_REG
     if (d.HLmax <= 64) {
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cell_factor_reg<T, 64>), dim3(ncells),
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cell_factor_reg<T, 64, 4, 0>), dim3(ncells),
                            dim3(GJ_THREADS), 0, st, cells_dev, diag, cz, e, Xpool, sing_flag);
         return;
     }
     if (d.HLmax <= 128) {
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cell_factor_reg<T, 128>), dim3(ncells),
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cell_factor_reg<T, 128, 8, 0>), dim3(ncells),
                            dim3(GJ_THREADS), 0, st, cells_dev, diag, cz, e, Xpool, sing_flag);
+        return;
+    }
+    if (d.HLmax <= 160) {
+        // 7 column slots in registers, 3 (48 columns) in LDS
+        constexpr size_t lds = fac_lds_bytes<T, 160, 3>();
+        static bool attr = false;
+        if (!attr) {
+            // if the device refuses, the launch fails and is reported
+            if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cell_factor_reg<T, 160, 7, 3>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+                (void)hipGetLastError();
+            attr = true;
+        }
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cell_factor_reg<T, 160, 7, 3>), dim3(ncells),
+                           dim3(GJ_THREADS), lds, st, cells_dev, diag, cz, e, Xpool, sing_flag);
         return;
     }
 #endif

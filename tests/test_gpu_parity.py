@@ -210,6 +210,25 @@ def test_single_layer_and_cell_counts():
         assert _rel(u, ref) < 1e-9
 
 
+@pytest.mark.parametrize("n,layers", [(60, 1), (100, 1), (140, 1)])
+def test_tall_cells(n, layers):
+    """Cells of height 72, 112 and 152 (padded to 80, 112 and 160): the three
+    layouts of the register-resident cell factorisation (all columns in
+    registers up to order 128, part of them in LDS up to 160)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c, omega = media.small_problem(n, 6, layers, 2, seed=11)
+    prob = Problem(c, omega, 6)
+    f = media.point_sources(n, (n // 3,), n // 2)
+    ref = prob.restrict(spla.splu(prob.H.tocsc()).solve(prob.extend(f[0]).ravel())
+                        .reshape(prob.W, prob.W))
+    _log(f"[solve] tall cells n={n} L={layers}")
+    s = hz.Solver(torch.from_numpy(c), omega, 6, layers, 2)
+    u = s.solve(torch.from_numpy(f), tol=1e-12).cpu().numpy()[0]
+    s.close()
+    assert _rel(u, ref) < 1e-9
+
+
 def test_residual_kernel(setup):
     c, omega, prob, solver, oracle = setup
     rng = np.random.default_rng(3)
