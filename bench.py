@@ -181,6 +181,39 @@ def cpu_baseline(c, omega, n_pml, src_x, src_z, nsample=8):
     }
 
 
+def local_refactor(solver, c, w, f_all, ref_idx, max_iter):
+    """Re-factorisation after a local model update (the inversion-loop use of
+    the method): velocity +2 % in a disk of radius 0.04 at the centre of the
+    domain.  Times the local path against a full re-factorisation of the same
+    model and compares the two solutions."""
+    import numpy as np
+    import torch
+    n = w.n
+    z, x = np.meshgrid(np.arange(1, n + 1) / (n + 1), np.arange(1, n + 1) / (n + 1), indexing="ij")
+    c2 = c * (1.0 + 0.02 * (((z - 0.5) ** 2 + (x - 0.5) ** 2) <= 0.04 ** 2))
+    m2 = torch.from_numpy(c2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    redone = solver.update_model_local(m2)
+    torch.cuda.synchronize()
+    t_loc = time.perf_counter() - t0
+    ua = solver.solve(f_all, tol=1e-10, max_iter=max_iter)
+    its = max(x["iters"] for x in solver.last_stats)
+    t0 = time.perf_counter()
+    solver.update_model(m2)
+    solver.factor()
+    torch.cuda.synchronize()
+    t_full = time.perf_counter() - t0
+    ub = solver.solve(f_all, tol=1e-10, max_iter=max_iter)
+    diff = max(float(torch.linalg.norm(ua[k] - ub[k]) / torch.linalg.norm(ub[k])) for k in ref_idx)
+    ncells = w.layers * w.cells
+    log(f"[bench] local update: {redone}/{ncells} cells refactored in {t_loc:.3f} s "
+        f"(full {t_full:.3f} s), rel. diff {diff:.1e}, {its} iterations")
+    return {"update": "velocity +2% in a disk of radius 0.04 at the centre",
+            "cells_refactored": redone, "cells": ncells, "local_refactor_s": t_loc,
+            "full_refactor_s": t_full, "gmres_iters": its, "max_rel_diff_vs_full": diff}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,8 +221,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="fp64,mixed",
-                    help="comma list of fp64, mixed, table3 (Krylov x preconditioner comparison)")
+    ap.add_argument("--forms", default="fp64,mixed,local",
+                    help="comma list of fp64, mixed, local (re-factorisation after a local "
+                         "model update, on the mixed context), table3 (Krylov x "
+                         "preconditioner comparison)")
     ap.add_argument("--roctx-form", default="",
                     help="mark this form's timed steps as the profiled region "
                          "(fp64_single, fp64_batched or mixed_batched)")
@@ -236,6 +271,7 @@ def main():
     for k in ref_idx:
         refs[k] = s64.solve(f_all[k:k + 1].contiguous(), tol=1e-12, max_iter=max_iter)[0]
     results = {}
+    local = None
     if "fp64" in args.forms:
         u, dt, prof = timed_solves(s64, f_all, 1e-10, args.steps, args.warmup, max_iter, True,
                                    region=args.roctx_form == "fp64_batched")
@@ -261,6 +297,8 @@ def main():
         its = max(x["iters"] for x in smx.last_stats)
         results["mixed_batched"] = (dt, prof, err, its, "c64+c128", t_facmx)
         log(f"[bench] mixed batched: {dt * 1e3:.1f} ms/step, err {err:.2e}, iters {its}")
+        if "local" in args.forms:
+            local = local_refactor(smx, c, w, f_all, ref_idx, max_iter)
         smx.close()
         del smx
     table3 = None
@@ -332,6 +370,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "table3": table3,
+        "local_refactor": local,
     }
     print(json.dumps(line), flush=True)
 

@@ -210,6 +210,20 @@ hz_status hz_misfit(hz_ctx* ctx, const void* u_ext_dev, const void* d_obs_dev, i
  * context returns to the "set up" state (hz_factor must be called again). */
 hz_status hz_update_model(hz_ctx* ctx, const double* model_dev);
 
+/* Local re-factorisation after a model update (Sec. 6: in an inversion loop
+ * the solver is modified only where the medium changed).  ctx must be
+ * factored.  model_dev: the new model, same size, kind and device layout as
+ * for hz_setup.  The coefficients are rebuilt; the cells whose local
+ * operators changed (bitwise) get new Schur factors and interface operators,
+ * and the inner SIE factors and composed operators are rebuilt for the
+ * layers holding a changed cell.  The result equals that of
+ * hz_update_model followed by hz_factor.  In the HZ_MIXED_REFINE form (whose
+ * FP64 operators are not kept) every cell is refactored.
+ * ncells_refactored: host int, or NULL; receives the number of cells redone.
+ * Errors: HZ_ESTATE if ctx is not factored; HZ_EINVAL for a bad model (ctx is
+ * then left "set up": hz_factor must be called); HZ_ESINGULAR as hz_factor. */
+hz_status hz_update_model_local(hz_ctx* ctx, const double* model_dev, int* ncells_refactored);
+
 /* Enqueue all further work of ctx on `hip_stream` (a hipStream_t, or NULL for
  * the null stream).  Waits for the work already enqueued; captured plans are
  * rebuilt for the new stream. */

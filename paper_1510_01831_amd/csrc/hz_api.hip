@@ -1099,9 +1099,9 @@ CellSolveArgs<T> base_args(hz_ctx* c) {
     return a;
 }
 
-__global__ void k_inner_diag(const LayerDesc* layers, const CellDesc* cells, const double2* CS,
-                             int j, double2* out, long long out_stride) {
-    const LayerDesc ld = layers[blockIdx.y];
+__global__ void k_inner_diag(const LayerDesc* layers, const int* lays, const CellDesc* cells,
+                             const double2* CS, int j, double2* out, long long out_stride) {
+    const LayerDesc ld = layers[lays[blockIdx.y]];
     const int HL = ld.HL;
     const int n2 = 2 * HL;
     const CellDesc cl = cells[ld.cell_begin + j];        // left of interface j
@@ -1131,6 +1131,37 @@ __global__ void k_eye(double2* a, int n) {
         a[i] = make_double2(i / n == i % n ? 1.0 : 0.0, 0.0);
 }
 
+// Per cell: whether any of its local-operator coefficients (diagonal,
+// vertical coupling, horizontal coupling) differs between two coefficient
+// sets (bitwise; the model check excludes NaN).
+__global__ void k_coef_changed(const CellDesc* cells, const double2* d0, const double2* z0,
+                               const double2* e0, const double2* d1, const double2* z1,
+                               const double2* e1, int* changed) {
+    const CellDesc cd = cells[blockIdx.x];
+    const long long n = (long long)cd.Wc * cd.HL;
+    const long long o = cd.off_coef;
+    auto ne = [](double2 a, double2 b) {
+        return __double_as_longlong(a.x) != __double_as_longlong(b.x) ||
+               __double_as_longlong(a.y) != __double_as_longlong(b.y);
+    };
+    int diff = 0;
+    for (long long i = threadIdx.x; i < n; i += blockDim.x)
+        diff |= ne(d0[o + i], d1[o + i]) || ne(z0[o + i], z1[o + i]) || ne(e0[o + i], e1[o + i]);
+    diff = __syncthreads_or(diff);
+    if (threadIdx.x == 0) changed[blockIdx.x] = diff ? 1 : 0;
+}
+
+// flag = 1 if the arrays differ anywhere (flag cleared by the caller)
+__global__ void k_any_diff(const double2* a, const double2* b, long long n, int* flag) {
+    int diff = 0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        diff |= __double_as_longlong(a[i].x) != __double_as_longlong(b[i].x) ||
+                __double_as_longlong(a[i].y) != __double_as_longlong(b[i].y);
+    diff = __syncthreads_or(diff);
+    if (threadIdx.x == 0 && diff) atomicOr(flag, 1);
+}
+
 template <typename T>
 void run_jobs(hz_ctx* c, const std::vector<LayerJob<T>>& jobs, int B);
 
@@ -1142,7 +1173,7 @@ void run_jobs(hz_ctx* c, const std::vector<LayerJob<T>>& jobs, int B);
 // [inner rhs; pair] gives the same samples as solving the inner SIE and then
 // applying [Q_x | Q_u]; the inner solve is taken out of the sequential path.
 // S^{-1} itself is the inner block LU applied to the identity.
-void build_composed(hz_ctx* c) {
+void build_composed(hz_ctx* c, const std::vector<char>& redo_layer) {
     const Dims& d = c->d;
     const int J = d.Lc - 1;
     Ops<double>& o = c->o64;
@@ -1172,6 +1203,7 @@ void build_composed(hz_ctx* c) {
     double2* IX = alloc_c<double>(c, nn);
     GemmTask<double>* tdev = (GemmTask<double>*)c->arena.alloc(sizeof(GemmTask<double>) * 2 * d.Lc);
     for (int l = 0; l < d.L; ++l) {
+        if (!redo_layer[l]) continue;
         const LayerDesc& ld = c->layers[l];
         const int NI = J * 2 * ld.HL;
         hipLaunchKernelGGL(k_eye, dim3(1024), dim3(256), 0, c->st, E, NI);
@@ -1254,10 +1286,18 @@ struct OfflineScope {              // marks launches as factorisation-stage laun
     ~OfflineScope() { c->offline = false; }
 };
 
-void factor_impl(hz_ctx* c) {
+// redo: per-cell flags of the cells to (re)factor; nullptr = every cell.
+// The inner SIE and the composed operators are rebuilt for the layers that
+// hold a redone cell.
+void factor_impl(hz_ctx* c, const std::vector<char>* redo = nullptr) {
     OfflineScope scope(c);
     const Dims& d = c->d;
     const int ncells = (int)c->cells.size();
+    std::vector<int> todo;
+    for (int i = 0; i < ncells; ++i)
+        if (!redo || (*redo)[i]) todo.push_back(i);
+    std::vector<char> redo_layer(d.L, 0);
+    for (int i : todo) redo_layer[c->cells[i].layer] = 1;
     Ops<double>& o = c->o64;
     if (!o.X) {
         o.X = alloc_c<double>(c, c->X_elems);
@@ -1268,19 +1308,26 @@ void factor_impl(hz_ctx* c) {
     }
     o.e = c->e;
     HIPCHK(hipMemsetAsync(c->flags, 0, 2 * sizeof(int), c->st));
-    // 1. cell Schur factors
+    const int nt = (int)todo.size();
+    if (nt == 0) return;
+    // 1. cell Schur factors (descriptors of the cells to factor, gathered)
     {
+        std::vector<CellDesc> sel(nt);
+        for (int i = 0; i < nt; ++i) sel[i] = c->cells[todo[i]];
+        CellDesc* d_sel = (CellDesc*)c->arena.alloc(sizeof(CellDesc) * nt);
+        upload(c, d_sel, sel.data(), sizeof(CellDesc) * nt);
         const long long ws = (long long)d.HLpmax * d.HLpmax;
-        const int batch = std::min(ncells, 1024);
+        const int batch = std::min(nt, 1024);
         double2* workbuf = alloc_c<double>(c, ws * batch);
-        for (int c0 = 0; c0 < ncells; c0 += batch) {
-            const int cnt = std::min(batch, ncells - c0);
-            launch_cell_factor<double>(c->d_cells + c0, cnt, d, c->diag, c->cz, c->e, o.X,
+        for (int c0 = 0; c0 < nt; c0 += batch) {
+            const int cnt = std::min(batch, nt - c0);
+            launch_cell_factor<double>(d_sel + c0, cnt, d, c->diag, c->cz, c->e, o.X,
                                        workbuf, ws, c->flags + 1, c->st);
             HIPCHK(hipGetLastError());
         }
         sync(c);
         c->arena.release(workbuf, sizeof(double2) * ws * batch);
+        c->arena.release(d_sel, sizeof(CellDesc) * nt);
     }
     int fl[2];
     HIPCHK(hipMemcpy(fl, c->flags, sizeof(fl), hipMemcpyDeviceToHost));
@@ -1300,12 +1347,10 @@ void factor_impl(hz_ctx* c) {
         if (hipMemGetInfo(&mfree, &mtot) != hipSuccess) { (void)hipGetLastError(); mfree = 0; }
         const long long budget = std::min<long long>(24LL << 30, std::max<long long>(4LL << 30, (long long)(mfree / 4)));
         long long budget_wgs = std::max<long long>(chunks, budget / (ystride * (long long)sizeof(double2)));
-        const int per = (int)std::min<long long>(ncells, std::max<long long>(1, budget_wgs / chunks));
+        const int per = (int)std::min<long long>(nt, std::max<long long>(1, budget_wgs / chunks));
         double2* Y = alloc_c<double>(c, ystride * (long long)per * chunks);
-        std::vector<int> list(ncells);
-        for (int i = 0; i < ncells; ++i) list[i] = i;
-        int* d_list = (int*)c->arena.alloc(sizeof(int) * ncells);
-        upload(c, d_list, list.data(), sizeof(int) * ncells);
+        int* d_list = (int*)c->arena.alloc(sizeof(int) * nt);
+        upload(c, d_list, todo.data(), sizeof(int) * nt);
         CellSolveArgs<double> a = base_args<double>(c);
         a.mode = SOLVE_PROBE;
         a.Qpool = o.Q;
@@ -1315,20 +1360,25 @@ void factor_impl(hz_ctx* c) {
         a.nb = nb;
         a.Y = Y;
         a.y_stride = ystride;
-        for (int g = 0; g < ncells; g += per) {
-            const int cnt = std::min(per, ncells - g);
+        for (int g = 0; g < nt; g += per) {
+            const int cnt = std::min(per, nt - g);
             a.cell_list = d_list + g;
             launch_cell_solve<double>(a, cnt, chunks, c->st);
             HIPCHK(hipGetLastError());
         }
         sync(c);
         c->arena.release(Y, sizeof(double2) * ystride * (long long)per * chunks);
-        c->arena.release(d_list, sizeof(int) * ncells);
+        c->arena.release(d_list, sizeof(int) * nt);
     }
     // 3. inner SIE block LU without pivoting (per layer, sequential over interfaces)
     const int J = d.Lc - 1;
+    std::vector<int> lay;                  // layers to refactor
+    for (int l = 0; l < d.L; ++l)
+        if (redo_layer[l]) lay.push_back(l);
     if (J > 0) {
-        const int L = d.L;
+        const int L = (int)lay.size();     // compact index i <-> layer lay[i]
+        int* d_lay = (int*)c->arena.alloc(sizeof(int) * L);
+        upload(c, d_lay, lay.data(), sizeof(int) * L);
         const long long bs = 4LL * d.HLmax * d.HLmax;       // (2 HLmax)^2
         double2* A = alloc_c<double>(c, bs * L);
         double2* wk = alloc_c<double>(c, bs * L);
@@ -1337,20 +1387,20 @@ void factor_impl(hz_ctx* c) {
         int* ns = (int*)c->arena.alloc(sizeof(int) * L);
         std::vector<int> hn(L);
         std::vector<double2*> hm(L), ho(L);
-        for (int l = 0; l < L; ++l) { hn[l] = 2 * c->layers[l].HL; hm[l] = A + bs * l; }
+        for (int i = 0; i < L; ++i) { hn[i] = 2 * c->layers[lay[i]].HL; hm[i] = A + bs * i; }
         upload(c, ns, hn.data(), sizeof(int) * L);
         upload(c, mats, hm.data(), sizeof(void*) * L);
         GemmTask<double>* tdev = (GemmTask<double>*)c->arena.alloc(sizeof(GemmTask<double>) * 2 * L);
         for (int j = 0; j < J; ++j) {
             hipLaunchKernelGGL(k_inner_diag, dim3(64, L), dim3(256), 0, c->st, c->d_layers,
-                               c->d_cells, o.CS, j, A, bs);
+                               d_lay, c->d_cells, o.CS, j, A, bs);
             HIPCHK(hipGetLastError());
             if (j > 0) {
                 // L_j^a = B_j^a Sinv_{j-1},  B_j^a = -(right-column samples of cell j, left probes)
                 std::vector<GemmTask<double>> t1, t2;
                 int mm = 0;
-                for (int l = 0; l < L; ++l) {
-                    const LayerDesc& ld = c->layers[l];
+                for (int i = 0; i < L; ++i) {
+                    const LayerDesc& ld = c->layers[lay[i]];
                     const int HL = ld.HL;
                     const CellDesc& cj = c->cells[ld.cell_begin + j];
                     GemmTask<double> t = blank_task<double>();
@@ -1375,8 +1425,8 @@ void factor_impl(hz_ctx* c) {
                     u.nseg = 1; u.seg_k0[0] = 0; u.seg_len[0] = HL;
                     u.seg_ptr[0] = o.CS + cj.off_CS + 2LL * HL;      // left rows, right probes
                     u.noseg = 1; u.oseg_i0[0] = 0; u.oseg_len[0] = HL;
-                    u.oseg_ptr[0] = A + bs * l;
-                    u.oseg_add0[0] = A + bs * l;
+                    u.oseg_ptr[0] = A + bs * i;
+                    u.oseg_add0[0] = A + bs * i;
                     u.alpha = 1.0;
                     u.ncol = 2 * HL;
                     t2.push_back(u);
@@ -1391,8 +1441,10 @@ void factor_impl(hz_ctx* c) {
                 HIPCHK(hipGetLastError());
                 sync(c);
             }
-            for (int l = 0; l < L; ++l)
-                ho[l] = o.Sinv + c->layers[l].off_Sinv + (long long)j * 4 * c->layers[l].HL * c->layers[l].HL;
+            for (int i = 0; i < L; ++i) {
+                const LayerDesc& ld = c->layers[lay[i]];
+                ho[i] = o.Sinv + ld.off_Sinv + (long long)j * 4 * ld.HL * ld.HL;
+            }
             upload(c, outs, ho.data(), sizeof(void*) * L);
             // inverse of an order-2HL block: pack with row stride 2HL (the A buffer is already)
             launch_invert_batch<double>(mats, outs, ns, L, wk, bs, c->flags + 1, c->st);
@@ -1407,9 +1459,10 @@ void factor_impl(hz_ctx* c) {
         c->arena.release(outs, sizeof(void*) * L);
         c->arena.release(ns, sizeof(int) * L);
         c->arena.release(tdev, sizeof(GemmTask<double>) * 2 * L);
+        c->arena.release(d_lay, sizeof(int) * L);
     }
     // 4. composed output operators
-    if (J > 0 && c->compose) build_composed(c);
+    if (J > 0 && c->compose) build_composed(c, redo_layer);
     // 5. mixed precision: complex64 copies of every operator
     if (c->prm.precision != HZ_FP64) {
         Ops<float>& f = c->o32;
@@ -2298,6 +2351,62 @@ hz_status hz_factor(hz_ctx* c) {
     clear_plans(c);
     c->state = 2;
     c->timing.t_factor = now_s() - t0;
+    return HZ_OK;
+    API_END
+}
+
+hz_status hz_update_model_local(hz_ctx* c, const double* model_dev, int* ncells_refactored) {
+    API_BEGIN
+    check_state(c, 2);
+    if (!model_dev) raise(HZ_EINVAL, "null model");
+    const Dims& d = c->d;
+    const int ncells = (int)c->cells.size();
+    double t0 = now_s();
+    std::vector<char> redo(ncells, 1);
+    if (c->prm.precision == HZ_MIXED_REFINE) {
+        // the FP64 operators of the unchanged cells were released: full factorisation
+        c->state = 1;
+        setup_coef(c, model_dev);
+    } else {
+        const long long ne = c->coef_elems;
+        const long long nax = (long long)ncells * d.Wcmax, naz = (long long)d.L * d.HLmax;
+        double2* old = alloc_c<double>(c, 3 * ne + nax + naz);
+        const size_t cb = sizeof(double2) * ne;
+        HIPCHK(hipMemcpyAsync(old, c->diag, cb, hipMemcpyDeviceToDevice, c->st));
+        HIPCHK(hipMemcpyAsync(old + ne, c->cz, cb, hipMemcpyDeviceToDevice, c->st));
+        HIPCHK(hipMemcpyAsync(old + 2 * ne, c->e, cb, hipMemcpyDeviceToDevice, c->st));
+        HIPCHK(hipMemcpyAsync(old + 3 * ne, c->ax_pool, sizeof(double2) * nax, hipMemcpyDeviceToDevice, c->st));
+        HIPCHK(hipMemcpyAsync(old + 3 * ne + nax, c->az_pool, sizeof(double2) * naz, hipMemcpyDeviceToDevice, c->st));
+        c->state = 1;                      // operators stale until refactored
+        try {
+            setup_coef(c, model_dev);
+        } catch (...) {
+            c->arena.release(old, sizeof(double2) * (3 * ne + nax + naz));
+            throw;
+        }
+        int* dchg = (int*)c->arena.alloc(sizeof(int) * (ncells + 1));
+        HIPCHK(hipMemsetAsync(dchg + ncells, 0, sizeof(int), c->st));
+        hipLaunchKernelGGL(k_coef_changed, dim3(ncells), dim3(256), 0, c->st, c->d_cells, old,
+                           old + ne, old + 2 * ne, c->diag, c->cz, c->e, dchg);
+        hipLaunchKernelGGL(k_any_diff, dim3(256), dim3(256), 0, c->st, old + 3 * ne, c->ax_pool,
+                           nax, dchg + ncells);
+        hipLaunchKernelGGL(k_any_diff, dim3(256), dim3(256), 0, c->st, old + 3 * ne + nax,
+                           c->az_pool, naz, dchg + ncells);
+        HIPCHK(hipGetLastError());
+        std::vector<int> chg(ncells + 1);
+        HIPCHK(hipMemcpyAsync(chg.data(), dchg, sizeof(int) * (ncells + 1), hipMemcpyDeviceToHost, c->st));
+        sync(c);
+        c->arena.release(dchg, sizeof(int) * (ncells + 1));
+        c->arena.release(old, sizeof(double2) * (3 * ne + nax + naz));
+        for (int i = 0; i < ncells; ++i) redo[i] = (chg[ncells] || chg[i]) ? 1 : 0;
+    }
+    int cnt = 0;
+    for (char r : redo) cnt += r;
+    factor_impl(c, &redo);
+    clear_plans(c);
+    c->state = 2;
+    c->timing.t_factor = now_s() - t0;
+    if (ncells_refactored) *ncells_refactored = cnt;
     return HZ_OK;
     API_END
 }

@@ -27,117 +27,152 @@ constexpr int GJ_NMAX = 448;    // largest matrix order handled (2 HL <= 448)
 template <typename T>
 __device__ inline T cabs2(C2<T> a) { return a.x * a.x + a.y * a.y; }
 
+// Maximum over the 64 lanes of a wave, returned to every lane: DPP steps
+// within each row of 16 lanes, row broadcasts across rows, then lane 63.
+template <int CTRL, int ROWMASK>
+__device__ inline double dpp_max_step(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xF, false);
+    const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xF, false);
+    return fmax(v, __hiloint2double(hi2, lo2));
+}
+template <int CTRL, int ROWMASK>
+__device__ inline float dpp_max_step(float v) {
+    const int b = __float_as_int(v);
+    return fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(b, b, CTRL, ROWMASK, 0xF, false)));
+}
+template <typename T>
+__device__ inline T wave_max(T v) {
+    v = dpp_max_step<0xB1, 0xF>(v);     // quad_perm [1,0,3,2]
+    v = dpp_max_step<0x4E, 0xF>(v);     // quad_perm [2,3,0,1]
+    v = dpp_max_step<0x124, 0xF>(v);    // row_ror:4
+    v = dpp_max_step<0x128, 0xF>(v);    // row_ror:8
+    v = dpp_max_step<0x142, 0xA>(v);    // row_bcast:15 into rows 1 and 3
+    v = dpp_max_step<0x143, 0xC>(v);    // row_bcast:31 into rows 2 and 3
+    if constexpr (sizeof(T) == 8) {
+        const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+        const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+        return __hiloint2double(hi, lo);
+    } else {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+    }
+}
+
 // Invert the n x n matrix in `work` (row-major, row stride n; thread-owned
 // entries: entry e = r*n + j is only ever touched by thread e % blockDim.x)
 // and write the inverse to `out` (row stride ldo).  `work` is destroyed.
-// LDS: colbuf[2][GJ_NMAX], prow[GJ_NMAX], pivrow/pivstep/used, reduction.
+// LDS: colbuf[2][GJ_NMAX], prow[GJ_NMAX], pivrow/pivstep.  Every wave runs
+// the pivot search itself (DPP wave max, then a ballot for the smallest row
+// attaining it) and keeps its own used-row flags, so a step costs two
+// barriers; a thread walks its entries with 32-bit row/column counters.
 // out_tiled > 0: write the inverse in the 16x4 MFMA tile layout of order
 // out_tiled (padded entries untouched); otherwise row-major with stride ldo.
 template <typename T>
 __device__ void gj_invert(C2<T>* work, C2<T>* out, int n, long long ldo, int* sing_flag,
                           int out_tiled = 0) {
+    constexpr int SR = (GJ_NMAX + 63) / 64;
     __shared__ C2<T> colbuf[2][GJ_NMAX];
     __shared__ C2<T> prow[GJ_NMAX];
     __shared__ int pivrow[GJ_NMAX];
     __shared__ int pivstep[GJ_NMAX];
-    __shared__ int used[GJ_NMAX];
-    __shared__ T redv[GJ_THREADS];
-    __shared__ int redi[GJ_THREADS];
-    __shared__ int s_pr;
-    __shared__ C2<T> s_inv;
 
     const int tid = threadIdx.x;
     const int nt = blockDim.x;
-    const long long nn = (long long)n * n;
-    for (int r = tid; r < n; r += nt) { used[r] = 0; pivrow[r] = r; pivstep[r] = r; }
-    // publish column 0
-    for (long long e = tid; e < nn; e += nt) {
-        int j = (int)(e % n);
-        if (j == 0) colbuf[0][e / n] = work[e];
+    const int lane = tid & 63;
+    const int nn = n * n;
+    // entry e = tid + q nt sits at (r0 + q dr + carries, c0 + q dc mod n)
+    const int dr = nt / n, dc = nt % n, r0 = tid / n, c0 = tid % n;
+    bool used[SR];
+#pragma unroll
+    for (int s = 0; s < SR; ++s) used[s] = false;
+    for (int r = tid; r < n; r += nt) { pivrow[r] = r; pivstep[r] = r; }
+    {   // publish column 0
+        int r = r0, j = c0;
+        for (int e = tid; e < nn; e += nt) {
+            if (j == 0) colbuf[0][r] = work[e];
+            r += dr; j += dc;
+            if (j >= n) { j -= n; ++r; }
+        }
     }
     __syncthreads();
     int cur = 0;
     for (int k = 0; k < n; ++k) {
         // ---- pivot search over unused rows (ties -> smallest row)
-        T best = (T)-1;
-        int bi = n;
-        for (int r = tid; r < n; r += nt) {
-            if (!used[r]) {
-                T v = cabs2<T>(colbuf[cur][r]);
-                if (v > best) { best = v; bi = r; }
-            }
+        T v[SR];
+#pragma unroll
+        for (int s = 0; s < SR; ++s) {
+            const int r = lane + 64 * s;
+            v[s] = (T)-1;
+            if (r < n && !used[s]) v[s] = cabs2<T>(colbuf[cur][r]);
         }
-        redv[tid] = best;
-        redi[tid] = bi;
-        __syncthreads();
-        for (int s = nt >> 1; s > 0; s >>= 1) {
-            if (tid < s) {
-                T v2 = redv[tid + s];
-                int i2 = redi[tid + s];
-                if (v2 > redv[tid] || (v2 == redv[tid] && i2 < redi[tid])) {
-                    redv[tid] = v2; redi[tid] = i2;
-                }
-            }
-            __syncthreads();
+        T best = v[0];
+#pragma unroll
+        for (int s = 1; s < SR; ++s) best = fmax(best, v[s]);
+        best = wave_max(best);
+        int pr = -1;
+#pragma unroll
+        for (int s = SR - 1; s >= 0; --s) {
+            const unsigned long long m = __ballot(v[s] >= (T)0 && v[s] == best);
+            if (m) pr = 64 * s + __ffsll((long long)m) - 1;
         }
-        if (tid == 0) {
-            // redi[0] == n only if no candidate compared (NaN input)
-            int pr = redi[0] < n ? redi[0] : 0;
-            C2<T> pv = colbuf[cur][pr];
-            if (redv[0] <= (T)0 || redi[0] >= n) {
-                atomicOr(sing_flag, 1);
-                s_inv = mk<T>((T)0, (T)0);
-            } else {
-                T den = (T)1 / (pv.x * pv.x + pv.y * pv.y);
-                s_inv = mk<T>(pv.x * den, -pv.y * den);
-            }
-            s_pr = pr;
-            used[pr] = 1;
-            pivrow[k] = pr;
-            pivstep[pr] = k;
+        // pr < 0 only if no candidate compared (NaN input): flag it and keep
+        // every index in range
+        if (pr < 0) { pr = 0; best = (T)0; }
+        pr = __builtin_amdgcn_readfirstlane(pr);
+#pragma unroll
+        for (int s = 0; s < SR; ++s)
+            if (pr == lane + 64 * s) used[s] = true;
+        const C2<T> pv = colbuf[cur][pr];
+        C2<T> inv = mk<T>((T)0, (T)0);
+        if (best <= (T)0) {
+            if (tid == 0) atomicOr(sing_flag, 1);
+        } else {
+            const T den = (T)1 / (pv.x * pv.x + pv.y * pv.y);
+            inv = mk<T>(pv.x * den, -pv.y * den);
         }
-        __syncthreads();
-        const int pr = s_pr;
-        const C2<T> inv = s_inv;
-        // ---- publish the pivot row (pre-update values); each thread reads
-        // only the entries of row pr it owns (e = tid mod nt)
+        if (tid == 0) { pivrow[k] = pr; pivstep[pr] = k; }
+        // ---- publish the pivot row (pre-update values); entry pr*n + j is
+        // owned by thread (pr*n + j) % nt
         {
-            const long long r0 = (long long)pr * n;
-            long long e0 = r0 + ((tid - (int)(r0 % nt)) % nt + nt) % nt;
-            for (long long e = e0; e < r0 + n; e += nt) prow[e - r0] = work[e];
+            const int rb = pr * n;
+            for (int j = ((tid - rb) % nt + nt) % nt; j < n; j += nt) prow[j] = work[rb + j];
         }
         __syncthreads();
         // ---- update, publishing column k+1 for the next search
         const int nxt = cur ^ 1;
-        for (long long e = tid; e < nn; e += nt) {
-            int r = (int)(e / n);
-            int j = (int)(e % n);
-            C2<T> v;
+        int r = r0, j = c0;
+        for (int e = tid; e < nn; e += nt) {
+            C2<T> w;
             if (r == pr) {
-                v = (j == k) ? inv : cmul(prow[j], inv);
+                w = (j == k) ? inv : cmul(prow[j], inv);
             } else {
-                C2<T> f = cmul(colbuf[cur][r], inv);
+                const C2<T> f = cmul(colbuf[cur][r], inv);
                 if (j == k) {
-                    v = mk<T>(-f.x, -f.y);
+                    w = mk<T>(-f.x, -f.y);
                 } else {
-                    C2<T> w = work[e];
-                    C2<T> pj = prow[j];
-                    v = mk<T>(w.x - (f.x * pj.x - f.y * pj.y), w.y - (f.x * pj.y + f.y * pj.x));
+                    const C2<T> a = work[e];
+                    const C2<T> pj = prow[j];
+                    w = mk<T>(a.x - (f.x * pj.x - f.y * pj.y), a.y - (f.x * pj.y + f.y * pj.x));
                 }
             }
-            work[e] = v;
-            if (j == k + 1) colbuf[nxt][r] = v;
+            work[e] = w;
+            if (j == k + 1) colbuf[nxt][r] = w;
+            r += dr; j += dc;
+            if (j >= n) { j -= n; ++r; }
         }
         cur = nxt;
         __syncthreads();
     }
     // ---- unscramble: X[pivstep[r]][pivrow[j]] = work[r][j]
-    for (long long e = tid; e < nn; e += nt) {
-        int r = (int)(e / n);
-        int j = (int)(e % n);
-        const int oi = pivstep[r], oj = pivrow[j];
-        if (out_tiled) out[xt_index(oi, oj, out_tiled)] = work[e];
-        else out[(long long)oi * ldo + oj] = work[e];
+    {
+        int r = r0, j = c0;
+        for (int e = tid; e < nn; e += nt) {
+            const int oi = pivstep[r], oj = pivrow[j];
+            if (out_tiled) out[xt_index(oi, oj, out_tiled)] = work[e];
+            else out[(long long)oi * ldo + oj] = work[e];
+            r += dr; j += dc;
+            if (j >= n) { j -= n; ++r; }
+        }
     }
     __syncthreads();
 }
@@ -215,37 +250,6 @@ k_cell_factor(const CellDesc* __restrict__ cells, const double2* __restrict__ di
 // i = p / 32 is wave-uniform but known only at run time; indexing the vector
 // with it compiles to register-relative moves (no scratch).  The column slot
 // k / 16 is made a compile-time constant by unrolling the step loop over it.
-// Maximum over the 64 lanes of a wave, returned to every lane: DPP steps
-// within each row of 16 lanes, row broadcasts across rows, then lane 63.
-template <int CTRL, int ROWMASK>
-__device__ inline double dpp_max_step(double v) {
-    const int lo = __double2loint(v), hi = __double2hiint(v);
-    const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xF, false);
-    const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xF, false);
-    return fmax(v, __hiloint2double(hi2, lo2));
-}
-template <int CTRL, int ROWMASK>
-__device__ inline float dpp_max_step(float v) {
-    const int b = __float_as_int(v);
-    return fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(b, b, CTRL, ROWMASK, 0xF, false)));
-}
-template <typename T>
-__device__ inline T wave_max(T v) {
-    v = dpp_max_step<0xB1, 0xF>(v);     // quad_perm [1,0,3,2]
-    v = dpp_max_step<0x4E, 0xF>(v);     // quad_perm [2,3,0,1]
-    v = dpp_max_step<0x124, 0xF>(v);    // row_ror:4
-    v = dpp_max_step<0x128, 0xF>(v);    // row_ror:8
-    v = dpp_max_step<0x142, 0xA>(v);    // row_bcast:15 into rows 1 and 3
-    v = dpp_max_step<0x143, 0xC>(v);    // row_bcast:31 into rows 2 and 3
-    if constexpr (sizeof(T) == 8) {
-        const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
-        const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
-        return __hiloint2double(hi, lo);
-    } else {
-        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
-    }
-}
-
 template <typename T, int N>
 using vecT = T __attribute__((ext_vector_type(N)));
 

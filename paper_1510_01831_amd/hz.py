@@ -21,7 +21,8 @@ HZ_KRYLOV_GMRES, HZ_KRYLOV_BICGSTAB = 0, 1
 
 EXPORTED = [
     "hz_setup", "hz_factor", "hz_solve", "hz_adjoint", "hz_solve_ext", "hz_adjoint_ext",
-    "hz_misfit_gradient", "hz_misfit", "hz_update_model", "hz_set_stream", "hz_get_info", "hz_get_timing",
+    "hz_misfit_gradient", "hz_misfit", "hz_update_model", "hz_update_model_local",
+    "hz_set_stream", "hz_get_info", "hz_get_timing",
     "hz_destroy", "hz_strerror", "hz_last_error", "hz_apply_layer", "hz_apply_sie",
     "hz_apply_precond", "hz_sie_rhs", "hz_cell_solve", "hz_cell_shape", "hz_residual",
     "hz_profile", "hz_profile_read",
@@ -85,6 +86,7 @@ def lib() -> ctypes.CDLL:
         L.hz_misfit_gradient.argtypes = [vp, vp, vp, i, vp]
         L.hz_misfit.argtypes = [vp, vp, vp, i, i, vp, ctypes.POINTER(d)]
         L.hz_update_model.argtypes = [vp, vp]
+        L.hz_update_model_local.argtypes = [vp, vp, ctypes.POINTER(i)]
         L.hz_set_stream.argtypes = [vp, vp]
         L.hz_get_info.argtypes = [vp, ctypes.POINTER(Info)]
         L.hz_get_timing.argtypes = [vp, ctypes.POINTER(Timing)]
@@ -170,6 +172,18 @@ class Solver:
     def update_model(self, model):
         self.model = model.to(device="cuda", dtype=self.torch.float64).contiguous()
         _check(lib().hz_update_model(self.ctx, _ptr(self.model)), "hz_update_model")
+
+    def update_model_local(self, model) -> int:
+        """New model and re-factorisation of the cells it changes (the context
+        must be factored); returns the number of cells redone."""
+        self.model = model.to(device="cuda", dtype=self.torch.float64).contiguous()
+        n = ctypes.c_int(0)
+        _check(lib().hz_update_model_local(self.ctx, _ptr(self.model), ctypes.byref(n)),
+               "hz_update_model_local")
+        info = Info()
+        _check(lib().hz_get_info(self.ctx, ctypes.byref(info)), "hz_get_info")
+        self.info = info
+        return int(n.value)
 
     def _solve(self, fn, f, tol, max_iter, ext, allow_noconv):
         torch = self.torch

@@ -210,11 +210,12 @@ def test_single_layer_and_cell_counts():
         assert _rel(u, ref) < 1e-9
 
 
-@pytest.mark.parametrize("n,layers", [(60, 1), (100, 1), (140, 1)])
+@pytest.mark.parametrize("n,layers", [(60, 1), (100, 1), (140, 1), (160, 1)])
 def test_tall_cells(n, layers):
-    """Cells of height 72, 112 and 152 (padded to 80, 112 and 160): the three
-    layouts of the register-resident cell factorisation (all columns in
-    registers up to order 128, part of them in LDS up to 160)."""
+    """Cells of height 72, 112, 152 and 172 (padded to 80, 112, 160 and 176):
+    the layouts of the register-resident cell factorisation (all columns in
+    registers up to order 128, part of them in LDS up to 160) and the general
+    Gauss-Jordan kernel beyond."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     c, omega = media.small_problem(n, 6, layers, 2, seed=11)
