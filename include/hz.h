@@ -43,6 +43,10 @@
  *      HZ_TUNE=0     fixed kernel heuristics instead of the autotuner (which
  *                    times the GEMM kernels of every solve plan and the
  *                    cell-solve batch width once per batch size);
+ *      HZ_GEMM_KIND=k  one matrix-core GEMM kernel for every solve launch
+ *                    (2: 32x32 tiles, 32-deep chunks; 3: 64x64, 16-deep;
+ *                    4: 32x32, 16-deep; 5: 32x32, 32-deep, two chunks in
+ *                    flight; 6: 64x64, two chunks in flight), no tuning;
  *      HZ_COMPOSE=0  inner SIE solved by block LU substitutions at every layer
  *                    application instead of the composed output operators;
  *      HZ_GRAPHS=0   plans launched kernel by kernel instead of replayed HIP

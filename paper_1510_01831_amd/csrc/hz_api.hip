@@ -187,6 +187,7 @@ struct hz_ctx {
     bool compose = true;           // output operators composed with the inner SIE inverse
     bool offline = false;          // inside the factorisation stage
     bool tune = true;              // autotune GEMM kernels and cell-solve widths (HZ_TUNE=0: off)
+    int force_kind = -1;           // HZ_GEMM_KIND: one matrix-core GEMM kernel for every launch
     std::map<std::string, int> cs_tuned;   // (mode, B, cells) -> cell-solve batch width
     Arena arena;
     std::vector<LayerDesc> layers;
@@ -664,6 +665,11 @@ void plan_launches(hz_ctx* c, const Plan<T>& pl, int B);
 // launch record.  Runs once, when the plan is built for a batch size.
 template <typename T>
 void tune_plan(hz_ctx* c, Plan<T>& pl, int B) {
+    if (c->force_kind >= GEMM_MFMA32) {
+        for (auto& r : pl.launches)
+            if (r.kind == L_GEMM) r.choice = c->force_kind;
+        return;
+    }
     if (!c->tune || B < 16 || pl.launches.empty()) return;
     long long in_elems = 1, out_elems = 1;
     int max_tasks = 1;
@@ -696,8 +702,9 @@ void tune_plan(hz_ctx* c, Plan<T>& pl, int B) {
         }
         upload(c, dt, tt.data(), sizeof(GemmTask<T>) * tt.size());
         float best = 1e30f;
-        for (int cand : {(int)GEMM_MFMA64, (int)GEMM_MFMA32, (int)GEMM_MFMA32K16}) {
-            if (cand == GEMM_MFMA64 && B < 64) continue;
+        for (int cand : {(int)GEMM_MFMA64, (int)GEMM_MFMA32, (int)GEMM_MFMA32K16,
+                         (int)GEMM_MFMA32D, (int)GEMM_MFMA64D}) {
+            if ((cand == GEMM_MFMA64 || cand == GEMM_MFMA64D) && B < 64) continue;
             launch_gemm<T>(dt, r.ntasks, r.max_m, B, c->st, false, cand);     // warm-up
             HIPCHK(hipEventRecord(e0, c->st));
             for (int rep = 0; rep < 3; ++rep)
@@ -2065,8 +2072,7 @@ void vol_resid(hz_ctx* c, const double2* u, const double2* f, int B, std::vector
     if (B <= 4096) {                        // one pass: norms without storing f - H u
         // gpart holds gpart_chunks * (m + 2) * B entries (m >= 1)
         const long long cap = (long long)c->gpart_chunks * (c->g_cap_m + 2);
-        const int nb = (int)std::min<long long>(std::min<long long>(cap, 2048),
-                                                std::max<long long>(1, N / 64));
+        const int nb = residual_norms_blocks(c->d.W, B, (int)std::min<long long>(cap, 1 << 20));
         launch_residual_norms(u, f, c->gdiag, c->gcx, c->gcz, c->d.W, B, c->gpart, nb, c->st);
         launch_reduce_partials(c->gpart, nb, B, c->gsmall, c->st);
         std::vector<double2> h(B);
@@ -2270,6 +2276,10 @@ hz_status hz_setup(const double* model_dev, const hz_params* prm, hz_ctx** out) 
     if (const char* g = std::getenv("HZ_GRAPHS")) c->use_graphs = std::atoi(g) != 0;
     if (const char* g = std::getenv("HZ_COMPOSE")) c->compose = std::atoi(g) != 0;
     if (const char* g = std::getenv("HZ_TUNE")) c->tune = std::atoi(g) != 0;
+    if (const char* g = std::getenv("HZ_GEMM_KIND")) {
+        const int k = std::atoi(g);
+        if (k >= GEMM_MFMA32 && k <= GEMM_MFMA64D) c->force_kind = k;
+    }
     if (c->prm.pml_beta <= 0.0) c->prm.pml_beta = 2.0;
     if (c->prm.max_batch <= 0) c->prm.max_batch = 1;
     Dims& d = c->d;

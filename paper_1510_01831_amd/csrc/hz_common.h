@@ -102,6 +102,25 @@ struct Dims {
     int HLmax, Wcmax, HLpmax;
 };
 
+// A device pointer seen as a global-memory pointer, so that accesses compile
+// to global_load / global_store.  Pointers read from a task table are
+// otherwise generic, and a generic (flat) access also counts against the LDS
+// wait counter: every LDS wait would then wait for the prefetch loads too.
+template <typename T>
+__device__ __forceinline__ C2<T> gload(const C2<T>* p) {
+    using V = T __attribute__((ext_vector_type(2)));
+    const V v = *(const __attribute__((address_space(1))) V*)p;
+    return mk<T>(v.x, v.y);
+}
+template <typename T>
+__device__ __forceinline__ void gstore(C2<T>* p, C2<T> v) {
+    using V = T __attribute__((ext_vector_type(2)));
+    V w;
+    w.x = v.x;
+    w.y = v.y;
+    *(__attribute__((address_space(1))) V*)p = w;
+}
+
 // Position of entry (i, j) of an HLp x HLp Schur inverse stored as 16x4 tiles
 // in MFMA operand order: tile (i/16, j/4), lane (i%16) + 16 (j%4).  A wave
 // reads one tile as 1 KB of contiguous complex values.
@@ -213,8 +232,10 @@ void launch_gemm(const GemmTask<T>* tasks_dev, int ntasks, int max_m, int B, hip
 // the GEMM kernel launch_gemm selects for a shape (for per-kernel profiles);
 // the matrix-core variants are 64x64 tiles / 16-deep chunks, 32x32 / 32-deep
 // and 32x32 / 16-deep
+// GEMM_MFMA32D / GEMM_MFMA64D: the 32x32 and 64x64 tiles with two chunks of
+// loads in flight (64x64 with 32-deep chunks in complex64).
 enum GemmKernel { GEMM_GEMV = 0, GEMM_TILED = 1, GEMM_MFMA32 = 2, GEMM_MFMA64 = 3,
-                  GEMM_MFMA32K16 = 4 };
+                  GEMM_MFMA32K16 = 4, GEMM_MFMA32D = 5, GEMM_MFMA64D = 6 };
 GemmKernel gemm_kernel(int ntasks, int max_m, int B);
 const char* gemm_kernel_name(GemmKernel k);
 
@@ -271,6 +292,7 @@ void launch_ext_to_out(const double2* u_ext, int B, int n, int p, int W, double2
                        int physical, int conj, hipStream_t st);
 // (sum |f - H u|^2, sum |f|^2) per column over node ranges -> partial[nblocks][B]
 // (needs 16 B bytes of LDS)
+int residual_norms_blocks(int W, int B, int cap);
 void launch_residual_norms(const double2* u, const double2* f, const double2* gdiag,
                            const double2* gcx, const double2* gcz, int W, int B, double2* partial,
                            int nblocks, hipStream_t st);

@@ -84,14 +84,14 @@ __device__ inline C2<T> cell_source(const CellSolveArgs<T>& a, const CellDesc& c
             if (top && (j == p || j == p - 1)) {
                 double2 ix = cinv(a.alpha_x[(long long)cd.gidx * a.Wcmax + k]);
                 C2<T> s = to_t<T>(mk<double>(ix.x * ih2, ix.y * ih2));
-                if (j == p) v = cfma(s, top[(0 * W + col) * B + b], v);
-                else v = csub(v, cmul(s, top[(1 * W + col) * B + b]));
+                if (j == p) v = cfma(s, gload<T>(top + (0 * W + col) * B + b), v);
+                else v = csub(v, cmul(s, gload<T>(top + (1 * W + col) * B + b)));
             }
             if (bot && (j == p + ld.nl - 1 || j == p + ld.nl)) {
                 double2 ix = cinv(a.alpha_x[(long long)cd.gidx * a.Wcmax + k]);
                 C2<T> s = to_t<T>(mk<double>(ix.x * ih2, ix.y * ih2));
-                if (j == p + ld.nl - 1) v = cfma(s, bot[(1 * W + col) * B + b], v);
-                else v = csub(v, cmul(s, bot[(0 * W + col) * B + b]));
+                if (j == p + ld.nl - 1) v = cfma(s, gload<T>(bot + (1 * W + col) * B + b), v);
+                else v = csub(v, cmul(s, gload<T>(bot + (0 * W + col) * B + b)));
             }
         }
         if (a.inner_v && ld.J > 0) {
@@ -104,13 +104,13 @@ __device__ inline C2<T> cell_source(const CellSolveArgs<T>& a, const CellDesc& c
                 C2<T> s = to_t<T>(mk<double>(iz.x * ih2, iz.y * ih2));
                 if (kl) {
                     const int jf = cd.cell - 1;
-                    if (k == p) v = cfma(s, iv[(((long long)jf * 2 + 0) * HL + j) * B + b], v);
-                    else v = csub(v, cmul(s, iv[(((long long)jf * 2 + 1) * HL + j) * B + b]));
+                    if (k == p) v = cfma(s, gload<T>(iv + (((long long)jf * 2 + 0) * HL + j) * B + b), v);
+                    else v = csub(v, cmul(s, gload<T>(iv + (((long long)jf * 2 + 1) * HL + j) * B + b)));
                 }
                 if (kr) {
                     const int jf = cd.cell;
-                    if (k == p + cd.nc) v = csub(v, cmul(s, iv[(((long long)jf * 2 + 0) * HL + j) * B + b]));
-                    else v = cfma(s, iv[(((long long)jf * 2 + 1) * HL + j) * B + b], v);
+                    if (k == p + cd.nc) v = csub(v, cmul(s, gload<T>(iv + (((long long)jf * 2 + 0) * HL + j) * B + b)));
+                    else v = cfma(s, gload<T>(iv + (((long long)jf * 2 + 1) * HL + j) * B + b), v);
                 }
             }
         }
@@ -185,13 +185,13 @@ __device__ inline C2<T> cell_source_ctx(const CellSolveArgs<T>& a, const CellDes
             const long long col = cd.col0 + k;
             if (sc.top && (j == p || j == p - 1)) {
                 const C2<T> s = to_t<T>(sc.ixs[k]);
-                if (j == p) v = cfma(s, sc.top[(0 * W + col) * B + b], v);
-                else v = csub(v, cmul(s, sc.top[(1 * W + col) * B + b]));
+                if (j == p) v = cfma(s, gload<T>(sc.top + (0 * W + col) * B + b), v);
+                else v = csub(v, cmul(s, gload<T>(sc.top + (1 * W + col) * B + b)));
             }
             if (sc.bot && (j == p + ld.nl - 1 || j == p + ld.nl)) {
                 const C2<T> s = to_t<T>(sc.ixs[k]);
-                if (j == p + ld.nl - 1) v = cfma(s, sc.bot[(1 * W + col) * B + b], v);
-                else v = csub(v, cmul(s, sc.bot[(0 * W + col) * B + b]));
+                if (j == p + ld.nl - 1) v = cfma(s, gload<T>(sc.bot + (1 * W + col) * B + b), v);
+                else v = csub(v, cmul(s, gload<T>(sc.bot + (0 * W + col) * B + b)));
             }
         }
         if (sc.iv) {
@@ -202,13 +202,13 @@ __device__ inline C2<T> cell_source_ctx(const CellSolveArgs<T>& a, const CellDes
                 const C2<T> s = to_t<T>(sc.izs[j]);
                 if (kl) {
                     const int jf = cd.cell - 1;
-                    if (k == p) v = cfma(s, sc.iv[(((long long)jf * 2 + 0) * HL + j) * B + b], v);
-                    else v = csub(v, cmul(s, sc.iv[(((long long)jf * 2 + 1) * HL + j) * B + b]));
+                    if (k == p) v = cfma(s, gload<T>(sc.iv + (((long long)jf * 2 + 0) * HL + j) * B + b), v);
+                    else v = csub(v, cmul(s, gload<T>(sc.iv + (((long long)jf * 2 + 1) * HL + j) * B + b)));
                 }
                 if (kr) {
                     const int jf = cd.cell;
-                    if (k == p + cd.nc) v = csub(v, cmul(s, sc.iv[(((long long)jf * 2 + 0) * HL + j) * B + b]));
-                    else v = cfma(s, sc.iv[(((long long)jf * 2 + 1) * HL + j) * B + b], v);
+                    if (k == p + cd.nc) v = csub(v, cmul(s, gload<T>(sc.iv + (((long long)jf * 2 + 0) * HL + j) * B + b)));
+                    else v = cfma(s, gload<T>(sc.iv + (((long long)jf * 2 + 1) * HL + j) * B + b), v);
                 }
             }
         }

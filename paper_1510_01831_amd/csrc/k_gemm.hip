@@ -31,9 +31,11 @@ __device__ inline void epilogue(const GemmTask<T>& t, int i, int b, C2<T> acc) {
         if (rel >= 0 && rel < t.oseg_len[s]) {
             const long long off = (long long)rel * t.ldo + b;
             C2<T> v = cscale(acc, t.alpha);
-            if (t.oseg_add0[s]) v = cadd(v, t.oseg_add0[s][off]);
-            if (t.oseg_add1[s]) v = cadd(v, cscale(t.oseg_add1[s][off], t.c1[s]));
-            t.oseg_ptr[s][off] = v;
+            const C2<T>* a0 = t.oseg_add0[s];
+            const C2<T>* a1 = t.oseg_add1[s];
+            if (a0) v = cadd(v, gload<T>(a0 + off));
+            if (a1) v = cadd(v, cscale(gload<T>(a1 + off), t.c1[s]));
+            gstore<T>(t.oseg_ptr[s] + off, v);
             return;
         }
     }
@@ -54,7 +56,9 @@ __global__ void __launch_bounds__(GV_THREADS) k_gemv(const GemmTask<T>* __restri
             const C2<T>* xp = t.seg_ptr[s];
             if (!xp) continue;
             const int k0 = t.seg_k0[s], len = t.seg_len[s];
-            for (int kk = lane; kk < len; kk += 64) acc = cfma(Ar[k0 + kk], xp[(long long)kk * t.ldx], acc);
+            const long long ldx = t.ldx;
+            for (int kk = lane; kk < len; kk += 64)
+                acc = cfma(gload<T>(Ar + k0 + kk), gload<T>(xp + (long long)kk * ldx), acc);
         }
         for (int d = 32; d > 0; d >>= 1) {
             C2<T> o = shfl_down_c<T>(acc, d);
@@ -93,13 +97,13 @@ k_gemm_tiled(const GemmTask<T>* __restrict__ tasks, int B) {
             for (int idx = tid; idx < TM * TK; idx += GV_THREADS) {
                 const int r = idx / TK, q = idx % TK;
                 const int i = i0 + r;
-                As[r][q] = (i < t.m && kc + q < len) ? t.A[(long long)i * t.lda + k0 + kc + q]
+                As[r][q] = (i < t.m && kc + q < len) ? gload<T>(t.A + (long long)i * t.lda + k0 + kc + q)
                                                      : mk<T>((T)0, (T)0);
             }
             for (int idx = tid; idx < TK * TB; idx += GV_THREADS) {
                 const int q = idx / TB, c = idx % TB;
                 const int b = b0 + c;
-                Xs[q][c] = (kc + q < len && b < B) ? xp[(long long)(kc + q) * t.ldx + b]
+                Xs[q][c] = (kc + q < len && b < B) ? gload<T>(xp + (long long)(kc + q) * t.ldx + b)
                                                    : mk<T>((T)0, (T)0);
             }
             __syncthreads();
@@ -138,18 +142,21 @@ struct GemmStage {
 
     __device__ __forceinline__ void load(const GemmTask<T>& t, int sg, int kc, int i0, int b0,
                                          int B, int tid) {
+        // task fields read once per chunk (not once per guarded load)
         const C2<T>* xp = t.seg_ptr[sg];
-        const int k0 = t.seg_k0[sg], len = t.seg_len[sg];
+        const C2<T>* Ap = t.A;
+        const long long lda = t.lda, ldx = t.ldx;
+        const int k0 = t.seg_k0[sg], len = t.seg_len[sg], m = t.m;
 #pragma unroll
         for (int e = 0; e < NA; ++e) {
             const int idx = tid + e * GV_THREADS, r = idx / KC, q = idx % KC, i = i0 + r;
-            a[e] = (i < t.m && kc + q < len) ? t.A[(long long)i * t.lda + k0 + kc + q]
-                                             : mk<T>((T)0, (T)0);
+            a[e] = (i < m && kc + q < len) ? gload<T>(Ap + (long long)i * lda + k0 + kc + q)
+                                           : mk<T>((T)0, (T)0);
         }
 #pragma unroll
         for (int e = 0; e < NX; ++e) {
             const int idx = tid + e * GV_THREADS, q = idx / TBM, c = idx % TBM;
-            x[e] = (kc + q < len && b0 + c < B) ? xp[(long long)(kc + q) * t.ldx + b0 + c]
+            x[e] = (kc + q < len && b0 + c < B) ? gload<T>(xp + (long long)(kc + q) * ldx + b0 + c)
                                                 : mk<T>((T)0, (T)0);
         }
     }
@@ -186,7 +193,10 @@ __device__ __forceinline__ int xcd_tile(int L, int total) {
     return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + local;
 }
 
-template <typename T, int MT, int TBM, int KC, bool OFFLINE>
+// DEEP: two register stages, so the loads of chunk c+2 are issued while chunk
+// c is multiplied and chunk c+1 waits in registers (two chunk periods to hide
+// the load latency instead of one).
+template <typename T, int MT, int TBM, int KC, bool OFFLINE, bool DEEP = false>
 __global__ void __launch_bounds__(GV_THREADS, 2)
 k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col_tiles) {
     constexpr int RTW = MT / 32;                 // row tiles per wave
@@ -213,9 +223,24 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
     for (int a = 0; a < RTW; ++a)
 #pragma unroll
         for (int c = 0; c < CTW; ++c) acc[a][c].zero();
+    auto multiply = [&](int buf) {
+#pragma unroll
+        for (int s4 = 0; s4 < KC / 4; ++s4) {
+            C2<T> av[RTW], bv[CTW];
+#pragma unroll
+            for (int a = 0; a < RTW; ++a) av[a] = As[buf][wr + a * 16 + lc][s4 * 4 + lk];
+#pragma unroll
+            for (int c = 0; c < CTW; ++c) bv[c] = Xs[buf][s4 * 4 + lk][wc + c * 16 + lc];
+#pragma unroll
+            for (int a = 0; a < RTW; ++a)
+#pragma unroll
+                for (int c = 0; c < CTW; ++c)
+                    acc[a][c].add(av[a].x, av[a].y, bv[c].x, bv[c].y);
+        }
+    };
     int sg = 0, kc = -KC;
     next_chunk<T, KC>(t, sg, kc);
-    if (sg < t.nseg) {
+    if (sg < t.nseg && !DEEP) {
         GemmStage<T, MT, TBM, KC> stage;
         stage.load(t, sg, kc, i0, b0, B, tid);
         stage.stash(As[0], Xs[0], tid);
@@ -226,25 +251,45 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
             next_chunk<T, KC>(t, ns, nk);
             const bool more = ns < t.nseg;
             if (more) stage.load(t, ns, nk, i0, b0, B, tid);
-#pragma unroll
-            for (int s4 = 0; s4 < KC / 4; ++s4) {
-                C2<T> av[RTW], bv[CTW];
-#pragma unroll
-                for (int a = 0; a < RTW; ++a) av[a] = As[buf][wr + a * 16 + lc][s4 * 4 + lk];
-#pragma unroll
-                for (int c = 0; c < CTW; ++c) bv[c] = Xs[buf][s4 * 4 + lk][wc + c * 16 + lc];
-#pragma unroll
-                for (int a = 0; a < RTW; ++a)
-#pragma unroll
-                    for (int c = 0; c < CTW; ++c)
-                        acc[a][c].add(av[a].x, av[a].y, bv[c].x, bv[c].y);
-            }
+            multiply(buf);
             if (!more) break;
             stage.stash(As[buf ^ 1], Xs[buf ^ 1], tid);   // last read two barriers ago
             __syncthreads();
             buf ^= 1;
             sg = ns;
             kc = nk;
+        }
+    } else if (sg < t.nseg) {
+        // chunk positions: (s0,k0) in LDS, (s1,k1) in registers p, (s2,k2)
+        // being loaded into registers q; the two register stages swap roles
+        // every chunk (loop unrolled by two so that they keep fixed names)
+        GemmStage<T, MT, TBM, KC> p, q;
+        p.load(t, sg, kc, i0, b0, B, tid);
+        p.stash(As[0], Xs[0], tid);
+        int s1 = sg, k1 = kc;
+        next_chunk<T, KC>(t, s1, k1);
+        if (s1 < t.nseg) p.load(t, s1, k1, i0, b0, B, tid);
+        __syncthreads();
+        int buf = 0;
+        while (true) {
+            int s2 = s1, k2 = k1;
+            if (s1 < t.nseg) next_chunk<T, KC>(t, s2, k2);
+            if (s2 < t.nseg) q.load(t, s2, k2, i0, b0, B, tid);
+            multiply(buf);
+            if (s1 >= t.nseg) break;
+            p.stash(As[buf ^ 1], Xs[buf ^ 1], tid);       // last read two barriers ago
+            __syncthreads();
+            buf ^= 1;
+            int s3 = s2, k3 = k2;
+            if (s2 < t.nseg) next_chunk<T, KC>(t, s3, k3);
+            if (s3 < t.nseg) p.load(t, s3, k3, i0, b0, B, tid);
+            multiply(buf);
+            if (s2 >= t.nseg) break;
+            q.stash(As[buf ^ 1], Xs[buf ^ 1], tid);
+            __syncthreads();
+            buf ^= 1;
+            s1 = s3;
+            k1 = k3;
         }
     }
 #pragma unroll
@@ -289,6 +334,8 @@ const char* gemm_kernel_name(GemmKernel k) {
     case GEMM_TILED: return "gemm_tiled";
     case GEMM_MFMA64: return "gemm_mfma64";
     case GEMM_MFMA32K16: return "gemm_mfma32k16";
+    case GEMM_MFMA32D: return "gemm_mfma32d";
+    case GEMM_MFMA64D: return "gemm_mfma64d";
     default: return "gemm_mfma32";
     }
 }
@@ -305,6 +352,15 @@ void launch_gemm_mfma(GemmKernel kind, const GemmTask<T>* tasks_dev, int ntasks,
     } else if (kind == GEMM_MFMA32K16) {
         const int rt = (max_m + 31) / 32, ct = (B + 31) / 32;
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 16, OFFLINE>),
+                           dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct);
+    } else if (kind == GEMM_MFMA32D) {
+        const int rt = (max_m + 31) / 32, ct = (B + 31) / 32;
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 32, OFFLINE, true>),
+                           dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct);
+    } else if (kind == GEMM_MFMA64D) {
+        const int rt = (max_m + 63) / 64, ct = (B + 63) / 64;
+        constexpr int KCD = sizeof(T) == 4 ? 32 : 16;
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 64, 64, KCD, OFFLINE, true>),
                            dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct);
     } else {
         const int rt = (max_m + 31) / 32, ct = (B + 31) / 32;

@@ -208,7 +208,8 @@ k_dots(const double2* V, long long vstride, int nv, const double2* w, long long 
 #pragma unroll
                 for (int v = 0; v < DV; ++v) {
                     if (v < nvb) {
-                        const double2 a = V ? V[(v0 + v) * vstride + q] : c;
+                        double2 a = c;
+                        if (V) a = gload<double>(V + (v0 + v) * vstride + q);
                         acc[v].x += a.x * c.x + a.y * c.y;
                         acc[v].y += a.x * c.y - a.y * c.x;
                     }
@@ -516,9 +517,91 @@ k_residual_norms(const double2* __restrict__ u, const double2* __restrict__ f,
     for (int b = threadIdx.x; b < B; b += blockDim.x)
         partial[(long long)blockIdx.x * B + b] = make_double2(rn_sh[2 * b], rn_sh[2 * b + 1]);
 }
+// Same norms for B <= 256 by marching down the grid: a workgroup owns XW =
+// 256 / B adjacent grid columns and a band of zb rows; a thread owns one
+// (column, RHS) and carries u at rows z - 1, z, z + 1 in registers, so each
+// entry of u and f is read from HBM once (a node-ordered sweep re-reads the
+// rows above and below: one row of the batch is larger than an XCD's L2).
+// Workgroups are numbered so that each XCD (slot L runs on XCD L mod 8)
+// takes one contiguous run of (band, column group): the x neighbours then
+// come from the same L2.
+__global__ void __launch_bounds__(256)
+k_residual_norms_march(const double2* __restrict__ u, const double2* __restrict__ f,
+                       const double2* __restrict__ gd, const double2* __restrict__ gcx,
+                       const double2* __restrict__ gcz, int W, int B, int XW, int nxg, int zb,
+                       double2* __restrict__ partial) {
+    extern __shared__ double rn_sh[];
+    for (int i = threadIdx.x; i < 2 * B; i += blockDim.x) rn_sh[i] = 0.0;
+    const int total = (int)gridDim.x, Lb = (int)blockIdx.x;
+    const int xcd = Lb & 7, loc = Lb >> 3, q8 = total >> 3, r8 = total & 7;
+    const int tile = (xcd < r8 ? xcd * (q8 + 1) : r8 * (q8 + 1) + (xcd - r8) * q8) + loc;
+    const int xg = tile % nxg, zc = tile / nxg;
+    const int xo = threadIdx.x / B, b = threadIdx.x % B;
+    const int x = xg * XW + xo;
+    const int z0 = zc * zb, z1 = min(W, z0 + zb);
+    __syncthreads();
+    double sr = 0.0, sf = 0.0;
+    if (xo < XW && x < W && z0 < z1) {
+        const long long WB = (long long)W * B;
+        const double2 zero = make_double2(0.0, 0.0);
+        auto at = [&](int z, int xx) { return ((long long)z * W + xx) * B + b; };
+        double2 up = zero;
+        if (z0 > 0) up = gload<double>(u + at(z0 - 1, x));
+        double2 uc = gload<double>(u + at(z0, x));
+#pragma unroll 4
+        for (int z = z0; z < z1; ++z) {
+            const long long q = at(z, x);
+            const long long g = (long long)z * W + x;
+            double2 un = zero;
+            if (z + 1 < W) un = gload<double>(u + q + WB);
+            double2 acc = cmul(gd[g], uc);
+            if (x + 1 < W) acc = cfma(gcx[g], gload<double>(u + q + B), acc);
+            if (x > 0) acc = cfma(gcx[g - 1], gload<double>(u + q - B), acc);
+            if (z + 1 < W) acc = cfma(gcz[g], un, acc);
+            if (z > 0) acc = cfma(gcz[g - W], up, acc);
+            const double2 fv = gload<double>(f + q);
+            const double rx = fv.x - acc.x, ry = fv.y - acc.y;
+            sr += rx * rx + ry * ry;
+            sf += fv.x * fv.x + fv.y * fv.y;
+            up = uc;
+            uc = un;
+        }
+    }
+    if (xo < XW) {
+        atomicAdd(&rn_sh[2 * b], sr);
+        atomicAdd(&rn_sh[2 * b + 1], sf);
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < B; c += blockDim.x)
+        partial[(long long)blockIdx.x * B + c] = make_double2(rn_sh[2 * c], rn_sh[2 * c + 1]);
+}
+
+// Workgroups (= partial rows) of launch_residual_norms for a partial buffer
+// of cap rows: up to 8 row bands per column group when marching, else the
+// node-ordered kernel with at most 2048 workgroups.
+int residual_norms_blocks(int W, int B, int cap) {
+    const long long nodes = (long long)W * W;
+    const int flat = (int)std::max<long long>(1, std::min<long long>(std::min(cap, 2048), nodes / 64));
+    if (B > 256) return flat;
+    const int XW = 256 / B, nxg = (W + XW - 1) / XW;
+    if (nxg > cap) return flat;
+    return nxg * std::max(1, std::min(8, cap / nxg));
+}
+
 void launch_residual_norms(const double2* u, const double2* f, const double2* gdiag,
                            const double2* gcx, const double2* gcz, int W, int B, double2* partial,
                            int nblocks, hipStream_t st) {
+    const int XW = B <= 256 ? 256 / B : 1, nxg = (W + XW - 1) / XW;
+    if (B <= 256 && nblocks >= nxg && nblocks % nxg == 0 && nblocks / nxg <= 8) {
+        // marching layout (residual_norms_blocks gives a multiple of nxg
+        // here; nz bands of zb rows cover all W rows)
+        const int nz = nblocks / nxg;
+        const int zb = (W + nz - 1) / nz;
+        hipLaunchKernelGGL(k_residual_norms_march, dim3(nblocks), dim3(256),
+                           sizeof(double) * 2 * B, st, u, f, gdiag, gcx, gcz, W, B, XW, nxg, zb,
+                           partial);
+        return;
+    }
     const long long nodes = (long long)W * W;
     const long long per = (nodes + nblocks - 1) / nblocks;
     hipLaunchKernelGGL(k_residual_norms, dim3(nblocks), dim3(256), sizeof(double) * 2 * B, st, u,

@@ -210,6 +210,28 @@ def test_single_layer_and_cell_counts():
         assert _rel(u, ref) < 1e-9
 
 
+@pytest.mark.parametrize("kind", [2, 3, 4, 5, 6])
+def test_every_gemm_kernel(kind, monkeypatch):
+    """Every matrix-core GEMM variant the autotuner may pick, forced for all
+    launches of the FP64 and the mixed form, against the sparse direct solve."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c, omega = media.small_problem(N, P, L, LC, seed=5)
+    prob = Problem(c, omega, P)
+    xs = tuple(range(1, 41))                          # 40 sources
+    f = media.point_sources(N, xs, 17)
+    lu = spla.splu(prob.H.tocsc())
+    monkeypatch.setenv("HZ_GEMM_KIND", str(kind))
+    for prec in (hz.HZ_FP64, hz.HZ_MIXED):
+        _log(f"[gemm kind={kind}] precision={prec} B={len(xs)}")
+        s = hz.Solver(torch.from_numpy(c), omega, P, L, LC, precision=prec, max_batch=len(xs))
+        u = s.solve(torch.from_numpy(f), tol=1e-12 if prec == hz.HZ_FP64 else 1e-11).cpu().numpy()
+        s.close()
+        for bb in (0, 17, 39):
+            ref = prob.restrict(lu.solve(prob.extend(f[bb]).ravel()).reshape(prob.W, prob.W))
+            assert _rel(u[bb], ref) < 1e-9
+
+
 @pytest.mark.parametrize("n,layers", [(60, 1), (100, 1), (140, 1), (160, 1)])
 def test_tall_cells(n, layers):
     """Cells of height 72, 112, 152 and 172 (padded to 80, 112, 160 and 176):
