@@ -134,31 +134,60 @@ k_gemm_tiled(const GemmTask<T>* __restrict__ tasks, int B) {
 // barrier per chunk separates the loads from the products.  The 4 waves form
 // a 2 x 2 grid, each computing (MT/2) x (TBM/2) as 16x16 complex tiles (four
 // real MFMAs per 4-deep k step).
+// Per-thread operand pointers for the current input segment: set once per
+// segment, so loading a chunk costs one offset add per element instead of
+// the row/column index arithmetic.
+template <typename T, int MT, int TBM, int KC>
+struct GemmCursor {
+    static constexpr int NA = MT * KC / GV_THREADS;    // A entries per thread
+    static constexpr int NX = KC * TBM / GV_THREADS;   // x entries per thread
+    const C2<T>* ab[NA];
+    const C2<T>* xb[NX];
+    int aq[NA], xq[NX];     // k offset inside a chunk; -1: row / column out of range
+    long long ldx;
+    int sg, len;
+
+    __device__ __forceinline__ void set(const GemmTask<T>& t, int s, int i0, int b0, int B,
+                                        int tid) {
+        sg = s;
+        len = t.seg_len[s];
+        ldx = t.ldx;
+        const C2<T>* A = t.A;
+        const C2<T>* xp = t.seg_ptr[s];
+        const long long lda = t.lda;
+        const int k0 = t.seg_k0[s], m = t.m;
+#pragma unroll
+        for (int e = 0; e < NA; ++e) {
+            const int idx = tid + e * GV_THREADS, r = idx / KC, q = idx % KC, i = i0 + r;
+            aq[e] = i < m ? q : -1;
+            ab[e] = A + (long long)(i < m ? i : 0) * lda + k0 + q;
+        }
+#pragma unroll
+        for (int e = 0; e < NX; ++e) {
+            const int idx = tid + e * GV_THREADS, q = idx / TBM, c = idx % TBM;
+            xq[e] = b0 + c < B ? q : -1;
+            xb[e] = xp + (long long)q * ldx + (b0 + c < B ? b0 + c : 0);
+        }
+    }
+};
+
 template <typename T, int MT, int TBM, int KC>
 struct GemmStage {
     static constexpr int NA = MT * KC / GV_THREADS;    // A entries per thread
     static constexpr int NX = KC * TBM / GV_THREADS;   // x entries per thread
     C2<T> a[NA], x[NX];
 
-    __device__ __forceinline__ void load(const GemmTask<T>& t, int sg, int kc, int i0, int b0,
-                                         int B, int tid) {
-        // task fields read once per chunk (not once per guarded load)
-        const C2<T>* xp = t.seg_ptr[sg];
-        const C2<T>* Ap = t.A;
-        const long long lda = t.lda, ldx = t.ldx;
-        const int k0 = t.seg_k0[sg], len = t.seg_len[sg], m = t.m;
+    // chunk starting at k offset kc of the cursor's segment
+    __device__ __forceinline__ void load(const GemmCursor<T, MT, TBM, KC>& cu, int kc) {
+        const long long xo = (long long)kc * cu.ldx;
 #pragma unroll
-        for (int e = 0; e < NA; ++e) {
-            const int idx = tid + e * GV_THREADS, r = idx / KC, q = idx % KC, i = i0 + r;
-            a[e] = (i < m && kc + q < len) ? gload<T>(Ap + (long long)i * lda + k0 + kc + q)
-                                           : mk<T>((T)0, (T)0);
-        }
+        for (int e = 0; e < NA; ++e)
+            a[e] = (cu.aq[e] >= 0 && kc + cu.aq[e] < cu.len) ? gload<T>(cu.ab[e] + kc)
+                                                               : mk<T>((T)0, (T)0);
 #pragma unroll
-        for (int e = 0; e < NX; ++e) {
-            const int idx = tid + e * GV_THREADS, q = idx / TBM, c = idx % TBM;
-            x[e] = (kc + q < len && b0 + c < B) ? gload<T>(xp + (long long)(kc + q) * ldx + b0 + c)
-                                                : mk<T>((T)0, (T)0);
-        }
+        for (int e = 0; e < NX; ++e)
+            x[e] = (cu.xq[e] >= 0 && kc + cu.xq[e] < cu.len) ? gload<T>(cu.xb[e] + xo)
+                                                               : mk<T>((T)0, (T)0);
     }
     __device__ __forceinline__ void stash(C2<T> (*As)[KC + 1], C2<T> (*Xs)[TBM + 1], int tid) const {
 #pragma unroll
@@ -240,9 +269,16 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
     };
     int sg = 0, kc = -KC;
     next_chunk<T, KC>(t, sg, kc);
+    GemmCursor<T, MT, TBM, KC> cu;
+    // load chunk (s, k), moving the cursor to segment s first if needed
+    auto load = [&](GemmStage<T, MT, TBM, KC>& st, int s, int k) {
+        if (s != cu.sg) cu.set(t, s, i0, b0, B, tid);
+        st.load(cu, k);
+    };
+    cu.sg = -1;
     if (sg < t.nseg && !DEEP) {
         GemmStage<T, MT, TBM, KC> stage;
-        stage.load(t, sg, kc, i0, b0, B, tid);
+        load(stage, sg, kc);
         stage.stash(As[0], Xs[0], tid);
         __syncthreads();
         int buf = 0;
@@ -250,7 +286,7 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
             int ns = sg, nk = kc;
             next_chunk<T, KC>(t, ns, nk);
             const bool more = ns < t.nseg;
-            if (more) stage.load(t, ns, nk, i0, b0, B, tid);
+            if (more) load(stage, ns, nk);
             multiply(buf);
             if (!more) break;
             stage.stash(As[buf ^ 1], Xs[buf ^ 1], tid);   // last read two barriers ago
@@ -264,17 +300,17 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
         // being loaded into registers q; the two register stages swap roles
         // every chunk (loop unrolled by two so that they keep fixed names)
         GemmStage<T, MT, TBM, KC> p, q;
-        p.load(t, sg, kc, i0, b0, B, tid);
+        load(p, sg, kc);
         p.stash(As[0], Xs[0], tid);
         int s1 = sg, k1 = kc;
         next_chunk<T, KC>(t, s1, k1);
-        if (s1 < t.nseg) p.load(t, s1, k1, i0, b0, B, tid);
+        if (s1 < t.nseg) load(p, s1, k1);
         __syncthreads();
         int buf = 0;
         while (true) {
             int s2 = s1, k2 = k1;
             if (s1 < t.nseg) next_chunk<T, KC>(t, s2, k2);
-            if (s2 < t.nseg) q.load(t, s2, k2, i0, b0, B, tid);
+            if (s2 < t.nseg) load(q, s2, k2);
             multiply(buf);
             if (s1 >= t.nseg) break;
             p.stash(As[buf ^ 1], Xs[buf ^ 1], tid);       // last read two barriers ago
@@ -282,7 +318,7 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
             buf ^= 1;
             int s3 = s2, k3 = k2;
             if (s2 < t.nseg) next_chunk<T, KC>(t, s3, k3);
-            if (s3 < t.nseg) p.load(t, s3, k3, i0, b0, B, tid);
+            if (s3 < t.nseg) load(p, s3, k3);
             multiply(buf);
             if (s2 >= t.nseg) break;
             q.stash(As[buf ^ 1], Xs[buf ^ 1], tid);
