@@ -703,8 +703,10 @@ void tune_plan(hz_ctx* c, Plan<T>& pl, int B) {
         upload(c, dt, tt.data(), sizeof(GemmTask<T>) * tt.size());
         float best = 1e30f;
         for (int cand : {(int)GEMM_MFMA64, (int)GEMM_MFMA32, (int)GEMM_MFMA32K16,
-                         (int)GEMM_MFMA32D, (int)GEMM_MFMA64D}) {
-            if ((cand == GEMM_MFMA64 || cand == GEMM_MFMA64D) && B < 64) continue;
+                         (int)GEMM_MFMA32D, (int)GEMM_MFMA64D, (int)GEMM_MFMA32X64,
+                         (int)GEMM_MFMA64X32}) {
+            if ((cand == GEMM_MFMA64 || cand == GEMM_MFMA64D || cand == GEMM_MFMA32X64) && B < 64)
+                continue;
             launch_gemm<T>(dt, r.ntasks, r.max_m, B, c->st, false, cand);     // warm-up
             HIPCHK(hipEventRecord(e0, c->st));
             for (int rep = 0; rep < 3; ++rep)
@@ -2278,7 +2280,7 @@ hz_status hz_setup(const double* model_dev, const hz_params* prm, hz_ctx** out) 
     if (const char* g = std::getenv("HZ_TUNE")) c->tune = std::atoi(g) != 0;
     if (const char* g = std::getenv("HZ_GEMM_KIND")) {
         const int k = std::atoi(g);
-        if (k >= GEMM_MFMA32 && k <= GEMM_MFMA64D) c->force_kind = k;
+        if (k >= GEMM_MFMA32 && k <= GEMM_MFMA64X32) c->force_kind = k;
     }
     if (c->prm.pml_beta <= 0.0) c->prm.pml_beta = 2.0;
     if (c->prm.max_batch <= 0) c->prm.max_batch = 1;

@@ -234,8 +234,11 @@ void launch_gemm(const GemmTask<T>* tasks_dev, int ntasks, int max_m, int B, hip
 // and 32x32 / 16-deep
 // GEMM_MFMA32D / GEMM_MFMA64D: the 32x32 and 64x64 tiles with two chunks of
 // loads in flight (64x64 with 32-deep chunks in complex64).
+// GEMM_MFMA32X64 / GEMM_MFMA64X32: 32 x 64 and 64 x 32 output tiles (rows x
+// batch columns), 32-deep chunks.
 enum GemmKernel { GEMM_GEMV = 0, GEMM_TILED = 1, GEMM_MFMA32 = 2, GEMM_MFMA64 = 3,
-                  GEMM_MFMA32K16 = 4, GEMM_MFMA32D = 5, GEMM_MFMA64D = 6 };
+                  GEMM_MFMA32K16 = 4, GEMM_MFMA32D = 5, GEMM_MFMA64D = 6,
+                  GEMM_MFMA32X64 = 7, GEMM_MFMA64X32 = 8 };
 GemmKernel gemm_kernel(int ntasks, int max_m, int B);
 const char* gemm_kernel_name(GemmKernel k);
 

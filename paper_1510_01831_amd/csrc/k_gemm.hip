@@ -372,6 +372,8 @@ const char* gemm_kernel_name(GemmKernel k) {
     case GEMM_MFMA32K16: return "gemm_mfma32k16";
     case GEMM_MFMA32D: return "gemm_mfma32d";
     case GEMM_MFMA64D: return "gemm_mfma64d";
+    case GEMM_MFMA32X64: return "gemm_mfma32x64";
+    case GEMM_MFMA64X32: return "gemm_mfma64x32";
     default: return "gemm_mfma32";
     }
 }
@@ -388,6 +390,14 @@ void launch_gemm_mfma(GemmKernel kind, const GemmTask<T>* tasks_dev, int ntasks,
     } else if (kind == GEMM_MFMA32K16) {
         const int rt = (max_m + 31) / 32, ct = (B + 31) / 32;
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 16, OFFLINE>),
+                           dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct);
+    } else if (kind == GEMM_MFMA32X64) {
+        const int rt = (max_m + 31) / 32, ct = (B + 63) / 64;
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 64, 32, OFFLINE>),
+                           dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct);
+    } else if (kind == GEMM_MFMA64X32) {
+        const int rt = (max_m + 63) / 64, ct = (B + 31) / 32;
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 64, 32, 32, OFFLINE>),
                            dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct);
     } else if (kind == GEMM_MFMA32D) {
         const int rt = (max_m + 31) / 32, ct = (B + 31) / 32;
