@@ -14,7 +14,7 @@
 namespace hz {
 
 constexpr int GV_THREADS = 256;
-constexpr int GV_ROWS = 16;          // rows per workgroup (4 per wave)
+constexpr int GV_ROWS = 4;           // rows per workgroup (one per wave)
 
 template <typename T>
 __device__ inline C2<T> shfl_down_c(C2<T> v, int d) {
@@ -51,15 +51,31 @@ __global__ void __launch_bounds__(GV_THREADS) k_gemv(const GemmTask<T>* __restri
         const int i = blockIdx.x * GV_ROWS + rr;
         if (i >= t.m) break;
         const C2<T>* Ar = t.A + (long long)i * t.lda;
-        C2<T> acc = mk<T>((T)0, (T)0);
+        // four independent accumulators: four loads of A and x in flight per
+        // lane (a single-RHS product is bound by memory latency otherwise)
+        C2<T> a4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a4[u] = mk<T>((T)0, (T)0);
         for (int s = 0; s < t.nseg; ++s) {
             const C2<T>* xp = t.seg_ptr[s];
             if (!xp) continue;
             const int k0 = t.seg_k0[s], len = t.seg_len[s];
             const long long ldx = t.ldx;
-            for (int kk = lane; kk < len; kk += 64)
-                acc = cfma(gload<T>(Ar + k0 + kk), gload<T>(xp + (long long)kk * ldx), acc);
+            int kk = lane;
+            for (; kk + 192 < len; kk += 256) {
+                C2<T> av[4], xv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    av[u] = gload<T>(Ar + k0 + kk + 64 * u);
+                    xv[u] = gload<T>(xp + (long long)(kk + 64 * u) * ldx);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) a4[u] = cfma(av[u], xv[u], a4[u]);
+            }
+            for (; kk < len; kk += 64)
+                a4[0] = cfma(gload<T>(Ar + k0 + kk), gload<T>(xp + (long long)kk * ldx), a4[0]);
         }
+        C2<T> acc = cadd(cadd(a4[0], a4[1]), cadd(a4[2], a4[3]));
         for (int d = 32; d > 0; d >>= 1) {
             C2<T> o = shfl_down_c<T>(acc, d);
             acc.x += o.x; acc.y += o.y;
