@@ -21,7 +21,7 @@
 
 namespace hz {
 
-constexpr int CS_THREADS = 256;
+constexpr int CS_THREADS = 1024;    // single-RHS cell solve (16 waves)
 constexpr int CS_HLPMAX = 224;
 
 template <typename T>
@@ -266,14 +266,23 @@ __device__ inline C2<T> e_coef(const C2<T>* ee, int k, int j, int HL) {
 // a 16-row tile; the 4 partial sums of a row are combined with two shuffles.
 template <typename T, int NB, int MODE>
 __global__ void __launch_bounds__(CS_THREADS) k_cs_gemv(CellSolveArgs<T> a) {
-    constexpr int MRT = (CS_HLPMAX / 16 + 3) / 4;   // row tiles per wave (4 for 224 rows)
+    // A step's matrix-vector product reads a whole HLp x HLp factor block
+    // and one workgroup serves a cell, so the step time is the time to have
+    // the block in flight: 16 waves, each taking one row tile over 1/NS of
+    // the column quads (NS = 2 for HLp > 64), with all of its loads issued
+    // before the products.  Partial row sums meet in LDS.
+    constexpr int NSMAX = 4;
+    constexpr int WAVES = CS_THREADS / 64;
     __shared__ C2<T> vs[CS_HLPMAX * NB];
+    __shared__ C2<T> part[2 * CS_HLPMAX * NB];     // NS * HLp <= 2 * CS_HLPMAX
 
     const int gc = a.cell_list[blockIdx.x];
     const CellDesc cd = a.cells[gc];
     const LayerDesc& ld = a.layers[cd.layer];
     const int HL = cd.HL, HLp = cd.HLp, Wc = cd.Wc;
     const int RT = HLp >> 4, KS = HLp >> 2;
+    const int NS = RT >= WAVES / 2 ? 2 : (RT >= WAVES / 4 ? 4 : NSMAX);
+    const int KSP = (KS + NS - 1) / NS;             // column quads per item
     const int b0 = blockIdx.y * NB;
     if (MODE == SOLVE_PROBE && a.probe0 + b0 >= cd.R) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -288,57 +297,59 @@ __global__ void __launch_bounds__(CS_THREADS) k_cs_gemv(CellSolveArgs<T> a) {
     for (int q = tid; q < HLp * NB; q += CS_THREADS) vs[q] = mk<T>((T)0, (T)0);
     __syncthreads();
 
-    C2<T> acc[MRT][NB];
+    // part[h][row][c] = sum over quad range h of X_k[row][.] vs[.][c]
     auto matvec = [&](const C2<T>* Xk) {
+        for (int item = w; item < RT * NS; item += WAVES) {
+            const int R = item % RT, h = item / RT;
+            const int s0 = h * KSP, s1 = min(KS, s0 + KSP);
+            C2<T> acc[NB];
 #pragma unroll
-        for (int m = 0; m < MRT; ++m)
+            for (int c = 0; c < NB; ++c) acc[c] = mk<T>((T)0, (T)0);
+            const C2<T>* base = Xk + ((long long)R * KS << 6) + lane;
+            constexpr int UL = NB >= 4 ? 4 : 8;     // loads in flight per lane
+            int s = s0;
+            for (; s + UL <= s1; s += UL) {
+                C2<T> x[UL];
 #pragma unroll
-            for (int c = 0; c < NB; ++c) acc[m][c] = mk<T>((T)0, (T)0);
+                for (int u = 0; u < UL; ++u) x[u] = gload<T>(base + ((long long)(s + u) << 6));
 #pragma unroll
-        for (int m = 0; m < MRT; ++m) {
-            const int R = w + 4 * m;
-            if (R < RT) {
-                const C2<T>* base = Xk + ((long long)R * KS << 6) + lane;
-#pragma unroll 8
-                for (int s = 0; s < KS; ++s) {
-                    const C2<T> x = base[(long long)s << 6];
-                    const int cc = 4 * s + (lane >> 4);
+                for (int u = 0; u < UL; ++u) {
+                    const int cc = 4 * (s + u) + (lane >> 4);
 #pragma unroll
-                    for (int c = 0; c < NB; ++c) acc[m][c] = cfma(x, vs[cc * NB + c], acc[m][c]);
+                    for (int c = 0; c < NB; ++c) acc[c] = cfma(x[u], vs[cc * NB + c], acc[c]);
                 }
             }
-        }
+            for (; s < s1; ++s) {
+                const C2<T> x = gload<T>(base + ((long long)s << 6));
+                const int cc = 4 * s + (lane >> 4);
 #pragma unroll
-        for (int m = 0; m < MRT; ++m)
+                for (int c = 0; c < NB; ++c) acc[c] = cfma(x, vs[cc * NB + c], acc[c]);
+            }
 #pragma unroll
             for (int c = 0; c < NB; ++c) {
-                C2<T> v = acc[m][c];
+                C2<T> v = acc[c];
                 v.x += __shfl_xor(v.x, 16, 64); v.y += __shfl_xor(v.y, 16, 64);
                 v.x += __shfl_xor(v.x, 32, 64); v.y += __shfl_xor(v.y, 32, 64);
-                acc[m][c] = v;
+                if (lane < 16) part[(h * HLp + R * 16 + lane) * NB + c] = v;
             }
+        }
+    };
+    auto rowsum = [&](int j, int c) {
+        C2<T> v = part[j * NB + c];
+        for (int h = 1; h < NS; ++h) v = cadd(v, part[(h * HLp + j) * NB + c]);
+        return v;
     };
 
     // ---- forward sweep
     for (int k = 0; k < Wc; ++k) {
         if (k > 0) matvec(Xf + (long long)(k - 1) * np2);
         __syncthreads();
-        if (lane < 16) {
-#pragma unroll
-            for (int m = 0; m < MRT; ++m) {
-                const int R = w + 4 * m;
-                if (R < RT) {
-                    const int j = R * 16 + lane;
-#pragma unroll
-                    for (int c = 0; c < NB; ++c) {
-                        C2<T> s = bval(c) ? cell_source<T, MODE>(a, cd, ld, k, j, b0 + c)
-                                          : mk<T>((T)0, (T)0);
-                        if (k > 0) s = csub(s, cmul(e_coef<T>(ee, k, j, HL), acc[m][c]));
-                        vs[j * NB + c] = s;
-                        Y[((long long)k * HLp + j) * NB + c] = s;
-                    }
-                }
-            }
+        for (int q = tid; q < HLp * NB; q += CS_THREADS) {
+            const int j = q / NB, c = q % NB;
+            C2<T> s = bval(c) ? cell_source<T, MODE>(a, cd, ld, k, j, b0 + c) : mk<T>((T)0, (T)0);
+            if (k > 0) s = csub(s, cmul(e_coef<T>(ee, k, j, HL), rowsum(j, c)));
+            vs[q] = s;
+            Y[(long long)k * HLp * NB + q] = s;
         }
         __syncthreads();
     }
@@ -353,19 +364,11 @@ __global__ void __launch_bounds__(CS_THREADS) k_cs_gemv(CellSolveArgs<T> a) {
         }
         matvec(Xf + (long long)k * np2);
         __syncthreads();
-        if (lane < 16) {
-#pragma unroll
-            for (int m = 0; m < MRT; ++m) {
-                const int R = w + 4 * m;
-                if (R < RT) {
-                    const int j = R * 16 + lane;
-#pragma unroll
-                    for (int c = 0; c < NB; ++c) {
-                        vs[j * NB + c] = acc[m][c];
-                        if (bval(c)) cell_emit<T, MODE>(a, cd, ld, k, j, b0 + c, acc[m][c]);
-                    }
-                }
-            }
+        for (int q = tid; q < HLp * NB; q += CS_THREADS) {
+            const int j = q / NB, c = q % NB;
+            const C2<T> x = rowsum(j, c);
+            vs[q] = x;
+            if (bval(c)) cell_emit<T, MODE>(a, cd, ld, k, j, b0 + c, x);
         }
         __syncthreads();
     }
