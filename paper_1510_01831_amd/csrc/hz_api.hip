@@ -188,6 +188,7 @@ struct hz_ctx {
     bool offline = false;          // inside the factorisation stage
     bool tune = true;              // autotune GEMM kernels and cell-solve widths (HZ_TUNE=0: off)
     int force_kind = -1;           // HZ_GEMM_KIND: one matrix-core GEMM kernel for every launch
+    GemmSplitWs gsw;               // workspace of the split-k GEMM variants (allocated once)
     std::map<std::string, int> cs_tuned;   // (mode, B, cells) -> cell-solve batch width
     Arena arena;
     std::vector<LayerDesc> layers;
@@ -663,8 +664,20 @@ void plan_launches(hz_ctx* c, const Plan<T>& pl, int B);
 // input segments and outputs redirected to scratch buffers (plans that update
 // vectors in place are not disturbed), and the fastest kernel is kept in the
 // launch record.  Runs once, when the plan is built for a batch size.
+// 64 MB of partial tiles and 64 K tile counters, zeroed once; the split-k
+// kernels leave the counters zero, so plans captured in graphs reuse them.
+void ensure_split_ws(hz_ctx* c) {
+    if (c->gsw.ws) return;
+    c->gsw.ws_bytes = 64LL << 20;
+    c->gsw.ncounters = 1 << 16;
+    c->gsw.ws = c->arena.alloc((size_t)c->gsw.ws_bytes);
+    c->gsw.counters = (int*)c->arena.alloc(sizeof(int) * (size_t)c->gsw.ncounters);
+    HIPCHK(hipMemsetAsync(c->gsw.counters, 0, sizeof(int) * (size_t)c->gsw.ncounters, c->st));
+}
+
 template <typename T>
 void tune_plan(hz_ctx* c, Plan<T>& pl, int B) {
+    ensure_split_ws(c);
     if (c->force_kind >= GEMM_MFMA32) {
         for (auto& r : pl.launches)
             if (r.kind == L_GEMM) r.choice = c->force_kind;
@@ -707,14 +720,15 @@ void tune_plan(hz_ctx* c, Plan<T>& pl, int B) {
         float best = 1e30f;
         for (int cand : {dflt, (int)GEMM_MFMA64, (int)GEMM_MFMA32, (int)GEMM_MFMA32K16,
                          (int)GEMM_MFMA32D, (int)GEMM_MFMA64D, (int)GEMM_MFMA32X64,
-                         (int)GEMM_MFMA64X32}) {
+                         (int)GEMM_MFMA64X32, (int)GEMM_MFMA64S2, (int)GEMM_MFMA64S4}) {
             if (cand == dflt && best < 1e30f) continue;
-            if ((cand == GEMM_MFMA64 || cand == GEMM_MFMA64D || cand == GEMM_MFMA32X64) && B < 64)
+            if ((cand == GEMM_MFMA64 || cand == GEMM_MFMA64D || cand == GEMM_MFMA32X64 ||
+                 cand == GEMM_MFMA64S2 || cand == GEMM_MFMA64S4) && B < 64)
                 continue;
-            launch_gemm<T>(dt, r.ntasks, r.max_m, B, c->st, false, cand);     // warm-up
+            launch_gemm<T>(dt, r.ntasks, r.max_m, B, c->st, false, cand, &c->gsw);   // warm-up
             HIPCHK(hipEventRecord(e0, c->st));
             for (int rep = 0; rep < 3; ++rep)
-                launch_gemm<T>(dt, r.ntasks, r.max_m, B, c->st, false, cand);
+                launch_gemm<T>(dt, r.ntasks, r.max_m, B, c->st, false, cand, &c->gsw);
             HIPCHK(hipEventRecord(e1, c->st));
             HIPCHK(hipEventSynchronize(e1));
             float ms = 0.f;
@@ -755,7 +769,8 @@ void plan_launches(hz_ctx* c, const Plan<T>& pl, int B) {
     for (const auto& r : pl.launches) {
         if (r.kind == L_GEMM) {
             size_t e0 = prof ? prof_event(c) : 0;
-            launch_gemm<T>(pl.dev + r.off, r.ntasks, r.max_m, B, c->st, c->offline, r.choice);
+            launch_gemm<T>(pl.dev + r.off, r.ntasks, r.max_m, B, c->st, c->offline, r.choice,
+                           &c->gsw);
             if (prof) {
                 size_t e1 = prof_event(c);
                 const GemmKernel kk = gemm_kernel(r.ntasks, r.max_m, B);
@@ -2285,7 +2300,7 @@ hz_status hz_setup(const double* model_dev, const hz_params* prm, hz_ctx** out) 
     if (const char* g = std::getenv("HZ_TUNE")) c->tune = std::atoi(g) != 0;
     if (const char* g = std::getenv("HZ_GEMM_KIND")) {
         const int k = std::atoi(g);
-        if (k >= GEMM_MFMA32 && k <= GEMM_MFMA64X32) c->force_kind = k;
+        if (k >= GEMM_MFMA32 && k <= GEMM_MFMA64S4) c->force_kind = k;
     }
     if (c->prm.pml_beta <= 0.0) c->prm.pml_beta = 2.0;
     if (c->prm.max_batch <= 0) c->prm.max_batch = 1;

@@ -158,6 +158,15 @@ struct GemmTask {
     int ncol;            // batch columns of this task (0 = the launch's B)
 };
 
+// Workspace of the split-k variants: partial tiles (bytes) and one counter
+// per output tile, zero between launches (the kernels leave them zero).
+struct GemmSplitWs {
+    void* ws = nullptr;
+    long long ws_bytes = 0;
+    int* counters = nullptr;
+    long long ncounters = 0;
+};
+
 // ---------------------------------------------------------------------------
 // cell solve (Schur recursion) arguments
 
@@ -227,7 +236,7 @@ void launch_cell_solve(const CellSolveArgs<T>& a, int ncells_launch, int nb_chun
 // kind_choice = a matrix-core variant picked by the autotuner (-1: default)
 template <typename T>
 void launch_gemm(const GemmTask<T>* tasks_dev, int ntasks, int max_m, int B, hipStream_t st,
-                 bool offline = false, int kind_choice = -1);
+                 bool offline = false, int kind_choice = -1, const GemmSplitWs* sw = nullptr);
 
 // the GEMM kernel launch_gemm selects for a shape (for per-kernel profiles);
 // the matrix-core variants are 64x64 tiles / 16-deep chunks, 32x32 / 32-deep
@@ -236,9 +245,13 @@ void launch_gemm(const GemmTask<T>* tasks_dev, int ntasks, int max_m, int B, hip
 // loads in flight (64x64 with 32-deep chunks in complex64).
 // GEMM_MFMA32X64 / GEMM_MFMA64X32: 32 x 64 and 64 x 32 output tiles (rows x
 // batch columns), 32-deep chunks.
+// GEMM_MFMA64S2 / GEMM_MFMA64S4: 64x64 tiles with the k chunks of a tile split
+// over 2 / 4 workgroups (needs a GemmSplitWs; without one, GEMM_MFMA64).
 enum GemmKernel { GEMM_GEMV = 0, GEMM_TILED = 1, GEMM_MFMA32 = 2, GEMM_MFMA64 = 3,
                   GEMM_MFMA32K16 = 4, GEMM_MFMA32D = 5, GEMM_MFMA64D = 6,
-                  GEMM_MFMA32X64 = 7, GEMM_MFMA64X32 = 8 };
+                  GEMM_MFMA32X64 = 7, GEMM_MFMA64X32 = 8, GEMM_MFMA64S2 = 9,
+                  GEMM_MFMA64S4 = 10 };
+
 GemmKernel gemm_kernel(int ntasks, int max_m, int B);
 const char* gemm_kernel_name(GemmKernel k);
 

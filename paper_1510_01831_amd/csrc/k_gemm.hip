@@ -241,15 +241,24 @@ __device__ __forceinline__ int xcd_tile(int L, int total) {
 // DEEP: two register stages, so the loads of chunk c+2 are issued while chunk
 // c is multiplied and chunk c+1 waits in registers (two chunk periods to hide
 // the load latency instead of one).
+//
+// splits > 1 (split k, non-DEEP only): the splits workgroups of an output
+// tile (adjacent slots, hence one XCD) each take a contiguous share of the
+// tile's k chunks and store their accumulators to ws; the last to finish
+// (per-tile counter) adds the shares in index order -- the same sum whichever
+// finishes last -- applies the epilogue and resets the counter to zero for
+// the next launch.
 template <typename T, int MT, int TBM, int KC, bool OFFLINE, bool DEEP = false>
 __global__ void __launch_bounds__(GV_THREADS, 2)
-k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col_tiles) {
+k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col_tiles,
+            int splits, C2<T>* __restrict__ ws, int* __restrict__ counters) {
     constexpr int RTW = MT / 32;                 // row tiles per wave
     constexpr int CTW = TBM / 32;                // column tiles per wave
-    const int per_task = row_tiles * col_tiles;
+    const int per_task = row_tiles * col_tiles * splits;
     const int tile = xcd_tile(blockIdx.x, (int)gridDim.x);
     const int task = tile / per_task, rem = tile - task * per_task;
-    const int rt = rem / col_tiles, ct = rem - rt * col_tiles;
+    const int sp = rem % splits, rc = rem / splits;
+    const int rt = rc / col_tiles, ct = rc - rt * col_tiles;
     const GemmTask<T>& t = tasks[task];
     const int i0 = rt * MT;
     if (i0 >= t.m) return;
@@ -285,6 +294,16 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
     };
     int sg = 0, kc = -KC;
     next_chunk<T, KC>(t, sg, kc);
+    int left = 1 << 30;                          // chunks this workgroup takes
+    if (!DEEP && splits > 1) {
+        int nch = 0;
+        for (int q = 0; q < t.nseg; ++q)
+            if (t.seg_ptr[q] && t.seg_len[q] > 0) nch += (t.seg_len[q] + KC - 1) / KC;
+        const int cb = (int)((long long)sp * nch / splits);
+        left = (int)((long long)(sp + 1) * nch / splits) - cb;
+        for (int q = 0; q < cb && sg < t.nseg; ++q) next_chunk<T, KC>(t, sg, kc);
+        if (left <= 0) sg = t.nseg;
+    }
     GemmCursor<T, MT, TBM, KC> cu;
     // load chunk (s, k), moving the cursor to segment s first if needed
     auto load = [&](GemmStage<T, MT, TBM, KC>& st, int s, int k) {
@@ -301,7 +320,7 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
         while (true) {
             int ns = sg, nk = kc;
             next_chunk<T, KC>(t, ns, nk);
-            const bool more = ns < t.nseg;
+            const bool more = ns < t.nseg && left > 1;
             if (more) load(stage, ns, nk);
             multiply(buf);
             if (!more) break;
@@ -310,6 +329,7 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
             buf ^= 1;
             sg = ns;
             kc = nk;
+            --left;
         }
     } else if (sg < t.nseg) {
         // chunk positions: (s0,k0) in LDS, (s1,k1) in registers p, (s2,k2)
@@ -343,6 +363,44 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
             s1 = s3;
             k1 = k3;
         }
+    }
+    if (!DEEP && splits > 1) {
+        constexpr int NV = RTW * CTW * 4;
+        const long long tile_id = ((long long)task * row_tiles + rt) * col_tiles + ct;
+        C2<T>* mine = ws + ((tile_id * splits + sp) * GV_THREADS + tid) * NV;
+#pragma unroll
+        for (int a = 0; a < RTW; ++a)
+#pragma unroll
+            for (int c = 0; c < CTW; ++c)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    gstore<T>(mine + (a * CTW + c) * 4 + v, mk<T>(acc[a][c].re(v), acc[a][c].im(v)));
+        __threadfence();
+        __syncthreads();
+        __shared__ int s_last;
+        if (tid == 0) s_last = atomicAdd(&counters[tile_id], 1) == splits - 1;
+        __syncthreads();
+        if (!s_last) return;
+        __threadfence();
+#pragma unroll
+        for (int a = 0; a < RTW; ++a)
+#pragma unroll
+            for (int c = 0; c < CTW; ++c)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int e = (a * CTW + c) * 4 + v;
+                    C2<T> sum = mk<T>((T)0, (T)0);
+                    for (int q = 0; q < splits; ++q) {
+                        const C2<T> y = q == sp ? mk<T>(acc[a][c].re(v), acc[a][c].im(v))
+                                                : gload<T>(ws + ((tile_id * splits + q) * GV_THREADS + tid) * NV + e);
+                        sum = cadd(sum, y);
+                    }
+                    const int i = i0 + wr + a * 16 + Mf<T>::row(lane, v);
+                    const int b = b0 + wc + c * 16 + lc;
+                    if (i < t.m && b < B) epilogue<T>(t, i, b, sum);
+                }
+        if (tid == 0) counters[tile_id] = 0;
+        return;
     }
 #pragma unroll
     for (int a = 0; a < RTW; ++a)
@@ -390,50 +448,72 @@ const char* gemm_kernel_name(GemmKernel k) {
     case GEMM_MFMA64D: return "gemm_mfma64d";
     case GEMM_MFMA32X64: return "gemm_mfma32x64";
     case GEMM_MFMA64X32: return "gemm_mfma64x32";
+    case GEMM_MFMA64S2: return "gemm_mfma64s2";
+    case GEMM_MFMA64S4: return "gemm_mfma64s4";
     default: return "gemm_mfma32";
     }
 }
 
 template <typename T, bool OFFLINE>
 void launch_gemm_mfma(GemmKernel kind, const GemmTask<T>* tasks_dev, int ntasks, int max_m, int B,
-                      hipStream_t st) {
+                      hipStream_t st, const GemmSplitWs* sw) {
+    if (kind == GEMM_MFMA64S2 || kind == GEMM_MFMA64S4) {
+        const int splits = kind == GEMM_MFMA64S2 ? 2 : 4;
+        const int rt = (max_m + 63) / 64, ct = (B + 63) / 64;
+        const long long tiles = (long long)rt * ct * ntasks;
+        const long long need = tiles * splits * GV_THREADS * 16 * (long long)sizeof(C2<T>);
+        if (sw && sw->ws && sw->counters && need <= sw->ws_bytes && tiles <= sw->ncounters) {
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 64, 64, 16, OFFLINE>),
+                               dim3(tiles * splits), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct,
+                               splits, (C2<T>*)sw->ws, sw->counters);
+            return;
+        }
+        kind = GEMM_MFMA64;                         // no room: the unsplit kernel
+    }
     // big launches: 64 x 64 tiles; otherwise 32 x 32 tiles with deeper
     // chunks, which keep more workgroups busy and fewer chunks in flight
     if (kind == GEMM_MFMA64) {
         const int rt = (max_m + 63) / 64, ct = (B + 63) / 64;
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 64, 64, 16, OFFLINE>),
-                           dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct);
+                           dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct, 1,
+                           (C2<T>*)nullptr, (int*)nullptr);
     } else if (kind == GEMM_MFMA32K16) {
         const int rt = (max_m + 31) / 32, ct = (B + 31) / 32;
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 16, OFFLINE>),
-                           dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct);
+                           dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct, 1,
+                           (C2<T>*)nullptr, (int*)nullptr);
     } else if (kind == GEMM_MFMA32X64) {
         const int rt = (max_m + 31) / 32, ct = (B + 63) / 64;
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 64, 32, OFFLINE>),
-                           dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct);
+                           dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct, 1,
+                           (C2<T>*)nullptr, (int*)nullptr);
     } else if (kind == GEMM_MFMA64X32) {
         const int rt = (max_m + 63) / 64, ct = (B + 31) / 32;
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 64, 32, 32, OFFLINE>),
-                           dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct);
+                           dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct, 1,
+                           (C2<T>*)nullptr, (int*)nullptr);
     } else if (kind == GEMM_MFMA32D) {
         const int rt = (max_m + 31) / 32, ct = (B + 31) / 32;
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 32, OFFLINE, true>),
-                           dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct);
+                           dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct, 1,
+                           (C2<T>*)nullptr, (int*)nullptr);
     } else if (kind == GEMM_MFMA64D) {
         const int rt = (max_m + 63) / 64, ct = (B + 63) / 64;
         constexpr int KCD = sizeof(T) == 4 ? 32 : 16;
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 64, 64, KCD, OFFLINE, true>),
-                           dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct);
+                           dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct, 1,
+                           (C2<T>*)nullptr, (int*)nullptr);
     } else {
         const int rt = (max_m + 31) / 32, ct = (B + 31) / 32;
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 32, OFFLINE>),
-                           dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct);
+                           dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct, 1,
+                           (C2<T>*)nullptr, (int*)nullptr);
     }
 }
 
 template <typename T>
 void launch_gemm(const GemmTask<T>* tasks_dev, int ntasks, int max_m, int B, hipStream_t st,
-                 bool offline, int kind_choice) {
+                 bool offline, int kind_choice, const GemmSplitWs* sw) {
     if (ntasks <= 0 || max_m <= 0) return;
     GemmKernel kind = gemm_kernel(ntasks, max_m, B);
     if (kind_choice >= GEMM_MFMA32 && kind >= GEMM_MFMA32) kind = (GemmKernel)kind_choice;
@@ -445,13 +525,15 @@ void launch_gemm(const GemmTask<T>* tasks_dev, int ntasks, int max_m, int B, hip
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_tiled<T>), grid, dim3(GV_THREADS), 0, st,
                            tasks_dev, B);
     } else if (offline) {
-        launch_gemm_mfma<T, true>(kind, tasks_dev, ntasks, max_m, B, st);
+        launch_gemm_mfma<T, true>(kind, tasks_dev, ntasks, max_m, B, st, sw);
     } else {
-        launch_gemm_mfma<T, false>(kind, tasks_dev, ntasks, max_m, B, st);
+        launch_gemm_mfma<T, false>(kind, tasks_dev, ntasks, max_m, B, st, sw);
     }
 }
 
-template void launch_gemm<double>(const GemmTask<double>*, int, int, int, hipStream_t, bool, int);
-template void launch_gemm<float>(const GemmTask<float>*, int, int, int, hipStream_t, bool, int);
+template void launch_gemm<double>(const GemmTask<double>*, int, int, int, hipStream_t, bool, int,
+                                  const GemmSplitWs*);
+template void launch_gemm<float>(const GemmTask<float>*, int, int, int, hipStream_t, bool, int,
+                                 const GemmSplitWs*);
 
 }  // namespace hz
