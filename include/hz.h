@@ -214,7 +214,8 @@ hz_status hz_misfit(hz_ctx* ctx, const void* u_ext_dev, const void* d_obs_dev, i
                     int B, void* adj_src_dev, double* J_host);
 
 /* Replace the model (same size and kind) and rebuild the coefficients; the
- * context returns to the "set up" state (hz_factor must be called again). */
+ * context returns to the "set up" state (hz_factor must be called again).
+ * HZ_EINVAL for a bad model (checked first: the context is then unchanged). */
 hz_status hz_update_model(hz_ctx* ctx, const double* model_dev);
 
 /* Local re-factorisation after a model update (Sec. 6: in an inversion loop
@@ -227,8 +228,9 @@ hz_status hz_update_model(hz_ctx* ctx, const double* model_dev);
  * hz_update_model followed by hz_factor.  In the HZ_MIXED_REFINE form (whose
  * FP64 operators are not kept) every cell is refactored.
  * ncells_refactored: host int, or NULL; receives the number of cells redone.
- * Errors: HZ_ESTATE if ctx is not factored; HZ_EINVAL for a bad model (ctx is
- * then left "set up": hz_factor must be called); HZ_ESINGULAR as hz_factor. */
+ * Errors: HZ_ESTATE if ctx is not factored; HZ_EINVAL for a bad model (NaN,
+ * infinite or non-positive entries: checked first, ctx unchanged);
+ * HZ_ESINGULAR as hz_factor. */
 hz_status hz_update_model_local(hz_ctx* ctx, const double* model_dev, int* ncells_refactored);
 
 /* Enqueue all further work of ctx on `hip_stream` (a hipStream_t, or NULL for

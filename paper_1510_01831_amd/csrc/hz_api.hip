@@ -2221,8 +2221,17 @@ hz_status solve_impl(hz_ctx* c, const void* rhs_dev, int B, void* out_dev, doubl
 
 hz_status setup_coef(hz_ctx* c, const double* model_dev) {
     const Dims& d = c->d;
-    HIPCHK(hipMemcpyAsync(c->model, model_dev, sizeof(double) * d.n * d.n, hipMemcpyDeviceToDevice, c->st));
+    // validate first: a rejected model leaves the context as it was
     HIPCHK(hipMemsetAsync(c->flags, 0, 2 * sizeof(int), c->st));
+    launch_check_model(model_dev, (long long)d.n * d.n, c->flags, c->st);
+    HIPCHK(hipGetLastError());
+    {
+        int bad = 0;
+        HIPCHK(hipMemcpyAsync(&bad, c->flags, sizeof(int), hipMemcpyDeviceToHost, c->st));
+        sync(c);
+        if (bad) raise(HZ_EINVAL, "model has NaN, infinite or non-positive entries");
+    }
+    HIPCHK(hipMemcpyAsync(c->model, model_dev, sizeof(double) * d.n * d.n, hipMemcpyDeviceToDevice, c->st));
     launch_build_coef(c->model, (int)c->prm.model_kind, d, c->d_cells, c->d_layers,
                       (int)c->cells.size(), c->cells.data(), c->diag, c->cz, c->e, c->ax_pool,
                       c->az_pool, c->gdiag, c->gcx, c->gcz, c->wext, c->flags, c->st);
@@ -2368,7 +2377,7 @@ hz_status hz_update_model(hz_ctx* c, const double* model_dev) {
     API_BEGIN
     check_state(c, 1);
     if (!model_dev) raise(HZ_EINVAL, "null model");
-    setup_coef(c, model_dev);
+    setup_coef(c, model_dev);              // a rejected model changes nothing
     c->state = 1;
     return HZ_OK;
     API_END
@@ -2397,8 +2406,8 @@ hz_status hz_update_model_local(hz_ctx* c, const double* model_dev, int* ncells_
     std::vector<char> redo(ncells, 1);
     if (c->prm.precision == HZ_MIXED_REFINE) {
         // the FP64 operators of the unchanged cells were released: full factorisation
-        c->state = 1;
         setup_coef(c, model_dev);
+        c->state = 1;
     } else {
         const long long ne = c->coef_elems;
         const long long nax = (long long)ncells * d.Wcmax, naz = (long long)d.L * d.HLmax;
@@ -2409,13 +2418,13 @@ hz_status hz_update_model_local(hz_ctx* c, const double* model_dev, int* ncells_
         HIPCHK(hipMemcpyAsync(old + 2 * ne, c->e, cb, hipMemcpyDeviceToDevice, c->st));
         HIPCHK(hipMemcpyAsync(old + 3 * ne, c->ax_pool, sizeof(double2) * nax, hipMemcpyDeviceToDevice, c->st));
         HIPCHK(hipMemcpyAsync(old + 3 * ne + nax, c->az_pool, sizeof(double2) * naz, hipMemcpyDeviceToDevice, c->st));
-        c->state = 1;                      // operators stale until refactored
         try {
-            setup_coef(c, model_dev);
+            setup_coef(c, model_dev);      // a rejected model changes nothing
         } catch (...) {
             c->arena.release(old, sizeof(double2) * (3 * ne + nax + naz));
             throw;
         }
+        c->state = 1;                      // operators stale until refactored
         int* dchg = (int*)c->arena.alloc(sizeof(int) * (ncells + 1));
         HIPCHK(hipMemsetAsync(dchg + ncells, 0, sizeof(int), c->st));
         hipLaunchKernelGGL(k_coef_changed, dim3(ncells), dim3(256), 0, c->st, c->d_cells, old,

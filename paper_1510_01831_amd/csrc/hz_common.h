@@ -211,6 +211,8 @@ struct CellSolveArgs {
 // ---------------------------------------------------------------------------
 // launchers (defined in the .hip files)
 
+void launch_check_model(const double* model, long long count, int* bad_flag, hipStream_t st);
+
 void launch_build_coef(const double* model, int model_kind, const Dims& d,
                        const CellDesc* cells_dev, const LayerDesc* layers_dev, int ncells,
                        const CellDesc* cells_host, double2* diag, double2* cz, double2* e,

@@ -98,6 +98,10 @@ __global__ void k_global_coef(const double* model, int kind, Dims d, double2* gd
     }
 }
 
+void launch_check_model(const double* model, long long count, int* bad_flag, hipStream_t st) {
+    hipLaunchKernelGGL(k_check_model, dim3(256), dim3(256), 0, st, model, count, bad_flag);
+}
+
 void launch_build_coef(const double* model, int model_kind, const Dims& d,
                        const CellDesc* cells_dev, const LayerDesc* layers_dev, int ncells,
                        const CellDesc* cells_host, double2* diag, double2* cz, double2* e,

@@ -79,10 +79,11 @@ def test_local_update_refine_form_and_errors():
     with pytest.raises(hz.HzError) as e:
         s.update_model_local(torch.from_numpy(bad))
     assert e.value.status == hz.HZ_EINVAL
-    with pytest.raises(hz.HzError) as e:                 # left "set up", not factored
-        s.solve(f)
-    assert e.value.status == hz.HZ_ESTATE
-    with pytest.raises(hz.HzError) as e:
+    u2 = s.solve(f, tol=1e-8).cpu().numpy()              # rejected model: context unchanged
+    assert np.linalg.norm(u2 - u) / np.linalg.norm(u) < 1e-7
+    s.close()
+    s = hz.Solver(torch.from_numpy(c0), omega, P, L, LC, max_batch=1, factor=False)
+    with pytest.raises(hz.HzError) as e:                  # not factored yet
         s.update_model_local(torch.from_numpy(c1))
     assert e.value.status == hz.HZ_ESTATE
     s.close()
