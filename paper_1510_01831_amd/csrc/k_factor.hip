@@ -138,10 +138,10 @@ __device__ void gj_invert(C2<T>* work, C2<T>* out, int n, long long ldo, int* si
             for (int j = ((tid - rb) % nt + nt) % nt; j < n; j += nt) prow[j] = work[rb + j];
         }
         __syncthreads();
-        // ---- update, publishing column k+1 for the next search
+        // ---- update, publishing column k+1 for the next search; a thread's
+        // entries go in groups of four so that four loads are in flight
         const int nxt = cur ^ 1;
-        int r = r0, j = c0;
-        for (int e = tid; e < nn; e += nt) {
+        auto upd = [&](int r, int j, C2<T> a) {
             C2<T> w;
             if (r == pr) {
                 w = (j == k) ? inv : cmul(prow[j], inv);
@@ -150,13 +150,30 @@ __device__ void gj_invert(C2<T>* work, C2<T>* out, int n, long long ldo, int* si
                 if (j == k) {
                     w = mk<T>(-f.x, -f.y);
                 } else {
-                    const C2<T> a = work[e];
                     const C2<T> pj = prow[j];
                     w = mk<T>(a.x - (f.x * pj.x - f.y * pj.y), a.y - (f.x * pj.y + f.y * pj.x));
                 }
             }
-            work[e] = w;
             if (j == k + 1) colbuf[nxt][r] = w;
+            return w;
+        };
+        int r = r0, j = c0;
+        int e = tid;
+        for (; e + 3 * nt < nn; e += 4 * nt) {
+            int rr[4], jj[4];
+            C2<T> a[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                rr[u] = r; jj[u] = j;
+                a[u] = work[e + u * nt];
+                r += dr; j += dc;
+                if (j >= n) { j -= n; ++r; }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) work[e + u * nt] = upd(rr[u], jj[u], a[u]);
+        }
+        for (; e < nn; e += nt) {
+            work[e] = upd(r, j, work[e]);
             r += dr; j += dc;
             if (j >= n) { j -= n; ++r; }
         }
