@@ -214,6 +214,14 @@ def local_refactor(solver, c, w, f_all, ref_idx, max_iter):
             "full_refactor_s": t_full, "gmres_iters": its, "max_rel_diff_vs_full": diff}
 
 
+MEDIUM = {"C1": "Gaussian bump c = 1 + 0.3 exp(-r^2/0.02)",
+          "C2": "Gaussian random field c in [1.5,3] (corr. 0.05, seed 0)",
+          "C3": "Gaussian random field c in [1.5,3] (corr. 0.05, seed 0)",
+          "C4": "layered medium (12 seeded layers, c in [1.5,4.5], depth gradient, two dipping "
+                "interfaces)",
+          "C5": "lens c = 2 + 0.4 exp(-r^2/(2 0.08^2))"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -356,10 +364,9 @@ def main():
         "vs_baseline": None,
         "dtype": dty,
         "data": "synthetic",
-        "config": {"workload": (f"{w.name}: n={n} (+{w.n_pml} PML), Gaussian random field "
-                                f"c in [1.5,3] (corr. 0.05, seed 0), omega={w.omega:.2f} "
-                                f"(10 ppw at c_min), {w.layers} layers x {w.cells} cells, "
-                                f"{B} point sources on depth row {w.src_z}"),
+        "config": {"workload": (f"{w.name}: n={n} (+{w.n_pml} PML), {MEDIUM[w.name]}, "
+                                f"omega={w.omega:.2f} (10 ppw at c_min), {w.layers} layers x "
+                                f"{w.cells} cells, {B} point sources on depth row {w.src_z}"),
                    "form": chosen, "batch": B, "tol": 1e-10,
                    "max_rel_err_vs_fp64": err, "gmres_iters": its,
                    "setup_factor_s": t_fac,
