@@ -19,6 +19,9 @@ Modules
   nested         -- Sec. 4.2: cells, inner SIE, block LU without pivoting
                     (Sec. 4.2.2), volume solve (Alg. 7) and the interface
                     factorisation (eq. factorization).
+  nested_pt      -- Sec. 4.2.1: nested polarized traces, the inner SIE as a
+                    polarized system over the cells, iterated by GMRES with
+                    the inner Gauss-Seidel sweeps.
   gmres          -- left-preconditioned GMRES (the Krylov driver of Alg. 6).
   forms          -- mixed-precision refinement and the adjoint-state
                     gradient of a least-squares misfit.

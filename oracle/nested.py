@@ -159,6 +159,11 @@ class NestedLayerSolver:
             x[:, j] = (y[:, j] - x[:, j + 1] @ self.Cup[j].T) @ self.Sinv[j].T
         return x.reshape(B, J, 2, HL)
 
+    def inner_traces(self, newton) -> np.ndarray:
+        """Inner traces v [B, J, 2, HL] of the layer solution from the cell
+        Newton potentials: the inner SIE solved by block LU (Sec. 4.2.2)."""
+        return self.inner_solve(self.inner_rhs(newton))
+
     # ----------------------------------------------- Alg. 7 volume mode
     def solve(self, g: np.ndarray) -> np.ndarray:
         """(H^l)^{-1} g through the cells (Alg. 7), g: [HL, W] or [B, HL, W]."""
@@ -173,7 +178,7 @@ class NestedLayerSolver:
             out[..., own + self.cells[0].col0] = w[..., own]
             return out[0] if single else out
         newton = [self.cell_solve(c, gc[c]) for c in range(self.Lc)]
-        v = self.inner_solve(self.inner_rhs(newton))
+        v = self.inner_traces(newton)
         out = np.zeros((B, self.HL, self.W), dtype=complex)
         for c in range(self.Lc):
             C = self.cells[c]

@@ -67,15 +67,22 @@ class LayeredSolver:
     preconditioner) on top of a pluggable layer solver."""
 
     def __init__(self, prob: Problem, layers: int, cells: int | None = None,
-                 dtype=np.complex128):
+                 dtype=np.complex128, inner: str = "lu", inner_tol: float = 1e-6):
         """``dtype`` = complex64 gives the single-precision local solver used
-        as the approximate inverse of the mixed-precision form."""
+        as the approximate inverse of the mixed-precision form.  ``inner``
+        selects the inner solver of a nested layer: "lu" (block LU, Sec.
+        4.2.2) or "pt" (nested polarized traces, Sec. 4.2.1, GMRES to
+        ``inner_tol``)."""
         self.prob = prob
         self.L = layers
         self.parts = partition(prob.n, layers)
         self.grids = [LayerGrid(prob, a, b, i, layers) for i, (a, b) in enumerate(self.parts)]
         if cells is None:
             self.solvers = [DirectLayerSolver(g, dtype) for g in self.grids]
+        elif inner == "pt":
+            from .nested_pt import PolarizedInnerSolver
+            self.solvers = [PolarizedInnerSolver(g, cells, inner_tol=inner_tol, dtype=dtype)
+                            for g in self.grids]
         else:
             from .nested import NestedLayerSolver
             self.solvers = [NestedLayerSolver(g, cells, dtype=dtype) for g in self.grids]
