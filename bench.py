@@ -231,8 +231,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="fp64,mixed,local",
                     help="comma list of fp64, mixed, local (re-factorisation after a local "
-                         "model update, on the mixed context), table3 (Krylov x "
-                         "preconditioner comparison)")
+                         "model update, on the mixed context), nested (nested polarized "
+                         "traces: inner GMRES instead of the inner block LU), table3 (Krylov "
+                         "x preconditioner comparison)")
     ap.add_argument("--roctx-form", default="",
                     help="mark this form's timed steps as the profiled region "
                          "(fp64_single, fp64_batched or mixed_batched)")
@@ -280,6 +281,7 @@ def main():
         refs[k] = s64.solve(f_all[k:k + 1].contiguous(), tol=1e-12, max_iter=max_iter)[0]
     results = {}
     local = None
+    mem = {"fp64_inner_lu_device_bytes": s64.info.device_bytes}
     if "fp64" in args.forms:
         u, dt, prof = timed_solves(s64, f_all, 1e-10, args.steps, args.warmup, max_iter, True,
                                    region=args.roctx_form == "fp64_batched")
@@ -309,6 +311,29 @@ def main():
             local = local_refactor(smx, c, w, f_all, ref_idx, max_iter)
         smx.close()
         del smx
+    if "nested" in args.forms:
+        # nested polarized traces (Sec. 4.2.1): no inner factorisation; every
+        # layer application iterates the inner polarized system (inner
+        # tolerance 1e-6 inside the preconditioner, flexible outer GMRES)
+        torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+        spt = hz.Solver(torch.from_numpy(c), w.omega, w.n_pml, w.layers, w.cells,
+                        precision=hz.HZ_FP64, max_batch=B, inner=hz.HZ_INNER_PT, inner_tol=1e-6)
+        torch.cuda.synchronize()
+        t_facpt = time.perf_counter() - t0
+        log(f"[bench] nested polarized traces setup+factor {t_facpt:.2f} s")
+        u, dt, prof = timed_solves(spt, f_all, 1e-10, args.steps, args.warmup, max_iter, True)
+        err = max(float(torch.linalg.norm(u[k] - refs[k]) / torch.linalg.norm(refs[k]))
+                  for k in ref_idx)
+        its = max(x["iters"] for x in spt.last_stats)
+        inner_its = spt.timing()["inner_iters"]
+        results["nested_pt_batched"] = (dt, prof, err, its, "c128", t_facpt)
+        mem["fp64_nested_pt_device_bytes"] = spt.info.device_bytes
+        log(f"[bench] nested polarized traces batched: {dt * 1e3:.1f} ms/step, err {err:.2e}, "
+            f"iters {its}, inner iters <= {inner_its}")
+        spt.close()
+        del spt
+        torch.cuda.empty_cache()
     table3 = None
     if "table3" in args.forms:
         # the iteration-count comparison of the paper (Table 3: GMRES and
@@ -378,6 +403,7 @@ def main():
         "cpu_baseline": cpu,
         "table3": table3,
         "local_refactor": local,
+        "memory": mem,
     }
     print(json.dumps(line), flush=True)
 

@@ -110,6 +110,16 @@ typedef enum {
                                 unpreconditioned SIE residual */
 } hz_krylov;
 
+typedef enum {
+    HZ_INNER_LU = 0,         /* inner SIE of each layer by block LU without pivoting,
+                                inverted diagonal blocks (Sec. 4.2.2) */
+    HZ_INNER_PT = 1          /* nested polarized traces (Sec. 4.2.1): the inner SIE as a
+                                polarized system over the cells, iterated by GMRES with the
+                                inner Gauss-Seidel sweeps; no inner factorisation.  Needs
+                                HZ_FP64, HZ_KRYLOV_GMRES (run flexible: the preconditioner's
+                                inner solves stop at inner_tol) and n_pml >= 1 */
+} hz_inner;
+
 typedef struct {
     int n_x, n_z;            /* physical nodes per side (must be equal) */
     double h;                /* grid step; must equal 1/(n+1) (unit square) */
@@ -123,6 +133,11 @@ typedef struct {
     int max_batch;           /* largest B accepted by hz_solve; <= 0 -> 1 */
     hz_precond precond;      /* preconditioner of the polarized SIE (0: Gauss-Seidel) */
     hz_krylov krylov;        /* Krylov method for the polarized SIE (0: GMRES) */
+    hz_inner inner;          /* inner solver of the layers (0: block LU) */
+    double inner_tol;        /* HZ_INNER_PT: relative tolerance of the inner GMRES inside the
+                                preconditioner (<= 0 -> 1e-6, the paper's value); the inner
+                                solves of the SIE matrix, the right-hand side and the
+                                reconstruction use min(1e-10, max(1e-13, tol / 100)) */
 } hz_params;
 
 typedef struct {
@@ -139,6 +154,8 @@ typedef struct {
     double t_rhs, t_gmres, t_recon;    /* seconds, last hz_solve, by phase */
     double t_solve;                    /* seconds, whole last hz_solve */
     int gmres_iters;                   /* max over the batch, last hz_solve */
+    int inner_iters;                   /* HZ_INNER_PT: largest inner GMRES iteration count,
+                                          last hz_solve (at most 40 per inner solve) */
 } hz_timing;
 
 typedef struct {

@@ -97,9 +97,10 @@ struct Ops {                       // factors and interface operators in precisi
     C2<T>* Sinv = nullptr;
     C2<T>* Lfac = nullptr;
     C2<T>* Qc = nullptr;           // composed output operators [Q_x S^{-1} | Q_u] per side and cell
+    C2<T>* CP = nullptr;           // pair-column samples (nested polarized traces)
 };
 
-enum LaunchKind { L_GEMM = 0, L_AXPBY = 1, L_COPY = 2 };
+enum LaunchKind { L_GEMM = 0, L_AXPBY = 1, L_COPY = 2, L_INNER = 3 };
 
 template <typename T>
 struct LaunchRec {
@@ -111,12 +112,42 @@ struct LaunchRec {
     int choice = -1;      // GEMM kernel picked by the autotuner (-1: default)
 };
 
+template <typename T> struct Plan;
+
+// Nested polarized traces: one inner solve of a set of independent layer
+// jobs (Sec. 4.2.1).  Job i's polarized inner right-hand side rhs_i
+// ([d|q][J][2][HL_i][B]) is packed into column block i of the workspace
+// vectors, rows [dq * 2 J HLmax, + 2 J HL_i) (the rest stays zero), so that
+// the whole set is one batch of NJ * B columns for GMRES; the traces
+// s = d + q go to out_i ([J][2][HL_i][B]).
+template <typename T>
+struct InnerRec {
+    struct Job { int layer; const C2<T>* rhs; C2<T>* out; };
+    std::vector<Job> jobs;
+    bool loose = false;          // inside the preconditioner: the loose inner tolerance
+    long long n = 0;             // rows of a workspace vector (4 J HLmax)
+    int ncols = 0;               // NJ * B
+    Arena* ar = nullptr;
+    C2<T>* wA = nullptr;         // inner M: wA -> wB, inner P^GS: wB -> wC
+    C2<T>* wB = nullptr;
+    C2<T>* wC = nullptr;
+    C2<T>* S = nullptr;          // s = d + q of wA (the d rows only)
+    void* jobtab = nullptr;      // device table of the jobs (pack / unpack)
+    std::unique_ptr<Plan<T>> M, P;
+    ~InnerRec() {
+        if (!ar) return;
+        for (void* q : {(void*)wA, (void*)wB, (void*)wC, (void*)S, jobtab}) ar->release(q, 0);
+    }
+};
+
 template <typename T>
 struct Plan {
     GemmTask<T>* dev = nullptr;
     size_t dev_bytes = 0;
     std::vector<GemmTask<T>> tasks;
     std::vector<LaunchRec<T>> launches;
+    std::vector<std::unique_ptr<InnerRec<T>>> inner;   // L_INNER records (off = index)
+    bool inner_loose = false;            // its inner solves are inside the preconditioner
     hipGraph_t graph = nullptr;          // the launches captured once, replayed after
     hipGraphExec_t exec = nullptr;
     std::string name;                    // profiling family of the whole replay
@@ -187,6 +218,11 @@ struct hz_ctx {
     bool compose = true;           // output operators composed with the inner SIE inverse
     bool offline = false;          // inside the factorisation stage
     bool tune = true;              // autotune GEMM kernels and cell-solve widths (HZ_TUNE=0: off)
+    bool inner_pt = false;         // nested polarized traces: the inner SIE iterated (Sec. 4.2.1)
+    double inner_tol_loose = 1e-6; // inner GMRES tolerance inside the preconditioner
+    double inner_tol_tight = 1e-12;// inner GMRES tolerance elsewhere (set per solve)
+    int inner_iters_max = 0;       // largest inner GMRES iteration count since the last reset
+    long long CP_elems = 0;
     int force_kind = -1;           // HZ_GEMM_KIND: one matrix-core GEMM kernel for every launch
     GemmSplitWs gsw;               // workspace of the split-k GEMM variants (allocated once)
     std::map<std::string, int> cs_tuned;   // (mode, B, cells) -> cell-solve batch width
@@ -219,6 +255,9 @@ struct hz_ctx {
             *gsmall = nullptr, *gcoef = nullptr;
     int gpart_chunks = 0;
     double2* gh = nullptr;         // GMRES projections of both passes and |w|^2, on the device
+    // inner GMRES (nested polarized traces): Krylov basis and reductions
+    long long i_cap = 0; int i_cap_m = 0, i_cap_cols = 0;
+    double2 *iV = nullptr, *ipart = nullptr, *ismall = nullptr, *icoef = nullptr, *ih = nullptr;
     double2 *u64 = nullptr, *f64 = nullptr, *r64 = nullptr;   // refinement [W][W][B]
     hz_timing timing{};
     Prof prof;
@@ -270,7 +309,7 @@ void build_descriptors(hz_ctx* c) {
     c->d.HLpmax = (HLmax + 15) / 16 * 16;
     const int J = d.Lc - 1;
     c->inner_per_layer = (long long)J * 2 * HLmax;
-    long long off_coef = 0, off_X = 0, off_Q = 0, off_CS = 0, off_Sinv = 0, off_Lfac = 0;
+    long long off_coef = 0, off_X = 0, off_Q = 0, off_CS = 0, off_Sinv = 0, off_Lfac = 0, off_CP = 0;
     for (int l = 0; l < d.L; ++l) {
         LayerDesc ld{};
         ld.index = l;
@@ -329,6 +368,8 @@ void build_descriptors(hz_ctx* c) {
             off_Q += (long long)cd.nslot * cd.s * cd.R;
             cd.off_CS = off_CS;
             off_CS += (long long)cd.adj * cd.HL * cd.R;
+            cd.off_CP = off_CP;
+            off_CP += (long long)cd.adj * 2 * cd.HL * cd.R;
             c->cells.push_back(cd);
         }
     }
@@ -338,6 +379,13 @@ void build_descriptors(hz_ctx* c) {
     c->CS_elems = off_CS;
     c->Sinv_elems = off_Sinv;
     c->Lfac_elems = off_Lfac;
+    c->CP_elems = off_CP;
+    if (c->inner_pt) {                 // no inner factorisation
+        c->Sinv_elems = 0;
+        c->Lfac_elems = 0;
+    } else {
+        c->CP_elems = 0;
+    }
 }
 
 void sync(hz_ctx* c) { HIPCHK(hipStreamSynchronize(c->st)); }
@@ -445,7 +493,8 @@ void plan_jobs(hz_ctx* c, Plan<T>& pl, const std::vector<LayerJob<T>>& jobs, int
     Ops<T>& o = ops<T>(c);
     // with the composed output operators, only jobs that need the inner
     // traces themselves (no phase 3) run the block LU substitutions
-    const bool comp = c->compose && J > 0 && o.Qc != nullptr;
+    const bool pt = c->inner_pt && J > 0;
+    const bool comp = !pt && c->compose && J > 0 && o.Qc != nullptr;
     std::vector<LayerJob<T>> p2;
     for (const auto& jb : jobs)
         if (!(comp && jb.phase3)) p2.push_back(jb);
@@ -462,6 +511,10 @@ void plan_jobs(hz_ctx* c, Plan<T>& pl, const std::vector<LayerJob<T>>& jobs, int
                 t.lda = cd.R;
                 t.m = cd.adj * cd.HL;
                 t.k = cd.nslot * cd.s;
+                if (pt) {                     // both columns of each pair
+                    t.A = o.CP + cd.off_CP + cd.ncol;
+                    t.m = cd.adj * 2 * cd.HL;
+                }
                 t.ldx = B;
                 t.ldo = B;
                 t.nseg = 0;
@@ -475,6 +528,28 @@ void plan_jobs(hz_ctx* c, Plan<T>& pl, const std::vector<LayerJob<T>>& jobs, int
                 }
                 t.noseg = 0;
                 const long long HLB = (long long)cd.HL * B;
+                if (pt) {
+                    // left pair -> q of interface k-1, right pair -> d of interface k
+                    if (cd.has_left) {
+                        const long long off = ((long long)J + k - 1) * 2 * HLB;
+                        t.oseg_i0[t.noseg] = 0;
+                        t.oseg_len[t.noseg] = 2 * cd.HL;
+                        t.oseg_ptr[t.noseg] = jb.iy + off;
+                        t.oseg_add0[t.noseg] = jb.inner_add ? jb.inner_add + off : nullptr;
+                        t.noseg++;
+                    }
+                    if (cd.has_right) {
+                        const long long off = (long long)k * 2 * HLB;
+                        t.oseg_i0[t.noseg] = cd.has_left ? 2 * cd.HL : 0;
+                        t.oseg_len[t.noseg] = 2 * cd.HL;
+                        t.oseg_ptr[t.noseg] = jb.iy + off;
+                        t.oseg_add0[t.noseg] = jb.inner_add ? jb.inner_add + off : nullptr;
+                        t.noseg++;
+                    }
+                    maxm = std::max(maxm, t.m);
+                    pl.tasks.push_back(t);
+                    continue;
+                }
                 if (cd.has_left) {
                     const long long off = ((long long)(k - 1) * 2 + 1) * HLB;
                     t.oseg_i0[t.noseg] = 0;
@@ -496,8 +571,20 @@ void plan_jobs(hz_ctx* c, Plan<T>& pl, const std::vector<LayerJob<T>>& jobs, int
             }
         }
         add_launch(pl, first, maxm, B);
+        // ---- phase 2 (nested polarized traces): the inner polarized systems
+        // of all jobs, iterated together
+        if (pt && !p2.empty()) {
+            auto ir = std::make_unique<InnerRec<T>>();
+            for (const auto& jb : p2) ir->jobs.push_back({jb.layer, jb.iy, jb.ix});
+            ir->loose = pl.inner_loose;
+            LaunchRec<T> r{};
+            r.kind = L_INNER;
+            r.off = (long long)pl.inner.size();
+            pl.inner.push_back(std::move(ir));
+            pl.launches.push_back(r);
+        }
         // ---- phase 2: block LU substitutions across the cells (inner sweeps)
-        if (!p2.empty()) {
+        if (!pt && !p2.empty()) {
             for (int j = 1; j < J; ++j) {                       // forward
                 long long f2 = pl.tasks.size();
                 int mm = 0;
@@ -657,7 +744,7 @@ void plan_upload(hz_ctx* c, Plan<T>& pl) {
 }
 
 template <typename T>
-void plan_launches(hz_ctx* c, const Plan<T>& pl, int B);
+void plan_launches(hz_ctx* c, Plan<T>& pl, int B);
 
 // Autotuner for the matrix-core GEMM launches of a solve plan.  Each launch is
 // timed with every candidate kernel on its own operator blocks, with the
@@ -744,11 +831,15 @@ void tune_plan(hz_ctx* c, Plan<T>& pl, int B) {
     c->arena.release(dt, 0);
 }
 
+template <typename T>
+void inner_solve(hz_ctx* c, InnerRec<T>& r, int B);
+
 // Replay a plan: through its captured HIP graph when graphs are enabled and
 // profiling is off, launch by launch (one event pair per kernel) otherwise.
 template <typename T>
 void plan_run(hz_ctx* c, Plan<T>& pl, int B) {
-    if (c->use_graphs && c->st && !pl.name.empty() && !c->prof.on) {
+    // plans with inner iterations read the inner residuals on the host
+    if (c->use_graphs && c->st && !pl.name.empty() && !c->prof.on && pl.inner.empty()) {
         if (!pl.exec) {
             HIPCHK(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
             plan_launches<T>(c, pl, B);
@@ -764,7 +855,7 @@ void plan_run(hz_ctx* c, Plan<T>& pl, int B) {
 }
 
 template <typename T>
-void plan_launches(hz_ctx* c, const Plan<T>& pl, int B) {
+void plan_launches(hz_ctx* c, Plan<T>& pl, int B) {
     const bool prof = c->prof.on;
     for (const auto& r : pl.launches) {
         if (r.kind == L_GEMM) {
@@ -782,6 +873,8 @@ void plan_launches(hz_ctx* c, const Plan<T>& pl, int B) {
             launch_axpby<T>(r.y, r.x, r.a, r.b, r.n, c->st);
         } else if (r.kind == L_COPY) {
             launch_copy<T>(r.y, r.x, r.n, c->st);
+        } else if (r.kind == L_INNER) {
+            inner_solve(c, *pl.inner[r.off], B);
         }
     }
     HIPCHK(hipGetLastError());
@@ -795,7 +888,12 @@ C2<T>* qvec(hz_ctx* c, C2<T>* v, int k, int B) { return v + (long long)(c->d.K +
 
 template <typename T>
 C2<T>* iy_of(hz_ctx* c, int set, int layer, int B) {
-    return work<T>(c).iy[set] + c->layers[layer].off_inner * B;
+    return work<T>(c).iy[set] + (c->inner_pt ? 2 : 1) * c->layers[layer].off_inner * B;
+}
+// inner right-hand side of the volume source in `layer` (written by SOLVE_SAMPLE)
+template <typename T>
+C2<T>* gf_of(hz_ctx* c, int layer, int B) {
+    return work<T>(c).gf + (c->inner_pt ? 2 : 1) * c->layers[layer].off_inner * B;
 }
 template <typename T>
 C2<T>* ix_of(hz_ctx* c, int set, int layer, int B) {
@@ -915,6 +1013,7 @@ Plan<T>& get_plan(hz_ctx* c, bool sie, int B) {
     if (it != mp.end()) return *it->second;
     auto pl = std::make_unique<Plan<T>>();
     pl->name = fam_name<T>(sie ? "sie_graph" : "precond_graph");
+    pl->inner_loose = !sie;
     if (sie) build_sie_plan<T>(c, *pl, B);
     else build_pre_plan<T>(c, *pl, B);
     tune_plan<T>(c, *pl, B);
@@ -922,6 +1021,430 @@ Plan<T>& get_plan(hz_ctx* c, bool sie, int B) {
     Plan<T>& ref = *pl;
     mp[B] = std::move(pl);
     return ref;
+}
+
+// ---------------------------------------------------------------------------
+// nested polarized traces (Sec. 4.2.1): the inner SIE of each layer job as a
+// polarized system over the cells (the outer system with layers -> cells),
+// iterated by GMRES with the inner Gauss-Seidel sweeps.  The blocks are the
+// pair-column samples CP of the cell probes: no inner block is factorised.
+
+constexpr int INNER_MAXIT = 40;
+
+void givens(std::complex<double> a, std::complex<double> b, double& cs, std::complex<double>& sn);
+
+struct InnerJobDev {
+    const void* rhs;
+    void* out;
+    int HL;
+    int pad;
+};
+
+// rhs_i [d|q][2 J HL_i][B] -> column block i of dst (rows dq 2 J HLmax + r)
+template <typename T>
+__global__ void k_inner_pack(const InnerJobDev* jobs, C2<T>* dst, int J, int HLmax, int B,
+                             long long ld) {
+    const InnerJobDev jb = jobs[blockIdx.y];
+    const long long rows = 2LL * J * jb.HL;
+    const long long total = 2 * rows * B;
+    const C2<T>* src = (const C2<T>*)jb.rhs;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
+         q += (long long)gridDim.x * blockDim.x) {
+        const long long rr = q / B;
+        const int b = (int)(q - rr * B);
+        const int dq = rr >= rows ? 1 : 0;
+        const long long r = rr - dq * rows;
+        dst[(dq * 2LL * J * HLmax + r) * ld + (long long)blockIdx.y * B + b] = src[q];
+    }
+}
+
+// traces s = d + q of column block i of x -> out_i [2 J HL_i][B]
+template <typename T>
+__global__ void k_inner_unpack(const InnerJobDev* jobs, const C2<T>* x, int J, int HLmax, int B,
+                               long long ld) {
+    const InnerJobDev jb = jobs[blockIdx.y];
+    const long long rows = 2LL * J * jb.HL;
+    const long long total = rows * B;
+    const long long qoff = 2LL * J * HLmax * ld;
+    C2<T>* out = (C2<T>*)jb.out;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
+         q += (long long)gridDim.x * blockDim.x) {
+        const long long r = q / B;
+        const int b = (int)(q - r * B);
+        const long long at = r * ld + (long long)blockIdx.y * B + b;
+        out[q] = cadd(x[at], x[at + qoff]);
+    }
+}
+
+// pair (rows a then b) of interface j, d (dq = 0) or q (dq = 1), job i
+template <typename T>
+C2<T>* iw_pair(hz_ctx* c, const InnerRec<T>& r, C2<T>* v, int i, int dq, int j) {
+    const int J = c->d.Lc - 1;
+    const int HL = c->layers[r.jobs[i].layer].HL;
+    const int B = r.ncols / (int)r.jobs.size();
+    return v + ((long long)dq * 2 * J * c->d.HLmax + (long long)j * 2 * HL) * r.ncols +
+           (long long)i * B;
+}
+
+// rows of cell cd's pair-column samples on its left (right = 0) or right pair
+template <typename T>
+const C2<T>* cp_rows(hz_ctx* c, const CellDesc& cd, int right) {
+    return ops<T>(c).CP + cd.off_CP + (right && cd.has_left ? 2LL * cd.HL : 0) * cd.R;
+}
+
+// inner M: wA -> wB (s = d + q in S)
+template <typename T>
+void build_inner_M(hz_ctx* c, InnerRec<T>& r, Plan<T>& pl, int B) {
+    const int J = c->d.Lc - 1;
+    const long long half = 2LL * J * c->d.HLmax * r.ncols;
+    const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
+    add_vec<T>(pl, L_COPY, r.S, r.wA, zero, zero, half);
+    add_vec<T>(pl, L_AXPBY, r.S, r.wA + half, one, one, half);
+    const long long first = pl.tasks.size();
+    int maxm = 0;
+    for (int i = 0; i < (int)r.jobs.size(); ++i) {
+        const LayerDesc& ld = c->layers[r.jobs[i].layer];
+        const int HL = ld.HL;
+        const long long hb = (long long)HL * r.ncols;
+        for (int j = 0; j < J; ++j) {
+            // right rows of cell j: d_j + E_a q_j - R_right[G_T(s_{j-1}) + G_B(q_j)]
+            const CellDesc& cj = c->cells[ld.cell_begin + j];
+            GemmTask<T> t = blank_task<T>();
+            t.A = cp_rows<T>(c, cj, 1);
+            t.lda = cj.R;
+            t.m = 2 * HL;
+            t.ldx = r.ncols; t.ldo = r.ncols;
+            t.nseg = 0;
+            if (cj.has_left) {
+                t.seg_k0[t.nseg] = 0; t.seg_len[t.nseg] = 2 * HL;
+                t.seg_ptr[t.nseg] = iw_pair<T>(c, r, r.S, i, 0, j - 1);
+                t.nseg++;
+            }
+            t.seg_k0[t.nseg] = cj.has_left ? 2 * HL : 0; t.seg_len[t.nseg] = 2 * HL;
+            t.seg_ptr[t.nseg] = iw_pair<T>(c, r, r.wA, i, 1, j);
+            t.nseg++;
+            t.k = (cj.has_left ? 2 * HL : 0) + 2 * HL;
+            t.noseg = 2;
+            t.oseg_i0[0] = 0; t.oseg_len[0] = HL;
+            t.oseg_ptr[0] = iw_pair<T>(c, r, r.wB, i, 0, j);
+            t.oseg_add0[0] = iw_pair<T>(c, r, r.wA, i, 0, j);
+            t.oseg_add1[0] = iw_pair<T>(c, r, r.wA, i, 1, j);
+            t.c1[0] = (T)1;
+            t.oseg_i0[1] = HL; t.oseg_len[1] = HL;
+            t.oseg_ptr[1] = iw_pair<T>(c, r, r.wB, i, 0, j) + hb;
+            t.oseg_add0[1] = iw_pair<T>(c, r, r.wA, i, 0, j) + hb;
+            t.alpha = (T)-1;
+            pl.tasks.push_back(t);
+            // left rows of cell j+1: q_j + E_b d_j - R_left[G_T(d_j) + G_B(s_{j+1})]
+            const CellDesc& cn = c->cells[ld.cell_begin + j + 1];
+            GemmTask<T> u = blank_task<T>();
+            u.A = cp_rows<T>(c, cn, 0);
+            u.lda = cn.R;
+            u.m = 2 * HL;
+            u.ldx = r.ncols; u.ldo = r.ncols;
+            u.nseg = 1;
+            u.seg_k0[0] = 0; u.seg_len[0] = 2 * HL;
+            u.seg_ptr[0] = iw_pair<T>(c, r, r.wA, i, 0, j);
+            if (cn.has_right) {
+                u.seg_k0[1] = 2 * HL; u.seg_len[1] = 2 * HL;
+                u.seg_ptr[1] = iw_pair<T>(c, r, r.S, i, 0, j + 1);
+                u.nseg = 2;
+            }
+            u.k = 2 * HL + (cn.has_right ? 2 * HL : 0);
+            u.noseg = 2;
+            u.oseg_i0[0] = 0; u.oseg_len[0] = HL;
+            u.oseg_ptr[0] = iw_pair<T>(c, r, r.wB, i, 1, j);
+            u.oseg_add0[0] = iw_pair<T>(c, r, r.wA, i, 1, j);
+            u.oseg_i0[1] = HL; u.oseg_len[1] = HL;
+            u.oseg_ptr[1] = iw_pair<T>(c, r, r.wB, i, 1, j) + hb;
+            u.oseg_add0[1] = iw_pair<T>(c, r, r.wA, i, 1, j) + hb;
+            u.oseg_add1[1] = iw_pair<T>(c, r, r.wA, i, 0, j) + hb;
+            u.c1[1] = (T)1;
+            u.alpha = (T)-1;
+            pl.tasks.push_back(u);
+            maxm = std::max(maxm, 2 * HL);
+        }
+    }
+    add_launch(pl, first, maxm, B);
+}
+
+// inner P^GS: wB -> wC (rightward sweep, reflections, leftward sweep)
+template <typename T>
+void build_inner_P(hz_ctx* c, InnerRec<T>& r, Plan<T>& pl, int B) {
+    const int J = c->d.Lc - 1;
+    const int NJ = (int)r.jobs.size();
+    const double2 zero = make_double2(0.0, 0.0);
+    add_vec<T>(pl, L_COPY, r.wC, r.wB, zero, zero, r.n * r.ncols);
+    for (int j = 1; j < J; ++j) {                   // x_j = v_j + R_right^j G_T^j(x_{j-1})
+        const long long first = pl.tasks.size();
+        int maxm = 0;
+        for (int i = 0; i < NJ; ++i) {
+            const LayerDesc& ld = c->layers[r.jobs[i].layer];
+            const int HL = ld.HL;
+            const CellDesc& cj = c->cells[ld.cell_begin + j];
+            GemmTask<T> t = blank_task<T>();
+            t.A = cp_rows<T>(c, cj, 1);
+            t.lda = cj.R;
+            t.m = 2 * HL; t.k = 2 * HL;
+            t.ldx = r.ncols; t.ldo = r.ncols;
+            t.nseg = 1;
+            t.seg_k0[0] = 0; t.seg_len[0] = 2 * HL;
+            t.seg_ptr[0] = iw_pair<T>(c, r, r.wC, i, 0, j - 1);
+            t.noseg = 1;
+            t.oseg_i0[0] = 0; t.oseg_len[0] = 2 * HL;
+            t.oseg_ptr[0] = iw_pair<T>(c, r, r.wC, i, 0, j);
+            t.oseg_add0[0] = iw_pair<T>(c, r, r.wB, i, 0, j);
+            t.alpha = (T)1;
+            pl.tasks.push_back(t);
+            maxm = std::max(maxm, 2 * HL);
+        }
+        add_launch(pl, first, maxm, B);
+    }
+    {   // t_j = v^q_j - E_b x_j + R_left^{j+1}[G_T(x_j) + G_B(x_{j+1})]  (all j at once)
+        const long long first = pl.tasks.size();
+        int maxm = 0;
+        for (int i = 0; i < NJ; ++i) {
+            const LayerDesc& ld = c->layers[r.jobs[i].layer];
+            const int HL = ld.HL;
+            const long long hb = (long long)HL * r.ncols;
+            for (int j = 0; j < J; ++j) {
+                const CellDesc& cn = c->cells[ld.cell_begin + j + 1];
+                GemmTask<T> t = blank_task<T>();
+                t.A = cp_rows<T>(c, cn, 0);
+                t.lda = cn.R;
+                t.m = 2 * HL;
+                t.ldx = r.ncols; t.ldo = r.ncols;
+                t.nseg = 1;
+                t.seg_k0[0] = 0; t.seg_len[0] = 2 * HL;
+                t.seg_ptr[0] = iw_pair<T>(c, r, r.wC, i, 0, j);
+                if (cn.has_right) {
+                    t.seg_k0[1] = 2 * HL; t.seg_len[1] = 2 * HL;
+                    t.seg_ptr[1] = iw_pair<T>(c, r, r.wC, i, 0, j + 1);
+                    t.nseg = 2;
+                }
+                t.k = 2 * HL + (cn.has_right ? 2 * HL : 0);
+                t.noseg = 2;
+                t.oseg_i0[0] = 0; t.oseg_len[0] = HL;
+                t.oseg_ptr[0] = iw_pair<T>(c, r, r.wC, i, 1, j);
+                t.oseg_add0[0] = iw_pair<T>(c, r, r.wB, i, 1, j);
+                t.oseg_i0[1] = HL; t.oseg_len[1] = HL;
+                t.oseg_ptr[1] = iw_pair<T>(c, r, r.wC, i, 1, j) + hb;
+                t.oseg_add0[1] = iw_pair<T>(c, r, r.wB, i, 1, j) + hb;
+                t.oseg_add1[1] = iw_pair<T>(c, r, r.wC, i, 0, j) + hb;
+                t.c1[1] = (T)-1;
+                t.alpha = (T)1;
+                pl.tasks.push_back(t);
+                maxm = std::max(maxm, 2 * HL);
+            }
+        }
+        add_launch(pl, first, maxm, B);
+    }
+    for (int j = J - 2; j >= 0; --j) {              // x_j = t_j + R_left^{j+1} G_B^{j+1}(x_{j+1})
+        const long long first = pl.tasks.size();
+        int maxm = 0;
+        for (int i = 0; i < NJ; ++i) {
+            const LayerDesc& ld = c->layers[r.jobs[i].layer];
+            const int HL = ld.HL;
+            const CellDesc& cn = c->cells[ld.cell_begin + j + 1];
+            GemmTask<T> t = blank_task<T>();
+            t.A = cp_rows<T>(c, cn, 0) + 2 * HL;          // right probes (cell j+1 has a left pair)
+            t.lda = cn.R;
+            t.m = 2 * HL; t.k = 2 * HL;
+            t.ldx = r.ncols; t.ldo = r.ncols;
+            t.nseg = 1;
+            t.seg_k0[0] = 0; t.seg_len[0] = 2 * HL;
+            t.seg_ptr[0] = iw_pair<T>(c, r, r.wC, i, 1, j + 1);
+            t.noseg = 1;
+            t.oseg_i0[0] = 0; t.oseg_len[0] = 2 * HL;
+            t.oseg_ptr[0] = iw_pair<T>(c, r, r.wC, i, 1, j);
+            t.oseg_add0[0] = iw_pair<T>(c, r, r.wC, i, 1, j);
+            t.alpha = (T)1;
+            pl.tasks.push_back(t);
+            maxm = std::max(maxm, 2 * HL);
+        }
+        add_launch(pl, first, maxm, B);
+    }
+}
+
+void ensure_inner_basis(hz_ctx* c, long long nB, int m, int cols) {
+    if (c->i_cap >= nB && c->i_cap_m >= m && c->i_cap_cols >= cols) return;
+    for (void* q : {(void*)c->iV, (void*)c->ipart, (void*)c->ismall, (void*)c->icoef, (void*)c->ih})
+        c->arena.release(q, 0);
+    nB = std::max(nB, c->i_cap);
+    m = std::max(m, c->i_cap_m);
+    cols = std::max(cols, c->i_cap_cols);
+    c->i_cap = nB; c->i_cap_m = m; c->i_cap_cols = cols;
+    c->iV = (double2*)c->arena.alloc(sizeof(double2) * nB * (m + 1));
+    c->ipart = (double2*)c->arena.alloc(sizeof(double2) * 32 * (m + 2) * (long long)cols);
+    c->ismall = (double2*)c->arena.alloc(sizeof(double2) * (m + 2) * (long long)cols);
+    c->icoef = (double2*)c->arena.alloc(sizeof(double2) * (m + 2) * (long long)cols);
+    c->ih = (double2*)c->arena.alloc(sizeof(double2) * (2 * (m + 1) + 1) * (long long)cols);
+}
+
+template <typename T>
+void inner_setup(hz_ctx* c, InnerRec<T>& r, int B) {
+    const Dims& d = c->d;
+    const int J = d.Lc - 1;
+    const int NJ = (int)r.jobs.size();
+    r.n = 4LL * J * d.HLmax;
+    r.ncols = NJ * B;
+    r.ar = &c->arena;
+    const long long nB = r.n * r.ncols;
+    r.wA = alloc_c<T>(c, nB);
+    r.wB = alloc_c<T>(c, nB);
+    r.wC = alloc_c<T>(c, nB);
+    r.S = alloc_c<T>(c, nB / 2);
+    // padding rows stay zero: the plans write the rows of each job only
+    for (C2<T>* q : {r.wA, r.wB, r.wC})
+        HIPCHK(hipMemsetAsync(q, 0, sizeof(C2<T>) * nB, c->st));
+    HIPCHK(hipMemsetAsync(r.S, 0, sizeof(C2<T>) * (nB / 2), c->st));
+    std::vector<InnerJobDev> tab(NJ);
+    for (int i = 0; i < NJ; ++i)
+        tab[i] = {r.jobs[i].rhs, r.jobs[i].out, c->layers[r.jobs[i].layer].HL, 0};
+    r.jobtab = c->arena.alloc(sizeof(InnerJobDev) * NJ);
+    upload(c, r.jobtab, tab.data(), sizeof(InnerJobDev) * NJ);
+    r.M = std::make_unique<Plan<T>>();
+    r.M->name = fam_name<T>("inner_m_graph");
+    build_inner_M<T>(c, r, *r.M, B);
+    tune_plan<T>(c, *r.M, B);
+    plan_upload<T>(c, *r.M);
+    r.P = std::make_unique<Plan<T>>();
+    r.P->name = fam_name<T>("inner_p_graph");
+    build_inner_P<T>(c, r, *r.P, B);
+    tune_plan<T>(c, *r.P, B);
+    plan_upload<T>(c, *r.P);
+}
+
+// Left-preconditioned GMRES on the inner polarized systems of a record, x0 =
+// 0, classical Gram-Schmidt with one re-orthogonalisation, per-column
+// stopping on the preconditioned residual (the outer driver's scheme, one
+// column per job and right-hand side).
+template <typename T>
+void inner_solve(hz_ctx* c, InnerRec<T>& r, int B) {
+    if constexpr (sizeof(T) != sizeof(double)) {
+        (void)c; (void)r; (void)B;
+        raise(HZ_EINVAL, "nested polarized traces run in complex128 only");
+    } else {
+        const Dims& d = c->d;
+        const int J = d.Lc - 1;
+        if (!r.M) inner_setup<T>(c, r, B);
+        const long long n = r.n;
+        const int NB = r.ncols;
+        const int NJ = (int)r.jobs.size();
+        const long long nB = n * NB;
+        const int m = INNER_MAXIT;
+        const double tol = r.loose ? c->inner_tol_loose : c->inner_tol_tight;
+        ensure_inner_basis(c, nB, m, NB);
+        const int chunks = (int)std::min<long long>(32, std::max<long long>(1, n / 32));
+        auto idots = [&](const double2* V, int nv, const double2* w, double2* out) {
+            launch_dots(V, nB, nv, w, n, NB, c->ipart, chunks, c->st);
+            launch_reduce_partials(c->ipart, chunks, nv * NB, out, c->st);
+        };
+        const dim3 pg(std::max<int>(1, (int)std::min<long long>(4096, (2 * n * B + 255) / 256)), NJ);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_inner_pack<T>), pg, dim3(256), 0, c->st,
+                           (const InnerJobDev*)r.jobtab, r.wB, J, d.HLmax, B, (long long)NB);
+        plan_run<T>(c, *r.P, B);                       // r0 = P b
+        double2* V = c->iV;
+        HIPCHK(hipMemcpyAsync(V, r.wC, sizeof(double2) * nB, hipMemcpyDeviceToDevice, c->st));
+        std::vector<double2> hb(NB);
+        idots(nullptr, 1, V, c->ismall);
+        HIPCHK(hipMemcpyAsync(hb.data(), c->ismall, sizeof(double2) * NB, hipMemcpyDeviceToHost, c->st));
+        sync(c);
+        std::vector<double> beta(NB);
+        std::vector<std::vector<std::complex<double>>> R(m);    // rotated Hessenberg columns
+        std::vector<std::complex<double>> g((size_t)(m + 1) * NB, 0.0);
+        std::vector<double> cs((size_t)m * NB, 1.0);
+        std::vector<std::complex<double>> sn((size_t)m * NB, 0.0);
+        std::vector<int> done(NB, 0), kfin(NB, 0);
+        std::vector<double2> sc(NB);
+        for (int q = 0; q < NB; ++q) {
+            beta[q] = std::sqrt(std::max(0.0, hb[q].x));
+            g[q] = beta[q];
+            if (beta[q] == 0.0) done[q] = 1;
+            sc[q] = make_double2(beta[q] > 0 ? 1.0 / beta[q] : 0.0, 0.0);
+        }
+        upload(c, c->icoef, sc.data(), sizeof(double2) * NB);
+        launch_scale_cols(V, V, c->icoef, n, NB, c->st);
+        int j = 0;
+        for (; j < m; ++j) {
+            if (std::all_of(done.begin(), done.end(), [](int v) { return v != 0; })) break;
+            double2* Vj = V + (long long)j * nB;
+            double2* Vn = V + (long long)(j + 1) * nB;
+            HIPCHK(hipMemcpyAsync(r.wA, Vj, sizeof(double2) * nB, hipMemcpyDeviceToDevice, c->st));
+            plan_run<T>(c, *r.M, B);
+            plan_run<T>(c, *r.P, B);                   // w = P M v_j in wC
+            double2* w = r.wC;
+            const size_t nh = (size_t)(j + 1) * NB;
+            double2* hA = c->ih;
+            double2* hB2 = c->ih + nh;
+            double2* hN = c->ih + 2 * nh;
+            idots(V, j + 1, w, hA);
+            launch_update_basis(w, V, nB, j + 1, hA, n, NB, c->st, -1.0);
+            idots(V, j + 1, w, hB2);
+            launch_update_basis(w, V, nB, j + 1, hB2, n, NB, c->st, -1.0);
+            idots(nullptr, 1, w, hN);
+            launch_inv_norms(hN, c->icoef, NB, c->st);
+            launch_scale_cols(Vn, w, c->icoef, n, NB, c->st);
+            std::vector<double2> hh(2 * nh + NB);
+            HIPCHK(hipMemcpyAsync(hh.data(), c->ih, sizeof(double2) * hh.size(),
+                                  hipMemcpyDeviceToHost, c->st));
+            sync(c);
+            R[j].assign((size_t)(j + 1) * NB, 0.0);
+            for (int q = 0; q < NB; ++q) {
+                if (done[q]) continue;
+                std::vector<std::complex<double>> col(j + 2);
+                for (int i = 0; i <= j; ++i) {
+                    const size_t at = (size_t)i * NB + q;
+                    col[i] = std::complex<double>(hh[at].x + hh[nh + at].x, hh[at].y + hh[nh + at].y);
+                }
+                const double nrm = std::sqrt(std::max(0.0, hh[2 * nh + q].x));
+                col[j + 1] = nrm;
+                for (int i = 0; i < j; ++i) {
+                    const double ci = cs[(size_t)i * NB + q];
+                    const std::complex<double> si = sn[(size_t)i * NB + q];
+                    const std::complex<double> a = col[i], b2 = col[i + 1];
+                    col[i] = ci * a + si * b2;
+                    col[i + 1] = -std::conj(si) * a + ci * b2;
+                }
+                double cj; std::complex<double> sj;
+                givens(col[j], col[j + 1], cj, sj);
+                cs[(size_t)j * NB + q] = cj;
+                sn[(size_t)j * NB + q] = sj;
+                col[j] = cj * col[j] + sj * col[j + 1];
+                for (int i = 0; i <= j; ++i) R[j][(size_t)i * NB + q] = col[i];
+                const std::complex<double> gj = g[(size_t)j * NB + q];
+                g[(size_t)(j + 1) * NB + q] = -std::conj(sj) * gj;
+                g[(size_t)j * NB + q] = cj * gj;
+                kfin[q] = j + 1;
+                const double rel = std::abs(g[(size_t)(j + 1) * NB + q]) / beta[q];
+                if (rel <= tol || nrm == 0.0) done[q] = 1;
+            }
+        }
+        c->inner_iters_max = std::max(c->inner_iters_max, j);
+        // x = V y into wA, then the traces s = d + q of every job
+        const int kmax = *std::max_element(kfin.begin(), kfin.end());
+        HIPCHK(hipMemsetAsync(r.wA, 0, sizeof(double2) * nB, c->st));
+        if (kmax > 0) {
+            std::vector<double2> coef((size_t)kmax * NB, make_double2(0, 0));
+            for (int q = 0; q < NB; ++q) {
+                const int k = kfin[q];
+                std::vector<std::complex<double>> y(k);
+                for (int i = k - 1; i >= 0; --i) {
+                    std::complex<double> sacc = g[(size_t)i * NB + q];
+                    for (int p2 = i + 1; p2 < k; ++p2) sacc -= R[p2][(size_t)i * NB + q] * y[p2];
+                    y[i] = sacc / R[i][(size_t)i * NB + q];
+                }
+                for (int i = 0; i < k; ++i)
+                    coef[(size_t)i * NB + q] = make_double2(y[i].real(), y[i].imag());
+            }
+            upload(c, c->icoef, coef.data(), sizeof(double2) * coef.size());
+            launch_update_basis(r.wA, V, nB, kmax, c->icoef, n, NB, c->st);
+        }
+        const dim3 ug(std::max<int>(1, (int)std::min<long long>(4096, (n * B / 2 + 255) / 256)), NJ);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_inner_unpack<T>), ug, dim3(256), 0, c->st,
+                           (const InnerJobDev*)r.jobtab, r.wA, J, d.HLmax, B, (long long)NB);
+        HIPCHK(hipGetLastError());
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -952,7 +1475,7 @@ void ensure_work(hz_ctx* c, int B, bool volume = true) {
         }
         w.rows_out = alloc_c<T>(c, (long long)d.L * MAXSLOT * W * B);
         const long long inner = std::max<long long>((long long)d.L * c->inner_per_layer * B, 1);
-        w.gf = alloc_c<T>(c, inner);
+        w.gf = alloc_c<T>(c, (c->inner_pt ? 2 : 1) * inner);
         // cell-solve scratch: one region per workgroup of a volume solve
         const int nb = cs_nb_cap(B);
         const int chunks = (B + nb - 1) / nb;
@@ -964,7 +1487,7 @@ void ensure_work(hz_ctx* c, int B, bool volume = true) {
     w.Bcap = B;
     const long long inner = std::max<long long>((long long)d.L * c->inner_per_layer * B, 1);
     for (int s = 0; s < 2; ++s) {
-        w.iy[s] = alloc_c<T>(c, inner);
+        w.iy[s] = alloc_c<T>(c, (c->inner_pt ? 2 : 1) * inner);   // polarized: [d|q]
         w.ix[s] = alloc_c<T>(c, inner);
     }
     const long long pol = std::max<long long>(4LL * d.K * W * B, 1);
@@ -1008,7 +1531,7 @@ void ensure_gmres(hz_ctx* c, int B, int m) {
     c->g_cap_m = m;
     const long long nb = std::max<long long>(n * B, 1);
     c->V = (double2*)c->arena.alloc(sizeof(double2) * nb * (m + 1));
-    if (c->prm.precision == HZ_MIXED) {
+    if (c->prm.precision == HZ_MIXED || c->inner_pt) {
         if (c->Z) c->arena.release(c->Z, 0);
         c->Z = (double2*)c->arena.alloc(sizeof(double2) * nb * m);
     }
@@ -1334,6 +1857,7 @@ void factor_impl(hz_ctx* c, const std::vector<char>* redo = nullptr) {
         o.CS = alloc_c<double>(c, std::max<long long>(c->CS_elems, 1));
         o.Sinv = alloc_c<double>(c, std::max<long long>(c->Sinv_elems, 1));
         o.Lfac = alloc_c<double>(c, std::max<long long>(c->Lfac_elems, 1));
+        if (c->inner_pt) o.CP = alloc_c<double>(c, std::max<long long>(c->CP_elems, 1));
     }
     o.e = c->e;
     HIPCHK(hipMemsetAsync(c->flags, 0, 2 * sizeof(int), c->st));
@@ -1384,6 +1908,7 @@ void factor_impl(hz_ctx* c, const std::vector<char>* redo = nullptr) {
         a.mode = SOLVE_PROBE;
         a.Qpool = o.Q;
         a.CSpool = o.CS;
+        a.CPpool = c->inner_pt ? o.CP : nullptr;
         a.probe0 = 0;
         a.B = Rmax;
         a.nb = nb;
@@ -1399,8 +1924,9 @@ void factor_impl(hz_ctx* c, const std::vector<char>* redo = nullptr) {
         c->arena.release(Y, sizeof(double2) * ystride * (long long)per * chunks);
         c->arena.release(d_list, sizeof(int) * nt);
     }
-    // 3. inner SIE block LU without pivoting (per layer, sequential over interfaces)
-    const int J = d.Lc - 1;
+    // 3. inner SIE block LU without pivoting (per layer, sequential over
+    // interfaces); the nested polarized traces iterate the inner SIE instead
+    const int J = c->inner_pt ? 0 : d.Lc - 1;
     std::vector<int> lay;                  // layers to refactor
     for (int l = 0; l < d.L; ++l)
         if (redo_layer[l]) lay.push_back(l);
@@ -1583,6 +2109,7 @@ bool sample_sources(hz_ctx* c, int B, const int* active_host) {
     a.f_ext = w.f_ext;
     a.layer_active = nullptr;
     a.inner_rhs = w.gf;
+    a.inner_pol = c->inner_pt ? 1 : 0;
     a.rows_out = w.rows_out;
     cell_solve_launch<T>(c, a, list, B);
     return true;
@@ -1605,7 +2132,7 @@ void sie_rhs_impl(hz_ctx* c, int B, C2<T>* out, const int* active_host) {
             if (side == 1 && !ld.has_bot) continue;
             LayerJob<T> jb;
             jb.layer = l;
-            jb.inner_add = w.gf + ld.off_inner * B;
+            jb.inner_add = gf_of<T>(c, l, B);
             jb.iy = iy_of<T>(c, side, l, B);
             jb.ix = ix_of<T>(c, side, l, B);
             jb.side = side;
@@ -1634,7 +2161,7 @@ void reconstruct_impl(hz_ctx* c, int B, const int* active_host) {
             jb.layer = l;
             jb.top = l > 0 ? w.sv + (long long)(l - 1) * pairn : nullptr;
             jb.bot = l < d.L - 1 ? w.sv + (long long)l * pairn : nullptr;
-            jb.inner_add = active_host[l] ? w.gf + c->layers[l].off_inner * B : nullptr;
+            jb.inner_add = active_host[l] ? gf_of<T>(c, l, B) : nullptr;
             jb.iy = iy_of<T>(c, 0, l, B);
             jb.ix = ix_of<T>(c, 0, l, B);
             jb.phase3 = false;
@@ -1805,7 +2332,8 @@ void gmres(hz_ctx* c, const double2* b, double2* x, int B, double tol, int maxit
         double2* Vj = V + (long long)j * vs;
         double2* Vn = V + (long long)(j + 1) * vs;
         if (flex) {
-            apply_P<float>(c, Vj, Z + (long long)j * vs, B);
+            if (c->inner_pt) apply_P<double>(c, Vj, Z + (long long)j * vs, B);
+            else apply_P<float>(c, Vj, Z + (long long)j * vs, B);
             apply_M64(c, Z + (long long)j * vs, c->gw, B);
         } else {
             apply_PM<T>(c, Vj, c->gw, B);
@@ -2150,10 +2678,17 @@ hz_status solve_impl(hz_ctx* c, const void* rhs_dev, int B, void* out_dev, doubl
     int refine_steps = 0;
     bool conv = true;
     std::vector<double> err_est(B, 0.0);
+    // nested polarized traces: the inner systems outside the preconditioner
+    // are solved well below the outer tolerance (the SIE matrix, the right-
+    // hand side and the reconstruction must be exact to it); the
+    // preconditioner's loose inner solves make it nonlinear, hence flexible
+    // GMRES
+    c->inner_tol_tight = std::min(1e-10, std::max(1e-13, 0.01 * tol));
+    c->inner_iters_max = 0;
     if (c->prm.precision == HZ_FP64 || c->prm.precision == HZ_MIXED) {
-        const bool flex = c->prm.precision == HZ_MIXED;
+        const bool flex = c->prm.precision == HZ_MIXED || c->inner_pt;
         ensure_work<double>(c, B);
-        if (flex) ensure_work<float>(c, B, false);
+        if (c->prm.precision == HZ_MIXED) ensure_work<float>(c, B, false);
         dd_solve<double>(c, B, tol, max_iter, active, iters, relres, &t_rhs, &t_gm, &t_rec, flex);
         for (int b = 0; b < B; ++b) if (!(relres[b] <= tol)) conv = false;
     } else {
@@ -2206,6 +2741,7 @@ hz_status solve_impl(hz_ctx* c, const void* rhs_dev, int B, void* out_dev, doubl
     c->timing.t_recon = t_rec;
     c->timing.t_solve = t_all;
     c->timing.gmres_iters = *std::max_element(iters.begin(), iters.end());
+    c->timing.inner_iters = c->inner_iters_max;
     if (timing) *timing = c->timing;
     if (stats) {
         for (int b = 0; b < B; ++b) {
@@ -2302,10 +2838,25 @@ hz_status hz_setup(const double* model_dev, const hz_params* prm, hz_ctx** out) 
         raise(HZ_EINVAL, "bad preconditioner");
     if (prm->krylov != HZ_KRYLOV_GMRES && prm->krylov != HZ_KRYLOV_BICGSTAB)
         raise(HZ_EINVAL, "bad Krylov method");
+    if (prm->inner != HZ_INNER_LU && prm->inner != HZ_INNER_PT) raise(HZ_EINVAL, "bad inner solver");
+    if (prm->inner == HZ_INNER_PT) {
+        if (prm->precision != HZ_FP64)
+            raise(HZ_EINVAL, "nested polarized traces need precision HZ_FP64");
+        if (prm->krylov != HZ_KRYLOV_GMRES)
+            raise(HZ_EINVAL, "nested polarized traces need the (flexible) GMRES driver");
+        if (prm->cells > 1 && prm->n_pml < 1)
+            raise(HZ_EINVAL, "nested polarized traces need n_pml >= 1");
+        if (!(prm->inner_tol < 1.0)) raise(HZ_EINVAL, "inner_tol must be < 1");
+    }
     c = new hz_ctx();
     c->prm = *prm;
+    c->inner_pt = prm->inner == HZ_INNER_PT && prm->cells > 1;
+    if (c->inner_pt) {
+        c->compose = false;
+        c->inner_tol_loose = prm->inner_tol > 0.0 ? prm->inner_tol : 1e-6;
+    }
     if (const char* g = std::getenv("HZ_GRAPHS")) c->use_graphs = std::atoi(g) != 0;
-    if (const char* g = std::getenv("HZ_COMPOSE")) c->compose = std::atoi(g) != 0;
+    if (const char* g = std::getenv("HZ_COMPOSE")) c->compose = !c->inner_pt && std::atoi(g) != 0;
     if (const char* g = std::getenv("HZ_TUNE")) c->tune = std::atoi(g) != 0;
     if (const char* g = std::getenv("HZ_GEMM_KIND")) {
         const int k = std::atoi(g);

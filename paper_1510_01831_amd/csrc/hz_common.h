@@ -94,6 +94,8 @@ struct CellDesc {
     long long off_X;         // X_k = S_k^{-1}: [Wc][HLp x HLp in 16x4 MFMA tiles, see xt_index]
     long long off_Q;         // Q = [M_u | D_loc]: [nslot * s][R]
     long long off_CS;        // column samples: [adj * HL][R] (left side first)
+    long long off_CP;        // pair-column samples (nested polarized traces): [adj * 2 HL][R],
+                             // left pair (positions 0, 1) first, then the right pair (n_c, n_c + 1)
 };
 
 struct Dims {
@@ -188,8 +190,9 @@ struct CellSolveArgs {
     long long y_stride;          // complex elements per launch-cell in Y
     // SOLVE_GRID: g/x on the cell grid [HL][Wc][B] (row-major grid) for one cell
     const C2<T>* g_grid; C2<T>* x_grid;
-    // SOLVE_PROBE: outputs Q (row samples) and CS (column samples) into the pools
-    C2<T>* Qpool; C2<T>* CSpool;
+    // SOLVE_PROBE: outputs Q (row samples) and CS (column samples) into the pools,
+    // and the pair-column samples into CPpool when it is set
+    C2<T>* Qpool; C2<T>* CSpool; C2<T>* CPpool;
     int probe0;                  // first probe handled (chunking over R)
     // SOLVE_SAMPLE / SOLVE_VOLUME: volume source on the extended grid [W][W][B] (or NULL)
     const C2<T>* f_ext;
@@ -202,6 +205,8 @@ struct CellSolveArgs {
     long long inner_ld;          // per-layer stride in complex elements (J*2*HLmax*B)
     // outputs
     C2<T>* inner_rhs;            // SOLVE_SAMPLE: column samples -> inner rhs (per layer)
+    int inner_pol;               // SOLVE_SAMPLE: inner rhs of the polarized inner system
+                                 // ([d|q][J][2][HL][B] per layer, stride 2 J 2 HLmax B)
     C2<T>* rows_out;             // SOLVE_SAMPLE: row samples [L][nslot=4][W][B]
     C2<T>* u_ext;                // SOLVE_VOLUME: [W][W][B]
     double h;

@@ -233,18 +233,38 @@ __device__ inline void cell_emit(const CellSolveArgs<T>& a, const CellDesc& cd,
         if (cd.has_left && k == p) CS[(long long)j * cd.R + probe] = x;
         if (cd.has_right && k == p + cd.nc - 1)
             CS[((long long)(cd.has_left ? cd.HL : 0) + j) * cd.R + probe] = x;
+        if (a.CPpool) {
+            C2<T>* CP = a.CPpool + cd.off_CP;
+            const int HL = cd.HL;
+            if (cd.has_left && (k == p - 1 || k == p))
+                CP[((long long)(k - p + 1) * HL + j) * cd.R + probe] = x;
+            if (cd.has_right && (k == p + cd.nc - 1 || k == p + cd.nc))
+                CP[((long long)((cd.has_left ? 2 : 0) + k - (p + cd.nc - 1)) * HL + j) * cd.R +
+                   probe] = x;
+        }
         if (own_col) {
             for (int si = 0; si < ld.nslot; ++si)
                 if (ld.slot_row[si] == j)
                     Q[((long long)si * cd.s + (k - cd.own_c0)) * cd.R + probe] = x;
         }
     } else if constexpr (MODE == SOLVE_SAMPLE) {
-        C2<T>* ir = a.inner_rhs + ld.off_inner * B;
         const int HL = cd.HL;
-        if (cd.has_left && k == p)
-            ir[(((long long)(cd.cell - 1) * 2 + 1) * HL + j) * B + b] = x;
-        if (cd.has_right && k == p + cd.nc - 1)
-            ir[(((long long)cd.cell * 2 + 0) * HL + j) * B + b] = x;
+        if (a.inner_pol) {
+            // left pair (positions 0, 1) -> q of interface cell-1, right pair
+            // (n_c, n_c + 1) -> d of interface cell
+            C2<T>* ir = a.inner_rhs + 2 * ld.off_inner * B;
+            const int J = ld.J;
+            if (cd.has_left && (k == p - 1 || k == p))
+                ir[((((long long)J + cd.cell - 1) * 2 + (k - p + 1)) * HL + j) * B + b] = x;
+            if (cd.has_right && (k == p + cd.nc - 1 || k == p + cd.nc))
+                ir[((((long long)cd.cell) * 2 + (k - (p + cd.nc - 1))) * HL + j) * B + b] = x;
+        } else {
+            C2<T>* ir = a.inner_rhs + ld.off_inner * B;
+            if (cd.has_left && k == p)
+                ir[(((long long)(cd.cell - 1) * 2 + 1) * HL + j) * B + b] = x;
+            if (cd.has_right && k == p + cd.nc - 1)
+                ir[(((long long)cd.cell * 2 + 0) * HL + j) * B + b] = x;
+        }
         if (own_col) {
             for (int si = 0; si < ld.nslot; ++si)
                 if (ld.slot_row[si] == j)

@@ -18,6 +18,7 @@ HZ_FP64, HZ_MIXED, HZ_MIXED_REFINE = 0, 1, 2
 HZ_MODEL_VELOCITY, HZ_MODEL_SLOWNESS2 = 0, 1
 HZ_PRECOND_GS, HZ_PRECOND_JACOBI = 0, 1
 HZ_KRYLOV_GMRES, HZ_KRYLOV_BICGSTAB = 0, 1
+HZ_INNER_LU, HZ_INNER_PT = 0, 1
 
 EXPORTED = [
     "hz_setup", "hz_factor", "hz_solve", "hz_adjoint", "hz_solve_ext", "hz_adjoint_ext",
@@ -35,7 +36,8 @@ class Params(ctypes.Structure):
                 ("pml_beta", ctypes.c_double), ("layers", ctypes.c_int),
                 ("cells", ctypes.c_int), ("precision", ctypes.c_int),
                 ("model_kind", ctypes.c_int), ("max_batch", ctypes.c_int),
-                ("precond", ctypes.c_int), ("krylov", ctypes.c_int)]
+                ("precond", ctypes.c_int), ("krylov", ctypes.c_int),
+                ("inner", ctypes.c_int), ("inner_tol", ctypes.c_double)]
 
 
 class RhsStats(ctypes.Structure):
@@ -48,7 +50,7 @@ class Timing(ctypes.Structure):
     _fields_ = [("t_setup", ctypes.c_double), ("t_factor", ctypes.c_double),
                 ("t_rhs", ctypes.c_double), ("t_gmres", ctypes.c_double),
                 ("t_recon", ctypes.c_double), ("t_solve", ctypes.c_double),
-                ("gmres_iters", ctypes.c_int)]
+                ("gmres_iters", ctypes.c_int), ("inner_iters", ctypes.c_int)]
 
 
 class KStat(ctypes.Structure):
@@ -142,7 +144,8 @@ class Solver:
     def __init__(self, model, omega: float, n_pml: int, layers: int, cells: int,
                  precision: int = HZ_FP64, model_kind: int = HZ_MODEL_VELOCITY,
                  pml_beta: float = 2.0, max_batch: int = 1, factor: bool = True,
-                 precond: int = HZ_PRECOND_GS, krylov: int = HZ_KRYLOV_GMRES):
+                 precond: int = HZ_PRECOND_GS, krylov: int = HZ_KRYLOV_GMRES,
+                 inner: int = HZ_INNER_LU, inner_tol: float = 0.0):
         import torch
 
         self.torch = torch
@@ -151,7 +154,8 @@ class Solver:
         self.model = model.to(device="cuda", dtype=torch.float64).contiguous()
         self.prm = Params(n, n, 1.0 / (n + 1), float(omega), int(n_pml), float(pml_beta),
                           int(layers), int(cells), int(precision), int(model_kind),
-                          int(max_batch), int(precond), int(krylov))
+                          int(max_batch), int(precond), int(krylov), int(inner),
+                          float(inner_tol))
         self.ctx = ctypes.c_void_p()
         L = lib()
         _check(L.hz_setup(_ptr(self.model), ctypes.byref(self.prm), ctypes.byref(self.ctx)),

@@ -90,6 +90,24 @@ def test_n1023_256_sources_one_launch(n1023, prec, bar):
     s.close()
 
 
+def test_n1023_nested_polarized_traces(n1023):
+    """The nested polarized traces (Sec. 4.2.1: inner GMRES with the inner
+    sweeps, tolerance 1e-6 inside the preconditioner) on the n = 1023
+    workload, all 256 sources in one solve; sampled sources against the
+    oracle."""
+    w, c, f, refs = n1023
+    _log("[n=1023] nested polarized traces: 256 sources")
+    s = hz.Solver(torch.from_numpy(c), w.omega, w.n_pml, w.layers, w.cells,
+                  max_batch=len(w.src_x), inner=hz.HZ_INNER_PT)
+    u = s.solve(torch.from_numpy(f), tol=1e-10)
+    t = s.timing()
+    for k, ref in refs.items():
+        err = _rel(u[k].cpu().numpy(), ref)
+        _log(f"  source {k}: err {err:.2e} (outer {t['gmres_iters']}, inner {t['inner_iters']})")
+        assert err <= 1e-9
+    s.close()
+
+
 def test_n2047_mixed_refinement_properties():
     """n = 2047 layered medium, 32 x 8 cells, 64 sources, complex64 nested
     solver inside FP64 refinement: reported error estimates, agreement with
