@@ -229,7 +229,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="fp64,mixed,local",
+    ap.add_argument("--forms", default="fp64,mixed,local,nested",
                     help="comma list of fp64, mixed, local (re-factorisation after a local "
                          "model update, on the mixed context), nested (nested polarized "
                          "traces: inner GMRES instead of the inner block LU), table3 (Krylov "
