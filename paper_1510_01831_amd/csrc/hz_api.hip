@@ -807,7 +807,8 @@ void tune_plan(hz_ctx* c, Plan<T>& pl, int B) {
         float best = 1e30f;
         for (int cand : {dflt, (int)GEMM_MFMA64, (int)GEMM_MFMA32, (int)GEMM_MFMA32K16,
                          (int)GEMM_MFMA32D, (int)GEMM_MFMA64D, (int)GEMM_MFMA32X64,
-                         (int)GEMM_MFMA64X32, (int)GEMM_MFMA64S2, (int)GEMM_MFMA64S4}) {
+                         (int)GEMM_MFMA64X32, (int)GEMM_MFMA64S2, (int)GEMM_MFMA64S4,
+                         (int)GEMM_MFMA32S2, (int)GEMM_MFMA32S4}) {
             if (cand == dflt && best < 1e30f) continue;
             if ((cand == GEMM_MFMA64 || cand == GEMM_MFMA64D || cand == GEMM_MFMA32X64 ||
                  cand == GEMM_MFMA64S2 || cand == GEMM_MFMA64S4) && B < 64)
@@ -2860,7 +2861,7 @@ hz_status hz_setup(const double* model_dev, const hz_params* prm, hz_ctx** out) 
     if (const char* g = std::getenv("HZ_TUNE")) c->tune = std::atoi(g) != 0;
     if (const char* g = std::getenv("HZ_GEMM_KIND")) {
         const int k = std::atoi(g);
-        if (k >= GEMM_MFMA32 && k <= GEMM_MFMA64S4) c->force_kind = k;
+        if (k >= GEMM_MFMA32 && k <= GEMM_MFMA32S4) c->force_kind = k;
     }
     if (c->prm.pml_beta <= 0.0) c->prm.pml_beta = 2.0;
     if (c->prm.max_batch <= 0) c->prm.max_batch = 1;

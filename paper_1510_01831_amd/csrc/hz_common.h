@@ -254,10 +254,12 @@ void launch_gemm(const GemmTask<T>* tasks_dev, int ntasks, int max_m, int B, hip
 // batch columns), 32-deep chunks.
 // GEMM_MFMA64S2 / GEMM_MFMA64S4: 64x64 tiles with the k chunks of a tile split
 // over 2 / 4 workgroups (needs a GemmSplitWs; without one, GEMM_MFMA64).
+// GEMM_MFMA32S2 / GEMM_MFMA32S4: the same split over 32x32 tiles, 32-deep
+// chunks (small launches: more workgroups per output tile).
 enum GemmKernel { GEMM_GEMV = 0, GEMM_TILED = 1, GEMM_MFMA32 = 2, GEMM_MFMA64 = 3,
                   GEMM_MFMA32K16 = 4, GEMM_MFMA32D = 5, GEMM_MFMA64D = 6,
                   GEMM_MFMA32X64 = 7, GEMM_MFMA64X32 = 8, GEMM_MFMA64S2 = 9,
-                  GEMM_MFMA64S4 = 10 };
+                  GEMM_MFMA64S4 = 10, GEMM_MFMA32S2 = 11, GEMM_MFMA32S4 = 12 };
 
 GemmKernel gemm_kernel(int ntasks, int max_m, int B);
 const char* gemm_kernel_name(GemmKernel k);

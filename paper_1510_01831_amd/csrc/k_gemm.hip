@@ -450,6 +450,8 @@ const char* gemm_kernel_name(GemmKernel k) {
     case GEMM_MFMA64X32: return "gemm_mfma64x32";
     case GEMM_MFMA64S2: return "gemm_mfma64s2";
     case GEMM_MFMA64S4: return "gemm_mfma64s4";
+    case GEMM_MFMA32S2: return "gemm_mfma32s2";
+    case GEMM_MFMA32S4: return "gemm_mfma32s4";
     default: return "gemm_mfma32";
     }
 }
@@ -469,6 +471,19 @@ void launch_gemm_mfma(GemmKernel kind, const GemmTask<T>* tasks_dev, int ntasks,
             return;
         }
         kind = GEMM_MFMA64;                         // no room: the unsplit kernel
+    }
+    if (kind == GEMM_MFMA32S2 || kind == GEMM_MFMA32S4) {
+        const int splits = kind == GEMM_MFMA32S2 ? 2 : 4;
+        const int rt = (max_m + 31) / 32, ct = (B + 31) / 32;
+        const long long tiles = (long long)rt * ct * ntasks;
+        const long long need = tiles * splits * GV_THREADS * 4 * (long long)sizeof(C2<T>);
+        if (sw && sw->ws && sw->counters && need <= sw->ws_bytes && tiles <= sw->ncounters) {
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 32, OFFLINE>),
+                               dim3(tiles * splits), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct,
+                               splits, (C2<T>*)sw->ws, sw->counters);
+            return;
+        }
+        kind = GEMM_MFMA32;                         // no room: the unsplit kernel
     }
     // big launches: 64 x 64 tiles; otherwise 32 x 32 tiles with deeper
     // chunks, which keep more workgroups busy and fewer chunks in flight
