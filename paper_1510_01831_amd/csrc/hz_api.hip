@@ -1033,6 +1033,9 @@ Plan<T>& get_plan(hz_ctx* c, bool sie, int B) {
 constexpr int INNER_MAXIT = 40;
 
 void givens(std::complex<double> a, std::complex<double> b, double& cs, std::complex<double>& sn);
+void update_dots_dev(hz_ctx* c, const double2* V, long long vstride, int nv, const double2* coef,
+                     double2* w, long long n, int B, int norm, double2* out_dev,
+                     double2* part, int max_chunks);
 
 struct InnerJobDev {
     const void* rhs;
@@ -1380,10 +1383,8 @@ void inner_solve(hz_ctx* c, InnerRec<T>& r, int B) {
             double2* hB2 = c->ih + nh;
             double2* hN = c->ih + 2 * nh;
             idots(V, j + 1, w, hA);
-            launch_update_basis(w, V, nB, j + 1, hA, n, NB, c->st, -1.0);
-            idots(V, j + 1, w, hB2);
-            launch_update_basis(w, V, nB, j + 1, hB2, n, NB, c->st, -1.0);
-            idots(nullptr, 1, w, hN);
+            update_dots_dev(c, V, nB, j + 1, hA, w, n, NB, 0, hB2, c->ipart, 32);
+            update_dots_dev(c, V, nB, j + 1, hB2, w, n, NB, 1, hN, c->ipart, 32);
             launch_inv_norms(hN, c->icoef, NB, c->st);
             launch_scale_cols(Vn, w, c->icoef, n, NB, c->st);
             std::vector<double2> hh(2 * nh + NB);
@@ -2251,6 +2252,21 @@ void dots_dev(hz_ctx* c, const double2* V, long long vstride, int nv, const doub
     launch_reduce_partials(c->gpart, chunks, nv * B, out_dev, c->st);
 }
 
+// One Gram-Schmidt pass w -= V coef fused with the next reductions (V^H w,
+// or |w|^2 when norm) into out_dev; the separate kernels beyond 8 vectors.
+void update_dots_dev(hz_ctx* c, const double2* V, long long vstride, int nv, const double2* coef,
+                     double2* w, long long n, int B, int norm, double2* out_dev,
+                     double2* part, int max_chunks) {
+    const int chunks = (int)std::min<long long>(max_chunks, std::max<long long>(1, n / 32));
+    if (launch_update_dots(w, V, vstride, nv, coef, -1.0, n, B, norm, part, chunks, c->st)) {
+        launch_reduce_partials(part, chunks, (norm ? 1 : nv) * B, out_dev, c->st);
+        return;
+    }
+    launch_update_basis(w, V, vstride, nv, coef, n, B, c->st, -1.0);
+    launch_dots(norm ? nullptr : V, vstride, norm ? 1 : nv, w, n, B, part, chunks, c->st);
+    launch_reduce_partials(part, chunks, (norm ? 1 : nv) * B, out_dev, c->st);
+}
+
 void norms(hz_ctx* c, const double2* w, long long n, int B, std::vector<double>& out) {
     std::vector<std::complex<double>> t;
     dots(c, nullptr, 0, 1, w, n, B, t);
@@ -2346,10 +2362,8 @@ void gmres(hz_ctx* c, const double2* b, double2* x, int B, double tol, int maxit
         double2* hB = c->gh + nh;
         double2* hN = c->gh + 2 * nh;
         dots_dev(c, V, vs, j + 1, c->gw, n, B, hA);
-        launch_update_basis(c->gw, V, vs, j + 1, hA, n, B, c->st, -1.0);
-        dots_dev(c, V, vs, j + 1, c->gw, n, B, hB);
-        launch_update_basis(c->gw, V, vs, j + 1, hB, n, B, c->st, -1.0);
-        dots_dev(c, nullptr, 0, 1, c->gw, n, B, hN);
+        update_dots_dev(c, V, vs, j + 1, hA, c->gw, n, B, 0, hB, c->gpart, c->gpart_chunks);
+        update_dots_dev(c, V, vs, j + 1, hB, c->gw, n, B, 1, hN, c->gpart, c->gpart_chunks);
         // next basis vector scaled on the device (columns that have converged
         // keep being normalised; their coefficients beyond convergence are 0)
         launch_inv_norms(hN, c->gcoef, B, c->st);

@@ -311,6 +311,11 @@ void launch_scale_cols(double2* y, const double2* x, const double2* s, long long
                        hipStream_t st);
 void launch_norms(const double2* w, long long n, int B, double2* partial, int nchunks,
                   hipStream_t st);
+// w += sgn * V coef, then partial sums of V^H w (norm = 0) or |w|^2 (norm = 1);
+// false (nothing launched) when nv is outside 1..8
+bool launch_update_dots(double2* w, const double2* V, long long vstride, int nv,
+                        const double2* coef, double sgn, long long n, int B, int norm,
+                        double2* partial, int nchunks, hipStream_t st);
 void launch_rhs_to_ext(const double2* rhs, int B, int n, int p, int W, double2* f_ext,
                        const LayerDesc* layers_dev, int L, int* layer_active, hipStream_t st);
 void launch_ext_to_out(const double2* u_ext, int B, int n, int p, int W, double2* out,

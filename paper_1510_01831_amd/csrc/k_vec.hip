@@ -242,6 +242,91 @@ void launch_dots(const double2* V, long long vstride, int nv, const double2* w, 
                        vstride, nv, w, n, B, partial, nchunks);
 }
 
+// One Gram-Schmidt pass fused with the reductions of the next step:
+//   w <- w + sgn * sum_{v < nv} coef[v][b] V_v      (stored back to w)
+// then, for the updated w, partial sums of conj(V_v) w for v < nv (norm = 0,
+// nv outputs) or of |w|^2 (norm = 1, one output), laid out as k_dots'.  The
+// basis values of an element stay in registers between the two halves, so
+// V and w are read once for both (nv <= UD_MAX = 8).
+constexpr int UD_MAX = 8;
+
+__global__ void __launch_bounds__(RD_THREADS)
+k_update_dots(double2* __restrict__ w, const double2* __restrict__ V, long long vstride, int nv,
+              const double2* __restrict__ coef, double sgn, long long n, int B, int norm,
+              double2* __restrict__ partial, int nchunks) {
+    __shared__ double2 red[RD_THREADS];
+    const int tid = threadIdx.x;
+    const int per = RD_THREADS / B > 0 ? RD_THREADS / B : 1;
+    const int bcols = B < RD_THREADS ? B : RD_THREADS;
+    const long long chunk = (n + nchunks - 1) / nchunks;
+    const long long i0 = blockIdx.x * chunk;
+    const long long i1 = (i0 + chunk < n) ? i0 + chunk : n;
+    const int nout = norm ? 1 : nv;
+    for (int bb = 0; bb < B; bb += bcols) {
+        double2 acc[UD_MAX];
+#pragma unroll
+        for (int v = 0; v < UD_MAX; ++v) acc[v] = make_double2(0.0, 0.0);
+        const int b = bb + tid % bcols;
+        const int sub = tid / bcols;
+        if (sub < per && b < B) {
+            double2 h[UD_MAX];
+#pragma unroll
+            for (int v = 0; v < UD_MAX; ++v)
+                h[v] = v < nv ? coef[(long long)v * B + b] : make_double2(0.0, 0.0);
+            for (long long i = i0 + sub; i < i1; i += per) {
+                const long long q = i * B + b;
+                double2 x = w[q];
+                double2 vv[UD_MAX];
+#pragma unroll
+                for (int v = 0; v < UD_MAX; ++v) {
+                    if (v < nv) {
+                        vv[v] = gload<double>(V + v * vstride + q);
+                        x.x += sgn * (h[v].x * vv[v].x - h[v].y * vv[v].y);
+                        x.y += sgn * (h[v].x * vv[v].y + h[v].y * vv[v].x);
+                    }
+                }
+                w[q] = x;
+                if (norm) {
+                    acc[0].x += x.x * x.x + x.y * x.y;
+                } else {
+#pragma unroll
+                    for (int v = 0; v < UD_MAX; ++v) {
+                        if (v < nv) {
+                            acc[v].x += vv[v].x * x.x + vv[v].y * x.y;
+                            acc[v].y += vv[v].x * x.y - vv[v].y * x.x;
+                        }
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < UD_MAX; ++v) {
+            if (v < nout) {                          // uniform: nout is a kernel argument
+                red[tid] = acc[v];
+                __syncthreads();
+                if (tid < bcols && bb + tid < B) {
+                    double2 sacc = make_double2(0.0, 0.0);
+                    for (int q = 0; q < per; ++q) {
+                        const double2 r = red[q * bcols + tid];
+                        sacc.x += r.x; sacc.y += r.y;
+                    }
+                    partial[((long long)blockIdx.x * nout + v) * B + bb + tid] = sacc;
+                }
+                __syncthreads();
+            }
+        }
+    }
+}
+
+bool launch_update_dots(double2* w, const double2* V, long long vstride, int nv,
+                        const double2* coef, double sgn, long long n, int B, int norm,
+                        double2* partial, int nchunks, hipStream_t st) {
+    if (nv < 1 || nv > UD_MAX) return false;
+    hipLaunchKernelGGL(k_update_dots, dim3(nchunks), dim3(RD_THREADS), 0, st, w, V, vstride, nv,
+                       coef, sgn, n, B, norm, partial, nchunks);
+    return true;
+}
+
 void launch_norms(const double2* w, long long n, int B, double2* partial, int nchunks,
                   hipStream_t st) {
     hipLaunchKernelGGL(k_dots, dim3(nchunks, 1), dim3(RD_THREADS), 0, st, nullptr, 0LL, 1, w, n,
@@ -521,14 +606,17 @@ k_residual_norms(const double2* __restrict__ u, const double2* __restrict__ f,
     for (int b = threadIdx.x; b < B; b += blockDim.x)
         partial[(long long)blockIdx.x * B + b] = make_double2(rn_sh[2 * b], rn_sh[2 * b + 1]);
 }
-// Same norms for B <= 256 by marching down the grid: a workgroup owns XW =
-// 256 / B adjacent grid columns and a band of zb rows; a thread owns one
-// (column, RHS) and carries u at rows z - 1, z, z + 1 in registers, so each
-// entry of u and f is read from HBM once (a node-ordered sweep re-reads the
-// rows above and below: one row of the batch is larger than an XCD's L2).
-// Workgroups are numbered so that each XCD (slot L runs on XCD L mod 8)
-// takes one contiguous run of (band, column group): the x neighbours then
-// come from the same L2.
+// Same norms for B <= 256 by marching down the grid: a workgroup holds XW =
+// 256 / B groups of B threads, group g owns RX adjacent grid columns and a
+// band of zb rows, and a thread owns one RHS of its group: it carries u at
+// rows z - 1, z, z + 1 over its RX columns and one halo column on each side
+// in registers, so u is read (RX + 2) / RX times and f once (a thread per
+// column would fetch each u entry three times, as the x neighbour of two
+// other workgroups).  Workgroups are numbered so that each XCD (slot L runs
+// on XCD L mod 8) takes one contiguous run of (band, column group): the
+// halo columns then come from the same L2.
+constexpr int RN_RX = 8;
+
 __global__ void __launch_bounds__(256)
 k_residual_norms_march(const double2* __restrict__ u, const double2* __restrict__ f,
                        const double2* __restrict__ gd, const double2* __restrict__ gcx,
@@ -541,34 +629,53 @@ k_residual_norms_march(const double2* __restrict__ u, const double2* __restrict_
     const int tile = (xcd < r8 ? xcd * (q8 + 1) : r8 * (q8 + 1) + (xcd - r8) * q8) + loc;
     const int xg = tile % nxg, zc = tile / nxg;
     const int xo = threadIdx.x / B, b = threadIdx.x % B;
-    const int x = xg * XW + xo;
+    const int xs = (xg * XW + xo) * RN_RX;           // first owned column
     const int z0 = zc * zb, z1 = min(W, z0 + zb);
     __syncthreads();
     double sr = 0.0, sf = 0.0;
-    if (xo < XW && x < W && z0 < z1) {
-        const long long WB = (long long)W * B;
+    if (xo < XW && xs < W && z0 < z1) {
         const double2 zero = make_double2(0.0, 0.0);
         auto at = [&](int z, int xx) { return ((long long)z * W + xx) * B + b; };
-        double2 up = zero;
-        if (z0 > 0) up = gload<double>(u + at(z0 - 1, x));
-        double2 uc = gload<double>(u + at(z0, x));
-#pragma unroll 4
+        // window columns xs - 1 .. xs + RN_RX (zero outside the grid)
+        auto load_row = [&](int z, double2* r) {
+#pragma unroll
+            for (int c = 0; c < RN_RX + 2; ++c) {
+                const int xx = xs - 1 + c;
+                r[c] = zero;
+                if (z >= 0 && z < W && xx >= 0 && xx < W) r[c] = gload<double>(u + at(z, xx));
+            }
+        };
+        double2 um[RN_RX + 2], uc[RN_RX + 2], un[RN_RX + 2];
+        load_row(z0 - 1, um);
+        load_row(z0, uc);
         for (int z = z0; z < z1; ++z) {
-            const long long q = at(z, x);
-            const long long g = (long long)z * W + x;
-            double2 un = zero;
-            if (z + 1 < W) un = gload<double>(u + q + WB);
-            double2 acc = cmul(gd[g], uc);
-            if (x + 1 < W) acc = cfma(gcx[g], gload<double>(u + q + B), acc);
-            if (x > 0) acc = cfma(gcx[g - 1], gload<double>(u + q - B), acc);
-            if (z + 1 < W) acc = cfma(gcz[g], un, acc);
-            if (z > 0) acc = cfma(gcz[g - W], up, acc);
-            const double2 fv = gload<double>(f + q);
-            const double rx = fv.x - acc.x, ry = fv.y - acc.y;
-            sr += rx * rx + ry * ry;
-            sf += fv.x * fv.x + fv.y * fv.y;
-            up = uc;
-            uc = un;
+            load_row(z + 1, un);
+            double2 fv[RN_RX];
+#pragma unroll
+            for (int c = 0; c < RN_RX; ++c) {
+                fv[c] = zero;
+                if (xs + c < W) fv[c] = gload<double>(f + at(z, xs + c));
+            }
+#pragma unroll
+            for (int c = 0; c < RN_RX; ++c) {
+                const int x = xs + c;
+                if (x < W) {
+                    const long long g = (long long)z * W + x;
+                    double2 acc = cmul(gd[g], uc[c + 1]);
+                    if (x + 1 < W) acc = cfma(gcx[g], uc[c + 2], acc);
+                    if (x > 0) acc = cfma(gcx[g - 1], uc[c], acc);
+                    if (z + 1 < W) acc = cfma(gcz[g], un[c + 1], acc);
+                    if (z > 0) acc = cfma(gcz[g - W], um[c + 1], acc);
+                    const double rx = fv[c].x - acc.x, ry = fv[c].y - acc.y;
+                    sr += rx * rx + ry * ry;
+                    sf += fv[c].x * fv[c].x + fv[c].y * fv[c].y;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < RN_RX + 2; ++c) {
+                um[c] = uc[c];
+                uc[c] = un[c];
+            }
         }
     }
     if (xo < XW) {
@@ -581,22 +688,22 @@ k_residual_norms_march(const double2* __restrict__ u, const double2* __restrict_
 }
 
 // Workgroups (= partial rows) of launch_residual_norms for a partial buffer
-// of cap rows: up to 8 row bands per column group when marching, else the
+// of cap rows: up to 16 row bands per column group when marching, else the
 // node-ordered kernel with at most 2048 workgroups.
 int residual_norms_blocks(int W, int B, int cap) {
     const long long nodes = (long long)W * W;
     const int flat = (int)std::max<long long>(1, std::min<long long>(std::min(cap, 2048), nodes / 64));
     if (B > 256) return flat;
-    const int XW = 256 / B, nxg = (W + XW - 1) / XW;
+    const int XW = 256 / B, nxg = (W + XW * RN_RX - 1) / (XW * RN_RX);
     if (nxg > cap) return flat;
-    return nxg * std::max(1, std::min(8, cap / nxg));
+    return nxg * std::max(1, std::min(16, cap / nxg));
 }
 
 void launch_residual_norms(const double2* u, const double2* f, const double2* gdiag,
                            const double2* gcx, const double2* gcz, int W, int B, double2* partial,
                            int nblocks, hipStream_t st) {
-    const int XW = B <= 256 ? 256 / B : 1, nxg = (W + XW - 1) / XW;
-    if (B <= 256 && nblocks >= nxg && nblocks % nxg == 0 && nblocks / nxg <= 8) {
+    const int XW = B <= 256 ? 256 / B : 1, nxg = (W + XW * RN_RX - 1) / (XW * RN_RX);
+    if (B <= 256 && nblocks >= nxg && nblocks % nxg == 0 && nblocks / nxg <= 16) {
         // marching layout (residual_norms_blocks gives a multiple of nxg
         // here; nz bands of zb rows cover all W rows)
         const int nz = nblocks / nxg;
