@@ -461,7 +461,11 @@ constexpr int TT = 32;
 
 // rhs[b][z][x] (physical) -> f_ext[Z][X][b] (extended, batch fastest), zero in
 // the PML, and flag the layer whose owned rows hold extended row Z when the
-// block carries a nonzero source.  Grid: (column tiles x batch tiles, W).
+// block carries a nonzero source.  Grid: (column tiles x batch tiles, row
+// groups of TZ rows); the loads of the next row are in flight while the
+// current tile is written out.
+constexpr int TZ = 4;
+
 __global__ void __launch_bounds__(256)
 k_rhs_to_ext(const double2* __restrict__ rhs, int B, int n, int p, int W,
              double2* __restrict__ f_ext, const LayerDesc* layers, int L, int* active) {
@@ -469,43 +473,58 @@ k_rhs_to_ext(const double2* __restrict__ rhs, int B, int n, int p, int W,
     __shared__ int any;
     const int xt = (W + TT - 1) / TT;
     const int X0 = (blockIdx.x % xt) * TT, b0 = (blockIdx.x / xt) * TT;
-    const int Z = blockIdx.y, z = Z - p;
-    const bool row_in = z >= 0 && z < n;
     const int tx = threadIdx.x % TT, ty = threadIdx.x / TT;      // 8 rows of 32 lanes
-    if (threadIdx.x == 0) any = 0;
-    __syncthreads();
-    bool nz = false;
-    for (int r = ty; r < TT; r += 256 / TT) {                    // r: batch column
-        const int b = b0 + r, x = X0 + tx - p;
-        double2 v = make_double2(0.0, 0.0);
-        if (row_in && b < B && x >= 0 && x < n) v = rhs[((long long)b * n + z) * n + x];
-        nz = nz || v.x != 0.0 || v.y != 0.0;
-        tile[r][tx] = v;
-    }
-    if (nz) any = 1;
-    __syncthreads();
-    for (int r = ty; r < TT; r += 256 / TT) {                    // r: grid column
-        const int X = X0 + r, b = b0 + tx;
-        if (X < W && b < B) f_ext[((long long)Z * W + X) * B + b] = tile[tx][r];
-    }
-    if (active && threadIdx.x == 0 && any) {
-        for (int l = 0; l < L; ++l) {
-            const int lo = layers[l].row0 + layers[l].own_r0;
-            const int hi = layers[l].row0 + layers[l].own_r1;
-            if (Z >= lo && Z <= hi) { atomicOr(&active[l], 1); break; }
+    constexpr int RPT = TT / (256 / TT);                          // tile rows per thread
+    double2 v[RPT];
+    auto load = [&](int Z) {
+        const int z = Z - p;
+        const bool row_in = z >= 0 && z < n;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {                            // r: batch column
+            const int r = ty + q * (256 / TT);
+            const int b = b0 + r, x = X0 + tx - p;
+            v[q] = make_double2(0.0, 0.0);
+            if (row_in && b < B && x >= 0 && x < n) v[q] = rhs[((long long)b * n + z) * n + x];
         }
+    };
+    const int Zb = blockIdx.y * TZ;
+    if (Zb < W) load(Zb);
+    for (int Z = Zb; Z < min(W, Zb + TZ); ++Z) {
+        if (threadIdx.x == 0) any = 0;
+        __syncthreads();
+        bool nz = false;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            nz = nz || v[q].x != 0.0 || v[q].y != 0.0;
+            tile[ty + q * (256 / TT)][tx] = v[q];
+        }
+        if (nz) any = 1;
+        __syncthreads();
+        if (Z + 1 < min(W, Zb + TZ)) load(Z + 1);
+        for (int r = ty; r < TT; r += 256 / TT) {                // r: grid column
+            const int X = X0 + r, b = b0 + tx;
+            if (X < W && b < B) f_ext[((long long)Z * W + X) * B + b] = tile[tx][r];
+        }
+        if (active && threadIdx.x == 0 && any) {
+            for (int l = 0; l < L; ++l) {
+                const int lo = layers[l].row0 + layers[l].own_r0;
+                const int hi = layers[l].row0 + layers[l].own_r1;
+                if (Z >= lo && Z <= hi) { atomicOr(&active[l], 1); break; }
+            }
+        }
+        __syncthreads();
     }
 }
 void launch_rhs_to_ext(const double2* rhs, int B, int n, int p, int W, double2* f_ext,
                        const LayerDesc* layers_dev, int L, int* layer_active, hipStream_t st) {
     const int xt = (W + TT - 1) / TT, bt = (B + TT - 1) / TT;
-    hipLaunchKernelGGL(k_rhs_to_ext, dim3(xt * bt, W), dim3(256), 0, st, rhs, B, n, p, W, f_ext,
-                       layers_dev, L, layer_active);
+    hipLaunchKernelGGL(k_rhs_to_ext, dim3(xt * bt, (W + TZ - 1) / TZ), dim3(256), 0, st, rhs, B,
+                       n, p, W, f_ext, layers_dev, L, layer_active);
 }
 
 // u[Z][X][b] (extended, batch fastest) -> out[b][z][x] on the physical grid
 // (physical = 1) or out[b][Z][X] on the extended grid, conjugated if asked.
-// Grid: (column tiles x batch tiles, side).
+// Grid: (column tiles x batch tiles, row groups of TZ rows).
 __global__ void __launch_bounds__(256)
 k_ext_to_out(const double2* __restrict__ u, int B, int n, int p, int W, double2* __restrict__ out,
              int physical, int conj) {
@@ -514,27 +533,39 @@ k_ext_to_out(const double2* __restrict__ u, int B, int n, int p, int W, double2*
     const int off = physical ? p : 0;
     const int xt = (side + TT - 1) / TT;
     const int x0 = (blockIdx.x % xt) * TT, b0 = (blockIdx.x / xt) * TT;
-    const int z = blockIdx.y;
     const int tx = threadIdx.x % TT, ty = threadIdx.x / TT;
-    for (int r = ty; r < TT; r += 256 / TT) {                    // r: grid column
-        const int x = x0 + r, b = b0 + tx;
-        double2 v = make_double2(0.0, 0.0);
-        if (x < side && b < B) v = u[((long long)(z + off) * W + x + off) * B + b];
-        if (conj) v.y = -v.y;
-        tile[r][tx] = v;
-    }
-    __syncthreads();
-    for (int r = ty; r < TT; r += 256 / TT) {                    // r: batch column
-        const int b = b0 + r, x = x0 + tx;
-        if (b < B && x < side) out[((long long)b * side + z) * side + x] = tile[tx][r];
+    constexpr int RPT = TT / (256 / TT);
+    double2 v[RPT];
+    auto load = [&](int z) {
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {                            // r: grid column
+            const int r = ty + q * (256 / TT);
+            const int x = x0 + r, b = b0 + tx;
+            v[q] = make_double2(0.0, 0.0);
+            if (x < side && b < B) v[q] = u[((long long)(z + off) * W + x + off) * B + b];
+            if (conj) v[q].y = -v[q].y;
+        }
+    };
+    const int zb = blockIdx.y * TZ;
+    if (zb < side) load(zb);
+    for (int z = zb; z < min(side, zb + TZ); ++z) {
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) tile[ty + q * (256 / TT)][tx] = v[q];
+        __syncthreads();
+        if (z + 1 < min(side, zb + TZ)) load(z + 1);
+        for (int r = ty; r < TT; r += 256 / TT) {                // r: batch column
+            const int b = b0 + r, x = x0 + tx;
+            if (b < B && x < side) out[((long long)b * side + z) * side + x] = tile[tx][r];
+        }
+        __syncthreads();
     }
 }
 void launch_ext_to_out(const double2* u_ext, int B, int n, int p, int W, double2* out,
                        int physical, int conj, hipStream_t st) {
     const int side = physical ? n : W;
     const int xt = (side + TT - 1) / TT, bt = (B + TT - 1) / TT;
-    hipLaunchKernelGGL(k_ext_to_out, dim3(xt * bt, side), dim3(256), 0, st, u_ext, B, n, p, W, out,
-                       physical, conj);
+    hipLaunchKernelGGL(k_ext_to_out, dim3(xt * bt, (side + TZ - 1) / TZ), dim3(256), 0, st, u_ext,
+                       B, n, p, W, out, physical, conj);
 }
 
 __global__ void k_transpose_bfast(const double2* src, double2* dst, int B, long long n, int to_bfast) {
