@@ -135,9 +135,11 @@ typedef struct {
     hz_krylov krylov;        /* Krylov method for the polarized SIE (0: GMRES) */
     hz_inner inner;          /* inner solver of the layers (0: block LU) */
     double inner_tol;        /* HZ_INNER_PT: relative tolerance of the inner GMRES inside the
-                                preconditioner (<= 0 -> 1e-6, the paper's value); the inner
+                                preconditioner (<= 0 -> 1e-6, the paper's value; also used by
+                                hz_apply_precond); inside hz_solve / hz_adjoint the inner
                                 solves of the SIE matrix, the right-hand side and the
-                                reconstruction use min(1e-10, max(1e-13, tol / 100)) */
+                                reconstruction use min(1e-10, max(1e-13, tol / 100)), and the
+                                other building blocks 1e-12 */
 } hz_params;
 
 typedef struct {

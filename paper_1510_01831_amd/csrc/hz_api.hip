@@ -220,7 +220,8 @@ struct hz_ctx {
     bool tune = true;              // autotune GEMM kernels and cell-solve widths (HZ_TUNE=0: off)
     bool inner_pt = false;         // nested polarized traces: the inner SIE iterated (Sec. 4.2.1)
     double inner_tol_loose = 1e-6; // inner GMRES tolerance inside the preconditioner
-    double inner_tol_tight = 1e-12;// inner GMRES tolerance elsewhere (set per solve)
+    double inner_tol_tight = 1e-12;// inner GMRES tolerance elsewhere (building blocks)
+    double inner_tol_solve = 0.0;  // the same inside hz_solve / hz_adjoint (0 outside)
     int inner_iters_max = 0;       // largest inner GMRES iteration count since the last reset
     long long CP_elems = 0;
     int force_kind = -1;           // HZ_GEMM_KIND: one matrix-core GEMM kernel for every launch
@@ -256,7 +257,7 @@ struct hz_ctx {
     int gpart_chunks = 0;
     double2* gh = nullptr;         // GMRES projections of both passes and |w|^2, on the device
     // inner GMRES (nested polarized traces): Krylov basis and reductions
-    long long i_cap = 0; int i_cap_m = 0, i_cap_cols = 0;
+    long long i_cap = 0; int i_cap_m = 0, i_cap_cols = 0, i_chunks = 0;
     double2 *iV = nullptr, *ipart = nullptr, *ismall = nullptr, *icoef = nullptr, *ih = nullptr;
     double2 *u64 = nullptr, *f64 = nullptr, *r64 = nullptr;   // refinement [W][W][B]
     hz_timing timing{};
@@ -1278,8 +1279,11 @@ void ensure_inner_basis(hz_ctx* c, long long nB, int m, int cols) {
     m = std::max(m, c->i_cap_m);
     cols = std::max(cols, c->i_cap_cols);
     c->i_cap = nB; c->i_cap_m = m; c->i_cap_cols = cols;
+    // reduction chunks: enough workgroups for short inner vectors, with the
+    // partial sums bounded to 2^25 entries
+    c->i_chunks = (int)std::max<long long>(8, std::min<long long>(256, (1LL << 25) / ((m + 2) * (long long)cols)));
     c->iV = (double2*)c->arena.alloc(sizeof(double2) * nB * (m + 1));
-    c->ipart = (double2*)c->arena.alloc(sizeof(double2) * 32 * (m + 2) * (long long)cols);
+    c->ipart = (double2*)c->arena.alloc(sizeof(double2) * c->i_chunks * (m + 2) * (long long)cols);
     c->ismall = (double2*)c->arena.alloc(sizeof(double2) * (m + 2) * (long long)cols);
     c->icoef = (double2*)c->arena.alloc(sizeof(double2) * (m + 2) * (long long)cols);
     c->ih = (double2*)c->arena.alloc(sizeof(double2) * (2 * (m + 1) + 1) * (long long)cols);
@@ -1337,9 +1341,10 @@ void inner_solve(hz_ctx* c, InnerRec<T>& r, int B) {
         const int NJ = (int)r.jobs.size();
         const long long nB = n * NB;
         const int m = INNER_MAXIT;
-        const double tol = r.loose ? c->inner_tol_loose : c->inner_tol_tight;
+        const double tol = r.loose ? c->inner_tol_loose
+                                   : (c->inner_tol_solve > 0 ? c->inner_tol_solve : c->inner_tol_tight);
         ensure_inner_basis(c, nB, m, NB);
-        const int chunks = (int)std::min<long long>(32, std::max<long long>(1, n / 32));
+        const int chunks = (int)std::min<long long>(c->i_chunks, std::max<long long>(1, n / 8));
         auto idots = [&](const double2* V, int nv, const double2* w, double2* out) {
             launch_dots(V, nB, nv, w, n, NB, c->ipart, chunks, c->st);
             launch_reduce_partials(c->ipart, chunks, nv * NB, out, c->st);
@@ -1383,8 +1388,8 @@ void inner_solve(hz_ctx* c, InnerRec<T>& r, int B) {
             double2* hB2 = c->ih + nh;
             double2* hN = c->ih + 2 * nh;
             idots(V, j + 1, w, hA);
-            update_dots_dev(c, V, nB, j + 1, hA, w, n, NB, 0, hB2, c->ipart, 32);
-            update_dots_dev(c, V, nB, j + 1, hB2, w, n, NB, 1, hN, c->ipart, 32);
+            update_dots_dev(c, V, nB, j + 1, hA, w, n, NB, 0, hB2, c->ipart, chunks);
+            update_dots_dev(c, V, nB, j + 1, hB2, w, n, NB, 1, hN, c->ipart, chunks);
             launch_inv_norms(hN, c->icoef, NB, c->st);
             launch_scale_cols(Vn, w, c->icoef, n, NB, c->st);
             std::vector<double2> hh(2 * nh + NB);
@@ -2257,7 +2262,7 @@ void dots_dev(hz_ctx* c, const double2* V, long long vstride, int nv, const doub
 void update_dots_dev(hz_ctx* c, const double2* V, long long vstride, int nv, const double2* coef,
                      double2* w, long long n, int B, int norm, double2* out_dev,
                      double2* part, int max_chunks) {
-    const int chunks = (int)std::min<long long>(max_chunks, std::max<long long>(1, n / 32));
+    const int chunks = (int)std::min<long long>(max_chunks, std::max<long long>(1, n / 8));
     if (launch_update_dots(w, V, vstride, nv, coef, -1.0, n, B, norm, part, chunks, c->st)) {
         launch_reduce_partials(part, chunks, (norm ? 1 : nv) * B, out_dev, c->st);
         return;
@@ -2698,7 +2703,11 @@ hz_status solve_impl(hz_ctx* c, const void* rhs_dev, int B, void* out_dev, doubl
     // hand side and the reconstruction must be exact to it); the
     // preconditioner's loose inner solves make it nonlinear, hence flexible
     // GMRES
-    c->inner_tol_tight = std::min(1e-10, std::max(1e-13, 0.01 * tol));
+    struct InnerTolScope {             // the solve's inner tolerance, reset on every exit
+        hz_ctx* c;
+        ~InnerTolScope() { c->inner_tol_solve = 0.0; }
+    } inner_scope{c};
+    c->inner_tol_solve = std::min(1e-10, std::max(1e-13, 0.01 * tol));
     c->inner_iters_max = 0;
     if (c->prm.precision == HZ_FP64 || c->prm.precision == HZ_MIXED) {
         const bool flex = c->prm.precision == HZ_MIXED || c->inner_pt;

@@ -148,3 +148,34 @@ def test_pt_matches_block_lu_inner():
         s.close()
     for bb in range(3):
         assert _rel(out[hz.HZ_INNER_PT][bb], out[hz.HZ_INNER_LU][bb]) < 1e-9
+
+
+def test_pt_adjoint_and_local_update():
+    """The adjoint solve (conjugate-solve-conjugate on the same operators) and
+    a local model update in the nested form: against the direct solves of the
+    old and the new model."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c0, omega = media.small_problem(N, P, L, LC, seed=21)
+    c1 = c0.copy()
+    c1[8:12, 30:34] *= 1.05
+    f = media.point_sources(N, (12, 33), 17)
+    s = hz.Solver(torch.from_numpy(c0), omega, P, L, LC, max_batch=2, inner=hz.HZ_INNER_PT)
+    prob0 = Problem(c0, omega, P)
+    lu0 = spla.splu(prob0.H.tocsc())
+    _log("[pt adjoint]")
+    lam = s.adjoint(torch.from_numpy(f), tol=1e-12).cpu().numpy()
+    for bb in range(2):
+        ref = prob0.restrict(np.conj(lu0.solve(np.conj(prob0.extend(f[bb]).ravel())))
+                             .reshape(prob0.W, prob0.W))
+        assert _rel(lam[bb], ref) < 1e-9
+    _log("[pt local update]")
+    redone = s.update_model_local(torch.from_numpy(c1))
+    assert 0 < redone < L * LC
+    u = s.solve(torch.from_numpy(f), tol=1e-12).cpu().numpy()
+    s.close()
+    prob1 = Problem(c1, omega, P)
+    lu1 = spla.splu(prob1.H.tocsc())
+    for bb in range(2):
+        ref = prob1.restrict(lu1.solve(prob1.extend(f[bb]).ravel()).reshape(prob1.W, prob1.W))
+        assert _rel(u[bb], ref) < 1e-9
