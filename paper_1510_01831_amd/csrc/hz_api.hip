@@ -260,6 +260,9 @@ struct hz_ctx {
     long long i_cap = 0; int i_cap_m = 0, i_cap_cols = 0, i_chunks = 0;
     double2 *iV = nullptr, *ipart = nullptr, *ismall = nullptr, *icoef = nullptr, *ih = nullptr;
     double2 *u64 = nullptr, *f64 = nullptr, *r64 = nullptr;   // refinement [W][W][B]
+    std::vector<std::vector<std::complex<double>>> g_hess;     // host Hessenberg storage of GMRES
+    double2* h_pin = nullptr;      // pinned host buffer for the small per-iteration reads
+    size_t h_pin_elems = 0;
     hz_timing timing{};
     Prof prof;
 };
@@ -390,6 +393,25 @@ void build_descriptors(hz_ctx* c) {
 }
 
 void sync(hz_ctx* c) { HIPCHK(hipStreamSynchronize(c->st)); }
+
+// Pinned host staging of at least `elems` complex values (reads of Krylov
+// projections: a pageable destination would be copied through a bounce
+// buffer on every iteration).  Valid until the next call.
+double2* pinned(hz_ctx* c, size_t elems) {
+    if (c->h_pin_elems < elems) {
+        if (c->h_pin) (void)hipHostFree(c->h_pin);
+        c->h_pin = nullptr;
+        c->h_pin_elems = 0;
+        const size_t want = std::max<size_t>(elems, 4096);
+        if (hipHostMalloc((void**)&c->h_pin, sizeof(double2) * want, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            c->h_pin = nullptr;
+            raise(HZ_ENOMEM, "hipHostMalloc of the staging buffer failed");
+        }
+        c->h_pin_elems = want;
+    }
+    return c->h_pin;
+}
 
 void upload(hz_ctx* c, void* dst, const void* src, size_t bytes) {
     HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->st));
@@ -1355,9 +1377,9 @@ void inner_solve(hz_ctx* c, InnerRec<T>& r, int B) {
         plan_run<T>(c, *r.P, B);                       // r0 = P b
         double2* V = c->iV;
         HIPCHK(hipMemcpyAsync(V, r.wC, sizeof(double2) * nB, hipMemcpyDeviceToDevice, c->st));
-        std::vector<double2> hb(NB);
         idots(nullptr, 1, V, c->ismall);
-        HIPCHK(hipMemcpyAsync(hb.data(), c->ismall, sizeof(double2) * NB, hipMemcpyDeviceToHost, c->st));
+        double2* hb = pinned(c, NB);
+        HIPCHK(hipMemcpyAsync(hb, c->ismall, sizeof(double2) * NB, hipMemcpyDeviceToHost, c->st));
         sync(c);
         std::vector<double> beta(NB);
         std::vector<std::vector<std::complex<double>>> R(m);    // rotated Hessenberg columns
@@ -1392,8 +1414,8 @@ void inner_solve(hz_ctx* c, InnerRec<T>& r, int B) {
             update_dots_dev(c, V, nB, j + 1, hB2, w, n, NB, 1, hN, c->ipart, chunks);
             launch_inv_norms(hN, c->icoef, NB, c->st);
             launch_scale_cols(Vn, w, c->icoef, n, NB, c->st);
-            std::vector<double2> hh(2 * nh + NB);
-            HIPCHK(hipMemcpyAsync(hh.data(), c->ih, sizeof(double2) * hh.size(),
+            double2* hh = pinned(c, 2 * nh + NB);
+            HIPCHK(hipMemcpyAsync(hh, c->ih, sizeof(double2) * (2 * nh + NB),
                                   hipMemcpyDeviceToHost, c->st));
             sync(c);
             R[j].assign((size_t)(j + 1) * NB, 0.0);
@@ -2245,8 +2267,10 @@ void dots(hz_ctx* c, const double2* V, long long vstride, int nv, const double2*
     launch_dots(V, vstride, nv, w, n, B, c->gpart, chunks, c->st);
     launch_reduce_partials(c->gpart, chunks, nv * B, c->gsmall, c->st);
     out.resize((size_t)nv * B);
-    HIPCHK(hipMemcpyAsync(out.data(), c->gsmall, sizeof(double2) * nv * B, hipMemcpyDeviceToHost, c->st));
+    double2* hp = pinned(c, (size_t)nv * B);
+    HIPCHK(hipMemcpyAsync(hp, c->gsmall, sizeof(double2) * nv * B, hipMemcpyDeviceToHost, c->st));
     sync(c);
+    for (size_t q = 0; q < out.size(); ++q) out[q] = std::complex<double>(hp[q].x, hp[q].y);
 }
 
 // the same reductions left on the device: out_dev[v * B + b]
@@ -2331,7 +2355,12 @@ void gmres(hz_ctx* c, const double2* b, double2* x, int B, double tol, int maxit
     }
     std::vector<double> beta;
     norms(c, V, n, B, beta);
-    std::vector<std::vector<std::complex<double>>> Hm(B, std::vector<std::complex<double>>((size_t)(maxit + 1) * maxit));
+    // Hessenberg columns per RHS, kept by the context between solves: every
+    // entry read (rows <= column + 1) is written first in the same solve
+    auto& Hm = c->g_hess;
+    if ((int)Hm.size() < B) Hm.resize(B);
+    for (int bb = 0; bb < B; ++bb)
+        if (Hm[bb].size() < (size_t)(maxit + 1) * maxit) Hm[bb].resize((size_t)(maxit + 1) * maxit);
     std::vector<std::vector<std::complex<double>>> g(B, std::vector<std::complex<double>>(maxit + 1));
     std::vector<std::vector<double>> cs(B, std::vector<double>(maxit));
     std::vector<std::vector<std::complex<double>>> sn(B, std::vector<std::complex<double>>(maxit));
@@ -2373,8 +2402,8 @@ void gmres(hz_ctx* c, const double2* b, double2* x, int B, double tol, int maxit
         // keep being normalised; their coefficients beyond convergence are 0)
         launch_inv_norms(hN, c->gcoef, B, c->st);
         launch_scale_cols(Vn, c->gw, c->gcoef, n, B, c->st);
-        std::vector<double2> hh(2 * nh + B);
-        HIPCHK(hipMemcpyAsync(hh.data(), c->gh, sizeof(double2) * hh.size(), hipMemcpyDeviceToHost,
+        double2* hh = pinned(c, 2 * nh + B);
+        HIPCHK(hipMemcpyAsync(hh, c->gh, sizeof(double2) * (2 * nh + B), hipMemcpyDeviceToHost,
                               c->st));
         sync(c);
         std::vector<std::complex<double>> hsum(nh);
@@ -2460,9 +2489,11 @@ void bicgstab(hz_ctx* c, const double2* b, double2* x, int B, double tol, int ma
     };
     std::vector<double2> hv(3 * (size_t)B), cf(3 * (size_t)B);
     auto read = [&](int count) {       // c->gh[0 .. count*B) -> hv
-        HIPCHK(hipMemcpyAsync(hv.data(), c->gh, sizeof(double2) * count * B,
+        double2* hp = pinned(c, (size_t)count * B);
+        HIPCHK(hipMemcpyAsync(hp, c->gh, sizeof(double2) * count * B,
                               hipMemcpyDeviceToHost, c->st));
         sync(c);
+        std::copy(hp, hp + (size_t)count * B, hv.begin());
     };
     auto coefs = [&]() {               // cf -> c->gcoef (3 per column: [j][b])
         HIPCHK(hipMemcpyAsync(c->gcoef, cf.data(), sizeof(double2) * 3 * B,
@@ -2645,8 +2676,8 @@ void vol_resid(hz_ctx* c, const double2* u, const double2* f, int B, std::vector
         const int nb = residual_norms_blocks(c->d.W, B, (int)std::min<long long>(cap, 1 << 20));
         launch_residual_norms(u, f, c->gdiag, c->gcx, c->gcz, c->d.W, B, c->gpart, nb, c->st);
         launch_reduce_partials(c->gpart, nb, B, c->gsmall, c->st);
-        std::vector<double2> h(B);
-        HIPCHK(hipMemcpyAsync(h.data(), c->gsmall, sizeof(double2) * B, hipMemcpyDeviceToHost, c->st));
+        double2* h = pinned(c, B);
+        HIPCHK(hipMemcpyAsync(h, c->gsmall, sizeof(double2) * B, hipMemcpyDeviceToHost, c->st));
         sync(c);
         for (int b = 0; b < B; ++b) out[b] = h[b].y > 0 ? std::sqrt(h[b].x / h[b].y) : 0.0;
         return;
@@ -3148,6 +3179,7 @@ void hz_destroy(hz_ctx* c) {
     for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
     clear_plans(c);
     c->arena.free_all();
+    if (c->h_pin) (void)hipHostFree(c->h_pin);
     if (c->own_st) (void)hipStreamDestroy(c->own_st);
     delete c;
 }

@@ -157,6 +157,8 @@ class Solver:
                           int(max_batch), int(precond), int(krylov), int(inner),
                           float(inner_tol))
         self.ctx = ctypes.c_void_p()
+        self._stats_raw = None
+        self._stats_list = None
         L = lib()
         _check(L.hz_setup(_ptr(self.model), ctypes.byref(self.prm), ctypes.byref(self.ctx)),
                "hz_setup")
@@ -205,10 +207,18 @@ class Solver:
         st = getattr(lib(), fn)(*args)
         _check(st, fn, allow=(HZ_ENOCONV,) if allow_noconv else ())
         self.last_status = st
-        self.last_stats = [dict(iters=s.iters, rel_resid=s.rel_resid, vol_resid=s.vol_resid,
-                                refine_steps=s.refine_steps, err_est=s.err_est)
-                           for s in stats]
+        self._stats_raw = stats            # converted on first access of last_stats
+        self._stats_list = None
         return u
+
+    @property
+    def last_stats(self):
+        """Per-RHS statistics of the last solve or adjoint (list of dicts)."""
+        if self._stats_list is None and self._stats_raw is not None:
+            self._stats_list = [dict(iters=s.iters, rel_resid=s.rel_resid, vol_resid=s.vol_resid,
+                                     refine_steps=s.refine_steps, err_est=s.err_est)
+                                for s in self._stats_raw]
+        return self._stats_list
 
     def solve(self, f, tol=1e-10, max_iter=100, ext=False, allow_noconv=False):
         return self._solve("hz_solve_ext" if ext else "hz_solve", f, tol, max_iter, ext,
