@@ -245,7 +245,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU layout is described in DESIGN.md, not run.", file=sys.stderr)
+              "sharding the path over several GPUs is designed but not built.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
