@@ -69,15 +69,19 @@ def n1023():
     picks = [0, 97, 255]
     refs = {k: prob.restrict(lu.solve(prob.extend(f[k]).ravel()).reshape(prob.W, prob.W))
             for k in picks}
+    # the single-source workload on the same medium: one source at (0.5, 0.1)
+    w2 = media.workload("C2")
+    f2 = media.point_sources(w2.n, w2.src_x, w2.src_z)
+    ref2 = prob.restrict(lu.solve(prob.extend(f2[0]).ravel()).reshape(prob.W, prob.W))
     del lu
-    return w, c, f, refs
+    return w, c, f, refs, (w2, f2, ref2)
 
 
 @pytest.mark.parametrize("prec,bar", [(hz.HZ_FP64, 1e-9), (hz.HZ_MIXED, 1e-8)])
 def test_n1023_256_sources_one_launch(n1023, prec, bar):
     """All 256 sources of the n = 1023 workload in one batched solve at the
     benchmark's tolerance; three sampled sources against the oracle."""
-    w, c, f, refs = n1023
+    w, c, f, refs, _ = n1023
     _log(f"[n=1023] precision {prec}: 256 sources")
     s = hz.Solver(torch.from_numpy(c), w.omega, w.n_pml, w.layers, w.cells, precision=prec,
                   max_batch=len(w.src_x))
@@ -90,12 +94,26 @@ def test_n1023_256_sources_one_launch(n1023, prec, bar):
     s.close()
 
 
+def test_n1023_single_source_fp64(n1023):
+    """The single-source n = 1023 workload (plain FP64, the single-RHS
+    matrix-vector kernels) against the oracle's direct solve."""
+    w, c, f, refs, (w2, f2, ref2) = n1023
+    _log("[n=1023] single source, FP64")
+    s = hz.Solver(torch.from_numpy(c), w2.omega, w2.n_pml, w2.layers, w2.cells, max_batch=1)
+    u = s.solve(torch.from_numpy(f2), tol=1e-10).cpu().numpy()[0]
+    its = s.last_stats[0]["iters"]
+    s.close()
+    err = _rel(u, ref2)
+    _log(f"  err {err:.2e} (GMRES iterations {its})")
+    assert err <= 1e-9
+
+
 def test_n1023_nested_polarized_traces(n1023):
     """The nested polarized traces (Sec. 4.2.1: inner GMRES with the inner
     sweeps, tolerance 1e-6 inside the preconditioner) on the n = 1023
     workload, all 256 sources in one solve; sampled sources against the
     oracle."""
-    w, c, f, refs = n1023
+    w, c, f, refs, _ = n1023
     _log("[n=1023] nested polarized traces: 256 sources")
     s = hz.Solver(torch.from_numpy(c), w.omega, w.n_pml, w.layers, w.cells,
                   max_batch=len(w.src_x), inner=hz.HZ_INNER_PT)
