@@ -360,7 +360,8 @@ def main():
                        "max_rel_err_vs_fp64": err, "gmres_iters": its,
                        "setup_factor_s": tf,
                        "amortized_dof_solves_per_s": B * n * n / (dt + tf),
-                       "kernels": prof}
+                       "kernels": prof,
+                       "roofline": roofline(max(prof, key=lambda k: k["ms"]), B)}
     ok = {k: v for k, v in results.items() if v[2] <= 1e-8}
     chosen = min(ok, key=lambda k: ok[k][0]) if ok else min(results, key=lambda k: results[k][0])
     dt, prof, err, its, dty, t_fac = results[chosen]
