@@ -456,8 +456,10 @@ void launch_scale_cols(double2* y, const double2* x, const double2* s, long long
 
 // Both conversions go through LDS: a workgroup moves a TT x TT block of
 // (batch column, grid column) pairs of one grid row, reading along the grid
-// row and writing along the batch (or the reverse), both coalesced.
-constexpr int TT = 32;
+// row and writing along the batch (or the reverse), both coalesced in 1 KB
+// runs (one wave per 64-element row).  The tile (66.5 KB) is dynamic LDS.
+constexpr int TT = 64;
+constexpr int TT_LDS = TT * (TT + 1) * (int)sizeof(double2);
 
 // rhs[b][z][x] (physical) -> f_ext[Z][X][b] (extended, batch fastest), zero in
 // the PML, and flag the layer whose owned rows hold extended row Z when the
@@ -469,19 +471,21 @@ constexpr int TZ = 4;
 __global__ void __launch_bounds__(256)
 k_rhs_to_ext(const double2* __restrict__ rhs, int B, int n, int p, int W,
              double2* __restrict__ f_ext, const LayerDesc* layers, int L, int* active) {
-    __shared__ double2 tile[TT][TT + 1];
+    extern __shared__ double2 cv_tile[];
     __shared__ int any;
+    auto tile = [&](int r, int c) -> double2& { return cv_tile[r * (TT + 1) + c]; };
     const int xt = (W + TT - 1) / TT;
     const int X0 = (blockIdx.x % xt) * TT, b0 = (blockIdx.x / xt) * TT;
-    const int tx = threadIdx.x % TT, ty = threadIdx.x / TT;      // 8 rows of 32 lanes
-    constexpr int RPT = TT / (256 / TT);                          // tile rows per thread
+    const int tx = threadIdx.x % TT, ty = threadIdx.x / TT;      // 4 rows of 64 lanes
+    constexpr int RS = 256 / TT;                                  // rows per pass
+    constexpr int RPT = TT / RS;                                  // tile rows per thread
     double2 v[RPT];
     auto load = [&](int Z) {
         const int z = Z - p;
         const bool row_in = z >= 0 && z < n;
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {                            // r: batch column
-            const int r = ty + q * (256 / TT);
+            const int r = ty + q * RS;
             const int b = b0 + r, x = X0 + tx - p;
             v[q] = make_double2(0.0, 0.0);
             if (row_in && b < B && x >= 0 && x < n) v[q] = rhs[((long long)b * n + z) * n + x];
@@ -496,14 +500,14 @@ k_rhs_to_ext(const double2* __restrict__ rhs, int B, int n, int p, int W,
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             nz = nz || v[q].x != 0.0 || v[q].y != 0.0;
-            tile[ty + q * (256 / TT)][tx] = v[q];
+            tile(ty + q * RS, tx) = v[q];
         }
         if (nz) any = 1;
         __syncthreads();
         if (Z + 1 < min(W, Zb + TZ)) load(Z + 1);
-        for (int r = ty; r < TT; r += 256 / TT) {                // r: grid column
+        for (int r = ty; r < TT; r += RS) {                       // r: grid column
             const int X = X0 + r, b = b0 + tx;
-            if (X < W && b < B) f_ext[((long long)Z * W + X) * B + b] = tile[tx][r];
+            if (X < W && b < B) f_ext[((long long)Z * W + X) * B + b] = tile(tx, r);
         }
         if (active && threadIdx.x == 0 && any) {
             for (int l = 0; l < L; ++l) {
@@ -515,11 +519,29 @@ k_rhs_to_ext(const double2* __restrict__ rhs, int B, int n, int p, int W,
         __syncthreads();
     }
 }
+
+// the conversions' dynamic LDS above the default limit, set once per device
+static void cv_lds_attr(const void* fn, int* done) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        (void)hipGetLastError();
+        dev = 0;
+    }
+    if (!done[dev]) {
+        if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, TT_LDS) !=
+            hipSuccess)
+            (void)hipGetLastError();
+        done[dev] = 1;
+    }
+}
+
 void launch_rhs_to_ext(const double2* rhs, int B, int n, int p, int W, double2* f_ext,
                        const LayerDesc* layers_dev, int L, int* layer_active, hipStream_t st) {
+    static int done[64] = {0};
+    cv_lds_attr(reinterpret_cast<const void*>(&k_rhs_to_ext), done);
     const int xt = (W + TT - 1) / TT, bt = (B + TT - 1) / TT;
-    hipLaunchKernelGGL(k_rhs_to_ext, dim3(xt * bt, (W + TZ - 1) / TZ), dim3(256), 0, st, rhs, B,
-                       n, p, W, f_ext, layers_dev, L, layer_active);
+    hipLaunchKernelGGL(k_rhs_to_ext, dim3(xt * bt, (W + TZ - 1) / TZ), dim3(256), TT_LDS, st, rhs,
+                       B, n, p, W, f_ext, layers_dev, L, layer_active);
 }
 
 // u[Z][X][b] (extended, batch fastest) -> out[b][z][x] on the physical grid
@@ -528,18 +550,20 @@ void launch_rhs_to_ext(const double2* rhs, int B, int n, int p, int W, double2* 
 __global__ void __launch_bounds__(256)
 k_ext_to_out(const double2* __restrict__ u, int B, int n, int p, int W, double2* __restrict__ out,
              int physical, int conj) {
-    __shared__ double2 tile[TT][TT + 1];
+    extern __shared__ double2 cv_tile[];
+    auto tile = [&](int r, int c) -> double2& { return cv_tile[r * (TT + 1) + c]; };
     const int side = physical ? n : W;
     const int off = physical ? p : 0;
     const int xt = (side + TT - 1) / TT;
     const int x0 = (blockIdx.x % xt) * TT, b0 = (blockIdx.x / xt) * TT;
     const int tx = threadIdx.x % TT, ty = threadIdx.x / TT;
-    constexpr int RPT = TT / (256 / TT);
+    constexpr int RS = 256 / TT;
+    constexpr int RPT = TT / RS;
     double2 v[RPT];
     auto load = [&](int z) {
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {                            // r: grid column
-            const int r = ty + q * (256 / TT);
+            const int r = ty + q * RS;
             const int x = x0 + r, b = b0 + tx;
             v[q] = make_double2(0.0, 0.0);
             if (x < side && b < B) v[q] = u[((long long)(z + off) * W + x + off) * B + b];
@@ -550,22 +574,24 @@ k_ext_to_out(const double2* __restrict__ u, int B, int n, int p, int W, double2*
     if (zb < side) load(zb);
     for (int z = zb; z < min(side, zb + TZ); ++z) {
 #pragma unroll
-        for (int q = 0; q < RPT; ++q) tile[ty + q * (256 / TT)][tx] = v[q];
+        for (int q = 0; q < RPT; ++q) tile(ty + q * RS, tx) = v[q];
         __syncthreads();
         if (z + 1 < min(side, zb + TZ)) load(z + 1);
-        for (int r = ty; r < TT; r += 256 / TT) {                // r: batch column
+        for (int r = ty; r < TT; r += RS) {                       // r: batch column
             const int b = b0 + r, x = x0 + tx;
-            if (b < B && x < side) out[((long long)b * side + z) * side + x] = tile[tx][r];
+            if (b < B && x < side) out[((long long)b * side + z) * side + x] = tile(tx, r);
         }
         __syncthreads();
     }
 }
 void launch_ext_to_out(const double2* u_ext, int B, int n, int p, int W, double2* out,
                        int physical, int conj, hipStream_t st) {
+    static int done[64] = {0};
+    cv_lds_attr(reinterpret_cast<const void*>(&k_ext_to_out), done);
     const int side = physical ? n : W;
     const int xt = (side + TT - 1) / TT, bt = (B + TT - 1) / TT;
-    hipLaunchKernelGGL(k_ext_to_out, dim3(xt * bt, (side + TZ - 1) / TZ), dim3(256), 0, st, u_ext,
-                       B, n, p, W, out, physical, conj);
+    hipLaunchKernelGGL(k_ext_to_out, dim3(xt * bt, (side + TZ - 1) / TZ), dim3(256), TT_LDS, st,
+                       u_ext, B, n, p, W, out, physical, conj);
 }
 
 __global__ void k_transpose_bfast(const double2* src, double2* dst, int B, long long n, int to_bfast) {
