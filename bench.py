@@ -274,7 +274,8 @@ def main():
     it1 = s64.last_stats[0]["iters"]
     log(f"[bench] fp64 single RHS: {dt1 * 1e3:.1f} ms/solve, {it1} GMRES iterations")
     forms = {"fp64_single": {"dof_solves_per_s": n * n / dt1, "ms_per_solve": dt1 * 1e3,
-                             "gmres_iters": it1, "setup_factor_s": t_fac64, "kernels": prof1}}
+                             "gmres_iters": it1, "setup_factor_s": t_fac64, "kernels": prof1,
+                             "roofline": roofline(max(prof1, key=lambda k: k["ms"]), 1)}}
     ref_idx = [0, B // 2, B - 1]
     refs = {}
     for k in ref_idx:
