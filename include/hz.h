@@ -117,14 +117,14 @@ typedef enum {
                                 polarized system over the cells, iterated by GMRES with the
                                 inner Gauss-Seidel sweeps; no inner factorisation.  Needs
                                 HZ_FP64, HZ_KRYLOV_GMRES (run flexible: the preconditioner's
-                                inner solves stop at inner_tol) and n_pml >= 1 */
+                                inner solves stop at inner_tol) */
 } hz_inner;
 
 typedef struct {
     int n_x, n_z;            /* physical nodes per side (must be equal) */
     double h;                /* grid step; must equal 1/(n+1) (unit square) */
     double omega;            /* angular frequency, > 0 */
-    int n_pml;               /* PML nodes per side, >= 0 */
+    int n_pml;               /* PML nodes per side, >= 0 (>= 1 when layers or cells > 1) */
     double pml_beta;         /* sigma_max = pml_beta * omega at the Dirichlet node; <= 0 -> 2 */
     int layers;              /* L: 1..n_z, each layer >= 2 rows */
     int cells;               /* L_c: 1..n_x, each cell >= 2 columns */

@@ -2882,6 +2882,10 @@ hz_status hz_setup(const double* model_dev, const hz_params* prm, hz_ctx** out) 
     if (std::fabs(prm->h * (n + 1) - 1.0) > 1e-9) raise(HZ_EINVAL, "h must be 1/(n+1)");
     if (!(prm->omega > 0.0) || !std::isfinite(prm->omega)) raise(HZ_EINVAL, "omega must be > 0");
     if (prm->n_pml < 0) raise(HZ_EINVAL, "n_pml must be >= 0");
+    // the equivalent sources of a layer / cell interface sit on the first
+    // artificial-PML row / column past the owned ones
+    if ((prm->layers > 1 || prm->cells > 1) && prm->n_pml < 1)
+        raise(HZ_EINVAL, "a decomposition (layers or cells > 1) needs n_pml >= 1");
     if (prm->layers < 1 || prm->layers > n / 2) raise(HZ_EINVAL, "layers must be in 1..n/2 (>= 2 rows each)");
     if (prm->cells < 1 || prm->cells > n / 2) raise(HZ_EINVAL, "cells must be in 1..n/2 (>= 2 columns each)");
     if (prm->precision != HZ_FP64 && prm->precision != HZ_MIXED &&
@@ -2899,8 +2903,6 @@ hz_status hz_setup(const double* model_dev, const hz_params* prm, hz_ctx** out) 
             raise(HZ_EINVAL, "nested polarized traces need precision HZ_FP64");
         if (prm->krylov != HZ_KRYLOV_GMRES)
             raise(HZ_EINVAL, "nested polarized traces need the (flexible) GMRES driver");
-        if (prm->cells > 1 && prm->n_pml < 1)
-            raise(HZ_EINVAL, "nested polarized traces need n_pml >= 1");
         if (!(prm->inner_tol < 1.0)) raise(HZ_EINVAL, "inner_tol must be < 1");
     }
     c = new hz_ctx();

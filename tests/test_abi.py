@@ -40,7 +40,8 @@ def test_status_strings():
     dict(n_z=100), dict(h=0.5), dict(omega=0.0), dict(omega=float("nan")), dict(n_pml=-1),
     dict(layers=0), dict(layers=64), dict(cells=0), dict(cells=64), dict(precision=7),
     dict(model_kind=5), dict(inner=5), dict(inner=1, precision=1), dict(inner=1, krylov=1),
-    dict(inner=1, n_pml=0), dict(inner=1, inner_tol=2.0)])
+    dict(inner=1, n_pml=0), dict(inner=1, inner_tol=2.0), dict(n_pml=0),
+    dict(n_pml=0, layers=1, cells=2)])
 def test_setup_rejects_bad_parameters_before_device_work(change):
     if not os.path.exists(hz.LIB_PATH):
         pytest.skip("libhz.so not built")
