@@ -126,6 +126,34 @@ def test_n1023_nested_polarized_traces(n1023):
     s.close()
 
 
+def test_n2047_nested_polarized_traces():
+    """The nested polarized traces on the n = 2047 layered medium (32 x 8
+    cells: seven inner interfaces per layer), all 64 sources in one solve,
+    against FP64 GPU solves (block-LU inner solver) of sampled sources."""
+    _need_gpu()
+    w = media.workload("C4")
+    c = torch.from_numpy(media.velocity("C4"))
+    f = torch.from_numpy(media.point_sources(w.n, w.src_x, w.src_z))
+    picks = [0, 40]
+    _log("[n=2047] FP64 reference solves (block-LU inner solver)")
+    s = hz.Solver(c, w.omega, w.n_pml, w.layers, w.cells, max_batch=2)
+    ref = s.solve(f[picks], tol=1e-12).cpu().numpy()
+    s.close()
+    torch.cuda.empty_cache()
+    _log("[n=2047] nested polarized traces, 64 sources")
+    s = hz.Solver(c, w.omega, w.n_pml, w.layers, w.cells, max_batch=len(w.src_x),
+                  inner=hz.HZ_INNER_PT)
+    u = s.solve(f, tol=1e-10)
+    t = s.timing()
+    for i, k in enumerate(picks):
+        err = _rel(u[k].cpu().numpy(), ref[i])
+        _log(f"  source {k}: nested vs block LU {err:.2e} (outer {t['gmres_iters']}, "
+             f"inner {t['inner_iters']})")
+        assert err <= 1e-9
+    s.close()
+    torch.cuda.empty_cache()
+
+
 def test_n2047_mixed_refinement_properties():
     """n = 2047 layered medium, 32 x 8 cells, 64 sources, complex64 nested
     solver inside FP64 refinement: reported error estimates, agreement with
