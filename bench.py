@@ -83,7 +83,7 @@ def kernel_src_hash(family):
     profiles/ are used only while the kernel is unchanged)."""
     import hashlib
 
-    group = "gemm" if family.startswith("gemm") else "cell_solve"
+    group = "gemm" if family.startswith(("gemm", "gemv")) else "cell_solve"
     h = hashlib.sha256()
     for f in KERNEL_SOURCES[group]:
         with open(os.path.join(ROOT, "paper_1510_01831_amd", "csrc", f), "rb") as fh:
