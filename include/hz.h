@@ -72,7 +72,7 @@ typedef enum {
     HZ_ENOMEM = -2,     /* device allocation failed */
     HZ_ESTATE = -3,     /* call out of order (e.g. hz_solve before hz_factor) */
     HZ_ENOCONV = -4,    /* some right-hand side missed tol within max_iter */
-    HZ_ESINGULAR = -5,  /* exactly zero pivot in a factorisation */
+    HZ_ESINGULAR = -5,  /* a block of a factorisation is singular to working precision */
     HZ_EDEVICE = -6     /* a HIP runtime error */
 } hz_status;
 
@@ -166,6 +166,9 @@ typedef struct {
     int trace_len;                     /* 4 (L-1) W: length of a polarized vector */
     int max_batch;
     long long device_bytes;            /* device memory held by the context */
+    double min_pivot_ratio;            /* smallest |pivot| / largest |pivot| over the block
+                                          inversions of the last hz_factor (cell Schur
+                                          complements, inner SIE diagonal blocks); 0 before */
 } hz_info_t;
 
 /* ---- life cycle ------------------------------------------------------- */
@@ -180,8 +183,14 @@ hz_status hz_setup(const double* model_dev, const hz_params* prm, hz_ctx** out);
  * (block-tridiagonal Schur recursion along x with explicitly inverted
  * diagonal blocks), precompute every cell's interface operators (eq.
  * factorization: M_f, M_u and the cell-local term) and factor every layer's
- * inner SIE by block LU without pivoting (Sec. 4.2.2).  HZ_ESINGULAR on an
- * exactly zero pivot.  May be called again after hz_update_model. */
+ * inner SIE by block LU without pivoting (Sec. 4.2.2).  The block recursions
+ * have no pivoting across blocks (Sec. 4.2.2), so a singular block cannot be
+ * avoided: HZ_ESINGULAR when a block inversion meets an exactly zero pivot or
+ * a smallest pivot magnitude at most 2^-26 times its largest (singular to
+ * working precision; hz_get_info reports the smallest ratio seen).  The
+ * context is then left set up but not factored (hz_solve returns
+ * HZ_ESTATE until a hz_factor succeeds).  May be called again after
+ * hz_update_model. */
 hz_status hz_factor(hz_ctx* ctx);
 
 /* Online stage (Alg. 6): solve H u = f for B right-hand sides.

@@ -238,7 +238,9 @@ struct hz_ctx {
     double2 *diag = nullptr, *cz = nullptr, *e = nullptr;
     double2 *ax_pool = nullptr, *az_pool = nullptr;
     double2 *gdiag = nullptr, *gcx = nullptr, *gcz = nullptr, *wext = nullptr;
-    int* flags = nullptr;          // [0] bad model, [1] singular
+    int* flags = nullptr;          // [0] bad model
+    FactorFlags* fflags = nullptr; // pivot status of the factorisation's block inversions
+    double min_pivot_ratio = 0.0;  // smallest pivot ratio of the last factorisation
     int* layer_active = nullptr;   // [L]
     long long coef_elems = 0, X_elems = 0, Q_elems = 0, CS_elems = 0, Sinv_elems = 0, Lfac_elems = 0;
     long long inner_per_layer = 0; // J * 2 * HLmax
@@ -1889,31 +1891,50 @@ void factor_impl(hz_ctx* c, const std::vector<char>* redo = nullptr) {
         if (c->inner_pt) o.CP = alloc_c<double>(c, std::max<long long>(c->CP_elems, 1));
     }
     o.e = c->e;
-    HIPCHK(hipMemsetAsync(c->flags, 0, 2 * sizeof(int), c->st));
+    {
+        FactorFlags ff0{0, 0, ~0ULL};
+        upload(c, c->fflags, &ff0, sizeof(ff0));
+    }
+    // temporaries of this call, released on every exit (also on HZ_ESINGULAR)
+    struct Temps {
+        Arena& a;
+        std::vector<void*> v;
+        void* keep(void* p) { v.push_back(p); return p; }
+        ~Temps() { for (void* p : v) a.release(p, 0); }
+    } tmp{c->arena, {}};
+    auto check_pivots = [&](const char* what) {
+        FactorFlags ff{};
+        HIPCHK(hipMemcpy(&ff, c->fflags, sizeof(ff), hipMemcpyDeviceToHost));
+        double r = 1.0;
+        if (ff.min_ratio_bits != ~0ULL) std::memcpy(&r, &ff.min_ratio_bits, sizeof(r));
+        c->min_pivot_ratio = r;
+        if (ff.singular) {
+            char buf[160];
+            std::snprintf(buf, sizeof buf, "%s: pivot ratio %.3g (zero pivot, or below 2^-26 of the "
+                          "block's largest pivot)", what, r);
+            raise(HZ_ESINGULAR, buf);
+        }
+    };
     const int nt = (int)todo.size();
     if (nt == 0) return;
     // 1. cell Schur factors (descriptors of the cells to factor, gathered)
     {
         std::vector<CellDesc> sel(nt);
         for (int i = 0; i < nt; ++i) sel[i] = c->cells[todo[i]];
-        CellDesc* d_sel = (CellDesc*)c->arena.alloc(sizeof(CellDesc) * nt);
+        CellDesc* d_sel = (CellDesc*)tmp.keep(c->arena.alloc(sizeof(CellDesc) * nt));
         upload(c, d_sel, sel.data(), sizeof(CellDesc) * nt);
         const long long ws = (long long)d.HLpmax * d.HLpmax;
         const int batch = std::min(nt, 1024);
-        double2* workbuf = alloc_c<double>(c, ws * batch);
+        double2* workbuf = (double2*)tmp.keep(alloc_c<double>(c, ws * batch));
         for (int c0 = 0; c0 < nt; c0 += batch) {
             const int cnt = std::min(batch, nt - c0);
             launch_cell_factor<double>(d_sel + c0, cnt, d, c->diag, c->cz, c->e, o.X,
-                                       workbuf, ws, c->flags + 1, c->st);
+                                       workbuf, ws, c->fflags, c->st);
             HIPCHK(hipGetLastError());
         }
         sync(c);
-        c->arena.release(workbuf, sizeof(double2) * ws * batch);
-        c->arena.release(d_sel, sizeof(CellDesc) * nt);
     }
-    int fl[2];
-    HIPCHK(hipMemcpy(fl, c->flags, sizeof(fl), hipMemcpyDeviceToHost));
-    if (fl[1]) raise(HZ_ESINGULAR, "zero pivot in a cell factorisation");
+    check_pivots("cell factorisation");
     // 2. probes: cell Green's functions sampled on the interface rows / columns
     int Rmax = 0;
     for (auto& cd : c->cells) Rmax = std::max(Rmax, cd.R);
@@ -1930,8 +1951,8 @@ void factor_impl(hz_ctx* c, const std::vector<char>* redo = nullptr) {
         const long long budget = std::min<long long>(24LL << 30, std::max<long long>(4LL << 30, (long long)(mfree / 4)));
         long long budget_wgs = std::max<long long>(chunks, budget / (ystride * (long long)sizeof(double2)));
         const int per = (int)std::min<long long>(nt, std::max<long long>(1, budget_wgs / chunks));
-        double2* Y = alloc_c<double>(c, ystride * (long long)per * chunks);
-        int* d_list = (int*)c->arena.alloc(sizeof(int) * nt);
+        double2* Y = (double2*)tmp.keep(alloc_c<double>(c, ystride * (long long)per * chunks));
+        int* d_list = (int*)tmp.keep(c->arena.alloc(sizeof(int) * nt));
         upload(c, d_list, todo.data(), sizeof(int) * nt);
         CellSolveArgs<double> a = base_args<double>(c);
         a.mode = SOLVE_PROBE;
@@ -1950,8 +1971,6 @@ void factor_impl(hz_ctx* c, const std::vector<char>* redo = nullptr) {
             HIPCHK(hipGetLastError());
         }
         sync(c);
-        c->arena.release(Y, sizeof(double2) * ystride * (long long)per * chunks);
-        c->arena.release(d_list, sizeof(int) * nt);
     }
     // 3. inner SIE block LU without pivoting (per layer, sequential over
     // interfaces); the nested polarized traces iterate the inner SIE instead
@@ -1961,20 +1980,20 @@ void factor_impl(hz_ctx* c, const std::vector<char>* redo = nullptr) {
         if (redo_layer[l]) lay.push_back(l);
     if (J > 0) {
         const int L = (int)lay.size();     // compact index i <-> layer lay[i]
-        int* d_lay = (int*)c->arena.alloc(sizeof(int) * L);
+        int* d_lay = (int*)tmp.keep(c->arena.alloc(sizeof(int) * L));
         upload(c, d_lay, lay.data(), sizeof(int) * L);
         const long long bs = 4LL * d.HLmax * d.HLmax;       // (2 HLmax)^2
-        double2* A = alloc_c<double>(c, bs * L);
-        double2* wk = alloc_c<double>(c, bs * L);
-        double2** mats = (double2**)c->arena.alloc(sizeof(void*) * L);
-        double2** outs = (double2**)c->arena.alloc(sizeof(void*) * L);
-        int* ns = (int*)c->arena.alloc(sizeof(int) * L);
+        double2* A = (double2*)tmp.keep(alloc_c<double>(c, bs * L));
+        double2* wk = (double2*)tmp.keep(alloc_c<double>(c, bs * L));
+        double2** mats = (double2**)tmp.keep(c->arena.alloc(sizeof(void*) * L));
+        double2** outs = (double2**)tmp.keep(c->arena.alloc(sizeof(void*) * L));
+        int* ns = (int*)tmp.keep(c->arena.alloc(sizeof(int) * L));
         std::vector<int> hn(L);
         std::vector<double2*> hm(L), ho(L);
         for (int i = 0; i < L; ++i) { hn[i] = 2 * c->layers[lay[i]].HL; hm[i] = A + bs * i; }
         upload(c, ns, hn.data(), sizeof(int) * L);
         upload(c, mats, hm.data(), sizeof(void*) * L);
-        GemmTask<double>* tdev = (GemmTask<double>*)c->arena.alloc(sizeof(GemmTask<double>) * 2 * L);
+        GemmTask<double>* tdev = (GemmTask<double>*)tmp.keep(c->arena.alloc(sizeof(GemmTask<double>) * 2 * L));
         for (int j = 0; j < J; ++j) {
             hipLaunchKernelGGL(k_inner_diag, dim3(64, L), dim3(256), 0, c->st, c->d_layers,
                                d_lay, c->d_cells, o.CS, j, A, bs);
@@ -2031,19 +2050,11 @@ void factor_impl(hz_ctx* c, const std::vector<char>* redo = nullptr) {
             }
             upload(c, outs, ho.data(), sizeof(void*) * L);
             // inverse of an order-2HL block: pack with row stride 2HL (the A buffer is already)
-            launch_invert_batch<double>(mats, outs, ns, L, wk, bs, c->flags + 1, c->st);
+            launch_invert_batch<double>(mats, outs, ns, L, wk, bs, c->fflags, c->st);
             HIPCHK(hipGetLastError());
             sync(c);
         }
-        HIPCHK(hipMemcpy(fl, c->flags, sizeof(fl), hipMemcpyDeviceToHost));
-        if (fl[1]) raise(HZ_ESINGULAR, "zero pivot in the inner block LU");
-        c->arena.release(A, sizeof(double2) * bs * L);
-        c->arena.release(wk, sizeof(double2) * bs * L);
-        c->arena.release(mats, sizeof(void*) * L);
-        c->arena.release(outs, sizeof(void*) * L);
-        c->arena.release(ns, sizeof(int) * L);
-        c->arena.release(tdev, sizeof(GemmTask<double>) * 2 * L);
-        c->arena.release(d_lay, sizeof(int) * L);
+        check_pivots("inner block LU");
     }
     // 4. composed output operators
     if (J > 0 && c->compose) build_composed(c, redo_layer);
@@ -2962,6 +2973,7 @@ hz_status hz_setup(const double* model_dev, const hz_params* prm, hz_ctx** out) 
     c->gcz = alloc_c<double>(c, N);
     c->wext = alloc_c<double>(c, N);
     c->flags = (int*)c->arena.alloc(sizeof(int) * 4);
+    c->fflags = (FactorFlags*)c->arena.alloc(sizeof(FactorFlags));
     c->layer_active = (int*)c->arena.alloc(sizeof(int) * d.L);
     setup_coef(c, model_dev);
     c->state = 1;
@@ -3106,14 +3118,14 @@ hz_status hz_misfit(hz_ctx* c, const void* u_ext, const void* d_obs, int rec_row
     check_state(c, 1);
     if (!u_ext || !d_obs || !adj || !J || B < 1 || rec_row < 1 || rec_row > c->d.n)
         raise(HZ_EINVAL, "bad misfit arguments");
-    double* part = (double*)c->arena.alloc(sizeof(double) * 256);
+    double* part = (double*)c->arena.alloc(sizeof(double) * MISFIT_PARTS);
     launch_misfit((const double2*)u_ext, (const double2*)d_obs, rec_row, B, c->d.n, c->d.p,
                   c->d.W, (double2*)adj, part, c->st);
     HIPCHK(hipGetLastError());
-    std::vector<double> hp(256);
-    HIPCHK(hipMemcpyAsync(hp.data(), part, sizeof(double) * 256, hipMemcpyDeviceToHost, c->st));
+    std::vector<double> hp(MISFIT_PARTS);
+    HIPCHK(hipMemcpyAsync(hp.data(), part, sizeof(double) * MISFIT_PARTS, hipMemcpyDeviceToHost, c->st));
     sync(c);
-    c->arena.release(part, sizeof(double) * 256);
+    c->arena.release(part, sizeof(double) * MISFIT_PARTS);
     double s = 0.0;
     for (double v : hp) s += v;
     *J = 0.5 * s;
@@ -3166,6 +3178,7 @@ hz_status hz_get_info(const hz_ctx* c, hz_info_t* info) {
     info->trace_len = 4 * c->d.K * c->d.W;
     info->max_batch = c->prm.max_batch;
     info->device_bytes = c->arena.bytes;
+    info->min_pivot_ratio = c->min_pivot_ratio;
     return HZ_OK;
 }
 

@@ -60,6 +60,19 @@ __host__ __device__ inline double2 cinv(double2 a) {
 // descriptors (plain structs, copied to the device)
 
 constexpr int MAXSLOT = 4;
+constexpr int MISFIT_PARTS = 256;
+// Status of the block inversions of a factorisation.  A block is reported
+// singular when a pivot is exactly zero or when its smallest pivot magnitude
+// is at most PIVOT_RATIO_MIN times its largest (partial pivoting: the pivots
+// bound the block's condition from below, and a ratio below 2^-26 leaves
+// fewer than half of the FP64 digits); min_ratio_bits holds the smallest
+// ratio seen, as the bits of a non-negative double (atomicMin order).
+struct FactorFlags {
+    int singular;
+    int pad;
+    unsigned long long min_ratio_bits;
+};
+constexpr double PIVOT_RATIO_MIN = 1.4901161193847656e-08;   // 2^-26   // workgroups (and partial sums) of k_misfit
 
 struct LayerDesc {
     int index;           // 0-based layer index
@@ -227,12 +240,12 @@ void launch_build_coef(const double* model, int model_kind, const Dims& d,
 template <typename T>
 void launch_cell_factor(const CellDesc* cells_dev, int ncells, const Dims& d,
                         const double2* diag, const double2* cz, const double2* e,
-                        C2<T>* Xpool, C2<T>* work, long long work_stride, int* sing_flag,
+                        C2<T>* Xpool, C2<T>* work, long long work_stride, FactorFlags* ff,
                         hipStream_t st);
 
 template <typename T>
 void launch_invert_batch(C2<T>* const* mats, C2<T>* const* outs, const int* ns, int count,
-                         C2<T>* work, long long work_stride, int* sing_flag, hipStream_t st);
+                         C2<T>* work, long long work_stride, FactorFlags* ff, hipStream_t st);
 
 template <typename T>
 void launch_cell_solve(const CellSolveArgs<T>& a, int ncells_launch, int nb_chunks,

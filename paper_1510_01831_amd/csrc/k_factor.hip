@@ -58,6 +58,27 @@ __device__ inline T wave_max(T v) {
     }
 }
 
+// Pivot statistics of one block inversion (wave-uniform values): exact zero
+// pivots are flagged at once; at the end, the ratio of the smallest to the
+// largest pivot magnitude is compared with PIVOT_RATIO_MIN and folded into
+// the launch's minimum.
+template <typename T>
+struct PivotStats {
+    T pmax2 = (T)0, pmin2 = (T)-1;
+    __device__ void add(T best2) {
+        pmax2 = fmax(pmax2, best2);
+        pmin2 = pmin2 < (T)0 ? best2 : fmin(pmin2, best2);
+    }
+    __device__ void finish(FactorFlags* ff) const {
+        if (threadIdx.x != 0) return;
+        double ratio = 0.0;
+        if (pmax2 > (T)0 && pmin2 > (T)0) ratio = sqrt((double)pmin2 / (double)pmax2);
+        if (!(ratio > PIVOT_RATIO_MIN)) atomicOr(&ff->singular, 1);
+        atomicMin(&ff->min_ratio_bits, (unsigned long long)__double_as_longlong(ratio));
+    }
+};
+
+
 // Invert the n x n matrix in `work` (row-major, row stride n; thread-owned
 // entries: entry e = r*n + j is only ever touched by thread e % blockDim.x)
 // and write the inverse to `out` (row stride ldo).  `work` is destroyed.
@@ -68,7 +89,7 @@ __device__ inline T wave_max(T v) {
 // out_tiled > 0: write the inverse in the 16x4 MFMA tile layout of order
 // out_tiled (padded entries untouched); otherwise row-major with stride ldo.
 template <typename T>
-__device__ void gj_invert(C2<T>* work, C2<T>* out, int n, long long ldo, int* sing_flag,
+__device__ void gj_invert(C2<T>* work, C2<T>* out, int n, long long ldo, FactorFlags* ff,
                           int out_tiled = 0) {
     constexpr int SR = (GJ_NMAX + 63) / 64;
     __shared__ C2<T> colbuf[2][GJ_NMAX];
@@ -96,6 +117,7 @@ __device__ void gj_invert(C2<T>* work, C2<T>* out, int n, long long ldo, int* si
     }
     __syncthreads();
     int cur = 0;
+    PivotStats<T> pst;
     for (int k = 0; k < n; ++k) {
         // ---- pivot search over unused rows (ties -> smallest row)
         T v[SR];
@@ -119,13 +141,14 @@ __device__ void gj_invert(C2<T>* work, C2<T>* out, int n, long long ldo, int* si
         // every index in range
         if (pr < 0) { pr = 0; best = (T)0; }
         pr = __builtin_amdgcn_readfirstlane(pr);
+        pst.add(best);
 #pragma unroll
         for (int s = 0; s < SR; ++s)
             if (pr == lane + 64 * s) used[s] = true;
         const C2<T> pv = colbuf[cur][pr];
         C2<T> inv = mk<T>((T)0, (T)0);
         if (best <= (T)0) {
-            if (tid == 0) atomicOr(sing_flag, 1);
+            if (tid == 0) atomicOr(&ff->singular, 1);
         } else {
             const T den = (T)1 / (pv.x * pv.x + pv.y * pv.y);
             inv = mk<T>(pv.x * den, -pv.y * den);
@@ -180,6 +203,7 @@ __device__ void gj_invert(C2<T>* work, C2<T>* out, int n, long long ldo, int* si
         cur = nxt;
         __syncthreads();
     }
+    pst.finish(ff);
     // ---- unscramble: X[pivstep[r]][pivrow[j]] = work[r][j]
     {
         int r = r0, j = c0;
@@ -200,7 +224,7 @@ __global__ void __launch_bounds__(GJ_THREADS)
 k_cell_factor(const CellDesc* __restrict__ cells, const double2* __restrict__ diag,
               const double2* __restrict__ cz, const double2* __restrict__ e,
               C2<T>* __restrict__ Xpool, C2<T>* __restrict__ workpool, long long work_stride,
-              int* sing_flag) {
+              FactorFlags* ff) {
     const CellDesc cd = cells[blockIdx.x];
     const int HL = cd.HL, Wc = cd.Wc, HLp = cd.HLp;
     const long long nn = (long long)HL * HL;
@@ -241,7 +265,7 @@ k_cell_factor(const CellDesc* __restrict__ cells, const double2* __restrict__ di
             }
         }
         __syncthreads();
-        gj_invert<T>(work, X + (long long)k * np2, HL, HL, sing_flag, HLp);
+        gj_invert<T>(work, X + (long long)k * np2, HL, HL, ff, HLp);
     }
 }
 
@@ -274,7 +298,7 @@ template <typename T, int NM, int CR, int CL>
 __global__ void __launch_bounds__(GJ_THREADS)
 k_cell_factor_reg(const CellDesc* __restrict__ cells, const double2* __restrict__ diag,
                   const double2* __restrict__ cz, const double2* __restrict__ e,
-                  C2<T>* __restrict__ Xpool, int* sing_flag) {
+                  C2<T>* __restrict__ Xpool, FactorFlags* ff) {
     constexpr int R = NM / 32, C = CR + CL, SR = (NM + 63) / 64, LW = 16 * CL;
     static_assert(NM % 32 == 0 && 16 * C >= NM, "layout must cover the block");
     using V = vecT<T, 2 * R>;
@@ -339,6 +363,7 @@ k_cell_factor_reg(const CellDesc* __restrict__ cells, const double2* __restrict_
         for (int r = tid; r < NM; r += GJ_THREADS) { pivrow[r] = r; pivstep[r] = r; }
         __syncthreads();
         int cur = 0;
+        PivotStats<T> pst;
 #pragma unroll
         for (int kj = 0; kj < C; ++kj) {
             for (int kc = 0; kc < 16; ++kc) {
@@ -367,10 +392,11 @@ k_cell_factor_reg(const CellDesc* __restrict__ cells, const double2* __restrict_
                 // and keep every index in range
                 if (pr < 0) { pr = 0; best = (T)0; }
                 pr = __builtin_amdgcn_readfirstlane(pr);
+                pst.add(best);
                 const C2<T> pv = colbuf[cur][pr];
                 C2<T> inv = zero;
                 if (best <= (T)0) {
-                    if (tid == 0) atomicOr(sing_flag, 1);
+                    if (tid == 0) atomicOr(&ff->singular, 1);
                 } else {
                     const T den = (T)1 / (pv.x * pv.x + pv.y * pv.y);
                     inv = mk<T>(pv.x * den, -pv.y * den);
@@ -457,6 +483,7 @@ k_cell_factor_reg(const CellDesc* __restrict__ cells, const double2* __restrict_
                 __syncthreads();
             }
         }
+        pst.finish(ff);
         // unscramble: X_col[pivstep[r]][pivrow[j]] = a[r][j]; padding zero
         C2<T>* Xk = X + (long long)col * np2;
         int ps[R];
@@ -488,30 +515,30 @@ constexpr size_t fac_lds_bytes() { return (size_t)NM * 16 * CL * sizeof(C2<T>); 
 template <typename T>
 __global__ void __launch_bounds__(GJ_THREADS)
 k_invert_batch(C2<T>* const* mats, C2<T>* const* outs, const int* ns, C2<T>* workpool,
-               long long work_stride, int* sing_flag) {
+               long long work_stride, FactorFlags* ff) {
     const int n = ns[blockIdx.x];
     C2<T>* work = workpool + (long long)blockIdx.x * work_stride;
     const C2<T>* src = mats[blockIdx.x];
     const long long nn = (long long)n * n;
     for (long long q = threadIdx.x; q < nn; q += blockDim.x) work[q] = src[q];
     __syncthreads();
-    gj_invert<T>(work, outs[blockIdx.x], n, n, sing_flag);
+    gj_invert<T>(work, outs[blockIdx.x], n, n, ff);
 }
 
 template <typename T>
 void launch_cell_factor(const CellDesc* cells_dev, int ncells, const Dims& d,
                         const double2* diag, const double2* cz, const double2* e,
-                        C2<T>* Xpool, C2<T>* work, long long work_stride, int* sing_flag,
+                        C2<T>* Xpool, C2<T>* work, long long work_stride, FactorFlags* ff,
                         hipStream_t st) {
 #if HZ_GJ_REG
     if (d.HLmax <= 64) {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cell_factor_reg<T, 64, 4, 0>), dim3(ncells),
-                           dim3(GJ_THREADS), 0, st, cells_dev, diag, cz, e, Xpool, sing_flag);
+                           dim3(GJ_THREADS), 0, st, cells_dev, diag, cz, e, Xpool, ff);
         return;
     }
     if (d.HLmax <= 128) {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cell_factor_reg<T, 128, 8, 0>), dim3(ncells),
-                           dim3(GJ_THREADS), 0, st, cells_dev, diag, cz, e, Xpool, sing_flag);
+                           dim3(GJ_THREADS), 0, st, cells_dev, diag, cz, e, Xpool, ff);
         return;
     }
     if (d.HLmax <= 160) {
@@ -526,30 +553,30 @@ void launch_cell_factor(const CellDesc* cells_dev, int ncells, const Dims& d,
             attr = true;
         }
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cell_factor_reg<T, 160, 7, 3>), dim3(ncells),
-                           dim3(GJ_THREADS), lds, st, cells_dev, diag, cz, e, Xpool, sing_flag);
+                           dim3(GJ_THREADS), lds, st, cells_dev, diag, cz, e, Xpool, ff);
         return;
     }
 #endif
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cell_factor<T>), dim3(ncells), dim3(GJ_THREADS), 0, st,
-                       cells_dev, diag, cz, e, Xpool, work, work_stride, sing_flag);
+                       cells_dev, diag, cz, e, Xpool, work, work_stride, ff);
 }
 
 template <typename T>
 void launch_invert_batch(C2<T>* const* mats, C2<T>* const* outs, const int* ns, int count,
-                         C2<T>* work, long long work_stride, int* sing_flag, hipStream_t st) {
+                         C2<T>* work, long long work_stride, FactorFlags* ff, hipStream_t st) {
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_invert_batch<T>), dim3(count), dim3(GJ_THREADS), 0, st,
-                       mats, outs, ns, work, work_stride, sing_flag);
+                       mats, outs, ns, work, work_stride, ff);
 }
 
 template void launch_cell_factor<double>(const CellDesc*, int, const Dims&, const double2*,
                                          const double2*, const double2*, double2*, double2*,
-                                         long long, int*, hipStream_t);
+                                         long long, FactorFlags*, hipStream_t);
 template void launch_cell_factor<float>(const CellDesc*, int, const Dims&, const double2*,
                                         const double2*, const double2*, float2*, float2*,
-                                        long long, int*, hipStream_t);
+                                        long long, FactorFlags*, hipStream_t);
 template void launch_invert_batch<double>(double2* const*, double2* const*, const int*, int,
-                                          double2*, long long, int*, hipStream_t);
+                                          double2*, long long, FactorFlags*, hipStream_t);
 template void launch_invert_batch<float>(float2* const*, float2* const*, const int*, int,
-                                         float2*, long long, int*, hipStream_t);
+                                         float2*, long long, FactorFlags*, hipStream_t);
 
 }  // namespace hz

@@ -838,7 +838,7 @@ __global__ void k_misfit(const double2* u, const double2* d, int rec_row, int B,
 }
 void launch_misfit(const double2* u_ext, const double2* d_obs, int rec_row, int B, int n, int p,
                    int W, double2* adj, double* Jpart, hipStream_t st) {
-    hipLaunchKernelGGL(k_misfit, dim3(256), dim3(256), 0, st, u_ext, d_obs, rec_row, B, n, p, W,
+    hipLaunchKernelGGL(k_misfit, dim3(MISFIT_PARTS), dim3(256), 0, st, u_ext, d_obs, rec_row, B, n, p, W,
                        adj, Jpart);
 }
 

@@ -63,7 +63,7 @@ class Info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("n_pml", ctypes.c_int), ("W", ctypes.c_int),
                 ("layers", ctypes.c_int), ("cells", ctypes.c_int),
                 ("trace_len", ctypes.c_int), ("max_batch", ctypes.c_int),
-                ("device_bytes", ctypes.c_longlong)]
+                ("device_bytes", ctypes.c_longlong), ("min_pivot_ratio", ctypes.c_double)]
 
 
 _lib = None
