@@ -241,6 +241,24 @@ hz_status hz_misfit_gradient(hz_ctx* ctx, const void* u_ext_dev, const void* lam
 hz_status hz_misfit(hz_ctx* ctx, const void* u_ext_dev, const void* d_obs_dev, int rec_row,
                     int B, void* adj_src_dev, double* J_host);
 
+/* Allocation-free variant of hz_misfit, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same inputs and adjoint source as
+ * hz_misfit; J is written to device memory (*J_dev, one double) instead of
+ * the host.  The kernel's partial sums live in a library-owned file-scope
+ * device array of 256 doubles (2 KB), one copy per device that the library
+ * runs on, held until the process ends; its size does not depend on B or n,
+ * so no input size is rejected for it, and every call overwrites all of it
+ * (nothing needs clearing).  The call allocates nothing (no hipMalloc /
+ * hipFree), enqueues its work on the context's stream and returns without
+ * waiting: synchronise that stream before reading *J_dev or adj_src_dev.
+ * J equals hz_misfit's value bit for bit (the partials are added in the same
+ * order).  Calls that overlap on one GPU (from any context, any stream)
+ * race on the shared array.  Errors: HZ_EINVAL as hz_misfit (or J_dev NULL),
+ * HZ_ESTATE before hz_setup, HZ_EDEVICE on a HIP error. */
+hz_status hz_misfit_noalloc(hz_ctx* ctx, const void* u_ext_dev, const void* d_obs_dev,
+                            int rec_row, int B, void* adj_src_dev, double* J_dev);
+
 /* Replace the model (same size and kind) and rebuild the coefficients; the
  * context returns to the "set up" state (hz_factor must be called again).
  * HZ_EINVAL for a bad model (checked first: the context is then unchanged). */

@@ -26,6 +26,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <memory>
 #include <string>
 #include <unordered_map>
@@ -264,6 +265,8 @@ struct hz_ctx {
     double2 *u64 = nullptr, *f64 = nullptr, *r64 = nullptr;   // refinement [W][W][B]
     std::vector<std::vector<std::complex<double>>> g_hess;     // host Hessenberg storage of GMRES
     double2* h_pin = nullptr;      // pinned host buffer for the small per-iteration reads
+    int device = 0;                // device current at hz_setup
+    double* misfit_scratch = nullptr; // this device's copy of the file-scope scratch array
     size_t h_pin_elems = 0;
     hz_timing timing{};
     Prof prof;
@@ -2866,6 +2869,44 @@ hz_status setup_coef(hz_ctx* c, const double* model_dev) {
 // ===========================================================================
 // C-ABI
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free misfit (hz_misfit_noalloc): the partial sums
+// of k_misfit.  One copy per device, held until the process ends.  Host code
+// reaches it only through the address hipGetSymbolAddress returns on that
+// device (the array's name is a host-side stand-in there).
+static __device__ __align__(256) double scratch[hz::MISFIT_PARTS];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_addr[kMaxDevices] = {};
+
+// address of `scratch` on `dev`, which must be the current device
+double* misfit_scratch_address(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) raise(HZ_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            raise(HZ_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        }
+        g_scratch_addr[dev] = (double*)p;
+    }
+    return g_scratch_addr[dev];
+}
+
+// J = 1/2 sum of the partials, summed in index order (the order in which
+// hz_misfit adds them on the host)
+__global__ void k_misfit_total(const double* part, int n, double* J) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += part[i];
+    *J = 0.5 * s;
+}
+}  // namespace
+
 extern "C" {
 
 const char* hz_strerror(hz_status s) {
@@ -2950,6 +2991,8 @@ hz_status hz_setup(const double* model_dev, const hz_params* prm, hz_ctx** out) 
     // stream, and capturable into graphs
     HIPCHK(hipStreamCreate(&c->own_st));
     c->st = c->own_st;
+    HIPCHK(hipGetDevice(&c->device));
+    c->misfit_scratch = misfit_scratch_address(c->device);
     c->d_layers = (LayerDesc*)c->arena.alloc(sizeof(LayerDesc) * d.L);
     c->d_cells = (CellDesc*)c->arena.alloc(sizeof(CellDesc) * c->cells.size());
     upload(c, c->d_layers, c->layers.data(), sizeof(LayerDesc) * d.L);
@@ -3129,6 +3172,24 @@ hz_status hz_misfit(hz_ctx* c, const void* u_ext, const void* d_obs, int rec_row
     double s = 0.0;
     for (double v : hp) s += v;
     *J = 0.5 * s;
+    return HZ_OK;
+    API_END
+}
+
+hz_status hz_misfit_noalloc(hz_ctx* c, const void* u_ext, const void* d_obs, int rec_row, int B,
+                            void* adj, double* J_dev) {
+    API_BEGIN
+    check_state(c, 1);
+    if (!u_ext || !d_obs || !adj || !J_dev || B < 1 || rec_row < 1 || rec_row > c->d.n)
+        raise(HZ_EINVAL, "bad misfit arguments");
+    if (!c->misfit_scratch) raise(HZ_ESTATE, "no scratch address for this context's device");
+    // the kernel writes every one of its MISFIT_PARTS partial sums, so the
+    // array needs no clearing; its size does not depend on B or n
+    launch_misfit((const double2*)u_ext, (const double2*)d_obs, rec_row, B, c->d.n, c->d.p,
+                  c->d.W, (double2*)adj, c->misfit_scratch, c->st);
+    hipLaunchKernelGGL(k_misfit_total, dim3(1), dim3(64), 0, c->st, c->misfit_scratch,
+                       MISFIT_PARTS, J_dev);
+    HIPCHK(hipGetLastError());
     return HZ_OK;
     API_END
 }

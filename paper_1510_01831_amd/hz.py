@@ -22,7 +22,7 @@ HZ_INNER_LU, HZ_INNER_PT = 0, 1
 
 EXPORTED = [
     "hz_setup", "hz_factor", "hz_solve", "hz_adjoint", "hz_solve_ext", "hz_adjoint_ext",
-    "hz_misfit_gradient", "hz_misfit", "hz_update_model", "hz_update_model_local",
+    "hz_misfit_gradient", "hz_misfit", "hz_misfit_noalloc", "hz_update_model", "hz_update_model_local",
     "hz_set_stream", "hz_get_info", "hz_get_timing",
     "hz_destroy", "hz_strerror", "hz_last_error", "hz_apply_layer", "hz_apply_sie",
     "hz_apply_precond", "hz_sie_rhs", "hz_cell_solve", "hz_cell_shape", "hz_residual",
@@ -87,6 +87,7 @@ def lib() -> ctypes.CDLL:
             getattr(L, name).argtypes = [vp, vp, i, vp, d, i, ctypes.POINTER(RhsStats)]
         L.hz_misfit_gradient.argtypes = [vp, vp, vp, i, vp]
         L.hz_misfit.argtypes = [vp, vp, vp, i, i, vp, ctypes.POINTER(d)]
+        L.hz_misfit_noalloc.argtypes = [vp, vp, vp, i, i, vp, vp]
         L.hz_update_model.argtypes = [vp, vp]
         L.hz_update_model_local.argtypes = [vp, vp, ctypes.POINTER(i)]
         L.hz_set_stream.argtypes = [vp, vp]
@@ -246,6 +247,14 @@ class Solver:
                                _ptr(d_obs.to(device="cuda", dtype=torch.complex128).contiguous()),
                                int(rec_row), B, _ptr(adj), ctypes.byref(J)), "hz_misfit")
         return J.value, adj
+
+    def misfit_noalloc(self, u_ext, d_obs, rec_row, adj_out, J_out):
+        """hz_misfit_noalloc into caller-owned outputs (adj_out: B x n x n
+        complex128, J_out: one float64 on the device); returns without
+        waiting for the context's stream."""
+        _check(lib().hz_misfit_noalloc(self.ctx, _ptr(u_ext), _ptr(d_obs), int(rec_row),
+                                       u_ext.shape[0], _ptr(adj_out), _ptr(J_out)),
+               "hz_misfit_noalloc")
 
     def profile(self, on: bool):
         _check(lib().hz_profile(self.ctx, int(bool(on))), "hz_profile")
