@@ -48,8 +48,11 @@
  *                    4: 32x32, 16-deep; 5: 32x32, 32-deep, two chunks in
  *                    flight; 6: 64x64, two chunks in flight; 7: 32 rows x
  *                    64 columns, 8: 64 x 32, both 32-deep; 9 / 10: 64x64
- *                    with each tile's k range split over 2 / 4 workgroups;
- *                    11 / 12: the same split over 32x32 tiles), no tuning;
+ *                    with each tile's k range split over 2 / 4 workgroups
+ *                    and the partial tiles added by a second kernel;
+ *                    11 / 12 / 13: the same split over 2 / 4 / 8
+ *                    workgroups of 32x32 tiles; 14: 64x64 split 8 ways;
+ *                    15 / 16: 32 x 64 split 4 / 8 ways), no tuning;
  *      HZ_COMPOSE=0  inner SIE solved by block LU substitutions at every layer
  *                    application instead of the composed output operators;
  *      HZ_GRAPHS=0   plans launched kernel by kernel instead of replayed HIP

@@ -779,15 +779,12 @@ void plan_launches(hz_ctx* c, Plan<T>& pl, int B);
 // input segments and outputs redirected to scratch buffers (plans that update
 // vectors in place are not disturbed), and the fastest kernel is kept in the
 // launch record.  Runs once, when the plan is built for a batch size.
-// 64 MB of partial tiles and 64 K tile counters, zeroed once; the split-k
-// kernels leave the counters zero, so plans captured in graphs reuse them.
+// 64 MB of partial tiles for the split-k GEMM variants (a launch whose
+// partials do not fit runs the unsplit kernel)
 void ensure_split_ws(hz_ctx* c) {
     if (c->gsw.ws) return;
     c->gsw.ws_bytes = 64LL << 20;
-    c->gsw.ncounters = 1 << 16;
     c->gsw.ws = c->arena.alloc((size_t)c->gsw.ws_bytes);
-    c->gsw.counters = (int*)c->arena.alloc(sizeof(int) * (size_t)c->gsw.ncounters);
-    HIPCHK(hipMemsetAsync(c->gsw.counters, 0, sizeof(int) * (size_t)c->gsw.ncounters, c->st));
 }
 
 template <typename T>
@@ -836,10 +833,12 @@ void tune_plan(hz_ctx* c, Plan<T>& pl, int B) {
         for (int cand : {dflt, (int)GEMM_MFMA64, (int)GEMM_MFMA32, (int)GEMM_MFMA32K16,
                          (int)GEMM_MFMA32D, (int)GEMM_MFMA64D, (int)GEMM_MFMA32X64,
                          (int)GEMM_MFMA64X32, (int)GEMM_MFMA64S2, (int)GEMM_MFMA64S4,
-                         (int)GEMM_MFMA32S2, (int)GEMM_MFMA32S4}) {
+                         (int)GEMM_MFMA32S2, (int)GEMM_MFMA32S4, (int)GEMM_MFMA32S8,
+                         (int)GEMM_MFMA64S8, (int)GEMM_MFMA32X64S4, (int)GEMM_MFMA32X64S8}) {
             if (cand == dflt && best < 1e30f) continue;
             if ((cand == GEMM_MFMA64 || cand == GEMM_MFMA64D || cand == GEMM_MFMA32X64 ||
-                 cand == GEMM_MFMA64S2 || cand == GEMM_MFMA64S4) && B < 64)
+                 cand == GEMM_MFMA64S2 || cand == GEMM_MFMA64S4 || cand == GEMM_MFMA64S8 ||
+                 cand == GEMM_MFMA32X64S4 || cand == GEMM_MFMA32X64S8) && B < 64)
                 continue;
             launch_gemm<T>(dt, r.ntasks, r.max_m, B, c->st, false, cand, &c->gsw);   // warm-up
             HIPCHK(hipEventRecord(e0, c->st));
@@ -1627,11 +1626,12 @@ void cell_solve_launch(hz_ctx* c, CellSolveArgs<T> a, const std::vector<int>& li
             }
         }
     };
-    int nb = cs_nb(Bcols, (int)list.size(), c->d.HLpmax);
+    int nb = cs_nb(Bcols, (int)list.size(), c->d.HLpmax, (int)sizeof(C2<T>));
     // Autotune the batch width once per (mode, batch, cells): both widths give
     // the same results column by column, so the solve itself is timed with
     // each and the last run's output is kept.
-    const bool tunable = c->tune && Bcols > 16 && c->d.HLpmax <= 128 && !std::getenv("HZ_CELL_NB") &&
+    const bool tunable = c->tune && Bcols > 16 && cs_nb_max(c->d.HLpmax, (int)sizeof(C2<T>)) == 32 &&
+                         !std::getenv("HZ_CELL_NB") &&
                          (a.mode == SOLVE_SAMPLE || a.mode == SOLVE_VOLUME);
     if (tunable) {
         const std::string key = std::to_string(a.mode) + "|" + std::to_string(Bcols) + "|" +
@@ -1942,7 +1942,7 @@ void factor_impl(hz_ctx* c, const std::vector<char>* redo = nullptr) {
     int Rmax = 0;
     for (auto& cd : c->cells) Rmax = std::max(Rmax, cd.R);
     if (Rmax > 0) {
-        const int nb = cs_nb(Rmax, ncells, d.HLpmax);
+        const int nb = cs_nb(Rmax, ncells, d.HLpmax, (int)sizeof(double2));
         const int chunks = (Rmax + nb - 1) / nb;
         const long long ystride = (long long)d.Wcmax * d.HLpmax * nb;
         // Forward-sweep scratch: a quarter of the free memory, between 4 and
@@ -2969,7 +2969,7 @@ hz_status hz_setup(const double* model_dev, const hz_params* prm, hz_ctx** out) 
     if (const char* g = std::getenv("HZ_TUNE")) c->tune = std::atoi(g) != 0;
     if (const char* g = std::getenv("HZ_GEMM_KIND")) {
         const int k = std::atoi(g);
-        if (k >= GEMM_MFMA32 && k <= GEMM_MFMA32S4) c->force_kind = k;
+        if (k >= GEMM_MFMA32 && k <= GEMM_MFMA32X64S8) c->force_kind = k;
     }
     if (c->prm.pml_beta <= 0.0) c->prm.pml_beta = 2.0;
     if (c->prm.max_batch <= 0) c->prm.max_batch = 1;

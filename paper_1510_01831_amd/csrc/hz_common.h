@@ -61,6 +61,17 @@ __host__ __device__ inline double2 cinv(double2 a) {
 
 constexpr int MAXSLOT = 4;
 constexpr int MISFIT_PARTS = 256;
+// Workgroup slot L of a 1-D launch runs on XCD L mod 8 (round-robin
+// dispatch).  xcd_tile maps slots to work items so that each XCD gets one
+// contiguous run of the item sequence: items next to each other in that
+// sequence (the tiles that share operands, the batch chunks of one cell)
+// run on one XCD at about the same time and share its L2.
+__device__ __forceinline__ int xcd_tile(int L, int total) {
+    const int xcd = L & 7, local = L >> 3;
+    const int q = total >> 3, r = total & 7;
+    return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + local;
+}
+
 // Status of the block inversions of a factorisation.  A block is reported
 // singular when a pivot is exactly zero or when its smallest pivot magnitude
 // is at most PIVOT_RATIO_MIN times its largest (partial pivoting: the pivots
@@ -176,10 +187,8 @@ struct GemmTask {
 // Workspace of the split-k variants: partial tiles (bytes) and one counter
 // per output tile, zero between launches (the kernels leave them zero).
 struct GemmSplitWs {
-    void* ws = nullptr;
+    void* ws = nullptr;              // partial tiles of the split-k variants
     long long ws_bytes = 0;
-    int* counters = nullptr;
-    long long ncounters = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -266,13 +275,18 @@ void launch_gemm(const GemmTask<T>* tasks_dev, int ntasks, int max_m, int B, hip
 // GEMM_MFMA32X64 / GEMM_MFMA64X32: 32 x 64 and 64 x 32 output tiles (rows x
 // batch columns), 32-deep chunks.
 // GEMM_MFMA64S2 / GEMM_MFMA64S4: 64x64 tiles with the k chunks of a tile split
-// over 2 / 4 workgroups (needs a GemmSplitWs; without one, GEMM_MFMA64).
-// GEMM_MFMA32S2 / GEMM_MFMA32S4: the same split over 32x32 tiles, 32-deep
-// chunks (small launches: more workgroups per output tile).
+// over 2 / 4 workgroups that store partial tiles, then a reduction kernel
+// (needs a GemmSplitWs large enough; otherwise GEMM_MFMA64).
+// GEMM_MFMA32S2 / S4 / S8: the same split over 32x32 tiles, 32-deep chunks
+// (short launches with long k: more workgroups per output tile);
+// GEMM_MFMA64S8, GEMM_MFMA32X64S4 / S8: 64x64 and 32 x 64 tiles split 8 / 4 / 8
+// ways.
 enum GemmKernel { GEMM_GEMV = 0, GEMM_TILED = 1, GEMM_MFMA32 = 2, GEMM_MFMA64 = 3,
                   GEMM_MFMA32K16 = 4, GEMM_MFMA32D = 5, GEMM_MFMA64D = 6,
                   GEMM_MFMA32X64 = 7, GEMM_MFMA64X32 = 8, GEMM_MFMA64S2 = 9,
-                  GEMM_MFMA64S4 = 10, GEMM_MFMA32S2 = 11, GEMM_MFMA32S4 = 12 };
+                  GEMM_MFMA64S4 = 10, GEMM_MFMA32S2 = 11, GEMM_MFMA32S4 = 12,
+                  GEMM_MFMA32S8 = 13, GEMM_MFMA64S8 = 14, GEMM_MFMA32X64S4 = 15,
+                  GEMM_MFMA32X64S8 = 16 };
 
 GemmKernel gemm_kernel(int ntasks, int max_m, int B);
 const char* gemm_kernel_name(GemmKernel k);
@@ -290,16 +304,23 @@ inline int cs_nb_cap(int B) {
 }
 
 // and the value used for a launch of `ncells` cells whose largest padded
-// height is `hlp`.  With few cells, 16 columns instead of 32 doubles the
-// workgroups and halves each one's sequential work; cells taller than 128
-// rows keep 16 columns (two row tiles per wave leave no registers for 32).
+// height is `hlp` (elements of `elem` bytes).  With few cells, 16 columns
+// instead of 32 doubles the workgroups and halves each one's sequential work;
+// cells taller than 160 rows keep 16 columns (two row tiles per wave leave no
+// registers for 32), and so do FP64 cells taller than 128 rows (the ten-wave
+// kernel has 170 registers per lane).
 // HZ_CELL_NB overrides the choice (1, 2, 4, 16 or 32; clamped to the cap).
-inline int cs_nb(int B, int ncells, int hlp) {
+inline int cs_nb_max(int hlp, int elem) {
+    return (hlp > 160 || (elem > 8 && hlp > 128)) ? 16 : 32;
+}
+inline int cs_nb(int B, int ncells, int hlp, int elem) {
     int nb = cs_nb_cap(B);
-    if (nb == 32 && ((long long)ncells * ((B + 31) / 32) < 512 || hlp > 128)) nb = 16;
+    if (nb == 32 && ((long long)ncells * ((B + 31) / 32) < 512 || cs_nb_max(hlp, elem) < 32))
+        nb = 16;
     if (const char* e = std::getenv("HZ_CELL_NB")) {
         const int o = std::atoi(e);
-        if (o == 1 || o == 2 || o == 4 || o == 16 || o == 32) nb = std::min(o, cs_nb_cap(B));
+        if (o == 1 || o == 2 || o == 4 || o == 16 || o == 32)
+            nb = std::min(std::min(o, cs_nb_cap(B)), cs_nb_max(hlp, elem));
     }
     return nb;
 }

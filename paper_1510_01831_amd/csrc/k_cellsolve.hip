@@ -395,17 +395,17 @@ __global__ void __launch_bounds__(CS_THREADS) k_cs_gemv(CellSolveArgs<T> a) {
 }
 
 // ===========================================================================
-// NB in {16, 32}: block products on the matrix cores, 8 waves per workgroup.
-// Wave w owns the 16-row tiles w and w + 8 (MC of them, a per-wave constant
-// chosen once by a wave-uniform switch).  The A operand (factor tile) streams
+// NB in {16, 32}: block products on the matrix cores, NW waves per workgroup
+// (8; 10 for cells of 129-160 rows, so that each wave owns one of their ten
+// row tiles).  Wave w owns the 16-row tiles w and w + NW (MC of them, a
+// per-wave constant chosen once by a wave-uniform switch).  The A operand (factor tile) streams
 // from global memory in MFMA order with a two-group register double buffer;
 // the B operand (current column block) is read from LDS.  The elementwise
 // updates y = b - e o t run on the accumulators in registers: each lane keeps
 // its own entries, so the forward iterates go to a lane-private, coalesced
 // scratch and the sources and scratch reads of the next step are issued
 // before the block product that they wait for.
-constexpr int CS_MF_THREADS = 512;
-constexpr int CS_MF_WAVES = CS_MF_THREADS / 64;
+constexpr int CS_MF_WAVES = 8;        // waves of the default instance
 #ifndef CS_U1
 #define CS_U1 4
 #endif
@@ -426,13 +426,15 @@ __device__ inline int probe_col(const CellDesc& cd, int p, int probe) {
     return cd.own_c0 + (probe - cd.ncol) % cd.s;
 }
 
-template <typename T, int NB, int MODE, int MC>
+template <typename T, int NB, int MODE, int MC, int NW>
 __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const CellDesc& cd,
                                              const LayerDesc& ld, C2<T>* vs, double2* izs,
-                                             double2* ixs, int b0) {
+                                             double2* ixs, int b0, long long slot) {
     constexpr int NCT = NB / 16;
     constexpr int MCA = MC > 0 ? MC : 1;
-    constexpr int U = MC > 1 ? CS_U2 : CS_U1; // k steps per register group
+    // k steps per register group (fewer with ten waves: three waves per SIMD
+    // leave 170 registers per lane)
+    constexpr int U = NW > CS_MF_WAVES ? 2 : (MC > 1 ? CS_U2 : CS_U1);
     const int HL = cd.HL, HLp = cd.HLp, Wc = cd.Wc;
     const int KS = HLp >> 2;                  // multiple of 4
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -441,12 +443,12 @@ __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const Ce
     const long long nq = (long long)HLp * NB;
     const C2<T>* __restrict__ Xf = a.X + cd.off_X;
     const C2<T>* __restrict__ ee = a.coef_e + cd.off_coef;
-    C2<T>* __restrict__ Y = a.Y + ((long long)blockIdx.x * gridDim.y + blockIdx.y) * a.y_stride;
+    C2<T>* __restrict__ Y = a.Y + slot * a.y_stride;
     const C2<T> z = mk<T>((T)0, (T)0);
 
-    auto row_of = [&](int m, int v) { return (w + CS_MF_WAVES * m) * 16 + Mf<T>::row(lane, v); };
+    auto row_of = [&](int m, int v) { return (w + NW * m) * 16 + Mf<T>::row(lane, v); };
     auto yidx = [&](int m, int t, int v) {
-        return ((long long)((w + CS_MF_WAVES * m) * NCT + t) * 4 + v) * 64 + lane;
+        return ((long long)((w + NW * m) * NCT + t) * 4 + v) * 64 + lane;
     };
     auto bval = [&](int c) {
         const int b = b0 + c;
@@ -463,7 +465,7 @@ __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const Ce
             const C2<T>* xp[MC];
 #pragma unroll
             for (int m = 0; m < MC; ++m)
-                xp[m] = Xk + (((long long)(w + CS_MF_WAVES * m) * KS) << 6) + lane;
+                xp[m] = Xk + (((long long)(w + NW * m) * KS) << 6) + lane;
             C2<T> xa[U][MC], xb[U][MC];
             auto load = [&](C2<T> (&dst)[U][MC], int s0) {
 #pragma unroll
@@ -498,7 +500,7 @@ __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const Ce
     // per-workgroup source constants
     {
         const double ih2 = 1.0 / (a.h * a.h);
-        for (int j = threadIdx.x; j < HLp; j += CS_MF_THREADS) {
+        for (int j = threadIdx.x; j < HLp; j += NW * 64) {
             double2 v = make_double2(0.0, 0.0);
             if (j < HL) {
                 const double2 iz = cinv(a.alpha_z[(long long)cd.layer * a.HLmax + j]);
@@ -506,7 +508,7 @@ __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const Ce
             }
             izs[j] = v;
         }
-        for (int k = threadIdx.x; k < Wc; k += CS_MF_THREADS) {
+        for (int k = threadIdx.x; k < Wc; k += NW * 64) {
             const double2 ix = cinv(a.alpha_x[(long long)cd.gidx * a.Wcmax + k]);
             ixs[k] = make_double2(ix.x * ih2, ix.y * ih2);
         }
@@ -608,41 +610,48 @@ __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const Ce
     }
 }
 
-// MCMAX = 1 serves cells of up to 8 row tiles (HLp <= 128) with fewer
-// registers; MCMAX = 2 serves up to 16.
-template <typename T, int NB, int MODE, int MCMAX>
-__global__ void __launch_bounds__(CS_MF_THREADS) k_cs_mfma(CellSolveArgs<T> a) {
+// MCMAX = 1 serves cells of up to NW row tiles with fewer registers;
+// MCMAX = 2 serves up to 2 NW.
+template <typename T, int NB, int MODE, int MCMAX, int NW>
+__global__ void __launch_bounds__(NW * 64) k_cs_mfma(CellSolveArgs<T> a) {
     extern __shared__ __align__(16) unsigned char cs_lds[];
     C2<T>* vs = reinterpret_cast<C2<T>*>(cs_lds);
     const int hlp_max = (a.HLmax + 15) / 16 * 16;
     double2* izs = reinterpret_cast<double2*>(cs_lds + (size_t)hlp_max * NB * sizeof(C2<T>));
     double2* ixs = izs + hlp_max;
-    const int gc = a.cell_list[blockIdx.x];
+    // 1-D grid over (cell, batch chunk), chunks fastest, in XCD-contiguous
+    // order: the chunks of a cell stream the same factor blocks through one
+    // XCD's L2 at about the same time
+    const int chunks = (a.B + NB - 1) / NB;
+    const int item = xcd_tile(blockIdx.x, (int)gridDim.x);
+    const int ci = item / chunks, ch = item - ci * chunks;
+    const int gc = a.cell_list[ci];
     const CellDesc cd = a.cells[gc];
     const LayerDesc& ld = a.layers[cd.layer];
-    const int b0 = blockIdx.y * NB;
+    const int b0 = ch * NB;
     if (MODE == SOLVE_PROBE && a.probe0 + b0 >= cd.R) return;   // whole workgroup
+    const long long slot = (long long)ci * chunks + ch;
     const int RT = cd.HLp >> 4;
     const int w = threadIdx.x >> 6;
-    // tiles w and w + 8 (HLp <= 224 gives at most 14 tiles)
-    const int mc = RT > w ? (RT - w + CS_MF_WAVES - 1) / CS_MF_WAVES : 0;
+    // tiles w and w + NW (HLp <= 224 gives at most 14 tiles)
+    const int mc = RT > w ? (RT - w + NW - 1) / NW : 0;
     // every branch passes the same sequence of barriers
-    if (mc == 0) cs_mfma_body<T, NB, MODE, 0>(a, cd, ld, vs, izs, ixs, b0);
-    else if (MCMAX == 1 || mc == 1) cs_mfma_body<T, NB, MODE, 1>(a, cd, ld, vs, izs, ixs, b0);
-    else cs_mfma_body<T, NB, MODE, MCMAX>(a, cd, ld, vs, izs, ixs, b0);
+    if (mc == 0) cs_mfma_body<T, NB, MODE, 0, NW>(a, cd, ld, vs, izs, ixs, b0, slot);
+    else if (MCMAX == 1 || mc == 1) cs_mfma_body<T, NB, MODE, 1, NW>(a, cd, ld, vs, izs, ixs, b0, slot);
+    else cs_mfma_body<T, NB, MODE, MCMAX, NW>(a, cd, ld, vs, izs, ixs, b0, slot);
 }
 
-template <typename T, int NB, int MODE, int MCMAX>
+template <typename T, int NB, int MODE, int MCMAX, int NW>
 void launch_cs_mfma_mc(const CellSolveArgs<T>& a, dim3 grid, size_t lds, hipStream_t st) {
     static bool attr = false;
     if (!attr) {
         // if the device refuses, a launch needing more LDS fails and is reported
-        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cs_mfma<T, NB, MODE, MCMAX>),
+        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cs_mfma<T, NB, MODE, MCMAX, NW>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
             (void)hipGetLastError();
         attr = true;
     }
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cs_mfma<T, NB, MODE, MCMAX>), grid, dim3(CS_MF_THREADS),
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cs_mfma<T, NB, MODE, MCMAX, NW>), grid, dim3(NW * 64),
                        lds, st, a);
 }
 
@@ -651,8 +660,9 @@ void launch_cs_mfma(const CellSolveArgs<T>& a, dim3 grid, hipStream_t st) {
     const int hlp = (a.HLmax + 15) / 16 * 16;     // largest HLp of any cell
     // column block, then the row and column PML scalings
     const size_t lds = (size_t)hlp * NB * sizeof(C2<T>) + (size_t)(hlp + a.Wcmax) * sizeof(double2);
-    if (hlp <= 16 * CS_MF_WAVES) launch_cs_mfma_mc<T, NB, MODE, 1>(a, grid, lds, st);
-    else launch_cs_mfma_mc<T, NB, MODE, 2>(a, grid, lds, st);
+    if (hlp <= 16 * CS_MF_WAVES) launch_cs_mfma_mc<T, NB, MODE, 1, CS_MF_WAVES>(a, grid, lds, st);
+    else if (hlp <= 160) launch_cs_mfma_mc<T, NB, MODE, 1, 10>(a, grid, lds, st);
+    else launch_cs_mfma_mc<T, NB, MODE, 2, CS_MF_WAVES>(a, grid, lds, st);
 }
 
 template <typename T, int MODE>
@@ -660,12 +670,13 @@ void launch_mode(const CellSolveArgs<T>& a, int ncells, hipStream_t st) {
     const int nb = a.nb > 0 ? a.nb : cs_nb_cap(a.B);
     const int chunks = (a.B + nb - 1) / nb;
     dim3 grid(ncells, chunks), blk(CS_THREADS);
+    const dim3 grid1((unsigned)(ncells * chunks));      // matrix-core kernels: 1-D
     switch (nb) {
     case 1: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cs_gemv<T, 1, MODE>), grid, blk, 0, st, a); break;
     case 2: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cs_gemv<T, 2, MODE>), grid, blk, 0, st, a); break;
     case 4: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cs_gemv<T, 4, MODE>), grid, blk, 0, st, a); break;
-    case 16: launch_cs_mfma<T, 16, MODE>(a, grid, st); break;
-    default: launch_cs_mfma<T, 32, MODE>(a, grid, st); break;
+    case 16: launch_cs_mfma<T, 16, MODE>(a, grid1, st); break;
+    default: launch_cs_mfma<T, 32, MODE>(a, grid1, st); break;
     }
 }
 

@@ -228,15 +228,10 @@ __device__ __forceinline__ void next_chunk(const GemmTask<T>& t, int& sg, int& k
 
 // OFFLINE selects a separate instantiation (same code) for the factorisation
 // stage, so per-kernel profiles of the solve phase hold only solve launches.
-// Tile order: workgroup slot L runs on XCD L mod 8 (round-robin dispatch), so
-// each XCD is given one contiguous run of the (task, row tile, column tile)
-// sequence, column tiles fastest: the workgroups that share a row block of A
-// and a task's x run together and read them once into that XCD's L2.
-__device__ __forceinline__ int xcd_tile(int L, int total) {
-    const int xcd = L & 7, local = L >> 3;
-    const int q = total >> 3, r = total & 7;
-    return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + local;
-}
+// Tile order (xcd_tile): each XCD is given one contiguous run of the (task,
+// row tile, column tile) sequence, column tiles fastest: the workgroups that
+// share a row block of A and a task's x run together and read them once into
+// that XCD's L2.
 
 // DEEP: two register stages, so the loads of chunk c+2 are issued while chunk
 // c is multiplied and chunk c+1 waits in registers (two chunk periods to hide
@@ -244,14 +239,14 @@ __device__ __forceinline__ int xcd_tile(int L, int total) {
 //
 // splits > 1 (split k, non-DEEP only): the splits workgroups of an output
 // tile (adjacent slots, hence one XCD) each take a contiguous share of the
-// tile's k chunks and store their accumulators to ws; the last to finish
-// (per-tile counter) adds the shares in index order -- the same sum whichever
-// finishes last -- applies the epilogue and resets the counter to zero for
-// the next launch.
+// tile's k chunks and store their raw accumulators to ws; a second kernel
+// (k_gemm_split_reduce) adds the shares in index order and applies the
+// epilogue.  The kernel boundary orders the two passes, so no workgroup
+// waits on another and no fence is needed.
 template <typename T, int MT, int TBM, int KC, bool OFFLINE, bool DEEP = false>
 __global__ void __launch_bounds__(GV_THREADS, 2)
 k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col_tiles,
-            int splits, C2<T>* __restrict__ ws, int* __restrict__ counters) {
+            int splits, C2<T>* __restrict__ ws) {
     constexpr int RTW = MT / 32;                 // row tiles per wave
     constexpr int CTW = TBM / 32;                // column tiles per wave
     const int per_task = row_tiles * col_tiles * splits;
@@ -375,31 +370,6 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
                     gstore<T>(mine + (a * CTW + c) * 4 + v, mk<T>(acc[a][c].re(v), acc[a][c].im(v)));
-        __threadfence();
-        __syncthreads();
-        __shared__ int s_last;
-        if (tid == 0) s_last = atomicAdd(&counters[tile_id], 1) == splits - 1;
-        __syncthreads();
-        if (!s_last) return;
-        __threadfence();
-#pragma unroll
-        for (int a = 0; a < RTW; ++a)
-#pragma unroll
-            for (int c = 0; c < CTW; ++c)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int e = (a * CTW + c) * 4 + v;
-                    C2<T> sum = mk<T>((T)0, (T)0);
-                    for (int q = 0; q < splits; ++q) {
-                        const C2<T> y = q == sp ? mk<T>(acc[a][c].re(v), acc[a][c].im(v))
-                                                : gload<T>(ws + ((tile_id * splits + q) * GV_THREADS + tid) * NV + e);
-                        sum = cadd(sum, y);
-                    }
-                    const int i = i0 + wr + a * 16 + Mf<T>::row(lane, v);
-                    const int b = b0 + wc + c * 16 + lc;
-                    if (i < t.m && b < B) epilogue<T>(t, i, b, sum);
-                }
-        if (tid == 0) counters[tile_id] = 0;
         return;
     }
 #pragma unroll
@@ -411,6 +381,46 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
                 const int i = i0 + wr + a * 16 + Mf<T>::row(lane, v);
                 const int b = b0 + wc + c * 16 + lc;
                 if (i < t.m && b < B) epilogue<T>(t, i, b, mk<T>(acc[a][c].re(v), acc[a][c].im(v)));
+            }
+}
+
+// Second pass of split k: one workgroup per output tile; thread tid adds, in
+// split order, the partial accumulators that thread tid of each split
+// workgroup stored (same register-to-element map as k_gemm_mfma) and applies
+// the task's epilogue.
+template <typename T, int MT, int TBM>
+__global__ void __launch_bounds__(GV_THREADS)
+k_gemm_split_reduce(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col_tiles,
+                    int splits, const C2<T>* __restrict__ ws) {
+    constexpr int RTW = MT / 32, CTW = TBM / 32, NV = RTW * CTW * 4;
+    const int per_task = row_tiles * col_tiles;
+    const int tile = blockIdx.x;
+    const int task = tile / per_task, rc = tile - task * per_task;
+    const int rt = rc / col_tiles, ct = rc - rt * col_tiles;
+    const GemmTask<T>& t = tasks[task];
+    const int i0 = rt * MT;
+    if (i0 >= t.m) return;
+    if (t.ncol > 0) B = t.ncol;
+    const int b0 = ct * TBM;
+    if (b0 >= B) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int lc = lane & 15;
+    const int wr = (w >> 1) * (MT / 2), wc = (w & 1) * (TBM / 2);
+    const C2<T>* base = ws + (long long)tile * splits * GV_THREADS * NV + (long long)tid * NV;
+#pragma unroll
+    for (int a = 0; a < RTW; ++a)
+#pragma unroll
+        for (int c = 0; c < CTW; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int e = (a * CTW + c) * 4 + v;
+                const int i = i0 + wr + a * 16 + Mf<T>::row(lane, v);
+                const int b = b0 + wc + c * 16 + lc;
+                if (i >= t.m || b >= B) continue;
+                C2<T> sum = gload<T>(base + e);
+                for (int q = 1; q < splits; ++q)
+                    sum = cadd(sum, gload<T>(base + (long long)q * GV_THREADS * NV + e));
+                epilogue<T>(t, i, b, sum);
             }
 }
 
@@ -452,6 +462,10 @@ const char* gemm_kernel_name(GemmKernel k) {
     case GEMM_MFMA64S4: return "gemm_mfma64s4";
     case GEMM_MFMA32S2: return "gemm_mfma32s2";
     case GEMM_MFMA32S4: return "gemm_mfma32s4";
+    case GEMM_MFMA32S8: return "gemm_mfma32s8";
+    case GEMM_MFMA64S8: return "gemm_mfma64s8";
+    case GEMM_MFMA32X64S4: return "gemm_mfma32x64s4";
+    case GEMM_MFMA32X64S8: return "gemm_mfma32x64s8";
     default: return "gemm_mfma32";
     }
 }
@@ -459,31 +473,46 @@ const char* gemm_kernel_name(GemmKernel k) {
 template <typename T, bool OFFLINE>
 void launch_gemm_mfma(GemmKernel kind, const GemmTask<T>* tasks_dev, int ntasks, int max_m, int B,
                       hipStream_t st, const GemmSplitWs* sw) {
-    if (kind == GEMM_MFMA64S2 || kind == GEMM_MFMA64S4) {
-        const int splits = kind == GEMM_MFMA64S2 ? 2 : 4;
-        const int rt = (max_m + 63) / 64, ct = (B + 63) / 64;
-        const long long tiles = (long long)rt * ct * ntasks;
-        const long long need = tiles * splits * GV_THREADS * 16 * (long long)sizeof(C2<T>);
-        if (sw && sw->ws && sw->counters && need <= sw->ws_bytes && tiles <= sw->ncounters) {
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 64, 64, 16, OFFLINE>),
-                               dim3(tiles * splits), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct,
-                               splits, (C2<T>*)sw->ws, sw->counters);
-            return;
-        }
-        kind = GEMM_MFMA64;                         // no room: the unsplit kernel
+    // split k: pass 1 stores each workgroup's partial tile, pass 2 adds them
+    int splits = 0, mt = 0, tbm = 0;
+    switch (kind) {
+    case GEMM_MFMA64S2: splits = 2; mt = 64; tbm = 64; break;
+    case GEMM_MFMA64S4: splits = 4; mt = 64; tbm = 64; break;
+    case GEMM_MFMA64S8: splits = 8; mt = 64; tbm = 64; break;
+    case GEMM_MFMA32S2: splits = 2; mt = 32; tbm = 32; break;
+    case GEMM_MFMA32S4: splits = 4; mt = 32; tbm = 32; break;
+    case GEMM_MFMA32S8: splits = 8; mt = 32; tbm = 32; break;
+    case GEMM_MFMA32X64S4: splits = 4; mt = 32; tbm = 64; break;
+    case GEMM_MFMA32X64S8: splits = 8; mt = 32; tbm = 64; break;
+    default: break;
     }
-    if (kind == GEMM_MFMA32S2 || kind == GEMM_MFMA32S4) {
-        const int splits = kind == GEMM_MFMA32S2 ? 2 : 4;
-        const int rt = (max_m + 31) / 32, ct = (B + 31) / 32;
+    if (splits > 0) {
+        const int rt = (max_m + mt - 1) / mt, ct = (B + tbm - 1) / tbm;
         const long long tiles = (long long)rt * ct * ntasks;
-        const long long need = tiles * splits * GV_THREADS * 4 * (long long)sizeof(C2<T>);
-        if (sw && sw->ws && sw->counters && need <= sw->ws_bytes && tiles <= sw->ncounters) {
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 32, OFFLINE>),
-                               dim3(tiles * splits), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct,
-                               splits, (C2<T>*)sw->ws, sw->counters);
+        const long long need = tiles * splits * (long long)mt * tbm * (long long)sizeof(C2<T>);
+        if (sw && sw->ws && need <= sw->ws_bytes) {
+            C2<T>* ws = (C2<T>*)sw->ws;
+            const dim3 g1((unsigned)(tiles * splits)), g2((unsigned)tiles), blk(GV_THREADS);
+            if (mt == 64) {
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 64, 64, 16, OFFLINE>), g1, blk, 0,
+                                   st, tasks_dev, B, rt, ct, splits, ws);
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_split_reduce<T, 64, 64>), g2, blk, 0, st,
+                                   tasks_dev, B, rt, ct, splits, (const C2<T>*)ws);
+            } else if (tbm == 64) {
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 64, 32, OFFLINE>), g1, blk, 0,
+                                   st, tasks_dev, B, rt, ct, splits, ws);
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_split_reduce<T, 32, 64>), g2, blk, 0, st,
+                                   tasks_dev, B, rt, ct, splits, (const C2<T>*)ws);
+            } else {
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 32, OFFLINE>), g1, blk, 0,
+                                   st, tasks_dev, B, rt, ct, splits, ws);
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_split_reduce<T, 32, 32>), g2, blk, 0, st,
+                                   tasks_dev, B, rt, ct, splits, (const C2<T>*)ws);
+            }
             return;
         }
-        kind = GEMM_MFMA32;                         // no room: the unsplit kernel
+        // no room for the partial tiles: the unsplit kernel of the same tile
+        kind = mt == 64 ? GEMM_MFMA64 : tbm == 64 ? GEMM_MFMA32X64 : GEMM_MFMA32;
     }
     // big launches: 64 x 64 tiles; otherwise 32 x 32 tiles with deeper
     // chunks, which keep more workgroups busy and fewer chunks in flight
@@ -491,38 +520,38 @@ void launch_gemm_mfma(GemmKernel kind, const GemmTask<T>* tasks_dev, int ntasks,
         const int rt = (max_m + 63) / 64, ct = (B + 63) / 64;
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 64, 64, 16, OFFLINE>),
                            dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct, 1,
-                           (C2<T>*)nullptr, (int*)nullptr);
+                           (C2<T>*)nullptr);
     } else if (kind == GEMM_MFMA32K16) {
         const int rt = (max_m + 31) / 32, ct = (B + 31) / 32;
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 16, OFFLINE>),
                            dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct, 1,
-                           (C2<T>*)nullptr, (int*)nullptr);
+                           (C2<T>*)nullptr);
     } else if (kind == GEMM_MFMA32X64) {
         const int rt = (max_m + 31) / 32, ct = (B + 63) / 64;
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 64, 32, OFFLINE>),
                            dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct, 1,
-                           (C2<T>*)nullptr, (int*)nullptr);
+                           (C2<T>*)nullptr);
     } else if (kind == GEMM_MFMA64X32) {
         const int rt = (max_m + 63) / 64, ct = (B + 31) / 32;
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 64, 32, 32, OFFLINE>),
                            dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct, 1,
-                           (C2<T>*)nullptr, (int*)nullptr);
+                           (C2<T>*)nullptr);
     } else if (kind == GEMM_MFMA32D) {
         const int rt = (max_m + 31) / 32, ct = (B + 31) / 32;
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 32, OFFLINE, true>),
                            dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct, 1,
-                           (C2<T>*)nullptr, (int*)nullptr);
+                           (C2<T>*)nullptr);
     } else if (kind == GEMM_MFMA64D) {
         const int rt = (max_m + 63) / 64, ct = (B + 63) / 64;
         constexpr int KCD = sizeof(T) == 4 ? 32 : 16;
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 64, 64, KCD, OFFLINE, true>),
                            dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct, 1,
-                           (C2<T>*)nullptr, (int*)nullptr);
+                           (C2<T>*)nullptr);
     } else {
         const int rt = (max_m + 31) / 32, ct = (B + 31) / 32;
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 32, OFFLINE>),
                            dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct, 1,
-                           (C2<T>*)nullptr, (int*)nullptr);
+                           (C2<T>*)nullptr);
     }
 }
 
