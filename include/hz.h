@@ -52,7 +52,8 @@
  *                    and the partial tiles added by a second kernel;
  *                    11 / 12 / 13: the same split over 2 / 4 / 8
  *                    workgroups of 32x32 tiles; 14: 64x64 split 8 ways;
- *                    15 / 16: 32 x 64 split 4 / 8 ways), no tuning;
+ *                    15 / 16: 32 x 64 split 4 / 8 ways; 17 / 18: kind
+ *                    5 split 4 / 8 ways), no tuning;
  *      HZ_COMPOSE=0  inner SIE solved by block LU substitutions at every layer
  *                    application instead of the composed output operators;
  *      HZ_GRAPHS=0   plans launched kernel by kernel instead of replayed HIP
@@ -88,9 +89,11 @@ typedef enum {
                            complex128 (Sec. 5: a low-accuracy operator for the
                            preconditioner, a high-accuracy one for M) */
     HZ_MIXED_REFINE = 2 /* every local operator (cell factors, interface
-                           operators, sweeps) in complex64 as an approximate
-                           inverse, wrapped in FP64 iterative refinement on
-                           the volume: u += Hhat^{-1}(f - H u) */
+                           operators, sweeps) computed and applied in
+                           complex64 with FP32 accumulation (the offline
+                           stage too) as an approximate inverse, wrapped in
+                           FP64 iterative refinement on the volume:
+                           u += Hhat^{-1}(f - H u) */
 } hz_precision;
 
 typedef enum {
@@ -274,8 +277,7 @@ hz_status hz_update_model(hz_ctx* ctx, const double* model_dev);
  * operators changed (bitwise) get new Schur factors and interface operators,
  * and the inner SIE factors and composed operators are rebuilt for the
  * layers holding a changed cell.  The result equals that of
- * hz_update_model followed by hz_factor.  In the HZ_MIXED_REFINE form (whose
- * FP64 operators are not kept) every cell is refactored.
+ * hz_update_model followed by hz_factor (in every precision form).
  * ncells_refactored: host int, or NULL; receives the number of cells redone.
  * Errors: HZ_ESTATE if ctx is not factored; HZ_EINVAL for a bad model (NaN,
  * infinite or non-positive entries: checked first, ctx unchanged);

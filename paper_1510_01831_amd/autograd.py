@@ -25,19 +25,22 @@ class HelmholtzMisfit(torch.autograd.Function):
                            model_kind=hz.HZ_MODEL_SLOWNESS2, max_batch=B)
         u = solver.solve(f, tol=tol, max_iter=max_iter, ext=True)
         J, adj = solver.misfit(u, d_obs, rec_row)
-        ctx.solver = solver
-        ctx.tol, ctx.max_iter = tol, max_iter
-        ctx.save_for_backward(u, adj)
+        if ctx.needs_input_grad[0]:
+            # the factors serve the adjoint solve; the context lives as long as
+            # the graph node (a second backward with retain_graph=True reuses it)
+            ctx.solver = solver
+            ctx.tol, ctx.max_iter = tol, max_iter
+            ctx.save_for_backward(u, adj)
+        else:
+            solver.close()                 # forward only: free the device memory now
+            ctx.solver = None
         return torch.tensor(J, dtype=torch.float64, device=m.device)
 
     @staticmethod
     def backward(ctx, gJ):
         u, adj = ctx.saved_tensors
-        solver = ctx.solver
-        lam = solver.adjoint(adj, tol=ctx.tol, max_iter=ctx.max_iter, ext=True)
-        g = solver.misfit_gradient(u, lam)
-        solver.close()
-        ctx.solver = None
+        lam = ctx.solver.adjoint(adj, tol=ctx.tol, max_iter=ctx.max_iter, ext=True)
+        g = ctx.solver.misfit_gradient(u, lam)
         return (gJ * g.to(gJ.device), None, None, None, None, None, None, None, None, None)
 
 

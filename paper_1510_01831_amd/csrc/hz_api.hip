@@ -834,7 +834,8 @@ void tune_plan(hz_ctx* c, Plan<T>& pl, int B) {
                          (int)GEMM_MFMA32D, (int)GEMM_MFMA64D, (int)GEMM_MFMA32X64,
                          (int)GEMM_MFMA64X32, (int)GEMM_MFMA64S2, (int)GEMM_MFMA64S4,
                          (int)GEMM_MFMA32S2, (int)GEMM_MFMA32S4, (int)GEMM_MFMA32S8,
-                         (int)GEMM_MFMA64S8, (int)GEMM_MFMA32X64S4, (int)GEMM_MFMA32X64S8}) {
+                         (int)GEMM_MFMA64S8, (int)GEMM_MFMA32X64S4, (int)GEMM_MFMA32X64S8,
+                         (int)GEMM_MFMA32DS4, (int)GEMM_MFMA32DS8}) {
             if (cand == dflt && best < 1e30f) continue;
             if ((cand == GEMM_MFMA64 || cand == GEMM_MFMA64D || cand == GEMM_MFMA32X64 ||
                  cand == GEMM_MFMA64S2 || cand == GEMM_MFMA64S4 || cand == GEMM_MFMA64S8 ||
@@ -1627,11 +1628,11 @@ void cell_solve_launch(hz_ctx* c, CellSolveArgs<T> a, const std::vector<int>& li
         }
     };
     int nb = cs_nb(Bcols, (int)list.size(), c->d.HLpmax, (int)sizeof(C2<T>));
-    // Autotune the batch width once per (mode, batch, cells): both widths give
-    // the same results column by column, so the solve itself is timed with
-    // each and the last run's output is kept.
-    const bool tunable = c->tune && Bcols > 16 && cs_nb_max(c->d.HLpmax, (int)sizeof(C2<T>)) == 32 &&
-                         !std::getenv("HZ_CELL_NB") &&
+    // Autotune the batch width once per (mode, batch, cells): the solve itself
+    // is timed with each candidate and the chosen width's output is kept (the
+    // matrix-core widths give the same results column by column; the
+    // 4-column kernel differs from them by rounding).
+    const bool tunable = c->tune && Bcols > 16 && !std::getenv("HZ_CELL_NB") &&
                          (a.mode == SOLVE_SAMPLE || a.mode == SOLVE_VOLUME);
     if (tunable) {
         const std::string key = std::to_string(a.mode) + "|" + std::to_string(Bcols) + "|" +
@@ -1645,20 +1646,29 @@ void cell_solve_launch(hz_ctx* c, CellSolveArgs<T> a, const std::vector<int>& li
             HIPCHK(hipEventCreate(&e1));
             float best = 1e30f;
             int best_nb = nb;
-            for (int cand : {32, 16}) {
+            // 4 columns per workgroup (the matrix-vector kernel) only for
+            // launches of few workgroups: it reads the factors once per 4
+            // columns, but keeps more of them in flight per cell
+            const bool narrow = (long long)list.size() * ((Bcols + 15) / 16) < 256;
+            int last = 0;
+            for (int cand : {32, 16, 4}) {
+                if (cand == 32 && cs_nb_max(c->d.HLpmax, (int)sizeof(C2<T>)) < 32) continue;
+                if (cand == 4 && !narrow) continue;
                 HIPCHK(hipEventRecord(e0, c->st));
                 run(cand, false);
                 HIPCHK(hipEventRecord(e1, c->st));
                 HIPCHK(hipEventSynchronize(e1));
+                last = cand;
                 float ms = 0.f;
                 HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                // 32 (tried first) is kept unless 16 is more than 3% faster
+                // the earlier candidate is kept unless a later one is more
+                // than 3% faster
                 if (best == 1e30f || ms < 0.97f * best) { best = ms; best_nb = cand; }
             }
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
             c->cs_tuned[key] = best_nb;
-            if (best_nb == 16) return;           // the last run already wrote the result
+            if (best_nb == last) return;         // the last run already wrote the result
             nb = best_nb;
         }
     }
@@ -1685,18 +1695,19 @@ CellSolveArgs<T> base_args(hz_ctx* c) {
     return a;
 }
 
+template <typename T>
 __global__ void k_inner_diag(const LayerDesc* layers, const int* lays, const CellDesc* cells,
-                             const double2* CS, int j, double2* out, long long out_stride) {
+                             const C2<T>* CS, int j, C2<T>* out, long long out_stride) {
     const LayerDesc ld = layers[lays[blockIdx.y]];
     const int HL = ld.HL;
     const int n2 = 2 * HL;
     const CellDesc cl = cells[ld.cell_begin + j];        // left of interface j
     const CellDesc cr = cells[ld.cell_begin + j + 1];    // right of interface j
-    double2* o = out + (long long)blockIdx.y * out_stride;
+    C2<T>* o = out + (long long)blockIdx.y * out_stride;
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < (long long)n2 * n2;
          q += (long long)gridDim.x * blockDim.x) {
         const int r = (int)(q / n2), col = (int)(q % n2);
-        double2 v;
+        C2<T> v;
         if (r < HL) {       // row a: right-column samples of cell j, its right probes
             const int row = (cl.has_left ? HL : 0) + r;
             const int pc = (cl.has_left ? 2 * HL : 0) + col;
@@ -1705,16 +1716,17 @@ __global__ void k_inner_diag(const LayerDesc* layers, const int* lays, const Cel
             v = CS[cr.off_CS + (long long)(r - HL) * cr.R + col];
         }
         v.x = -v.x; v.y = -v.y;
-        if (r == col) v.x += 1.0;
+        if (r == col) v.x += (T)1;
         o[q] = v;
     }
 }
 
-__global__ void k_eye(double2* a, int n) {
+template <typename T>
+__global__ void k_eye(C2<T>* a, int n) {
     const long long nn = (long long)n * n;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nn;
          i += (long long)gridDim.x * blockDim.x)
-        a[i] = make_double2(i / n == i % n ? 1.0 : 0.0, 0.0);
+        a[i] = mk<T>(i / n == i % n ? (T)1 : (T)0, (T)0);
 }
 
 // Per cell: whether any of its local-operator coefficients (diagonal,
@@ -1759,10 +1771,11 @@ void run_jobs(hz_ctx* c, const std::vector<LayerJob<T>>& jobs, int B);
 // [inner rhs; pair] gives the same samples as solving the inner SIE and then
 // applying [Q_x | Q_u]; the inner solve is taken out of the sequential path.
 // S^{-1} itself is the inner block LU applied to the identity.
+template <typename T>
 void build_composed(hz_ctx* c, const std::vector<char>& redo_layer) {
     const Dims& d = c->d;
     const int J = d.Lc - 1;
-    Ops<double>& o = c->o64;
+    Ops<T>& o = ops<T>(c);
     c->qc_off.assign((size_t)d.L * 2 * d.Lc, -1);
     c->qc_ld.assign((size_t)d.L * 2 * d.Lc, 0);
     long long tot = 0;
@@ -1781,27 +1794,27 @@ void build_composed(hz_ctx* c, const std::vector<char>& redo_layer) {
         }
     }
     c->Qc_elems = tot;
-    if (!o.Qc) o.Qc = alloc_c<double>(c, std::max<long long>(tot, 1));
+    if (!o.Qc) o.Qc = alloc_c<T>(c, std::max<long long>(tot, 1));
     const int NImax = J * 2 * d.HLmax;
     const long long nn = (long long)NImax * NImax;
-    double2* E = alloc_c<double>(c, nn);
-    double2* IY = alloc_c<double>(c, nn);
-    double2* IX = alloc_c<double>(c, nn);
-    GemmTask<double>* tdev = (GemmTask<double>*)c->arena.alloc(sizeof(GemmTask<double>) * 2 * d.Lc);
+    C2<T>* E = alloc_c<T>(c, nn);
+    C2<T>* IY = alloc_c<T>(c, nn);
+    C2<T>* IX = alloc_c<T>(c, nn);
+    GemmTask<T>* tdev = (GemmTask<T>*)c->arena.alloc(sizeof(GemmTask<T>) * 2 * d.Lc);
     for (int l = 0; l < d.L; ++l) {
         if (!redo_layer[l]) continue;
         const LayerDesc& ld = c->layers[l];
         const int NI = J * 2 * ld.HL;
-        hipLaunchKernelGGL(k_eye, dim3(1024), dim3(256), 0, c->st, E, NI);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_eye<T>), dim3(1024), dim3(256), 0, c->st, E, NI);
         HIPCHK(hipGetLastError());
-        LayerJob<double> jb;
+        LayerJob<T> jb;
         jb.layer = l;
         jb.inner_add = E;                 // phase 1 without sources: iy = I
         jb.iy = IY;
         jb.ix = IX;                       // -> S^{-1}, [NI][NI]
         jb.phase3 = false;
-        run_jobs<double>(c, {jb}, NI);
-        std::vector<GemmTask<double>> tasks;
+        run_jobs<T>(c, {jb}, NI);
+        std::vector<GemmTask<T>> tasks;
         int maxm = 0;
         for (int side = 0; side < 2; ++side) {
             const int so_a = ld.slot_of[side == 0 ? 0 : 2];
@@ -1810,9 +1823,9 @@ void build_composed(hz_ctx* c, const std::vector<char>& redo_layer) {
                 const CellDesc& cd = c->cells[ld.cell_begin + k];
                 const size_t q = ((size_t)l * 2 + side) * d.Lc + k;
                 const int NC = c->qc_ld[q];
-                double2* dst = o.Qc + c->qc_off[q];
-                const double2* src = o.Q + cd.off_Q + (long long)so_a * cd.s * cd.R;
-                GemmTask<double> t = blank_task<double>();
+                C2<T>* dst = o.Qc + c->qc_off[q];
+                const C2<T>* src = o.Q + cd.off_Q + (long long)so_a * cd.s * cd.R;
+                GemmTask<T> t = blank_task<T>();
                 t.A = src;
                 t.lda = cd.R;
                 t.m = 2 * cd.s;
@@ -1840,22 +1853,22 @@ void build_composed(hz_ctx* c, const std::vector<char>& redo_layer) {
                 tasks.push_back(t);
                 maxm = std::max(maxm, t.m);
                 // Q_u: the interface-row-source columns, copied
-                HIPCHK(hipMemcpy2DAsync(dst + NI, sizeof(double2) * NC, src + cd.ncol,
-                                        sizeof(double2) * cd.R, sizeof(double2) * ld.nslot * cd.s,
+                HIPCHK(hipMemcpy2DAsync(dst + NI, sizeof(C2<T>) * NC, src + cd.ncol,
+                                        sizeof(C2<T>) * cd.R, sizeof(C2<T>) * ld.nslot * cd.s,
                                         2 * cd.s, hipMemcpyDeviceToDevice, c->st));
             }
         }
         if (!tasks.empty()) {
-            upload(c, tdev, tasks.data(), sizeof(GemmTask<double>) * tasks.size());
-            launch_gemm<double>(tdev, (int)tasks.size(), maxm, NI, c->st, true);
+            upload(c, tdev, tasks.data(), sizeof(GemmTask<T>) * tasks.size());
+            launch_gemm<T>(tdev, (int)tasks.size(), maxm, NI, c->st, true);
             HIPCHK(hipGetLastError());
         }
         sync(c);
     }
-    c->arena.release(E, sizeof(double2) * nn);
-    c->arena.release(IY, sizeof(double2) * nn);
-    c->arena.release(IX, sizeof(double2) * nn);
-    c->arena.release(tdev, sizeof(GemmTask<double>) * 2 * d.Lc);
+    c->arena.release(E, 0);
+    c->arena.release(IY, 0);
+    c->arena.release(IX, 0);
+    c->arena.release(tdev, 0);
 }
 
 template <typename T>
@@ -1874,8 +1887,12 @@ struct OfflineScope {              // marks launches as factorisation-stage laun
 
 // redo: per-cell flags of the cells to (re)factor; nullptr = every cell.
 // The inner SIE and the composed operators are rebuilt for the layers that
-// hold a redone cell.
-void factor_impl(hz_ctx* c, const std::vector<char>* redo = nullptr) {
+// hold a redone cell.  T is the precision of the whole offline stage:
+// complex128 (HZ_FP64, and HZ_MIXED, which then keeps complex64 copies) or
+// complex64 (HZ_MIXED_REFINE: factors, probes, inner LU and composed
+// operators computed in FP32, no FP64 operators at all).
+template <typename T>
+void factor_impl_t(hz_ctx* c, const std::vector<char>* redo) {
     OfflineScope scope(c);
     const Dims& d = c->d;
     const int ncells = (int)c->cells.size();
@@ -1884,16 +1901,23 @@ void factor_impl(hz_ctx* c, const std::vector<char>* redo = nullptr) {
         if (!redo || (*redo)[i]) todo.push_back(i);
     std::vector<char> redo_layer(d.L, 0);
     for (int i : todo) redo_layer[c->cells[i].layer] = 1;
-    Ops<double>& o = c->o64;
+    Ops<T>& o = ops<T>(c);
     if (!o.X) {
-        o.X = alloc_c<double>(c, c->X_elems);
-        o.Q = alloc_c<double>(c, std::max<long long>(c->Q_elems, 1));
-        o.CS = alloc_c<double>(c, std::max<long long>(c->CS_elems, 1));
-        o.Sinv = alloc_c<double>(c, std::max<long long>(c->Sinv_elems, 1));
-        o.Lfac = alloc_c<double>(c, std::max<long long>(c->Lfac_elems, 1));
-        if (c->inner_pt) o.CP = alloc_c<double>(c, std::max<long long>(c->CP_elems, 1));
+        o.X = alloc_c<T>(c, c->X_elems);
+        o.Q = alloc_c<T>(c, std::max<long long>(c->Q_elems, 1));
+        o.CS = alloc_c<T>(c, std::max<long long>(c->CS_elems, 1));
+        o.Sinv = alloc_c<T>(c, std::max<long long>(c->Sinv_elems, 1));
+        o.Lfac = alloc_c<T>(c, std::max<long long>(c->Lfac_elems, 1));
+        if (c->inner_pt) o.CP = alloc_c<T>(c, std::max<long long>(c->CP_elems, 1));
     }
-    o.e = c->e;
+    if constexpr (sizeof(T) == sizeof(double)) {
+        o.e = (C2<T>*)c->e;
+    } else {            // the cell solves of the probes read complex64 couplings
+        if (!o.e) o.e = alloc_c<T>(c, std::max<long long>(c->coef_elems, 1));
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cast_pool<float>), dim3(4096), dim3(256), 0, c->st,
+                           (float2*)o.e, c->e, c->coef_elems);
+        HIPCHK(hipGetLastError());
+    }
     {
         FactorFlags ff0{0, 0, ~0ULL};
         upload(c, c->fflags, &ff0, sizeof(ff0));
@@ -1928,10 +1952,10 @@ void factor_impl(hz_ctx* c, const std::vector<char>* redo = nullptr) {
         upload(c, d_sel, sel.data(), sizeof(CellDesc) * nt);
         const long long ws = (long long)d.HLpmax * d.HLpmax;
         const int batch = std::min(nt, 1024);
-        double2* workbuf = (double2*)tmp.keep(alloc_c<double>(c, ws * batch));
+        C2<T>* workbuf = (C2<T>*)tmp.keep(alloc_c<T>(c, ws * batch));
         for (int c0 = 0; c0 < nt; c0 += batch) {
             const int cnt = std::min(batch, nt - c0);
-            launch_cell_factor<double>(d_sel + c0, cnt, d, c->diag, c->cz, c->e, o.X,
+            launch_cell_factor<T>(d_sel + c0, cnt, d, c->diag, c->cz, c->e, o.X,
                                        workbuf, ws, c->fflags, c->st);
             HIPCHK(hipGetLastError());
         }
@@ -1942,7 +1966,7 @@ void factor_impl(hz_ctx* c, const std::vector<char>* redo = nullptr) {
     int Rmax = 0;
     for (auto& cd : c->cells) Rmax = std::max(Rmax, cd.R);
     if (Rmax > 0) {
-        const int nb = cs_nb(Rmax, ncells, d.HLpmax, (int)sizeof(double2));
+        const int nb = cs_nb(Rmax, ncells, d.HLpmax, (int)sizeof(C2<T>));
         const int chunks = (Rmax + nb - 1) / nb;
         const long long ystride = (long long)d.Wcmax * d.HLpmax * nb;
         // Forward-sweep scratch: a quarter of the free memory, between 4 and
@@ -1952,12 +1976,12 @@ void factor_impl(hz_ctx* c, const std::vector<char>* redo = nullptr) {
         size_t mfree = 0, mtot = 0;
         if (hipMemGetInfo(&mfree, &mtot) != hipSuccess) { (void)hipGetLastError(); mfree = 0; }
         const long long budget = std::min<long long>(24LL << 30, std::max<long long>(4LL << 30, (long long)(mfree / 4)));
-        long long budget_wgs = std::max<long long>(chunks, budget / (ystride * (long long)sizeof(double2)));
+        long long budget_wgs = std::max<long long>(chunks, budget / (ystride * (long long)sizeof(C2<T>)));
         const int per = (int)std::min<long long>(nt, std::max<long long>(1, budget_wgs / chunks));
-        double2* Y = (double2*)tmp.keep(alloc_c<double>(c, ystride * (long long)per * chunks));
+        C2<T>* Y = (C2<T>*)tmp.keep(alloc_c<T>(c, ystride * (long long)per * chunks));
         int* d_list = (int*)tmp.keep(c->arena.alloc(sizeof(int) * nt));
         upload(c, d_list, todo.data(), sizeof(int) * nt);
-        CellSolveArgs<double> a = base_args<double>(c);
+        CellSolveArgs<T> a = base_args<T>(c);
         a.mode = SOLVE_PROBE;
         a.Qpool = o.Q;
         a.CSpool = o.CS;
@@ -1970,7 +1994,7 @@ void factor_impl(hz_ctx* c, const std::vector<char>* redo = nullptr) {
         for (int g = 0; g < nt; g += per) {
             const int cnt = std::min(per, nt - g);
             a.cell_list = d_list + g;
-            launch_cell_solve<double>(a, cnt, chunks, c->st);
+            launch_cell_solve<T>(a, cnt, chunks, c->st);
             HIPCHK(hipGetLastError());
         }
         sync(c);
@@ -1986,30 +2010,30 @@ void factor_impl(hz_ctx* c, const std::vector<char>* redo = nullptr) {
         int* d_lay = (int*)tmp.keep(c->arena.alloc(sizeof(int) * L));
         upload(c, d_lay, lay.data(), sizeof(int) * L);
         const long long bs = 4LL * d.HLmax * d.HLmax;       // (2 HLmax)^2
-        double2* A = (double2*)tmp.keep(alloc_c<double>(c, bs * L));
-        double2* wk = (double2*)tmp.keep(alloc_c<double>(c, bs * L));
-        double2** mats = (double2**)tmp.keep(c->arena.alloc(sizeof(void*) * L));
-        double2** outs = (double2**)tmp.keep(c->arena.alloc(sizeof(void*) * L));
+        C2<T>* A = (C2<T>*)tmp.keep(alloc_c<T>(c, bs * L));
+        C2<T>* wk = (C2<T>*)tmp.keep(alloc_c<T>(c, bs * L));
+        C2<T>** mats = (C2<T>**)tmp.keep(c->arena.alloc(sizeof(void*) * L));
+        C2<T>** outs = (C2<T>**)tmp.keep(c->arena.alloc(sizeof(void*) * L));
         int* ns = (int*)tmp.keep(c->arena.alloc(sizeof(int) * L));
         std::vector<int> hn(L);
-        std::vector<double2*> hm(L), ho(L);
+        std::vector<C2<T>*> hm(L), ho(L);
         for (int i = 0; i < L; ++i) { hn[i] = 2 * c->layers[lay[i]].HL; hm[i] = A + bs * i; }
         upload(c, ns, hn.data(), sizeof(int) * L);
         upload(c, mats, hm.data(), sizeof(void*) * L);
-        GemmTask<double>* tdev = (GemmTask<double>*)tmp.keep(c->arena.alloc(sizeof(GemmTask<double>) * 2 * L));
+        GemmTask<T>* tdev = (GemmTask<T>*)tmp.keep(c->arena.alloc(sizeof(GemmTask<T>) * 2 * L));
         for (int j = 0; j < J; ++j) {
-            hipLaunchKernelGGL(k_inner_diag, dim3(64, L), dim3(256), 0, c->st, c->d_layers,
-                               d_lay, c->d_cells, o.CS, j, A, bs);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_inner_diag<T>), dim3(64, L), dim3(256), 0, c->st,
+                               c->d_layers, d_lay, c->d_cells, o.CS, j, A, bs);
             HIPCHK(hipGetLastError());
             if (j > 0) {
                 // L_j^a = B_j^a Sinv_{j-1},  B_j^a = -(right-column samples of cell j, left probes)
-                std::vector<GemmTask<double>> t1, t2;
+                std::vector<GemmTask<T>> t1, t2;
                 int mm = 0;
                 for (int i = 0; i < L; ++i) {
                     const LayerDesc& ld = c->layers[lay[i]];
                     const int HL = ld.HL;
                     const CellDesc& cj = c->cells[ld.cell_begin + j];
-                    GemmTask<double> t = blank_task<double>();
+                    GemmTask<T> t = blank_task<T>();
                     t.A = o.CS + cj.off_CS + (long long)HL * cj.R;    // right rows, left probes
                     t.lda = cj.R;
                     t.m = HL; t.k = 2 * HL;
@@ -2023,7 +2047,7 @@ void factor_impl(hz_ctx* c, const std::vector<char>* redo = nullptr) {
                     t1.push_back(t);
                     // S_j^a = A_j^a - L_j^a[:, b] C_{j-1}^b,  C_{j-1}^b = -(left-column samples
                     // of cell j, right probes)  ->  A_j^a + L_j^a[:, b] * samples
-                    GemmTask<double> u = blank_task<double>();
+                    GemmTask<T> u = blank_task<T>();
                     u.A = o.Lfac + ld.off_Lfac + (long long)(j - 1) * HL * 2 * HL + HL;
                     u.lda = 2 * HL;
                     u.m = HL; u.k = HL;
@@ -2038,12 +2062,12 @@ void factor_impl(hz_ctx* c, const std::vector<char>* redo = nullptr) {
                     t2.push_back(u);
                     mm = std::max(mm, 2 * HL);
                 }
-                upload(c, tdev, t1.data(), sizeof(GemmTask<double>) * L);
-                launch_gemm<double>(tdev, L, mm, 2 * d.HLmax, c->st, true);
+                upload(c, tdev, t1.data(), sizeof(GemmTask<T>) * L);
+                launch_gemm<T>(tdev, L, mm, 2 * d.HLmax, c->st, true);
                 HIPCHK(hipGetLastError());
                 sync(c);
-                upload(c, tdev + L, t2.data(), sizeof(GemmTask<double>) * L);
-                launch_gemm<double>(tdev + L, L, mm, 2 * d.HLmax, c->st, true);
+                upload(c, tdev + L, t2.data(), sizeof(GemmTask<T>) * L);
+                launch_gemm<T>(tdev + L, L, mm, 2 * d.HLmax, c->st, true);
                 HIPCHK(hipGetLastError());
                 sync(c);
             }
@@ -2053,16 +2077,17 @@ void factor_impl(hz_ctx* c, const std::vector<char>* redo = nullptr) {
             }
             upload(c, outs, ho.data(), sizeof(void*) * L);
             // inverse of an order-2HL block: pack with row stride 2HL (the A buffer is already)
-            launch_invert_batch<double>(mats, outs, ns, L, wk, bs, c->fflags, c->st);
+            launch_invert_batch<T>(mats, outs, ns, L, wk, bs, c->fflags, c->st);
             HIPCHK(hipGetLastError());
             sync(c);
         }
         check_pivots("inner block LU");
     }
     // 4. composed output operators
-    if (J > 0 && c->compose) build_composed(c, redo_layer);
-    // 5. mixed precision: complex64 copies of every operator
-    if (c->prm.precision != HZ_FP64) {
+    if (J > 0 && c->compose) build_composed<T>(c, redo_layer);
+    // 5. HZ_MIXED: complex64 copies of every operator for the preconditioner
+    if constexpr (sizeof(T) == sizeof(double)) {
+      if (c->prm.precision == HZ_MIXED) {
         Ops<float>& f = c->o32;
         auto cast = [&](float2*& dst, const double2* src, long long n) {
             if (!dst) dst = alloc_c<float>(c, std::max<long long>(n, 1));
@@ -2079,16 +2104,13 @@ void factor_impl(hz_ctx* c, const std::vector<char>* redo = nullptr) {
         if (o.Qc) cast(f.Qc, o.Qc, c->Qc_elems);
         HIPCHK(hipGetLastError());
         sync(c);
+      }
     }
-    if (c->prm.precision == HZ_MIXED_REFINE) {      // the FP64 operators are not used
-        c->arena.release(o.X, sizeof(double2) * c->X_elems);
-        c->arena.release(o.Q, sizeof(double2) * std::max<long long>(c->Q_elems, 1));
-        c->arena.release(o.CS, sizeof(double2) * std::max<long long>(c->CS_elems, 1));
-        c->arena.release(o.Sinv, sizeof(double2) * std::max<long long>(c->Sinv_elems, 1));
-        c->arena.release(o.Lfac, sizeof(double2) * std::max<long long>(c->Lfac_elems, 1));
-        if (o.Qc) c->arena.release(o.Qc, sizeof(double2) * std::max<long long>(c->Qc_elems, 1));
-        o = Ops<double>();
-    }
+}
+
+void factor_impl(hz_ctx* c, const std::vector<char>* redo = nullptr) {
+    if (c->prm.precision == HZ_MIXED_REFINE) factor_impl_t<float>(c, redo);
+    else factor_impl_t<double>(c, redo);
 }
 
 // ---------------------------------------------------------------------------
@@ -2969,7 +2991,7 @@ hz_status hz_setup(const double* model_dev, const hz_params* prm, hz_ctx** out) 
     if (const char* g = std::getenv("HZ_TUNE")) c->tune = std::atoi(g) != 0;
     if (const char* g = std::getenv("HZ_GEMM_KIND")) {
         const int k = std::atoi(g);
-        if (k >= GEMM_MFMA32 && k <= GEMM_MFMA32X64S8) c->force_kind = k;
+        if (k >= GEMM_MFMA32 && k <= GEMM_MFMA32DS8) c->force_kind = k;
     }
     if (c->prm.pml_beta <= 0.0) c->prm.pml_beta = 2.0;
     if (c->prm.max_batch <= 0) c->prm.max_batch = 1;
@@ -3067,11 +3089,7 @@ hz_status hz_update_model_local(hz_ctx* c, const double* model_dev, int* ncells_
     const int ncells = (int)c->cells.size();
     double t0 = now_s();
     std::vector<char> redo(ncells, 1);
-    if (c->prm.precision == HZ_MIXED_REFINE) {
-        // the FP64 operators of the unchanged cells were released: full factorisation
-        setup_coef(c, model_dev);
-        c->state = 1;
-    } else {
+    {
         const long long ne = c->coef_elems;
         const long long nax = (long long)ncells * d.Wcmax, naz = (long long)d.L * d.HLmax;
         double2* old = alloc_c<double>(c, 3 * ne + nax + naz);

@@ -280,13 +280,14 @@ void launch_gemm(const GemmTask<T>* tasks_dev, int ntasks, int max_m, int B, hip
 // GEMM_MFMA32S2 / S4 / S8: the same split over 32x32 tiles, 32-deep chunks
 // (short launches with long k: more workgroups per output tile);
 // GEMM_MFMA64S8, GEMM_MFMA32X64S4 / S8: 64x64 and 32 x 64 tiles split 8 / 4 / 8
-// ways.
+// ways; GEMM_MFMA32DS4 / DS8: 32x32 tiles with two chunks in flight, split
+// 4 / 8 ways.
 enum GemmKernel { GEMM_GEMV = 0, GEMM_TILED = 1, GEMM_MFMA32 = 2, GEMM_MFMA64 = 3,
                   GEMM_MFMA32K16 = 4, GEMM_MFMA32D = 5, GEMM_MFMA64D = 6,
                   GEMM_MFMA32X64 = 7, GEMM_MFMA64X32 = 8, GEMM_MFMA64S2 = 9,
                   GEMM_MFMA64S4 = 10, GEMM_MFMA32S2 = 11, GEMM_MFMA32S4 = 12,
                   GEMM_MFMA32S8 = 13, GEMM_MFMA64S8 = 14, GEMM_MFMA32X64S4 = 15,
-                  GEMM_MFMA32X64S8 = 16 };
+                  GEMM_MFMA32X64S8 = 16, GEMM_MFMA32DS4 = 17, GEMM_MFMA32DS8 = 18 };
 
 GemmKernel gemm_kernel(int ntasks, int max_m, int B);
 const char* gemm_kernel_name(GemmKernel k);

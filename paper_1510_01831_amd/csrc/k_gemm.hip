@@ -237,7 +237,7 @@ __device__ __forceinline__ void next_chunk(const GemmTask<T>& t, int& sg, int& k
 // c is multiplied and chunk c+1 waits in registers (two chunk periods to hide
 // the load latency instead of one).
 //
-// splits > 1 (split k, non-DEEP only): the splits workgroups of an output
+// splits > 1 (split k): the splits workgroups of an output
 // tile (adjacent slots, hence one XCD) each take a contiguous share of the
 // tile's k chunks and store their raw accumulators to ws; a second kernel
 // (k_gemm_split_reduce) adds the shares in index order and applies the
@@ -290,7 +290,7 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
     int sg = 0, kc = -KC;
     next_chunk<T, KC>(t, sg, kc);
     int left = 1 << 30;                          // chunks this workgroup takes
-    if (!DEEP && splits > 1) {
+    if (splits > 1) {
         int nch = 0;
         for (int q = 0; q < t.nseg; ++q)
             if (t.seg_ptr[q] && t.seg_len[q] > 0) nch += (t.seg_len[q] + KC - 1) / KC;
@@ -331,16 +331,24 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
         // being loaded into registers q; the two register stages swap roles
         // every chunk (loop unrolled by two so that they keep fixed names)
         GemmStage<T, MT, TBM, KC> p, q;
+        // chunk positions are produced in order; after `left` of them the
+        // workgroup's share of a split tile is done
+        int remaining = left - 1;
+        auto nxt = [&](int& s, int& k) {
+            if (remaining <= 0) { s = t.nseg; return; }
+            --remaining;
+            next_chunk<T, KC>(t, s, k);
+        };
         load(p, sg, kc);
         p.stash(As[0], Xs[0], tid);
         int s1 = sg, k1 = kc;
-        next_chunk<T, KC>(t, s1, k1);
+        nxt(s1, k1);
         if (s1 < t.nseg) load(p, s1, k1);
         __syncthreads();
         int buf = 0;
         while (true) {
             int s2 = s1, k2 = k1;
-            if (s1 < t.nseg) next_chunk<T, KC>(t, s2, k2);
+            if (s1 < t.nseg) nxt(s2, k2);
             if (s2 < t.nseg) load(q, s2, k2);
             multiply(buf);
             if (s1 >= t.nseg) break;
@@ -348,7 +356,7 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
             __syncthreads();
             buf ^= 1;
             int s3 = s2, k3 = k2;
-            if (s2 < t.nseg) next_chunk<T, KC>(t, s3, k3);
+            if (s2 < t.nseg) nxt(s3, k3);
             if (s3 < t.nseg) load(p, s3, k3);
             multiply(buf);
             if (s2 >= t.nseg) break;
@@ -359,7 +367,7 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
             k1 = k3;
         }
     }
-    if (!DEEP && splits > 1) {
+    if (splits > 1) {
         constexpr int NV = RTW * CTW * 4;
         const long long tile_id = ((long long)task * row_tiles + rt) * col_tiles + ct;
         C2<T>* mine = ws + ((tile_id * splits + sp) * GV_THREADS + tid) * NV;
@@ -466,6 +474,8 @@ const char* gemm_kernel_name(GemmKernel k) {
     case GEMM_MFMA64S8: return "gemm_mfma64s8";
     case GEMM_MFMA32X64S4: return "gemm_mfma32x64s4";
     case GEMM_MFMA32X64S8: return "gemm_mfma32x64s8";
+    case GEMM_MFMA32DS4: return "gemm_mfma32ds4";
+    case GEMM_MFMA32DS8: return "gemm_mfma32ds8";
     default: return "gemm_mfma32";
     }
 }
@@ -484,8 +494,11 @@ void launch_gemm_mfma(GemmKernel kind, const GemmTask<T>* tasks_dev, int ntasks,
     case GEMM_MFMA32S8: splits = 8; mt = 32; tbm = 32; break;
     case GEMM_MFMA32X64S4: splits = 4; mt = 32; tbm = 64; break;
     case GEMM_MFMA32X64S8: splits = 8; mt = 32; tbm = 64; break;
+    case GEMM_MFMA32DS4: splits = 4; mt = 32; tbm = 32; break;
+    case GEMM_MFMA32DS8: splits = 8; mt = 32; tbm = 32; break;
     default: break;
     }
+    const bool deep = kind == GEMM_MFMA32DS4 || kind == GEMM_MFMA32DS8;
     if (splits > 0) {
         const int rt = (max_m + mt - 1) / mt, ct = (B + tbm - 1) / tbm;
         const long long tiles = (long long)rt * ct * ntasks;
@@ -504,15 +517,19 @@ void launch_gemm_mfma(GemmKernel kind, const GemmTask<T>* tasks_dev, int ntasks,
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_split_reduce<T, 32, 64>), g2, blk, 0, st,
                                    tasks_dev, B, rt, ct, splits, (const C2<T>*)ws);
             } else {
-                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 32, OFFLINE>), g1, blk, 0,
-                                   st, tasks_dev, B, rt, ct, splits, ws);
+                if (deep)
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 32, OFFLINE, true>), g1,
+                                       blk, 0, st, tasks_dev, B, rt, ct, splits, ws);
+                else
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 32, OFFLINE>), g1, blk,
+                                       0, st, tasks_dev, B, rt, ct, splits, ws);
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_split_reduce<T, 32, 32>), g2, blk, 0, st,
                                    tasks_dev, B, rt, ct, splits, (const C2<T>*)ws);
             }
             return;
         }
         // no room for the partial tiles: the unsplit kernel of the same tile
-        kind = mt == 64 ? GEMM_MFMA64 : tbm == 64 ? GEMM_MFMA32X64 : GEMM_MFMA32;
+        kind = mt == 64 ? GEMM_MFMA64 : tbm == 64 ? GEMM_MFMA32X64 : deep ? GEMM_MFMA32D : GEMM_MFMA32;
     }
     // big launches: 64 x 64 tiles; otherwise 32 x 32 tiles with deeper
     // chunks, which keep more workgroups busy and fewer chunks in flight

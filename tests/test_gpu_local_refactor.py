@@ -67,7 +67,7 @@ def test_local_update_refine_form_and_errors():
     _log("[local] refine form, error paths")
     s = hz.Solver(torch.from_numpy(c0), omega, P, L, LC, precision=hz.HZ_MIXED_REFINE,
                   max_batch=1)
-    assert s.update_model_local(torch.from_numpy(c1)) == L * LC   # FP64 operators not kept
+    assert s.update_model_local(torch.from_numpy(c1)) == 2        # complex64 operators kept
     u = s.solve(f, tol=1e-8).cpu().numpy()
     sb = hz.Solver(torch.from_numpy(c1), omega, P, L, LC, precision=hz.HZ_MIXED_REFINE,
                    max_batch=1)

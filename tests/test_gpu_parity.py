@@ -210,7 +210,7 @@ def test_single_layer_and_cell_counts():
         assert _rel(u, ref) < 1e-9
 
 
-@pytest.mark.parametrize("kind", list(range(2, 17)))
+@pytest.mark.parametrize("kind", list(range(2, 19)))
 def test_every_gemm_kernel(kind, monkeypatch):
     """Every matrix-core GEMM variant the autotuner may pick, forced for all
     launches of the FP64 and the mixed form, against the sparse direct solve."""
