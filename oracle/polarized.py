@@ -67,12 +67,16 @@ class LayeredSolver:
     preconditioner) on top of a pluggable layer solver."""
 
     def __init__(self, prob: Problem, layers: int, cells: int | None = None,
-                 dtype=np.complex128, inner: str = "lu", inner_tol: float = 1e-6):
+                 dtype=np.complex128, inner: str = "lu", inner_tol: float = 1e-6,
+                 pre_plr_eps: float | None = None, pre_plr_tile: int = 64):
         """``dtype`` = complex64 gives the single-precision local solver used
         as the approximate inverse of the mixed-precision form.  ``inner``
         selects the inner solver of a nested layer: "lu" (block LU, Sec.
         4.2.2) or "pt" (nested polarized traces, Sec. 4.2.1, GMRES to
-        ``inner_tol``)."""
+        ``inner_tol``).  ``pre_plr_eps``: the preconditioner's Green's
+        integrals use the interface operators compressed in partitioned
+        low-rank form at that accuracy (oracle.plr), the SIE matrix the exact
+        ones (nested block-LU layers only)."""
         self.prob = prob
         self.L = layers
         self.parts = partition(prob.n, layers)
@@ -86,6 +90,11 @@ class LayeredSolver:
         else:
             from .nested import NestedLayerSolver
             self.solvers = [NestedLayerSolver(g, cells, dtype=dtype) for g in self.grids]
+        self.pre_solvers = None
+        if pre_plr_eps is not None:
+            from .plr import PLRLayerView
+            assert cells is not None and inner == "lu"
+            self.pre_solvers = [PLRLayerView(s, pre_plr_eps, pre_plr_tile) for s in self.solvers]
         self.W = prob.W
 
     # ------------------------------------------------------------------ rows
@@ -133,9 +142,10 @@ class LayeredSolver:
         return g
 
     # --------------------------------------------------- layer operator
-    def layer_op(self, l: int, top, bot, side: str) -> np.ndarray:
+    def layer_op(self, l: int, top, bot, side: str, pre: bool = False) -> np.ndarray:
         """R_side (H^l)^{-1}[T_l(top) + B_l(bot)], side in {'top', 'bot'};
-        ``top``/``bot`` may be None (absent)."""
+        ``top``/``bot`` may be None (absent).  ``pre``: inside the
+        preconditioner (compressed operators when the solver has them)."""
         G = self.grids[l]
         g = np.zeros((G.HL, self.W), dtype=complex)
         if top is not None:
@@ -143,7 +153,8 @@ class LayeredSolver:
         if bot is not None:
             g += self.src_B(l, bot)
         rows = self.interface_rows(l)
-        w_rows = self.solvers[l].interface_op(g[rows], rows)
+        solver = self.pre_solvers[l] if (pre and self.pre_solvers) else self.solvers[l]
+        w_rows = solver.interface_op(g[rows], rows)
         want = self.rows_top(l) if side == "top" else self.rows_bot(l)
         return np.stack([w_rows[rows.index(r)] for r in want])
 
@@ -189,7 +200,7 @@ class LayeredSolver:
         for k in range(self.L - 1):
             x[k] = v[k]
             if k > 0:
-                x[k] = x[k] + self.layer_op(k, x[k - 1], None, "bot")
+                x[k] = x[k] + self.layer_op(k, x[k - 1], None, "bot", pre=True)
         return x
 
     def sweep_up(self, v: np.ndarray) -> np.ndarray:
@@ -199,7 +210,7 @@ class LayeredSolver:
         for k in range(K - 1, -1, -1):
             x[k] = v[k]
             if k < K - 1:
-                x[k] = x[k] + self.layer_op(k + 1, None, x[k + 1], "top")
+                x[k] = x[k] + self.layer_op(k + 1, None, x[k + 1], "top", pre=True)
         return x
 
     def apply_Lrefl(self, d: np.ndarray) -> np.ndarray:
@@ -208,7 +219,7 @@ class LayeredSolver:
         K = self.L - 1
         out = np.zeros_like(d)
         for k in range(K):
-            out[k] = -self.layer_op(k + 1, d[k], d[k + 1] if k + 1 < K else None, "top")
+            out[k] = -self.layer_op(k + 1, d[k], d[k + 1] if k + 1 < K else None, "top", pre=True)
             out[k, 1] += d[k, 1]
         return out
 
