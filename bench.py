@@ -336,6 +336,7 @@ def golden_errors(u, golden):
 
 def run_workload(name, forms_wanted, steps, warmup, roctx_form="", want_local=False):
     """Time the forms of one workload; returns (forms, results, extras)."""
+    import numpy as np
     import torch
 
     from paper_1510_01831_amd import hz, media
@@ -374,6 +375,43 @@ def run_workload(name, forms_wanted, steps, warmup, roctx_form="", want_local=Fa
                                 "vol_resid": st1[0]["vol_resid"], "setup_factor_s": t_fac64,
                                 "kernels": prof1,
                                 "roofline": roofline(max(prof1, key=lambda k: k["ms"]), 1, name)}
+
+    if "plr" in forms_wanted:
+        # single-RHS FP64 solves whose preconditioner applies the interface
+        # operators in partitioned low-rank form (eps = 1e-8, compressed in
+        # hz_factor); the SIE matrix stays dense
+        t0 = time.perf_counter()
+        spl = hz.Solver(torch.from_numpy(c), w.omega, w.n_pml, w.layers, w.cells,
+                        precision=hz.HZ_FP64, max_batch=1, plr=1, plr_eps=1e-8)
+        torch.cuda.synchronize()
+        t_facp = time.perf_counter() - t0
+        info = spl.info
+        k = B // 2
+        f1 = f_all[k:k + 1].contiguous()
+        up, dtp, profp, dtpp, stp = timed_solves(spl, f1, 1e-10, steps, warmup, max_iter,
+                                                 region=roctx_form == "fp64_single_plr")
+        errp = float(torch.linalg.norm(up[0] - refs[k]) / torch.linalg.norm(refs[k]))
+        gp = None
+        if golden is not None:
+            gp = {}
+            for i, g0 in enumerate(golden["sources"]):
+                ug = spl.solve(f_all[g0:g0 + 1].contiguous(), tol=1e-10, max_iter=max_iter)
+                got = ug[0][golden["rows"] - 1].cpu().numpy()
+                gp[g0] = float(np.linalg.norm(got - golden["u"][i]) / np.linalg.norm(golden["u"][i]))
+                del ug
+        spl.close()
+        del spl, up
+        torch.cuda.empty_cache()
+        log(f"[bench] fp64 single RHS with PLR preconditioner: {dtp * 1e3:.1f} ms/solve "
+            f"({dtpp * 1e3:.1f} profiled), {stp[0]['iters']} iterations, err vs fp64 {errp:.1e}, "
+            f"stored {info.plr_bytes / max(info.plr_dense_bytes, 1):.3f} of dense")
+        forms["fp64_single_plr"] = {
+            "dof_solves_per_s": n * n / dtp, "ms_per_solve": dtp * 1e3,
+            "ms_per_solve_profiled": dtpp * 1e3, "gmres_iters": stp[0]["iters"],
+            "rel_err_vs_fp64": errp, "rel_err_vs_oracle_rows": gp, "plr_eps": 1e-8,
+            "plr_bytes": info.plr_bytes, "plr_dense_bytes": info.plr_dense_bytes,
+            "setup_factor_compress_s": t_facp, "kernels": profp,
+            "roofline": roofline(max(profp, key=lambda k: k["ms"]), 1, name)}
 
     def record(key, solver, tol, dty, t_fac, region):
         u, dt, prof, dtp, st = timed_solves(solver, f_all, tol, steps, warmup, max_iter,
@@ -482,8 +520,10 @@ def main():
                     help="comma list of further workloads timed in the fp64 / mixed / refine "
                          "batched forms (reported under other_workloads; '' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="single,fp64,mixed,refine,nested",
-                    help="comma list of single (FP64, one RHS per solve), fp64, mixed, refine, "
+    ap.add_argument("--forms", default="single,plr,fp64,mixed,refine,nested",
+                    help="comma list of single (FP64, one RHS per solve), plr (the same with the "
+                         "preconditioner's operators in partitioned low-rank form), fp64, mixed, "
+                         "refine, "
                          "nested (nested polarized traces: inner GMRES instead of the inner "
                          "block LU), local (re-factorisation after a local model update, on "
                          "the mixed context), table3 (Krylov x preconditioner comparison)")

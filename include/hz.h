@@ -146,6 +146,13 @@ typedef struct {
                                 solves of the SIE matrix, the right-hand side and the
                                 reconstruction use min(1e-10, max(1e-13, tol / 100)), and the
                                 other building blocks 1e-12 */
+    int plr;                 /* 1: the Gauss-Seidel preconditioner of single-right-hand-side
+                                solves (B = 1) applies the interface operators in partitioned
+                                low-rank form (eq. factorization and its PLR footnote; accuracy
+                                of the caption of Fig. 9), compressed by hz_factor; the SIE
+                                matrix stays dense.  Needs HZ_INNER_LU.  0: dense. */
+    double plr_eps;          /* relative Frobenius accuracy of every compressed operator block,
+                                ||A - A_plr||_F <= plr_eps ||A||_F (<= 0 -> 1e-8) */
 } hz_params;
 
 typedef struct {
@@ -172,6 +179,8 @@ typedef struct {
     int trace_len;                     /* 4 (L-1) W: length of a polarized vector */
     int max_batch;
     long long device_bytes;            /* device memory held by the context */
+    long long plr_bytes;               /* device bytes of the compressed operators (0 if none) */
+    long long plr_dense_bytes;         /* the same operators stored dense */
     double min_pivot_ratio;            /* smallest |pivot| / largest |pivot| over the block
                                           inversions of the last hz_factor (cell Schur
                                           complements, inner SIE diagonal blocks); 0 before */

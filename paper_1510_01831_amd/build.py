@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhz.so")
 
-SOURCES = ["k_factor.hip", "k_cellsolve.hip", "k_gemm.hip", "k_vec.hip", "hz_api.hip"]
+SOURCES = ["k_factor.hip", "k_cellsolve.hip", "k_gemm.hip", "k_vec.hip", "k_plr.hip", "hz_api.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-munsafe-fp-atomics", "-Wno-unused-result", f"-I{INCLUDE}", f"-I{CSRC}"]

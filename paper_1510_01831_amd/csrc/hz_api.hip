@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -111,6 +112,24 @@ struct LaunchRec {
     C2<T>* y; const C2<T>* x; double2 a, b; long long n;   // vector ops
     double bytes, flops;  // algorithmic traffic / work of a GEMM launch
     int choice = -1;      // GEMM kernel picked by the autotuner (-1: default)
+    bool plr = false;     // every task applies its operator in PLR form (B = 1)
+    int plr_tiles = 0, plr_rows = 0;   // largest tile count / tile-row count of a task
+};
+
+// Partitioned low-rank operators of the preconditioner (precision T): the
+// factors of all compressed blocks in one pool, the tiles in one table, and
+// per block (keyed by its first entry, as plan tasks point to it) the first
+// tile and the tile grid.
+template <typename T>
+struct PlrStore {
+    C2<T>* pool = nullptr;
+    PlrTile* tiles = nullptr;
+    std::vector<PlrTile> host;
+    struct Ref { long long first; int ntr, ntc; };
+    std::map<const void*, Ref> blocks;
+    long long stored = 0, dense = 0;   // complex elements
+    C2<T>* part = nullptr;             // partial products of one launch's tiles
+    long long part_tiles = 0;
 };
 
 template <typename T> struct Plan;
@@ -252,6 +271,8 @@ struct hz_ctx {
     Ops<float> o32;
     Work<double> w64;
     Work<float> w32;
+    PlrStore<double> plr64;
+    PlrStore<float> plr32;
     // FP64 GMRES / refinement workspace
     int g_cap_B = 0, g_cap_m = 0;
     double2 *Z = nullptr;          // flexible GMRES: preconditioned basis
@@ -283,6 +304,9 @@ template <> Ops<float>& ops<float>(hz_ctx* c) { return c->o32; }
 template <typename T> Work<T>& work(hz_ctx* c);
 template <> Work<double>& work<double>(hz_ctx* c) { return c->w64; }
 template <> Work<float>& work<float>(hz_ctx* c) { return c->w32; }
+template <typename T> PlrStore<T>& plr_store(hz_ctx* c);
+template <> PlrStore<double>& plr_store<double>(hz_ctx* c) { return c->plr64; }
+template <> PlrStore<float>& plr_store<float>(hz_ctx* c) { return c->plr32; }
 
 template <typename T>
 C2<T>* alloc_c(hz_ctx* c, long long n) {
@@ -887,7 +911,15 @@ template <typename T>
 void plan_launches(hz_ctx* c, Plan<T>& pl, int B) {
     const bool prof = c->prof.on;
     for (const auto& r : pl.launches) {
-        if (r.kind == L_GEMM) {
+        if (r.kind == L_GEMM && r.plr) {
+            size_t e0 = prof ? prof_event(c) : 0;
+            launch_plr_apply<T>(pl.dev + r.off, r.ntasks, r.plr_tiles, r.plr_rows,
+                                plr_store<T>(c).part, c->st);
+            if (prof) {
+                size_t e1 = prof_event(c);
+                c->prof.pend.push_back({fam_name<T>("plr_gemv"), e0, e1, r.bytes, r.flops});
+            }
+        } else if (r.kind == L_GEMM) {
             size_t e0 = prof ? prof_event(c) : 0;
             launch_gemm<T>(pl.dev + r.off, r.ntasks, r.max_m, B, c->st, c->offline, r.choice,
                            &c->gsw);
@@ -1034,6 +1066,64 @@ void build_pre_plan(hz_ctx* c, Plan<T>& pl, int B) {
     (void)pairn;
 }
 
+// Switch the GEMM launches of a single-RHS preconditioner plan whose tasks
+// all have compressed operators to the PLR kernels (tasks get their tile
+// tables and their place in the partial-product scratch).
+template <typename T>
+void plr_mark(hz_ctx* c, Plan<T>& pl) {
+    PlrStore<T>& ps = plr_store<T>(c);
+    if (!c->prm.plr || !ps.pool) return;
+    const double cs = sizeof(C2<T>);
+    long long need = 0;
+    for (auto& r : pl.launches) {
+        if (r.kind != L_GEMM) continue;
+        bool all = true;
+        for (int q = 0; q < r.ntasks && all; ++q)
+            all = ps.blocks.count((const void*)pl.tasks[r.off + q].A) > 0;
+        if (!all) continue;
+        long long tot = 0;
+        int mt = 0, mr = 0;
+        double bytes = 0;
+        for (int q = 0; q < r.ntasks; ++q) {
+            GemmTask<T>& t = pl.tasks[r.off + q];
+            const auto& ref = ps.blocks.at((const void*)t.A);
+            t.plr = ps.tiles + ref.first;
+            t.plr_pool = ps.pool;
+            t.plr_ntr = ref.ntr;
+            t.plr_ntc = ref.ntc;
+            t.plr_part = tot;
+            tot += (long long)ref.ntr * ref.ntc;
+            mt = std::max(mt, ref.ntr * ref.ntc);
+            mr = std::max(mr, ref.ntr);
+            // algorithmic traffic: the stored entries of the tiles that meet a
+            // present input segment, the input and output rows
+            long long kk = 0;
+            for (int s2 = 0; s2 < t.nseg; ++s2)
+                if (t.seg_ptr[s2]) kk += t.seg_len[s2];
+            for (long long e = ref.first; e < ref.first + (long long)ref.ntr * ref.ntc; ++e) {
+                const PlrTile& tl = ps.host[e];
+                bool live = false;
+                for (int s2 = 0; s2 < t.nseg && !live; ++s2)
+                    live = t.seg_ptr[s2] && t.seg_k0[s2] < tl.j0 + tl.tc &&
+                           tl.j0 < t.seg_k0[s2] + t.seg_len[s2];
+                if (!live) continue;
+                bytes += cs * (tl.rank < 0 ? (double)tl.tr * tl.tc : (double)tl.rank * (tl.tr + tl.tc));
+            }
+            bytes += cs * ((double)kk + 2.0 * t.m);
+        }
+        r.plr = true;
+        r.plr_tiles = mt;
+        r.plr_rows = mr;
+        r.bytes = bytes;
+        need = std::max(need, tot);
+    }
+    if (need > ps.part_tiles) {
+        if (ps.part) c->arena.release(ps.part, 0);
+        ps.part = alloc_c<T>(c, need * PLR_TILE);
+        ps.part_tiles = need;
+    }
+}
+
 template <typename T>
 Plan<T>& get_plan(hz_ctx* c, bool sie, int B) {
     Work<T>& w = work<T>(c);
@@ -1045,6 +1135,7 @@ Plan<T>& get_plan(hz_ctx* c, bool sie, int B) {
     pl->inner_loose = !sie;
     if (sie) build_sie_plan<T>(c, *pl, B);
     else build_pre_plan<T>(c, *pl, B);
+    if (!sie && B == 1) plr_mark<T>(c, *pl);
     tune_plan<T>(c, *pl, B);
     plan_upload<T>(c, *pl);
     Plan<T>& ref = *pl;
@@ -2108,9 +2199,121 @@ void factor_impl_t(hz_ctx* c, const std::vector<char>* redo) {
     }
 }
 
+// Compress the preconditioner's operator blocks in PLR form (offline): the
+// composed output operators Qc of every layer side and cell and the
+// interface-row columns of the cell samples (M_f).  Tile norms first (the
+// per-tile budget eps ||A||_F / sqrt(T) needs the block norm), then the
+// ranks (rank-revealing QR without output), then the factors into a pool
+// of exactly the stored size.
+template <typename T>
+void plr_build(hz_ctx* c) {
+    PlrStore<T>& ps = plr_store<T>(c);
+    if (ps.pool) c->arena.release(ps.pool, 0);
+    if (ps.tiles) c->arena.release(ps.tiles, 0);
+    ps.pool = nullptr;
+    ps.tiles = nullptr;
+    ps.host.clear();
+    ps.blocks.clear();
+    ps.stored = ps.dense = 0;
+    const Dims& d = c->d;
+    const int J = d.Lc - 1;
+    if (!c->prm.plr || J <= 0 || !c->compose) return;
+    Ops<T>& o = ops<T>(c);
+    if (!o.Qc || !o.CS) return;
+    std::vector<PlrBlock<T>> blocks;
+    std::vector<long long> bfirst;
+    auto add_block = [&](const C2<T>* A, long long lda, int m, int k) {
+        if (m <= 0 || k <= 0 || ps.blocks.count((const void*)A)) return;
+        const int b = (int)blocks.size();
+        blocks.push_back({A, lda});
+        const int ntr = (m + PLR_TILE - 1) / PLR_TILE, ntc = (k + PLR_TILE - 1) / PLR_TILE;
+        ps.blocks[(const void*)A] = {(long long)ps.host.size(), ntr, ntc};
+        bfirst.push_back((long long)ps.host.size());
+        for (int i = 0; i < ntr; ++i)
+            for (int j = 0; j < ntc; ++j) {
+                PlrTile t{};
+                t.block = b;
+                t.i0 = i * PLR_TILE;
+                t.j0 = j * PLR_TILE;
+                t.tr = std::min(PLR_TILE, m - t.i0);
+                t.tc = std::min(PLR_TILE, k - t.j0);
+                t.rank = -1;
+                ps.host.push_back(t);
+                ps.dense += (long long)t.tr * t.tc;
+            }
+    };
+    for (int l = 0; l < d.L; ++l) {
+        const LayerDesc& ld = c->layers[l];
+        for (int side = 0; side < 2; ++side)
+            for (int k = 0; k < d.Lc; ++k) {
+                const size_t q = ((size_t)l * 2 + side) * d.Lc + k;
+                if (c->qc_off[q] < 0) continue;
+                const CellDesc& cd = c->cells[ld.cell_begin + k];
+                add_block(o.Qc + c->qc_off[q], c->qc_ld[q], 2 * cd.s, c->qc_ld[q]);
+            }
+        if (ld.nslot == 0) continue;
+        for (int k = 0; k < d.Lc; ++k) {
+            const CellDesc& cd = c->cells[ld.cell_begin + k];
+            add_block(o.CS + cd.off_CS + cd.ncol, cd.R, cd.adj * cd.HL, ld.nslot * cd.s);
+        }
+    }
+    const long long nt = (long long)ps.host.size();
+    bfirst.push_back(nt);
+    if (nt == 0) return;
+    if (nt > INT_MAX) raise(HZ_EINVAL, "too many PLR tiles");
+    struct Temps {
+        Arena& a;
+        std::vector<void*> v;
+        void* keep(void* p) { v.push_back(p); return p; }
+        ~Temps() { for (void* p : v) a.release(p, 0); }
+    } tmp{c->arena, {}};
+    auto* dblk = (PlrBlock<T>*)tmp.keep(c->arena.alloc(sizeof(PlrBlock<T>) * blocks.size()));
+    auto* dtile = (PlrTile*)c->arena.alloc(sizeof(PlrTile) * nt);
+    ps.tiles = dtile;
+    auto* dnorm = (double*)tmp.keep(c->arena.alloc(sizeof(double) * nt));
+    auto* drank = (int*)tmp.keep(c->arena.alloc(sizeof(int) * nt));
+    upload(c, dblk, blocks.data(), sizeof(PlrBlock<T>) * blocks.size());
+    upload(c, dtile, ps.host.data(), sizeof(PlrTile) * nt);
+    launch_plr_tile_norms<T>(dblk, dtile, (int)nt, dnorm, c->st);
+    HIPCHK(hipGetLastError());
+    std::vector<double> norm2(nt), delta2(nt);
+    HIPCHK(hipMemcpyAsync(norm2.data(), dnorm, sizeof(double) * nt, hipMemcpyDeviceToHost, c->st));
+    sync(c);
+    const double eps = c->prm.plr_eps;
+    for (size_t b = 0; b + 1 < bfirst.size(); ++b) {
+        double fro2 = 0.0;
+        for (long long e = bfirst[b]; e < bfirst[b + 1]; ++e) fro2 += norm2[e];
+        const double ntb = (double)(bfirst[b + 1] - bfirst[b]);
+        for (long long e = bfirst[b]; e < bfirst[b + 1]; ++e) delta2[e] = eps * eps * fro2 / ntb;
+    }
+    upload(c, dnorm, delta2.data(), sizeof(double) * nt);
+    launch_plr_compress<T>(dblk, dtile, (int)nt, dnorm, drank, nullptr, 0, c->st);
+    HIPCHK(hipGetLastError());
+    std::vector<int> rank(nt);
+    HIPCHK(hipMemcpyAsync(rank.data(), drank, sizeof(int) * nt, hipMemcpyDeviceToHost, c->st));
+    sync(c);
+    long long off = 0;
+    for (long long e = 0; e < nt; ++e) {
+        PlrTile& t = ps.host[e];
+        t.rank = rank[e];
+        t.off = off;
+        off += t.rank < 0 ? (long long)t.tr * t.tc : (long long)t.rank * (t.tr + t.tc);
+    }
+    ps.stored = off;
+    ps.pool = alloc_c<T>(c, std::max<long long>(off, 1));
+    upload(c, dtile, ps.host.data(), sizeof(PlrTile) * nt);
+    launch_plr_compress<T>(dblk, dtile, (int)nt, dnorm, drank, ps.pool, 1, c->st);
+    HIPCHK(hipGetLastError());
+    sync(c);
+}
+
 void factor_impl(hz_ctx* c, const std::vector<char>* redo = nullptr) {
     if (c->prm.precision == HZ_MIXED_REFINE) factor_impl_t<float>(c, redo);
     else factor_impl_t<double>(c, redo);
+    // the preconditioner's operators: FP64 in HZ_FP64, complex64 otherwise
+    OfflineScope scope(c);
+    if (c->prm.precision == HZ_FP64) plr_build<double>(c);
+    else plr_build<float>(c);
 }
 
 // ---------------------------------------------------------------------------
@@ -2979,6 +3182,10 @@ hz_status hz_setup(const double* model_dev, const hz_params* prm, hz_ctx** out) 
             raise(HZ_EINVAL, "nested polarized traces need the (flexible) GMRES driver");
         if (!(prm->inner_tol < 1.0)) raise(HZ_EINVAL, "inner_tol must be < 1");
     }
+    if (prm->plr != 0 && prm->plr != 1) raise(HZ_EINVAL, "plr must be 0 or 1");
+    if (prm->plr && prm->inner != HZ_INNER_LU)
+        raise(HZ_EINVAL, "PLR operators need the block-LU inner solver");
+    if (prm->plr && !(prm->plr_eps < 1.0)) raise(HZ_EINVAL, "plr_eps must be < 1");
     c = new hz_ctx();
     c->prm = *prm;
     c->inner_pt = prm->inner == HZ_INNER_PT && prm->cells > 1;
@@ -2994,6 +3201,7 @@ hz_status hz_setup(const double* model_dev, const hz_params* prm, hz_ctx** out) 
         if (k >= GEMM_MFMA32 && k <= GEMM_MFMA32DS8) c->force_kind = k;
     }
     if (c->prm.pml_beta <= 0.0) c->prm.pml_beta = 2.0;
+    if (c->prm.plr_eps <= 0.0) c->prm.plr_eps = 1e-8;
     if (c->prm.max_batch <= 0) c->prm.max_batch = 1;
     Dims& d = c->d;
     d.n = n;
@@ -3257,6 +3465,13 @@ hz_status hz_get_info(const hz_ctx* c, hz_info_t* info) {
     info->trace_len = 4 * c->d.K * c->d.W;
     info->max_batch = c->prm.max_batch;
     info->device_bytes = c->arena.bytes;
+    if (c->prm.precision == HZ_FP64) {
+        info->plr_bytes = c->plr64.stored * (long long)sizeof(double2);
+        info->plr_dense_bytes = c->plr64.dense * (long long)sizeof(double2);
+    } else {
+        info->plr_bytes = c->plr32.stored * (long long)sizeof(float2);
+        info->plr_dense_bytes = c->plr32.dense * (long long)sizeof(float2);
+    }
     info->min_pivot_ratio = c->min_pivot_ratio;
     return HZ_OK;
 }

@@ -162,6 +162,24 @@ __host__ __device__ inline long long xt_index(int i, int j, int HLp) {
 constexpr int NSEG = 6;
 constexpr int NOSEG = 4;
 
+// Partitioned low-rank form of an operator block (k_plr.hip): square tiles
+// of PLR_TILE, each dense (column-major, rank -1), zero (rank 0) or the
+// factors U (tr x r) then W (r x tc), both column-major, at `off` complex
+// elements into the pool.  Ranks above PLR_RMAX are stored dense.
+constexpr int PLR_TILE = 64;
+constexpr int PLR_RMAX = 32;
+struct PlrTile {
+    int block;           // index of the block (offline compression only)
+    int i0, j0, tr, tc;  // tile origin and size in the block
+    int rank;
+    long long off;
+};
+template <typename T>
+struct PlrBlock {        // a dense block to compress: row-major, row stride lda
+    const C2<T>* A;
+    long long lda;
+};
+
 template <typename T>
 struct GemmTask {
     const C2<T>* A;      // row-major, row stride lda
@@ -182,10 +200,15 @@ struct GemmTask {
     long long ldx;       // row stride of every x segment (complex elements)
     long long ldo;       // row stride of the output / add0 / add1 segments
     int ncol;            // batch columns of this task (0 = the launch's B)
+    // PLR form of A (single-RHS launches of the preconditioner), or NULL:
+    // plr_ntr x plr_ntc tiles, row-major, factors in plr_pool
+    const PlrTile* plr;
+    const C2<T>* plr_pool;
+    int plr_ntr, plr_ntc;
+    long long plr_part;  // first tile of this task in the launch's partial-product scratch
 };
 
-// Workspace of the split-k variants: partial tiles (bytes) and one counter
-// per output tile, zero between launches (the kernels leave them zero).
+// Workspace of the split-k variants: partial tiles (bytes).
 struct GemmSplitWs {
     void* ws = nullptr;              // partial tiles of the split-k variants
     long long ws_bytes = 0;
@@ -259,6 +282,19 @@ void launch_invert_batch(C2<T>* const* mats, C2<T>* const* outs, const int* ns, 
 template <typename T>
 void launch_cell_solve(const CellSolveArgs<T>& a, int ncells_launch, int nb_chunks,
                        hipStream_t st);
+
+// PLR compression and application (k_plr.hip)
+template <typename T>
+void launch_plr_tile_norms(const PlrBlock<T>* blocks, const PlrTile* tiles, int ntiles,
+                           double* norm2, hipStream_t st);
+template <typename T>
+void launch_plr_compress(const PlrBlock<T>* blocks, const PlrTile* tiles, int ntiles,
+                         const double* delta2, int* ranks, C2<T>* pool, int write,
+                         hipStream_t st);
+// part: PLR_TILE partial entries per tile, a task's tiles from its plr_part
+template <typename T>
+void launch_plr_apply(const GemmTask<T>* tasks_dev, int ntasks, int max_tiles, int max_rows,
+                      C2<T>* part, hipStream_t st);
 
 // B = number of batch columns; ldx/ldo come from the tasks.
 // offline = launch from the factorisation stage (separate kernel instance);

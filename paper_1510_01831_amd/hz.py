@@ -37,7 +37,8 @@ class Params(ctypes.Structure):
                 ("cells", ctypes.c_int), ("precision", ctypes.c_int),
                 ("model_kind", ctypes.c_int), ("max_batch", ctypes.c_int),
                 ("precond", ctypes.c_int), ("krylov", ctypes.c_int),
-                ("inner", ctypes.c_int), ("inner_tol", ctypes.c_double)]
+                ("inner", ctypes.c_int), ("inner_tol", ctypes.c_double),
+                ("plr", ctypes.c_int), ("plr_eps", ctypes.c_double)]
 
 
 class RhsStats(ctypes.Structure):
@@ -63,7 +64,8 @@ class Info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("n_pml", ctypes.c_int), ("W", ctypes.c_int),
                 ("layers", ctypes.c_int), ("cells", ctypes.c_int),
                 ("trace_len", ctypes.c_int), ("max_batch", ctypes.c_int),
-                ("device_bytes", ctypes.c_longlong), ("min_pivot_ratio", ctypes.c_double)]
+                ("device_bytes", ctypes.c_longlong), ("plr_bytes", ctypes.c_longlong),
+                ("plr_dense_bytes", ctypes.c_longlong), ("min_pivot_ratio", ctypes.c_double)]
 
 
 _lib = None
@@ -146,7 +148,8 @@ class Solver:
                  precision: int = HZ_FP64, model_kind: int = HZ_MODEL_VELOCITY,
                  pml_beta: float = 2.0, max_batch: int = 1, factor: bool = True,
                  precond: int = HZ_PRECOND_GS, krylov: int = HZ_KRYLOV_GMRES,
-                 inner: int = HZ_INNER_LU, inner_tol: float = 0.0):
+                 inner: int = HZ_INNER_LU, inner_tol: float = 0.0, plr: int = 0,
+                 plr_eps: float = 0.0):
         import torch
 
         self.torch = torch
@@ -156,7 +159,7 @@ class Solver:
         self.prm = Params(n, n, 1.0 / (n + 1), float(omega), int(n_pml), float(pml_beta),
                           int(layers), int(cells), int(precision), int(model_kind),
                           int(max_batch), int(precond), int(krylov), int(inner),
-                          float(inner_tol))
+                          float(inner_tol), int(plr), float(plr_eps))
         self.ctx = ctypes.c_void_p()
         self._stats_raw = None
         self._stats_list = None

@@ -125,6 +125,25 @@ def test_n1023_single_source_fp64(n1023):
     assert err <= 1e-9
 
 
+def test_n1023_single_source_plr(n1023):
+    """The single-source n = 1023 workload with the preconditioner's
+    interface operators in partitioned low-rank form (eps = 1e-8) against the
+    oracle's direct solve."""
+    w, c, f, refs, (w2, f2, ref2) = n1023
+    _log("[n=1023] single source, FP64, PLR preconditioner")
+    s = hz.Solver(torch.from_numpy(c), w2.omega, w2.n_pml, w2.layers, w2.cells, max_batch=1,
+                  plr=1, plr_eps=1e-8)
+    u = s.solve(torch.from_numpy(f2), tol=1e-10).cpu().numpy()[0]
+    its = s.last_stats[0]["iters"]
+    info = s.info
+    s.close()
+    err = _rel(u, ref2)
+    _log(f"  err {err:.2e} (GMRES iterations {its}), stored {info.plr_bytes / info.plr_dense_bytes:.3f}"
+         f" of dense")
+    assert err <= 1e-9
+    assert info.plr_bytes < info.plr_dense_bytes
+
+
 def test_n1023_nested_polarized_traces(n1023):
     """The nested polarized traces (Sec. 4.2.1: inner GMRES with the inner
     sweeps, tolerance 1e-6 inside the preconditioner) on the n = 1023
@@ -250,6 +269,35 @@ def test_failure_paths():
     with pytest.raises(hz.HzError) as e:
         hz.Solver(torch.from_numpy(bad), omega, 6, 2, 2)
     assert e.value.status == hz.HZ_EINVAL
+
+
+def test_n2047_single_source_plr(n2047):
+    """n = 2047, the stored sources one at a time (single right-hand side)
+    with the PLR preconditioner against the oracle's direct solve on the
+    stored rows, and their volume residuals with the oracle's H."""
+    w, c, f, z, prob, H = n2047
+    _log("[n=2047] single sources, FP64, PLR preconditioner")
+    s = hz.Solver(torch.from_numpy(c), w.omega, w.n_pml, w.layers, w.cells, max_batch=1,
+                  plr=1, plr_eps=1e-8)
+    rows = z["rows"] - 1 + w.n_pml
+    cols = slice(w.n_pml, w.n_pml + w.n)
+    for i, k in enumerate(z["sources"]):
+        k = int(k)
+        u = s.solve(torch.from_numpy(f[k:k + 1]), tol=1e-10, ext=True)
+        its = s.last_stats[0]["iters"]
+        err = _rel(u[0][rows][:, cols].cpu().numpy(), z["u"][i])
+        ue = u[0].cpu().numpy().ravel()
+        fe = prob.extend(f[k]).ravel()
+        r = np.linalg.norm(fe - H @ ue) / np.linalg.norm(fe)
+        _log(f"  source {k}: rel. error vs oracle rows {err:.2e}, volume residual {r:.2e}, "
+             f"iterations {its}")
+        assert err <= 1e-9
+        assert r <= N2047_RESID_FACTOR * 1e-9
+    info = s.info
+    s.close()
+    _log(f"  stored {info.plr_bytes / info.plr_dense_bytes:.3f} of dense "
+         f"({info.plr_bytes / 1e9:.2f} GB)")
+    assert info.plr_bytes < info.plr_dense_bytes
 
 
 def test_singular_factorisation():
