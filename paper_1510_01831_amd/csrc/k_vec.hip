@@ -187,14 +187,55 @@ constexpr int RD_THREADS = 256;
 // Up to DV basis vectors per workgroup, so w is read once per DV of them.
 constexpr int DV = 8;
 
+// Threads per batch column of the reduction kernels: the largest power of
+// two with per * B <= RD_THREADS (at least 1).
+__device__ inline int rd_per(int B) {
+    int per = 1;
+    while (2 * per * B <= RD_THREADS) per *= 2;
+    return per;
+}
+
+// Column sums of NV quantities per thread: thread tid = sub * bcols + col
+// (sub < per, a power of two) holds acc[v] of column col; the sums over sub
+// are formed by halving, all quantities at once, and left in acc of the
+// threads with sub = 0.  red: NV * RD_THREADS entries of LDS.
+template <int NV>
+__device__ inline void reduce_columns(double2 (&acc)[NV], int nout, int per, int bcols,
+                                      double2* red) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+        if (v < nout) red[v * RD_THREADS + tid] = acc[v];
+    __syncthreads();
+    const int sub = tid / bcols;
+    for (int h = per / 2; h > 0; h >>= 1) {
+        if (sub < h) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                if (v < nout) {
+                    const double2 o = red[v * RD_THREADS + tid + h * bcols];
+                    red[v * RD_THREADS + tid].x += o.x;
+                    red[v * RD_THREADS + tid].y += o.y;
+                }
+        }
+        __syncthreads();
+    }
+    if (tid < bcols) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            if (v < nout) acc[v] = red[v * RD_THREADS + tid];
+    }
+    __syncthreads();
+}
+
 __global__ void __launch_bounds__(RD_THREADS)
 k_dots(const double2* V, long long vstride, int nv, const double2* w, long long n, int B,
        double2* partial, int nchunks) {
-    __shared__ double2 red[RD_THREADS];
+    __shared__ double2 red[DV * RD_THREADS];
     const int v0 = blockIdx.y * DV;
     const int nvb = nv - v0 < DV ? nv - v0 : DV;
     const int tid = threadIdx.x;
-    const int per = RD_THREADS / B > 0 ? RD_THREADS / B : 1;     // threads per column
+    const int per = rd_per(B);                                    // threads per column
     const int bcols = B < RD_THREADS ? B : RD_THREADS;
     const long long chunk = (n + nchunks - 1) / nchunks;
     const long long i0 = blockIdx.x * chunk;
@@ -220,19 +261,10 @@ k_dots(const double2* V, long long vstride, int nv, const double2* w, long long 
                 }
             }
         }
-        for (int v = 0; v < nvb; ++v) {
-            red[tid] = acc[v];
-            __syncthreads();
-            if (tid < bcols && bb + tid < B) {
-                double2 s = make_double2(0.0, 0.0);
-                for (int q = 0; q < per; ++q) {
-                    double2 r = red[q * bcols + tid];
-                    s.x += r.x; s.y += r.y;
-                }
-                partial[((long long)blockIdx.x * nv + v0 + v) * B + bb + tid] = s;
-            }
-            __syncthreads();
-        }
+        reduce_columns<DV>(acc, nvb, per, bcols, red);
+        if (tid < bcols && bb + tid < B)
+            for (int v = 0; v < nvb; ++v)
+                partial[((long long)blockIdx.x * nv + v0 + v) * B + bb + tid] = acc[v];
     }
 }
 
@@ -254,9 +286,9 @@ __global__ void __launch_bounds__(RD_THREADS)
 k_update_dots(double2* __restrict__ w, const double2* __restrict__ V, long long vstride, int nv,
               const double2* __restrict__ coef, double sgn, long long n, int B, int norm,
               double2* __restrict__ partial, int nchunks) {
-    __shared__ double2 red[RD_THREADS];
+    __shared__ double2 red[UD_MAX * RD_THREADS];
     const int tid = threadIdx.x;
-    const int per = RD_THREADS / B > 0 ? RD_THREADS / B : 1;
+    const int per = rd_per(B);
     const int bcols = B < RD_THREADS ? B : RD_THREADS;
     const long long chunk = (n + nchunks - 1) / nchunks;
     const long long i0 = blockIdx.x * chunk;
@@ -299,22 +331,10 @@ k_update_dots(double2* __restrict__ w, const double2* __restrict__ V, long long 
                 }
             }
         }
-#pragma unroll
-        for (int v = 0; v < UD_MAX; ++v) {
-            if (v < nout) {                          // uniform: nout is a kernel argument
-                red[tid] = acc[v];
-                __syncthreads();
-                if (tid < bcols && bb + tid < B) {
-                    double2 sacc = make_double2(0.0, 0.0);
-                    for (int q = 0; q < per; ++q) {
-                        const double2 r = red[q * bcols + tid];
-                        sacc.x += r.x; sacc.y += r.y;
-                    }
-                    partial[((long long)blockIdx.x * nout + v) * B + bb + tid] = sacc;
-                }
-                __syncthreads();
-            }
-        }
+        reduce_columns<UD_MAX>(acc, nout, per, bcols, red);
+        if (tid < bcols && bb + tid < B)
+            for (int v = 0; v < nout; ++v)
+                partial[((long long)blockIdx.x * nout + v) * B + bb + tid] = acc[v];
     }
 }
 
