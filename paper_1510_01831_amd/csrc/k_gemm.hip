@@ -237,13 +237,20 @@ __device__ __forceinline__ void next_chunk(const GemmTask<T>& t, int& sg, int& k
 // c is multiplied and chunk c+1 waits in registers (two chunk periods to hide
 // the load latency instead of one).
 //
+// NBUF: LDS buffers per operand.  Two let the next chunk be stashed while the
+// current one is multiplied (one barrier per chunk); one halves the LDS of a
+// workgroup at the price of a second barrier.  The 32 x 32 tiles with 32-deep
+// chunks use one: at two (33.8 KB for complex64) only four workgroups fit on
+// a CU, so a launch of 1216 split-k workgroups ran in two rounds; at one
+// (16.9 KB) registers allow five per CU (complex128: two -> four).
+//
 // splits > 1 (split k): the splits workgroups of an output
 // tile (adjacent slots, hence one XCD) each take a contiguous share of the
 // tile's k chunks and store their raw accumulators to ws; a second kernel
 // (k_gemm_split_reduce) adds the shares in index order and applies the
 // epilogue.  The kernel boundary orders the two passes, so no workgroup
 // waits on another and no fence is needed.
-template <typename T, int MT, int TBM, int KC, bool OFFLINE, bool DEEP = false>
+template <typename T, int MT, int TBM, int KC, bool OFFLINE, bool DEEP = false, int NBUF = 2>
 __global__ void __launch_bounds__(GV_THREADS, 2)
 k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col_tiles,
             int splits, C2<T>* __restrict__ ws) {
@@ -260,8 +267,11 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
     if (t.ncol > 0) B = t.ncol;
     const int b0 = ct * TBM;
     if (b0 >= B) return;
-    __shared__ C2<T> As[2][MT][KC + 1];
-    __shared__ C2<T> Xs[2][KC][TBM + 1];
+    __shared__ C2<T> As[NBUF][MT][KC + 1];
+    __shared__ C2<T> Xs[NBUF][KC][TBM + 1];
+    // the LDS buffer a chunk is stashed into: with one buffer the stash waits
+    // behind a barrier until every wave has finished multiplying the last one
+    auto nbuf = [](int b) { return NBUF == 2 ? b : 0; };
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int lc = lane & 15, lk = lane >> 4;
     const int wr = (w >> 1) * (MT / 2), wc = (w & 1) * (TBM / 2);
@@ -273,6 +283,7 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
 #pragma unroll
         for (int c = 0; c < CTW; ++c) acc[a][c].zero();
     auto multiply = [&](int buf) {
+        buf = nbuf(buf);
 #pragma unroll
         for (int s4 = 0; s4 < KC / 4; ++s4) {
             C2<T> av[RTW], bv[CTW];
@@ -319,7 +330,8 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
             if (more) load(stage, ns, nk);
             multiply(buf);
             if (!more) break;
-            stage.stash(As[buf ^ 1], Xs[buf ^ 1], tid);   // last read two barriers ago
+            if (NBUF == 1) __syncthreads();
+            stage.stash(As[nbuf(buf ^ 1)], Xs[nbuf(buf ^ 1)], tid);
             __syncthreads();
             buf ^= 1;
             sg = ns;
@@ -352,7 +364,8 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
             if (s2 < t.nseg) load(q, s2, k2);
             multiply(buf);
             if (s1 >= t.nseg) break;
-            p.stash(As[buf ^ 1], Xs[buf ^ 1], tid);       // last read two barriers ago
+            if (NBUF == 1) __syncthreads();
+            p.stash(As[nbuf(buf ^ 1)], Xs[nbuf(buf ^ 1)], tid);
             __syncthreads();
             buf ^= 1;
             int s3 = s2, k3 = k2;
@@ -360,7 +373,8 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
             if (s3 < t.nseg) load(p, s3, k3);
             multiply(buf);
             if (s2 >= t.nseg) break;
-            q.stash(As[buf ^ 1], Xs[buf ^ 1], tid);
+            if (NBUF == 1) __syncthreads();
+            q.stash(As[nbuf(buf ^ 1)], Xs[nbuf(buf ^ 1)], tid);
             __syncthreads();
             buf ^= 1;
             s1 = s3;
@@ -518,11 +532,11 @@ void launch_gemm_mfma(GemmKernel kind, const GemmTask<T>* tasks_dev, int ntasks,
                                    tasks_dev, B, rt, ct, splits, (const C2<T>*)ws);
             } else {
                 if (deep)
-                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 32, OFFLINE, true>), g1,
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 32, OFFLINE, true, 1>), g1,
                                        blk, 0, st, tasks_dev, B, rt, ct, splits, ws);
                 else
-                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 32, OFFLINE>), g1, blk,
-                                       0, st, tasks_dev, B, rt, ct, splits, ws);
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 32, OFFLINE, false, 1>), g1,
+                                       blk, 0, st, tasks_dev, B, rt, ct, splits, ws);
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_split_reduce<T, 32, 32>), g2, blk, 0, st,
                                    tasks_dev, B, rt, ct, splits, (const C2<T>*)ws);
             }
@@ -555,7 +569,7 @@ void launch_gemm_mfma(GemmKernel kind, const GemmTask<T>* tasks_dev, int ntasks,
                            (C2<T>*)nullptr);
     } else if (kind == GEMM_MFMA32D) {
         const int rt = (max_m + 31) / 32, ct = (B + 31) / 32;
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 32, OFFLINE, true>),
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 32, OFFLINE, true, 1>),
                            dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct, 1,
                            (C2<T>*)nullptr);
     } else if (kind == GEMM_MFMA64D) {
@@ -566,7 +580,7 @@ void launch_gemm_mfma(GemmKernel kind, const GemmTask<T>* tasks_dev, int ntasks,
                            (C2<T>*)nullptr);
     } else {
         const int rt = (max_m + 31) / 32, ct = (B + 31) / 32;
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 32, OFFLINE>),
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_gemm_mfma<T, 32, 32, 32, OFFLINE, false, 1>),
                            dim3(rt * ct * ntasks), dim3(GV_THREADS), 0, st, tasks_dev, B, rt, ct, 1,
                            (C2<T>*)nullptr);
     }
