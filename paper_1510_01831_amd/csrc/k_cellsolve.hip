@@ -409,6 +409,9 @@ constexpr int CS_MF_WAVES = 8;        // waves of the default instance
 #ifndef CS_U1
 #define CS_U1 4
 #endif
+#ifndef CS_U10
+#define CS_U10 4
+#endif
 #ifndef CS_U2
 #define CS_U2 2
 #endif
@@ -432,9 +435,14 @@ __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const Ce
                                              double2* ixs, int b0, long long slot) {
     constexpr int NCT = NB / 16;
     constexpr int MCA = MC > 0 ? MC : 1;
-    // k steps per register group (fewer with ten waves: three waves per SIMD
-    // leave 170 registers per lane)
-    constexpr int U = NW > CS_MF_WAVES ? 2 : (MC > 1 ? CS_U2 : CS_U1);
+    // k steps per register group.  Ten waves run at three waves per SIMD,
+    // 170 registers per lane: four k steps (4 KB of factor in flight per
+    // wave) fit except for the FP64 volume solve and the 32-column FP32
+    // probes, which keep two (with four they spill)
+    constexpr bool U10_SMALL = (sizeof(T) == 8 && MODE == SOLVE_VOLUME) ||
+                               (sizeof(T) == 4 && NB == 32 && MODE == SOLVE_PROBE);
+    constexpr int U = NW > CS_MF_WAVES ? (U10_SMALL ? 2 : CS_U10)
+                                       : (MC > 1 ? CS_U2 : CS_U1);
     const int HL = cd.HL, HLp = cd.HLp, Wc = cd.Wc;
     const int KS = HLp >> 2;                  // multiple of 4
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
