@@ -569,7 +569,7 @@ def main():
 
     others = {}
     for name in [x for x in args.also.split(",") if x and x != args.workload]:
-        wo, fo, _, _ = run_workload(name, {"fp64", "mixed", "refine"} & forms_wanted,
+        wo, fo, _, _ = run_workload(name, {"fp64", "mixed", "refine", "nested"} & forms_wanted,
                                     args.steps, args.warmup)
         others[name] = {"workload": (f"{wo.name}: n={wo.n} (+{wo.n_pml} PML), {MEDIUM[wo.name]}, "
                                      f"{wo.layers} layers x {wo.cells} cells, {wo.n_rhs} sources"),

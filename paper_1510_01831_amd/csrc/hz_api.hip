@@ -283,6 +283,14 @@ struct hz_ctx {
     // inner GMRES (nested polarized traces): Krylov basis and reductions
     long long i_cap = 0; int i_cap_m = 0, i_cap_cols = 0, i_chunks = 0;
     double2 *iV = nullptr, *ipart = nullptr, *ismall = nullptr, *icoef = nullptr, *ih = nullptr;
+    // its Givens state on the device (rotated Hessenberg columns packed by
+    // column, rotations, rotated residual, per-column status) and the
+    // per-iteration convergence flags with their pinned host copies
+    double2 *iR = nullptr, *isn = nullptr, *ig = nullptr;
+    double *ics = nullptr, *ibeta = nullptr;
+    int *idone = nullptr, *ikfin = nullptr, *iflag = nullptr;
+    int* h_iflag = nullptr;
+    hipEvent_t iev = nullptr;
     double2 *u64 = nullptr, *f64 = nullptr, *r64 = nullptr;   // refinement [W][W][B]
     std::vector<std::vector<std::complex<double>>> g_hess;     // host Hessenberg storage of GMRES
     double2* h_pin = nullptr;      // pinned host buffer for the small per-iteration reads
@@ -1152,6 +1160,108 @@ Plan<T>& get_plan(hz_ctx* c, bool sie, int B) {
 constexpr int INNER_MAXIT = 40;
 
 void givens(std::complex<double> a, std::complex<double> b, double& cs, std::complex<double>& sn);
+
+// The inner GMRES keeps its least-squares bookkeeping on the device, one
+// thread per right-hand-side column (a single workgroup: the columns are at
+// most a few thousand and each does O(j) work per iteration), so that the
+// host reads one convergence flag per iteration instead of the Hessenberg
+// column.  The arithmetic is that of the host GMRES: complex Givens
+// rotations r = (c, s) with c real, zeroing the subdiagonal entry.
+constexpr int INNER_STEP_THREADS = 1024;
+
+__device__ inline double cabs_d(double2 a) { return hypot(a.x, a.y); }
+
+// rotation (cs, sn) with  [cs sn; -conj(sn) cs] [a; b] = [r; 0]
+__device__ inline void givens_dev(double2 a, double2 b, double& cs, double2& sn) {
+    const double ab = cabs_d(b), aa = cabs_d(a);
+    if (ab == 0.0) { cs = 1.0; sn = make_double2(0.0, 0.0); return; }
+    if (aa == 0.0) { cs = 0.0; sn = make_double2(b.x / ab, -b.y / ab); return; }
+    const double t = hypot(aa, ab);
+    cs = aa / t;
+    const double2 an = make_double2(a.x / aa, a.y / aa);
+    sn = cscale(cmul(an, cconj(b)), 1.0 / t);
+}
+
+// start: beta = |r0| per column (hb holds |r0|^2), g = beta e_1, columns with
+// r0 = 0 done; scale = 1 / beta for the first basis vector
+__global__ void __launch_bounds__(INNER_STEP_THREADS)
+k_inner_start(const double2* __restrict__ hb, int NB, double* __restrict__ beta,
+              double2* __restrict__ g, int* __restrict__ done, int* __restrict__ kfin,
+              double2* __restrict__ scale) {
+    for (int q = threadIdx.x; q < NB; q += blockDim.x) {
+        const double b = sqrt(fmax(0.0, hb[q].x));
+        beta[q] = b;
+        g[q] = make_double2(b, 0.0);
+        done[q] = b == 0.0;
+        kfin[q] = 0;
+        scale[q] = make_double2(b > 0.0 ? 1.0 / b : 0.0, 0.0);
+    }
+}
+
+// Arnoldi step j: the new Hessenberg column (projections of both Gram-Schmidt
+// passes hA + hB, subdiagonal sqrt(hN)) is rotated by the stored rotations,
+// a new rotation zeroes its subdiagonal, the rotated residual g is updated
+// and the column is done once |g_{j+1}| <= tol beta.  flag[j] = 1 when every
+// column is done.
+__global__ void __launch_bounds__(INNER_STEP_THREADS)
+k_inner_step(int j, int NB, const double2* __restrict__ hA, const double2* __restrict__ hB,
+             const double2* __restrict__ hN, double2* __restrict__ R, double* __restrict__ cs,
+             double2* __restrict__ sn, double2* __restrict__ g, const double* __restrict__ beta,
+             int* __restrict__ done, int* __restrict__ kfin, double tol, int* __restrict__ flag) {
+    int mine = 1;
+    double2* Rc = R + (long long)j * (j + 1) / 2 * NB;     // packed column j
+    for (int q = threadIdx.x; q < NB; q += blockDim.x) {
+        if (done[q]) continue;
+        double2 a = cadd(hA[q], hB[q]);
+        for (int i = 0; i < j; ++i) {
+            const long long at = (long long)(i + 1) * NB + q;
+            const double2 b = cadd(hA[at], hB[at]);
+            const double ci = cs[(long long)i * NB + q];
+            const double2 si = sn[(long long)i * NB + q];
+            Rc[(long long)i * NB + q] = cadd(cscale(a, ci), cmul(si, b));
+            a = cadd(cscale(cmul(cconj(si), a), -1.0), cscale(b, ci));
+        }
+        const double nrm = sqrt(fmax(0.0, hN[q].x));
+        double cj;
+        double2 sj;
+        givens_dev(a, make_double2(nrm, 0.0), cj, sj);
+        cs[(long long)j * NB + q] = cj;
+        sn[(long long)j * NB + q] = sj;
+        Rc[(long long)j * NB + q] = cadd(cscale(a, cj), cscale(sj, nrm));
+        const double2 gj = g[(long long)j * NB + q];
+        const double2 gn = cscale(cmul(cconj(sj), gj), -1.0);
+        g[(long long)(j + 1) * NB + q] = gn;
+        g[(long long)j * NB + q] = cscale(gj, cj);
+        kfin[q] = j + 1;
+        if (cabs_d(gn) / beta[q] <= tol || nrm == 0.0) done[q] = 1;
+        else mine = 0;
+    }
+    const int all = __syncthreads_and(mine);
+    if (threadIdx.x == 0) flag[j] = all;
+}
+
+// y = R^{-1} g over the first kfin[q] rows of each column; coefficients of the
+// basis vectors, zero from kfin[q] to kmax
+__global__ void k_inner_solve_y(int NB, int kmax, const double2* __restrict__ R,
+                                const double2* __restrict__ g, const int* __restrict__ kfin,
+                                double2* __restrict__ coef) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= NB) return;
+    const int k = kfin[q];
+    for (int i = kmax - 1; i >= 0; --i) {
+        double2 y = make_double2(0.0, 0.0);
+        if (i < k) {
+            double2 acc = g[(long long)i * NB + q];
+            for (int p2 = i + 1; p2 < k; ++p2)
+                acc = csub(acc, cmul(R[((long long)p2 * (p2 + 1) / 2 + i) * NB + q],
+                                     coef[(long long)p2 * NB + q]));
+            const double2 d = R[((long long)i * (i + 1) / 2 + i) * NB + q];
+            const double den = 1.0 / (d.x * d.x + d.y * d.y);
+            y = cscale(cmul(acc, cconj(d)), den);
+        }
+        coef[(long long)i * NB + q] = y;
+    }
+}
 void update_dots_dev(hz_ctx* c, const double2* V, long long vstride, int nv, const double2* coef,
                      double2* w, long long n, int B, int norm, double2* out_dev,
                      double2* part, int max_chunks);
@@ -1391,7 +1501,9 @@ void build_inner_P(hz_ctx* c, InnerRec<T>& r, Plan<T>& pl, int B) {
 
 void ensure_inner_basis(hz_ctx* c, long long nB, int m, int cols) {
     if (c->i_cap >= nB && c->i_cap_m >= m && c->i_cap_cols >= cols) return;
-    for (void* q : {(void*)c->iV, (void*)c->ipart, (void*)c->ismall, (void*)c->icoef, (void*)c->ih})
+    for (void* q : {(void*)c->iV, (void*)c->ipart, (void*)c->ismall, (void*)c->icoef, (void*)c->ih,
+                    (void*)c->iR, (void*)c->isn, (void*)c->ig, (void*)c->ics, (void*)c->ibeta,
+                    (void*)c->idone, (void*)c->ikfin, (void*)c->iflag})
         c->arena.release(q, 0);
     nB = std::max(nB, c->i_cap);
     m = std::max(m, c->i_cap_m);
@@ -1405,6 +1517,23 @@ void ensure_inner_basis(hz_ctx* c, long long nB, int m, int cols) {
     c->ismall = (double2*)c->arena.alloc(sizeof(double2) * (m + 2) * (long long)cols);
     c->icoef = (double2*)c->arena.alloc(sizeof(double2) * (m + 2) * (long long)cols);
     c->ih = (double2*)c->arena.alloc(sizeof(double2) * (2 * (m + 1) + 1) * (long long)cols);
+    const long long cl = cols;
+    c->iR = (double2*)c->arena.alloc(sizeof(double2) * ((long long)m * (m + 1) / 2) * cl);
+    c->isn = (double2*)c->arena.alloc(sizeof(double2) * m * cl);
+    c->ig = (double2*)c->arena.alloc(sizeof(double2) * (m + 1) * cl);
+    c->ics = (double*)c->arena.alloc(sizeof(double) * m * cl);
+    c->ibeta = (double*)c->arena.alloc(sizeof(double) * cl);
+    c->idone = (int*)c->arena.alloc(sizeof(int) * cl);
+    c->ikfin = (int*)c->arena.alloc(sizeof(int) * cl);
+    c->iflag = (int*)c->arena.alloc(sizeof(int) * (m + 1));
+    if (c->h_iflag) (void)hipHostFree(c->h_iflag);
+    c->h_iflag = nullptr;
+    if (hipHostMalloc((void**)&c->h_iflag, sizeof(int) * (m + 1), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        c->h_iflag = nullptr;
+        raise(HZ_ENOMEM, "hipHostMalloc of the inner convergence flags failed");
+    }
+    if (!c->iev) HIPCHK(hipEventCreateWithFlags(&c->iev, hipEventDisableTiming));
 }
 
 template <typename T>
@@ -1433,11 +1562,11 @@ void inner_setup(hz_ctx* c, InnerRec<T>& r, int B) {
     r.M->name = fam_name<T>("inner_m_graph");
     build_inner_M<T>(c, r, *r.M, B);
     tune_plan<T>(c, *r.M, B);
-    plan_upload<T>(c, *r.M);
     r.P = std::make_unique<Plan<T>>();
     r.P->name = fam_name<T>("inner_p_graph");
     build_inner_P<T>(c, r, *r.P, B);
     tune_plan<T>(c, *r.P, B);
+    plan_upload<T>(c, *r.M);
     plan_upload<T>(c, *r.P);
 }
 
@@ -1474,27 +1603,14 @@ void inner_solve(hz_ctx* c, InnerRec<T>& r, int B) {
         double2* V = c->iV;
         HIPCHK(hipMemcpyAsync(V, r.wC, sizeof(double2) * nB, hipMemcpyDeviceToDevice, c->st));
         idots(nullptr, 1, V, c->ismall);
-        double2* hb = pinned(c, NB);
-        HIPCHK(hipMemcpyAsync(hb, c->ismall, sizeof(double2) * NB, hipMemcpyDeviceToHost, c->st));
-        sync(c);
-        std::vector<double> beta(NB);
-        std::vector<std::vector<std::complex<double>>> R(m);    // rotated Hessenberg columns
-        std::vector<std::complex<double>> g((size_t)(m + 1) * NB, 0.0);
-        std::vector<double> cs((size_t)m * NB, 1.0);
-        std::vector<std::complex<double>> sn((size_t)m * NB, 0.0);
-        std::vector<int> done(NB, 0), kfin(NB, 0);
-        std::vector<double2> sc(NB);
-        for (int q = 0; q < NB; ++q) {
-            beta[q] = std::sqrt(std::max(0.0, hb[q].x));
-            g[q] = beta[q];
-            if (beta[q] == 0.0) done[q] = 1;
-            sc[q] = make_double2(beta[q] > 0 ? 1.0 / beta[q] : 0.0, 0.0);
-        }
-        upload(c, c->icoef, sc.data(), sizeof(double2) * NB);
+        hipLaunchKernelGGL(k_inner_start, dim3(1), dim3(INNER_STEP_THREADS), 0, c->st, c->ismall, NB,
+                           c->ibeta, c->ig, c->idone, c->ikfin, c->icoef);
         launch_scale_cols(V, V, c->icoef, n, NB, c->st);
+        // The host reads one flag per iteration: every column done.  (Reading
+        // it one iteration behind, so that the next one is already queued,
+        // was slower: the extra iteration costs more than the wait.)
         int j = 0;
         for (; j < m; ++j) {
-            if (std::all_of(done.begin(), done.end(), [](int v) { return v != 0; })) break;
             double2* Vj = V + (long long)j * nB;
             double2* Vn = V + (long long)(j + 1) * nB;
             HIPCHK(hipMemcpyAsync(r.wA, Vj, sizeof(double2) * nB, hipMemcpyDeviceToDevice, c->st));
@@ -1510,59 +1626,25 @@ void inner_solve(hz_ctx* c, InnerRec<T>& r, int B) {
             update_dots_dev(c, V, nB, j + 1, hB2, w, n, NB, 1, hN, c->ipart, chunks);
             launch_inv_norms(hN, c->icoef, NB, c->st);
             launch_scale_cols(Vn, w, c->icoef, n, NB, c->st);
-            double2* hh = pinned(c, 2 * nh + NB);
-            HIPCHK(hipMemcpyAsync(hh, c->ih, sizeof(double2) * (2 * nh + NB),
-                                  hipMemcpyDeviceToHost, c->st));
-            sync(c);
-            R[j].assign((size_t)(j + 1) * NB, 0.0);
-            for (int q = 0; q < NB; ++q) {
-                if (done[q]) continue;
-                std::vector<std::complex<double>> col(j + 2);
-                for (int i = 0; i <= j; ++i) {
-                    const size_t at = (size_t)i * NB + q;
-                    col[i] = std::complex<double>(hh[at].x + hh[nh + at].x, hh[at].y + hh[nh + at].y);
-                }
-                const double nrm = std::sqrt(std::max(0.0, hh[2 * nh + q].x));
-                col[j + 1] = nrm;
-                for (int i = 0; i < j; ++i) {
-                    const double ci = cs[(size_t)i * NB + q];
-                    const std::complex<double> si = sn[(size_t)i * NB + q];
-                    const std::complex<double> a = col[i], b2 = col[i + 1];
-                    col[i] = ci * a + si * b2;
-                    col[i + 1] = -std::conj(si) * a + ci * b2;
-                }
-                double cj; std::complex<double> sj;
-                givens(col[j], col[j + 1], cj, sj);
-                cs[(size_t)j * NB + q] = cj;
-                sn[(size_t)j * NB + q] = sj;
-                col[j] = cj * col[j] + sj * col[j + 1];
-                for (int i = 0; i <= j; ++i) R[j][(size_t)i * NB + q] = col[i];
-                const std::complex<double> gj = g[(size_t)j * NB + q];
-                g[(size_t)(j + 1) * NB + q] = -std::conj(sj) * gj;
-                g[(size_t)j * NB + q] = cj * gj;
-                kfin[q] = j + 1;
-                const double rel = std::abs(g[(size_t)(j + 1) * NB + q]) / beta[q];
-                if (rel <= tol || nrm == 0.0) done[q] = 1;
-            }
+            hipLaunchKernelGGL(k_inner_step, dim3(1), dim3(INNER_STEP_THREADS), 0, c->st, j, NB,
+                               (const double2*)hA, (const double2*)hB2, (const double2*)hN, c->iR,
+                               c->ics, c->isn, c->ig, (const double*)c->ibeta, c->idone, c->ikfin,
+                               tol, c->iflag);
+            HIPCHK(hipMemcpyAsync(c->h_iflag + j, c->iflag + j, sizeof(int), hipMemcpyDeviceToHost,
+                                  c->st));
+            HIPCHK(hipEventRecord(c->iev, c->st));
+            HIPCHK(hipEventSynchronize(c->iev));
+            if (c->h_iflag[j]) { ++j; break; }
         }
         c->inner_iters_max = std::max(c->inner_iters_max, j);
-        // x = V y into wA, then the traces s = d + q of every job
-        const int kmax = *std::max_element(kfin.begin(), kfin.end());
+        // x = V y into wA (coefficients zero beyond each column's own
+        // iteration count), then the traces s = d + q of every job
+        const int kmax = j;
         HIPCHK(hipMemsetAsync(r.wA, 0, sizeof(double2) * nB, c->st));
         if (kmax > 0) {
-            std::vector<double2> coef((size_t)kmax * NB, make_double2(0, 0));
-            for (int q = 0; q < NB; ++q) {
-                const int k = kfin[q];
-                std::vector<std::complex<double>> y(k);
-                for (int i = k - 1; i >= 0; --i) {
-                    std::complex<double> sacc = g[(size_t)i * NB + q];
-                    for (int p2 = i + 1; p2 < k; ++p2) sacc -= R[p2][(size_t)i * NB + q] * y[p2];
-                    y[i] = sacc / R[i][(size_t)i * NB + q];
-                }
-                for (int i = 0; i < k; ++i)
-                    coef[(size_t)i * NB + q] = make_double2(y[i].real(), y[i].imag());
-            }
-            upload(c, c->icoef, coef.data(), sizeof(double2) * coef.size());
+            hipLaunchKernelGGL(k_inner_solve_y, dim3((NB + 255) / 256), dim3(256), 0, c->st, NB, kmax,
+                               (const double2*)c->iR, (const double2*)c->ig,
+                               (const int*)c->ikfin, c->icoef);
             launch_update_basis(r.wA, V, nB, kmax, c->icoef, n, NB, c->st);
         }
         const dim3 ug(std::max<int>(1, (int)std::min<long long>(4096, (n * B / 2 + 255) / 256)), NJ);
@@ -3489,6 +3571,8 @@ void hz_destroy(hz_ctx* c) {
     clear_plans(c);
     c->arena.free_all();
     if (c->h_pin) (void)hipHostFree(c->h_pin);
+    if (c->h_iflag) (void)hipHostFree(c->h_iflag);
+    if (c->iev) (void)hipEventDestroy(c->iev);
     if (c->own_st) (void)hipStreamDestroy(c->own_st);
     delete c;
 }
