@@ -222,8 +222,12 @@ hz_status hz_solve(hz_ctx* ctx, const void* rhs_dev, int B, void* u_dev,
                    double tol, int max_iter, hz_rhs_stats* stats_host,
                    hz_timing* timing);
 
-/* Adjoint solve H^H lam = rhs (same layout and semantics as hz_solve).  H is
- * complex symmetric, so this is conj(H^{-1} conj(rhs)) on the same factors. */
+/* Adjoint solve H^H lam = rhs (same layout and semantics as hz_solve), the
+ * second solve of an adjoint-state misfit gradient (hz_misfit).  The
+ * five-point discretisation of App. A, each row divided by the PML factors
+ * alpha_x alpha_z of its node, is complex symmetric (H = H^T), so
+ * H^H lam = rhs is solved as lam = conj(H^{-1} conj(rhs)) on the same
+ * factors. */
 hz_status hz_adjoint(hz_ctx* ctx, const void* rhs_dev, int B, void* lam_dev,
                      double tol, int max_iter, hz_rhs_stats* stats_host);
 
