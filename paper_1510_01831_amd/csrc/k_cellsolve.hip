@@ -281,6 +281,19 @@ __device__ inline C2<T> e_coef(const C2<T>* ee, int k, int j, int HL) {
     return j < HL ? ee[(long long)k * HL + j] : mk<T>((T)0, (T)0);
 }
 
+// First column of a cell that holds a source or an output: the left pair of
+// the inner interface (p - 1, p) or the first own column.  The columns left
+// of it (the overlap into the left neighbour's PML) carry neither, so the
+// forward sweep starts there (its iterates are zero before) and the backward
+// sweep stops there (nothing left of it is read).  Grid solves use them all.
+template <int MODE>
+__device__ inline int first_live_col(const CellDesc& cd, int p) {
+    if (MODE == SOLVE_GRID) return 0;
+    int k = cd.own_c0;
+    if (cd.has_left && p - 1 < k) k = p - 1;
+    return k < 0 ? 0 : k;
+}
+
 // ===========================================================================
 // NB <= 4: lanes run along the tile's 4 columns, each lane owning one row of
 // a 16-row tile; the 4 partial sums of a row are combined with two shuffles.
@@ -360,21 +373,22 @@ __global__ void __launch_bounds__(CS_THREADS) k_cs_gemv(CellSolveArgs<T> a) {
         return v;
     };
 
+    const int k0 = first_live_col<MODE>(cd, a.p);
     // ---- forward sweep
-    for (int k = 0; k < Wc; ++k) {
-        if (k > 0) matvec(Xf + (long long)(k - 1) * np2);
+    for (int k = k0; k < Wc; ++k) {
+        if (k > k0) matvec(Xf + (long long)(k - 1) * np2);
         __syncthreads();
         for (int q = tid; q < HLp * NB; q += CS_THREADS) {
             const int j = q / NB, c = q % NB;
             C2<T> s = bval(c) ? cell_source<T, MODE>(a, cd, ld, k, j, b0 + c) : mk<T>((T)0, (T)0);
-            if (k > 0) s = csub(s, cmul(e_coef<T>(ee, k, j, HL), rowsum(j, c)));
+            if (k > k0) s = csub(s, cmul(e_coef<T>(ee, k, j, HL), rowsum(j, c)));
             vs[q] = s;
             Y[(long long)k * HLp * NB + q] = s;
         }
         __syncthreads();
     }
     // ---- backward sweep
-    for (int k = Wc - 1; k >= 0; --k) {
+    for (int k = Wc - 1; k >= k0; --k) {
         if (k < Wc - 1) {
             for (int q = tid; q < HLp * NB; q += CS_THREADS) {
                 const int j = q / NB;
@@ -534,9 +548,11 @@ __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const Ce
     C2<T> pv[MCA][NCT][4];   // prefetched sources (forward) / iterates (backward)
     C2<T> pe[MCA][4];        // prefetched coupling coefficients
 
-    // A probe batch's sources are point sources; y_k = 0 before the first
-    // column kmin that holds one, so the forward sweep starts there.
-    int kmin = 0;
+    // The forward sweep starts at the first live column (above); a probe
+    // batch's sources are point sources, so for it y_k = 0 before the first
+    // column kmin that holds one, and the sweep starts there.
+    const int kstop = first_live_col<MODE>(cd, a.p);
+    int kmin = kstop;
     if constexpr (MODE == SOLVE_PROBE) {
         int c = Wc;
         if (lane < NB && bval(lane)) c = probe_col(cd, a.p, a.probe0 + b0 + lane);
@@ -580,9 +596,10 @@ __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const Ce
                 for (int v = 0; v < 4; ++v) vs[row_of(m, v) * NB + t * 16 + lc] = pv[m][t][v];
         __syncthreads();
     }
-    // ---- backward sweep: x_{W-1} = X_{W-1} y_{W-1}, x_k = X_k (y_k - e_{k+1} o x_{k+1})
-    for (int k = Wc - 1; k >= 0; --k) {
-        if (k > 0) {
+    // ---- backward sweep: x_{W-1} = X_{W-1} y_{W-1}, x_k = X_k (y_k - e_{k+1} o x_{k+1}),
+    // down to the first live column
+    for (int k = Wc - 1; k >= kstop; --k) {
+        if (k > kstop) {
 #pragma unroll
             for (int m = 0; m < MC; ++m)
 #pragma unroll
@@ -605,7 +622,7 @@ __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const Ce
                     if (bval(c)) cell_emit<T, MODE>(a, cd, ld, k, row_of(m, v), b0 + c, x);
                     pv[m][t][v] = csub(pv[m][t][v], cmul(pe[m][v], x));
                 }
-        if (k > 0) {
+        if (k > kstop) {
             __syncthreads();
 #pragma unroll
             for (int m = 0; m < MC; ++m)
