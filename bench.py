@@ -47,6 +47,11 @@ METRIC = "DOF-solves/sec at rel. err 1e-8: chosen form vs plain FP64, one MI355X
 PEAK = {"c128": 78.6e12, "c64": 157.3e12}          # dense FP64 / FP32 MFMA peak
 HBM_PEAK = 8.0e12
 ERR_BAR = 1e-8
+# Krylov tolerance of every timed solve: one decade below the metric's error
+# target, so that the measured errors (against FP64 reference solves at
+# 1e-12 and the oracle's direct solve) meet ERR_BAR with margin.  For the
+# refinement form it bounds the estimated error of the refined solution.
+SOLVE_TOL = 1e-9
 
 
 def log(msg):
@@ -365,7 +370,7 @@ def run_workload(name, forms_wanted, steps, warmup, roctx_form="", want_local=Fa
         refs[k] = s64.solve(f_all[k:k + 1].contiguous(), tol=1e-12, max_iter=max_iter)[0]
     if "single" in forms_wanted:
         f1 = f_all[B // 2: B // 2 + 1].contiguous()
-        u1, dt1, prof1, dtp1, st1 = timed_solves(s64, f1, 1e-10, steps, warmup, max_iter,
+        u1, dt1, prof1, dtp1, st1 = timed_solves(s64, f1, SOLVE_TOL, steps, warmup, max_iter,
                                                  region=roctx_form == "fp64_single")
         it1 = st1[0]["iters"]
         log(f"[bench] fp64 single RHS: {dt1 * 1e3:.1f} ms/solve ({dtp1 * 1e3:.1f} profiled), "
@@ -388,14 +393,14 @@ def run_workload(name, forms_wanted, steps, warmup, roctx_form="", want_local=Fa
         info = spl.info
         k = B // 2
         f1 = f_all[k:k + 1].contiguous()
-        up, dtp, profp, dtpp, stp = timed_solves(spl, f1, 1e-10, steps, warmup, max_iter,
+        up, dtp, profp, dtpp, stp = timed_solves(spl, f1, SOLVE_TOL, steps, warmup, max_iter,
                                                  region=roctx_form == "fp64_single_plr")
         errp = float(torch.linalg.norm(up[0] - refs[k]) / torch.linalg.norm(refs[k]))
         gp = None
         if golden is not None:
             gp = {}
             for i, g0 in enumerate(golden["sources"]):
-                ug = spl.solve(f_all[g0:g0 + 1].contiguous(), tol=1e-10, max_iter=max_iter)
+                ug = spl.solve(f_all[g0:g0 + 1].contiguous(), tol=SOLVE_TOL, max_iter=max_iter)
                 got = ug[0][golden["rows"] - 1].cpu().numpy()
                 gp[g0] = float(np.linalg.norm(got - golden["u"][i]) / np.linalg.norm(golden["u"][i]))
                 del ug
@@ -429,7 +434,7 @@ def run_workload(name, forms_wanted, steps, warmup, roctx_form="", want_local=Fa
         del u
 
     if "fp64" in forms_wanted:
-        record("fp64_batched", s64, 1e-10, "c128", t_fac64, "fp64_batched")
+        record("fp64_batched", s64, SOLVE_TOL, "c128", t_fac64, "fp64_batched")
     s64.close()
     del s64
     torch.cuda.empty_cache()
@@ -440,7 +445,7 @@ def run_workload(name, forms_wanted, steps, warmup, roctx_form="", want_local=Fa
         torch.cuda.synchronize()
         t_fac = time.perf_counter() - t0
         log(f"[bench] mixed setup+factor {t_fac:.2f} s")
-        record("mixed_batched", smx, 1e-10, "c64+c128", t_fac, "mixed_batched")
+        record("mixed_batched", smx, SOLVE_TOL, "c64+c128", t_fac, "mixed_batched")
         if want_local:
             extras["local_refactor"] = local_refactor(smx, c, w, f_all, ref_idx, max_iter)
         smx.close()
@@ -454,7 +459,7 @@ def run_workload(name, forms_wanted, steps, warmup, roctx_form="", want_local=Fa
         t_fac = time.perf_counter() - t0
         log(f"[bench] refine setup+factor {t_fac:.2f} s")
         # tolerance: estimated relative error of the refined volume solution
-        record("refine_batched", srf, 1e-9, "c64+c128", t_fac, "refine_batched")
+        record("refine_batched", srf, SOLVE_TOL, "c64+c128", t_fac, "refine_batched")
         srf.close()
         del srf
         torch.cuda.empty_cache()
@@ -469,7 +474,7 @@ def run_workload(name, forms_wanted, steps, warmup, roctx_form="", want_local=Fa
         t_fac = time.perf_counter() - t0
         log(f"[bench] nested polarized traces setup+factor {t_fac:.2f} s")
         extras["memory"]["fp64_nested_pt_device_bytes"] = spt.info.device_bytes
-        record("nested_pt_batched", spt, 1e-10, "c128", t_fac, "nested_pt_batched")
+        record("nested_pt_batched", spt, SOLVE_TOL, "c128", t_fac, "nested_pt_batched")
         spt.close()
         del spt
         torch.cuda.empty_cache()
@@ -601,7 +606,7 @@ def main():
         "config": {"workload": (f"{w.name}: n={n} (+{w.n_pml} PML), {MEDIUM[w.name]}, "
                                 f"omega={w.omega:.2f} (10 ppw at c_min), {w.layers} layers x "
                                 f"{w.cells} cells, {B} point sources on depth row {w.src_z}"),
-                   "form": chosen, "batch": B if pool else 1,
+                   "form": chosen, "batch": B if pool else 1, "krylov_tol": SOLVE_TOL,
                    "max_rel_err_vs_fp64": r["err"],
                    "rel_err_vs_oracle_rows": r["gerr"], "gmres_iters": r["its"],
                    "setup_factor_s": r["t_fac"],
