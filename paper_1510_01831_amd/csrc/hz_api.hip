@@ -828,19 +828,24 @@ void tune_plan(hz_ctx* c, Plan<T>& pl, int B) {
         return;
     }
     if (!c->tune || B < 16 || pl.launches.empty()) return;
-    long long in_elems = 1, out_elems = 1;
+    // Trials read the launch's own inputs (reading disturbs nothing) and write
+    // every output segment to its own place in a scratch buffer, so that they
+    // see the launch's real memory traffic: with one shared input buffer the
+    // inputs stayed in L2 and tiles that re-read them looked cheaper than they
+    // are.  add0 / add1 are dropped (they only add a read per output entry).
+    long long out_elems = 1;
     int max_tasks = 1;
-    for (const auto& r : pl.launches) max_tasks = std::max(max_tasks, r.ntasks);
-    for (const auto& t : pl.tasks) {
-        for (int q = 0; q < t.nseg; ++q)
-            if (t.seg_ptr[q]) in_elems = std::max(in_elems, (long long)t.seg_len[q] * t.ldx);
-        for (int q = 0; q < t.noseg; ++q)
-            out_elems = std::max(out_elems, (long long)t.oseg_len[q] * t.ldo);
+    for (const auto& r : pl.launches) {
+        max_tasks = std::max(max_tasks, r.ntasks);
+        long long tot = 0;
+        for (int q2 = 0; q2 < r.ntasks; ++q2) {
+            const GemmTask<T>& t = pl.tasks[r.off + q2];
+            for (int q = 0; q < t.noseg; ++q) tot += (long long)t.oseg_len[q] * t.ldo;
+        }
+        out_elems = std::max(out_elems, tot);
     }
-    C2<T>* sin = alloc_c<T>(c, in_elems);
     C2<T>* sout = alloc_c<T>(c, out_elems);
     GemmTask<T>* dt = (GemmTask<T>*)c->arena.alloc(sizeof(GemmTask<T>) * max_tasks);
-    HIPCHK(hipMemsetAsync(sin, 0, sizeof(C2<T>) * in_elems, c->st));
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -848,11 +853,11 @@ void tune_plan(hz_ctx* c, Plan<T>& pl, int B) {
         if (r.kind != L_GEMM) continue;
         if (gemm_kernel(r.ntasks, r.max_m, B) < GEMM_MFMA32) continue;
         std::vector<GemmTask<T>> tt(pl.tasks.begin() + r.off, pl.tasks.begin() + r.off + r.ntasks);
+        long long at = 0;
         for (auto& t : tt) {
-            for (int q = 0; q < t.nseg; ++q)
-                if (t.seg_ptr[q]) t.seg_ptr[q] = sin;
             for (int q = 0; q < t.noseg; ++q) {
-                t.oseg_ptr[q] = sout;
+                t.oseg_ptr[q] = sout + at;
+                at += (long long)t.oseg_len[q] * t.ldo;
                 t.oseg_add0[q] = nullptr;
                 t.oseg_add1[q] = nullptr;
             }
@@ -869,6 +874,13 @@ void tune_plan(hz_ctx* c, Plan<T>& pl, int B) {
                          (int)GEMM_MFMA64S8, (int)GEMM_MFMA32X64S4, (int)GEMM_MFMA32X64S8,
                          (int)GEMM_MFMA32DS4, (int)GEMM_MFMA32DS8}) {
             if (cand == dflt && best < 1e30f) continue;
+            // launches big enough for 64 x 64 tiles keep 64-row tiles: there
+            // the back-to-back trial launches find their inputs in cache and
+            // favour 32-row tiles that re-read them, which lose in the solve
+            if (dflt == GEMM_MFMA64 &&
+                !(cand == GEMM_MFMA64 || cand == GEMM_MFMA64D || cand == GEMM_MFMA64X32 ||
+                  cand == GEMM_MFMA64S2 || cand == GEMM_MFMA64S4 || cand == GEMM_MFMA64S8))
+                continue;
             if ((cand == GEMM_MFMA64 || cand == GEMM_MFMA64D || cand == GEMM_MFMA32X64 ||
                  cand == GEMM_MFMA64S2 || cand == GEMM_MFMA64S4 || cand == GEMM_MFMA64S8 ||
                  cand == GEMM_MFMA32X64S4 || cand == GEMM_MFMA32X64S8) && B < 64)
@@ -887,7 +899,6 @@ void tune_plan(hz_ctx* c, Plan<T>& pl, int B) {
     HIPCHK(hipGetLastError());
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    c->arena.release(sin, 0);
     c->arena.release(sout, 0);
     c->arena.release(dt, 0);
 }

@@ -150,17 +150,27 @@ k_gemm_tiled(const GemmTask<T>* __restrict__ tasks, int B) {
 // barrier per chunk separates the loads from the products.  The 4 waves form
 // a 2 x 2 grid, each computing (MT/2) x (TBM/2) as 16x16 complex tiles (four
 // real MFMAs per 4-deep k step).
-// Per-thread operand pointers for the current input segment: set once per
-// segment, so loading a chunk costs one offset add per element instead of
-// the row/column index arithmetic.
+// Operand cursor for the current input segment, set once per segment.  The
+// block size (256) is a multiple of KC and of TBM, so entry e of a thread's
+// share of a chunk sits at a fixed row or k offset from entry 0: one base
+// pointer per operand plus uniform strides (few registers per lane, so more
+// workgroups and chunks in flight fit on a CU).
+//   A entry e: row  tid / KC + e (256 / KC),   k offset tid % KC
+//   x entry e: k offset tid / TBM + e (256 / TBM), column tid % TBM
 template <typename T, int MT, int TBM, int KC>
 struct GemmCursor {
     static constexpr int NA = MT * KC / GV_THREADS;    // A entries per thread
     static constexpr int NX = KC * TBM / GV_THREADS;   // x entries per thread
-    const C2<T>* ab[NA];
-    const C2<T>* xb[NX];
-    int aq[NA], xq[NX];     // k offset inside a chunk; -1: row / column out of range
+    static constexpr int RA = GV_THREADS / KC;         // A rows between entries
+    static constexpr int QX = GV_THREADS / TBM;        // x rows between entries
+    static_assert(GV_THREADS % KC == 0 && GV_THREADS % TBM == 0, "cursor layout");
+    const C2<T>* a0;        // A entry 0 (row clamped into range)
+    const C2<T>* x0;        // x entry 0 (column clamped into range)
+    long long astep;        // RA * lda
     long long ldx;
+    int qa, qx;             // k offset of A entries / of x entry 0 inside a chunk
+    unsigned amask;         // bit e: A entry e's row is inside the task
+    bool xok;               // the thread's x column is inside the batch
     int sg, len;
 
     __device__ __forceinline__ void set(const GemmTask<T>& t, int s, int i0, int b0, int B,
@@ -168,42 +178,43 @@ struct GemmCursor {
         sg = s;
         len = t.seg_len[s];
         ldx = t.ldx;
-        const C2<T>* A = t.A;
-        const C2<T>* xp = t.seg_ptr[s];
         const long long lda = t.lda;
         const int k0 = t.seg_k0[s], m = t.m;
+        const int r0 = i0 + tid / KC;
+        qa = tid % KC;
+        amask = 0;
 #pragma unroll
-        for (int e = 0; e < NA; ++e) {
-            const int idx = tid + e * GV_THREADS, r = idx / KC, q = idx % KC, i = i0 + r;
-            aq[e] = i < m ? q : -1;
-            ab[e] = A + (long long)(i < m ? i : 0) * lda + k0 + q;
-        }
-#pragma unroll
-        for (int e = 0; e < NX; ++e) {
-            const int idx = tid + e * GV_THREADS, q = idx / TBM, c = idx % TBM;
-            xq[e] = b0 + c < B ? q : -1;
-            xb[e] = xp + (long long)q * ldx + (b0 + c < B ? b0 + c : 0);
-        }
+        for (int e = 0; e < NA; ++e)
+            if (r0 + e * RA < m) amask |= 1u << e;
+        astep = (long long)RA * lda;
+        a0 = t.A + (long long)(r0 < m ? r0 : 0) * lda + k0 + qa;
+        const int c = tid % TBM;
+        qx = tid / TBM;
+        xok = b0 + c < B;
+        x0 = t.seg_ptr[s] + (long long)qx * ldx + (xok ? b0 + c : 0);
     }
 };
 
 template <typename T, int MT, int TBM, int KC>
 struct GemmStage {
-    static constexpr int NA = MT * KC / GV_THREADS;    // A entries per thread
-    static constexpr int NX = KC * TBM / GV_THREADS;   // x entries per thread
+    using Cur = GemmCursor<T, MT, TBM, KC>;
+    static constexpr int NA = Cur::NA;
+    static constexpr int NX = Cur::NX;
     C2<T> a[NA], x[NX];
 
     // chunk starting at k offset kc of the cursor's segment
-    __device__ __forceinline__ void load(const GemmCursor<T, MT, TBM, KC>& cu, int kc) {
-        const long long xo = (long long)kc * cu.ldx;
+    __device__ __forceinline__ void load(const Cur& cu, int kc) {
+        const bool ka = kc + cu.qa < cu.len;
 #pragma unroll
         for (int e = 0; e < NA; ++e)
-            a[e] = (cu.aq[e] >= 0 && kc + cu.aq[e] < cu.len) ? gload<T>(cu.ab[e] + kc)
-                                                               : mk<T>((T)0, (T)0);
+            a[e] = (ka && ((cu.amask >> e) & 1u)) ? gload<T>(cu.a0 + e * cu.astep + kc)
+                                                  : mk<T>((T)0, (T)0);
+        const long long xo = (long long)kc * cu.ldx;
 #pragma unroll
         for (int e = 0; e < NX; ++e)
-            x[e] = (cu.xq[e] >= 0 && kc + cu.xq[e] < cu.len) ? gload<T>(cu.xb[e] + xo)
-                                                               : mk<T>((T)0, (T)0);
+            x[e] = (cu.xok && kc + cu.qx + e * Cur::QX < cu.len)
+                       ? gload<T>(cu.x0 + (long long)e * Cur::QX * cu.ldx + xo)
+                       : mk<T>((T)0, (T)0);
     }
     __device__ __forceinline__ void stash(C2<T> (*As)[KC + 1], C2<T> (*Xs)[TBM + 1], int tid) const {
 #pragma unroll
