@@ -420,12 +420,15 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
 // Second pass of split k: one workgroup per output tile; thread tid adds, in
 // split order, the partial accumulators that thread tid of each split
 // workgroup stored (same register-to-element map as k_gemm_mfma) and applies
-// the task's epilogue.
+// the task's epilogue (same arithmetic order as the unsplit kernels).  All
+// partial loads of a thread are issued before the sums and all epilogue reads
+// before the stores, instead of two dependent round trips per entry.
 template <typename T, int MT, int TBM>
 __global__ void __launch_bounds__(GV_THREADS)
 k_gemm_split_reduce(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col_tiles,
                     int splits, const C2<T>* __restrict__ ws) {
     constexpr int RTW = MT / 32, CTW = TBM / 32, NV = RTW * CTW * 4;
+    constexpr int SMAX = 8;                      // largest split of the split kinds
     const int per_task = row_tiles * col_tiles;
     const int tile = blockIdx.x;
     const int task = tile / per_task, rc = tile - task * per_task;
@@ -440,6 +443,22 @@ k_gemm_split_reduce(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles,
     const int lc = lane & 15;
     const int wr = (w >> 1) * (MT / 2), wc = (w & 1) * (TBM / 2);
     const C2<T>* base = ws + (long long)tile * splits * GV_THREADS * NV + (long long)tid * NV;
+    const long long sstride = (long long)GV_THREADS * NV;
+    C2<T> sum[NV];
+#pragma unroll
+    for (int e = 0; e < NV; ++e) sum[e] = gload<T>(base + e);
+#pragma unroll
+    for (int q = 1; q < SMAX; ++q) {
+        if (q >= splits) break;
+        C2<T> part[NV];
+#pragma unroll
+        for (int e = 0; e < NV; ++e) part[e] = gload<T>(base + q * sstride + e);
+#pragma unroll
+        for (int e = 0; e < NV; ++e) sum[e] = cadd(sum[e], part[e]);
+    }
+    // epilogue: output segment and offset of every entry, then the adds
+    C2<T>* dst[NV];
+    C2<T> ad0[NV], ad1[NV];        // add0 and c1 * add1 of each entry (zero when absent)
 #pragma unroll
     for (int a = 0; a < RTW; ++a)
 #pragma unroll
@@ -449,12 +468,23 @@ k_gemm_split_reduce(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles,
                 const int e = (a * CTW + c) * 4 + v;
                 const int i = i0 + wr + a * 16 + Mf<T>::row(lane, v);
                 const int b = b0 + wc + c * 16 + lc;
+                dst[e] = nullptr;
+                ad0[e] = mk<T>((T)0, (T)0);
+                ad1[e] = mk<T>((T)0, (T)0);
                 if (i >= t.m || b >= B) continue;
-                C2<T> sum = gload<T>(base + e);
-                for (int q = 1; q < splits; ++q)
-                    sum = cadd(sum, gload<T>(base + (long long)q * GV_THREADS * NV + e));
-                epilogue<T>(t, i, b, sum);
+                for (int sg = 0; sg < t.noseg; ++sg) {
+                    const int rel = i - t.oseg_i0[sg];
+                    if (rel < 0 || rel >= t.oseg_len[sg]) continue;
+                    const long long off = (long long)rel * t.ldo + b;
+                    dst[e] = t.oseg_ptr[sg] + off;
+                    if (t.oseg_add0[sg]) ad0[e] = gload<T>(t.oseg_add0[sg] + off);
+                    if (t.oseg_add1[sg]) ad1[e] = cscale(gload<T>(t.oseg_add1[sg] + off), t.c1[sg]);
+                    break;
+                }
             }
+#pragma unroll
+    for (int e = 0; e < NV; ++e)
+        if (dst[e]) gstore<T>(dst[e], cadd(cadd(cscale(sum[e], t.alpha), ad0[e]), ad1[e]));
 }
 
 template <typename T>
