@@ -405,6 +405,36 @@ k_gemm_mfma(const GemmTask<T>* __restrict__ tasks, int B, int row_tiles, int col
                     gstore<T>(mine + (a * CTW + c) * 4 + v, mk<T>(acc[a][c].re(v), acc[a][c].im(v)));
         return;
     }
+    if constexpr (RTW * CTW == 1) {
+        // 32 x 32 tiles (short launches of the sweeps): the epilogue reads
+        // of the thread's four entries are issued together before the stores
+        C2<T>* dst[4];
+        C2<T> ad0[4], ad1[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = i0 + wr + Mf<T>::row(lane, v);
+            const int b = b0 + wc + lc;
+            dst[v] = nullptr;
+            ad0[v] = mk<T>((T)0, (T)0);
+            ad1[v] = mk<T>((T)0, (T)0);
+            if (i >= t.m || b >= B) continue;
+            for (int sg = 0; sg < t.noseg; ++sg) {
+                const int rel = i - t.oseg_i0[sg];
+                if (rel < 0 || rel >= t.oseg_len[sg]) continue;
+                const long long off = (long long)rel * t.ldo + b;
+                dst[v] = t.oseg_ptr[sg] + off;
+                if (t.oseg_add0[sg]) ad0[v] = gload<T>(t.oseg_add0[sg] + off);
+                if (t.oseg_add1[sg]) ad1[v] = cscale(gload<T>(t.oseg_add1[sg] + off), t.c1[sg]);
+                break;
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            if (dst[v])
+                gstore<T>(dst[v], cadd(cadd(cscale(mk<T>(acc[0][0].re(v), acc[0][0].im(v)), t.alpha),
+                                            ad0[v]), ad1[v]));
+        return;
+    }
 #pragma unroll
     for (int a = 0; a < RTW; ++a)
 #pragma unroll
