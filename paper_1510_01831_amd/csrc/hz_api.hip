@@ -1799,11 +1799,16 @@ void cell_solve_launch(hz_ctx* c, CellSolveArgs<T> a, const std::vector<int>& li
                 double bytes = 0, flops = 0;
                 for (int q = 0; q < cnt; ++q) {
                     const CellDesc& cd = c->cells[list[g + q]];
-                    const double blk = (double)cd.Wc * cd.HL * cd.HL;
+                    // the sweeps run over the live columns only (from the left
+                    // pair column or the first own column; see the kernels)
+                    int k0 = cd.own_c0;
+                    if (cd.has_left) k0 = std::min(k0, c->d.p - 1);
+                    const double wl = (double)(cd.Wc - std::max(k0, 0));
+                    const double blk = wl * cd.HL * cd.HL;
                     // factors read in both sweeps, forward iterates written and
                     // read back, one source and one result per grid node
-                    bytes += sizeof(C2<T>) * (2.0 * blk + 4.0 * (double)cd.Wc * cd.HL * Bcols);
-                    flops += 8.0 * (2.0 * cd.Wc - 1.0) * cd.HL * cd.HL * Bcols;
+                    bytes += sizeof(C2<T>) * (2.0 * blk + 4.0 * wl * cd.HL * Bcols);
+                    flops += 8.0 * (2.0 * wl - 1.0) * cd.HL * cd.HL * Bcols;
                 }
                 const char* fam = a.mode == SOLVE_VOLUME ? "cell_solve_volume"
                                   : a.mode == SOLVE_SAMPLE ? "cell_solve_sample" : "cell_solve_other";

@@ -51,31 +51,32 @@ __global__ void __launch_bounds__(GV_THREADS) k_gemv(const GemmTask<T>* __restri
         const int i = blockIdx.x * GV_ROWS + rr;
         if (i >= t.m) break;
         const C2<T>* Ar = t.A + (long long)i * t.lda;
-        // four independent accumulators: four loads of A and x in flight per
-        // lane (a single-RHS product is bound by memory latency otherwise)
-        C2<T> a4[4];
+        // GV_U loads of A and x in flight per lane, guarded at the end of a
+        // segment instead of a one-load remainder loop (a single-RHS product
+        // is bound by memory latency: every round trip of a row's stream
+        // counts); three accumulators leave the registers to the loads
+        constexpr int GV_U = 6, GV_ACC = 3;
+        C2<T> au[GV_ACC];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) a4[u] = mk<T>((T)0, (T)0);
+        for (int u = 0; u < GV_ACC; ++u) au[u] = mk<T>((T)0, (T)0);
         for (int s = 0; s < t.nseg; ++s) {
             const C2<T>* xp = t.seg_ptr[s];
             if (!xp) continue;
             const int k0 = t.seg_k0[s], len = t.seg_len[s];
             const long long ldx = t.ldx;
-            int kk = lane;
-            for (; kk + 192 < len; kk += 256) {
-                C2<T> av[4], xv[4];
+            for (int kk = lane; kk < len; kk += 64 * GV_U) {
+                C2<T> av[GV_U], xv[GV_U];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    av[u] = gload<T>(Ar + k0 + kk + 64 * u);
-                    xv[u] = gload<T>(xp + (long long)(kk + 64 * u) * ldx);
+                for (int u = 0; u < GV_U; ++u) {
+                    const bool in = kk + 64 * u < len;
+                    av[u] = in ? gload<T>(Ar + k0 + kk + 64 * u) : mk<T>((T)0, (T)0);
+                    xv[u] = in ? gload<T>(xp + (long long)(kk + 64 * u) * ldx) : mk<T>((T)0, (T)0);
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) a4[u] = cfma(av[u], xv[u], a4[u]);
+                for (int u = 0; u < GV_U; ++u) au[u % GV_ACC] = cfma(av[u], xv[u], au[u % GV_ACC]);
             }
-            for (; kk < len; kk += 64)
-                a4[0] = cfma(gload<T>(Ar + k0 + kk), gload<T>(xp + (long long)kk * ldx), a4[0]);
         }
-        C2<T> acc = cadd(cadd(a4[0], a4[1]), cadd(a4[2], a4[3]));
+        C2<T> acc = cadd(cadd(au[0], au[1]), au[2]);
         for (int d = 32; d > 0; d >>= 1) {
             C2<T> o = shfl_down_c<T>(acc, d);
             acc.x += o.x; acc.y += o.y;
