@@ -118,10 +118,12 @@ def kernel_src_hash(family):
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(family, workload):
+def recorded_traffic(family, workload, alg_bytes=None):
     """HBM bytes per launch measured with the FETCH_SIZE / WRITE_SIZE
-    counters for this kernel on this workload, from the summaries in
-    profiles/; None when no summary covers the kernel as it is now."""
+    counters for this kernel on this workload and launch shape (a summary's
+    alg_bytes, when present, must equal the record's algorithmic bytes per
+    launch), from the summaries in profiles/; None when no summary covers
+    the kernel as it is now."""
     pdir = os.path.join(ROOT, "profiles")
     if not os.path.isdir(pdir):
         return None
@@ -135,7 +137,9 @@ def recorded_traffic(family, workload):
                     continue
                 kv = dict(x.split("=", 1) for x in line.split()[1:])
                 if (kv.get("kernel") == family and kv.get("src") == want
-                        and kv.get("workload", workload) == workload):
+                        and kv.get("workload", workload) == workload
+                        and (alg_bytes is None or "alg_bytes" not in kv
+                             or abs(float(kv["alg_bytes"]) - alg_bytes) <= 5e-3 * alg_bytes)):
                     return float(kv["bytes_per_launch"])
     return None
 
@@ -149,7 +153,7 @@ def roofline(k, B, workload):
     rec = {"kernel": k["name"], "launches": k["launches"], "avg_launch_ms": avg_ms,
            "flops_per_launch": k["flops"] / k["launches"],
            "bytes_per_launch": k["bytes"] / k["launches"],
-           "traffic": recorded_traffic(k["name"], workload)}
+           "traffic": recorded_traffic(k["name"], workload, k["bytes"] / k["launches"])}
     if B > 1:
         achieved = k["flops"] / (k["ms"] * 1e-3)
         rec.update({"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12,

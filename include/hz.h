@@ -309,7 +309,7 @@ hz_status hz_set_stream(hz_ctx* ctx, void* hip_stream);
  * and flops are accumulated per kernel family.  hz_profile(ctx, 1) clears
  * the counters; hz_profile_read fills up to `max` records. */
 typedef struct {
-    char name[32];           /* kernel family */
+    char name[32];           /* kernel family (one record per family and launch shape) */
     int launches;
     double ms;               /* summed launch durations (event to event) */
     double bytes;            /* summed algorithmic bytes */

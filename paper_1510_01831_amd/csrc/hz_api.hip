@@ -477,7 +477,12 @@ void prof_flush(hz_ctx* c) {
     for (const auto& q : P.pend) {
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, P.pool[q.e0], P.pool[q.e1]));
-        hz_kstat& k = P.acc[q.fam];
+        // one record per kernel family and launch shape (launches of one
+        // shape have the same algorithmic flops), so per-launch averages
+        // describe one kind of launch
+        const std::string key = q.fam + "#" + std::to_string(std::llround(q.flops)) + "#" +
+                                std::to_string(std::llround(q.bytes));
+        hz_kstat& k = P.acc[key];
         std::snprintf(k.name, sizeof(k.name), "%s", q.fam.c_str());
         k.launches += 1;
         k.ms += ms;

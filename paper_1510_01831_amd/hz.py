@@ -263,11 +263,11 @@ class Solver:
         _check(lib().hz_profile(self.ctx, int(bool(on))), "hz_profile")
 
     def profile_read(self) -> list:
-        arr = (KStat * 32)()
+        arr = (KStat * 256)()
         cnt = ctypes.c_int()
-        _check(lib().hz_profile_read(self.ctx, arr, 32, ctypes.byref(cnt)), "hz_profile_read")
+        _check(lib().hz_profile_read(self.ctx, arr, 256, ctypes.byref(cnt)), "hz_profile_read")
         return [dict(name=k.name.decode(), launches=k.launches, ms=k.ms, bytes=k.bytes,
-                     flops=k.flops) for k in arr[:min(cnt.value, 32)]]
+                     flops=k.flops) for k in arr[:min(cnt.value, 256)]]
 
     def timing(self) -> dict:
         t = Timing()
