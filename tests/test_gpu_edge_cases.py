@@ -1,0 +1,87 @@
+"""Degenerate inputs of the solve on the GPU: right-hand sides that are zero
+(one column of a batch, a whole batch, a single source) in every precision
+form and with the iterated inner solver, and a ragged batch.  A zero source
+has the zero solution (H is nonsingular); the Krylov drivers must report it
+without dividing by the zero residual norm, and the other columns of the
+batch must not change.  The nonzero columns are checked against the
+oracle's direct solve."""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle.discretization import Problem  # noqa: E402
+from paper_1510_01831_amd import hz, media  # noqa: E402
+
+N, P, L, LC = 47, 8, 3, 3
+FORMS = [(hz.HZ_FP64, hz.HZ_INNER_LU, 1e-9), (hz.HZ_MIXED, hz.HZ_INNER_LU, 1e-8),
+         (hz.HZ_MIXED_REFINE, hz.HZ_INNER_LU, 1e-8), (hz.HZ_FP64, hz.HZ_INNER_PT, 1e-8)]
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def small():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c, omega = media.small_problem(N, P, L, LC, seed=8)
+    prob = Problem(c, omega, P)
+    lu = spla.splu(prob.H.tocsc())
+    return c, omega, prob, lu
+
+
+def _direct(prob, lu, f):
+    return prob.restrict(lu.solve(prob.extend(f).ravel()).reshape(prob.W, prob.W))
+
+
+@pytest.mark.parametrize("prec,inner,bar", FORMS)
+def test_zero_right_hand_sides(small, prec, inner, bar):
+    c, omega, prob, lu = small
+    _log(f"[edge] zero columns: precision={prec} inner={inner}")
+    f = media.point_sources(N, (10, 30, 36), 20)
+    f[1] = 0.0
+    s = hz.Solver(torch.from_numpy(c), omega, P, L, LC, precision=prec, max_batch=3, inner=inner)
+    tol = 1e-11 if prec == hz.HZ_FP64 else 1e-10
+    u = s.solve(torch.from_numpy(f), tol=tol).cpu().numpy()
+    assert np.all(np.isfinite(u))
+    assert not np.any(u[1])                          # exactly zero
+    for b in (0, 2):
+        ref = _direct(prob, lu, f[b])
+        err = np.linalg.norm(u[b] - ref) / np.linalg.norm(ref)
+        _log(f"  column {b}: err {err:.2e}")
+        assert err <= bar
+    # a batch of zeros and a single zero source
+    z = s.solve(torch.zeros((3, N, N), dtype=torch.complex128)).cpu().numpy()
+    assert np.all(np.isfinite(z)) and not np.any(z)
+    z1 = s.solve(torch.zeros((1, N, N), dtype=torch.complex128)).cpu().numpy()
+    assert np.all(np.isfinite(z1)) and not np.any(z1)
+    # the context still solves afterwards
+    u2 = s.solve(torch.from_numpy(f), tol=tol).cpu().numpy()
+    assert np.linalg.norm(u2 - u) <= 1e-12 * np.linalg.norm(u)
+    s.close()
+
+
+def test_ragged_batch_matches_single_solves(small):
+    """B = 19 (not a multiple of the 16- or 32-column kernel widths) in one
+    solve against the same sources solved one at a time."""
+    c, omega, prob, lu = small
+    xs = tuple(range(4, 42, 2))[:19]
+    f = media.point_sources(N, xs, 15)
+    s = hz.Solver(torch.from_numpy(c), omega, P, L, LC, max_batch=19)
+    u = s.solve(torch.from_numpy(f), tol=1e-12).cpu().numpy()
+    worst = 0.0
+    for b in (0, 7, 18):
+        ub = s.solve(torch.from_numpy(f[b:b + 1].copy()), tol=1e-12).cpu().numpy()[0]
+        ref = _direct(prob, lu, f[b])
+        worst = max(worst, np.linalg.norm(u[b] - ref) / np.linalg.norm(ref))
+        assert np.linalg.norm(u[b] - ub) / np.linalg.norm(ub) <= 1e-9
+    _log(f"[edge] ragged batch of 19: worst err vs direct {worst:.2e}")
+    assert worst <= 1e-9
+    s.close()
