@@ -106,7 +106,8 @@ def timed_solves(solver, f, tol, steps, warmup, max_iter, prof_steps=1, region=F
 
 
 KERNEL_SOURCES = {"gemm": ["k_gemm.hip", "hz_mfma.h", "hz_common.h"],
-                  "cell_solve": ["k_cellsolve.hip", "hz_mfma.h", "hz_common.h"]}
+                  "cell_solve": ["k_cellsolve.hip", "hz_mfma.h", "hz_common.h"],
+                  "plr": ["k_plr.hip", "hz_common.h"]}
 
 
 def kernel_src_hash(family):
@@ -114,7 +115,8 @@ def kernel_src_hash(family):
     profiles/ are used only while the kernel is unchanged)."""
     import hashlib
 
-    group = "gemm" if family.startswith(("gemm", "gemv")) else "cell_solve"
+    group = ("plr" if family.startswith("plr") else
+             "gemm" if family.startswith(("gemm", "gemv")) else "cell_solve")
     h = hashlib.sha256()
     for f in KERNEL_SOURCES[group]:
         with open(os.path.join(ROOT, "paper_1510_01831_amd", "csrc", f), "rb") as fh:
