@@ -114,6 +114,7 @@ struct LaunchRec {
     int choice = -1;      // GEMM kernel picked by the autotuner (-1: default)
     bool plr = false;     // every task applies its operator in PLR form (B = 1)
     int plr_tiles = 0, plr_rows = 0;   // largest tile count / tile-row count of a task
+    double bytes_dense = 0;            // algorithmic bytes of the dense form of a PLR launch
 };
 
 // Partitioned low-rank operators of the preconditioner (precision T): the
@@ -1138,6 +1139,7 @@ void plr_mark(hz_ctx* c, Plan<T>& pl) {
         r.plr = true;
         r.plr_tiles = mt;
         r.plr_rows = mr;
+        r.bytes_dense = r.bytes;
         r.bytes = bytes;
         need = std::max(need, tot);
     }
@@ -1146,6 +1148,74 @@ void plr_mark(hz_ctx* c, Plan<T>& pl) {
         ps.part = alloc_c<T>(c, need * PLR_TILE);
         ps.part_tiles = need;
     }
+}
+
+// Single-RHS plans with compressed operators: every PLR launch is timed
+// against the dense matrix-vector launch of the same tasks (outputs
+// redirected to scratch) and keeps the compressed form only where it is
+// faster.  The PLR apply is two dependent kernels, so for short launches of
+// small operators its latency outweighs the bytes it saves.
+template <typename T>
+void tune_plr(hz_ctx* c, Plan<T>& pl) {
+    if (!c->tune) return;
+    long long out_elems = 1;
+    int max_tasks = 0;
+    for (const auto& r : pl.launches) {
+        if (r.kind != L_GEMM || !r.plr) continue;
+        max_tasks = std::max(max_tasks, r.ntasks);
+        long long tot = 0;
+        for (int q2 = 0; q2 < r.ntasks; ++q2) {
+            const GemmTask<T>& t = pl.tasks[r.off + q2];
+            for (int q = 0; q < t.noseg; ++q) tot += (long long)t.oseg_len[q] * t.ldo;
+        }
+        out_elems = std::max(out_elems, tot);
+    }
+    if (max_tasks == 0) return;
+    PlrStore<T>& ps = plr_store<T>(c);
+    C2<T>* sout = alloc_c<T>(c, out_elems);
+    GemmTask<T>* dt = (GemmTask<T>*)c->arena.alloc(sizeof(GemmTask<T>) * max_tasks);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    for (auto& r : pl.launches) {
+        if (r.kind != L_GEMM || !r.plr) continue;
+        std::vector<GemmTask<T>> tt(pl.tasks.begin() + r.off, pl.tasks.begin() + r.off + r.ntasks);
+        long long at = 0;
+        for (auto& t : tt)
+            for (int q = 0; q < t.noseg; ++q) {
+                t.oseg_ptr[q] = sout + at;
+                at += (long long)t.oseg_len[q] * t.ldo;
+                t.oseg_add0[q] = nullptr;
+                t.oseg_add1[q] = nullptr;
+            }
+        upload(c, dt, tt.data(), sizeof(GemmTask<T>) * tt.size());
+        auto timed = [&](bool compressed) {
+            auto once = [&] {
+                if (compressed)
+                    launch_plr_apply<T>(dt, r.ntasks, r.plr_tiles, r.plr_rows, ps.part, c->st);
+                else
+                    launch_gemm<T>(dt, r.ntasks, r.max_m, 1, c->st, false, -1, &c->gsw);
+            };
+            once();                                    // warm-up
+            HIPCHK(hipEventRecord(e0, c->st));
+            for (int rep = 0; rep < 3; ++rep) once();
+            HIPCHK(hipEventRecord(e1, c->st));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            return ms;
+        };
+        const float tp = timed(true), td = timed(false);
+        if (td < tp) {
+            r.plr = false;
+            r.bytes = r.bytes_dense;
+        }
+    }
+    HIPCHK(hipGetLastError());
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->arena.release(sout, 0);
+    c->arena.release(dt, 0);
 }
 
 template <typename T>
@@ -1159,7 +1229,10 @@ Plan<T>& get_plan(hz_ctx* c, bool sie, int B) {
     pl->inner_loose = !sie;
     if (sie) build_sie_plan<T>(c, *pl, B);
     else build_pre_plan<T>(c, *pl, B);
-    if (!sie && B == 1) plr_mark<T>(c, *pl);
+    if (!sie && B == 1) {
+        plr_mark<T>(c, *pl);
+        tune_plr<T>(c, *pl);
+    }
     tune_plan<T>(c, *pl, B);
     plan_upload<T>(c, *pl);
     Plan<T>& ref = *pl;
