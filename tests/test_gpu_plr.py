@@ -37,11 +37,15 @@ def small():
     return c, omega, prob, lu
 
 
+@pytest.mark.parametrize("tune", ["1", "0"])
 @pytest.mark.parametrize("prec,bar", [(hz.HZ_FP64, 1e-9), (hz.HZ_MIXED, 1e-8)])
-def test_plr_single_rhs_solve(small, prec, bar):
+def test_plr_single_rhs_solve(small, prec, bar, tune, monkeypatch):
     """Solves with the compressed preconditioner (eps = 1e-8) against the
     direct solve, the same iteration count as the dense preconditioner
-    (within one), and compressed storage below the dense size."""
+    (within one), and compressed storage below the dense size.  With the
+    autotuner off every preconditioner launch applies the compressed form;
+    with it on each launch keeps the faster of compressed and dense."""
+    monkeypatch.setenv("HZ_TUNE", tune)
     c, omega, prob, lu = small
     f = media.point_sources(N, (40,), 20)
     ref = prob.restrict(lu.solve(prob.extend(f[0]).ravel()).reshape(prob.W, prob.W))
@@ -64,11 +68,13 @@ def test_plr_single_rhs_solve(small, prec, bar):
     assert 0 < info.plr_bytes < info.plr_dense_bytes
 
 
-def test_plr_preconditioner_against_oracle(small):
+def test_plr_preconditioner_against_oracle(small, monkeypatch):
     """P^GS applied with the compressed operators (B = 1) against the
     oracle's exact P^GS: the difference is of the order of the compression
     accuracy (each of the 3(L-1) - 2 Green's-integral applications errs by
-    at most eps relative in the Frobenius norm)."""
+    at most eps relative in the Frobenius norm).  The autotuner is off, so
+    every launch applies the compressed form."""
+    monkeypatch.setenv("HZ_TUNE", "0")
     c, omega, prob, lu = small
     s = hz.Solver(torch.from_numpy(c), omega, P, L, LC, plr=1, plr_eps=1e-8)
     oracle = LayeredSolver(prob, L, LC)
@@ -83,6 +89,9 @@ def test_plr_preconditioner_against_oracle(small):
     err = _rel(y, ref)
     _log(f"[plr] P^GS vs exact oracle: {err:.2e}")
     assert err <= 1e-6
+    # the compressed form was applied: its error is far above the rounding
+    # level of the dense operators (about 1e-14 here)
+    assert err > 1e-11
 
 
 def test_plr_rejects_iterated_inner_solver():
