@@ -236,7 +236,8 @@ struct hz_ctx {
     hipStream_t st = nullptr;
     hipStream_t own_st = nullptr;  // stream created by the context (blocking, default priority)
     bool use_graphs = true;
-    bool compose = true;           // output operators composed with the inner SIE inverse
+    int compose = 1;               // output operators composed with the inner SIE inverse:
+                                   // 0 never, 1 where it pays (compose_jobs), 2 always
     bool offline = false;          // inside the factorisation stage
     bool tune = true;              // autotune GEMM kernels and cell-solve widths (HZ_TUNE=0: off)
     bool inner_pt = false;         // nested polarized traces: the inner SIE iterated (Sec. 4.2.1)
@@ -550,9 +551,47 @@ void add_vec(Plan<T>& pl, int kind, C2<T>* y, const C2<T>* x, double2 a, double2
     pl.launches.push_back(r);
 }
 
-// Append the three phases of a set of independent layer jobs to a plan.
+// Whether a set of jobs takes its samples through the composed operators
+// Qc = [Q_x S^{-1} | Q_u] or through the inner block-LU substitutions and
+// Q = [Q_x | Q_u].  Qc has J 2 HL columns for the inner right-hand side where
+// Q has the cell's adj 2 HL inner-trace columns, so composing costs
+// 2 s (J 2 HL - adj 2 HL) more operator entries per cell and job; the
+// substitutions cost (8J - 4) HL^2 entries per job and 3J - 2 dependent
+// launches, shared by all jobs of the set.  A sequential sweep step (one
+// job) is worth composing; a batch of many parallel jobs (the SIE product,
+// the reflections) is not once J is large (n = 2047, L_c = 8: Qc doubles the
+// SIE product's flops).  The estimate takes the saved entries at the
+// matrix-core rate (B >= 16) or at the HBM rate (streamed once, small B),
+// against 25 us per added dependent launch.  mode 2 (HZ_COMPOSE=2) composes
+// every set, 0 none.
 template <typename T>
-void plan_jobs(hz_ctx* c, Plan<T>& pl, const std::vector<LayerJob<T>>& jobs, int B) {
+bool compose_jobs(hz_ctx* c, const std::vector<LayerJob<T>>& jobs, int B) {
+    const Dims& d = c->d;
+    const int J = d.Lc - 1;
+    if (c->inner_pt || J <= 0 || c->compose == 0 || ops<T>(c).Qc == nullptr) return false;
+    if (c->compose == 2) return true;
+    double saved = 0.0;                       // operator entries per right-hand side
+    for (const auto& jb : jobs) {
+        if (!jb.phase3) continue;
+        const LayerDesc& ld = c->layers[jb.layer];
+        const double HL = ld.HL, NI = 2.0 * J * HL;
+        for (int k = 0; k < d.Lc; ++k) {
+            const CellDesc& cd = c->cells[ld.cell_begin + k];
+            saved += 2.0 * cd.s * (NI - cd.ncol);
+        }
+        saved -= (8.0 * J - 4.0) * HL * HL;
+    }
+    const double rate = sizeof(T) == sizeof(double) ? 60e12 : 120e12;
+    const double t_saved = std::max(saved * B * 8.0 / rate, saved * sizeof(C2<T>) / 5e12);
+    return t_saved <= (3.0 * J - 2.0) * 25e-6;
+}
+
+// Append the three phases of a set of independent layer jobs to a plan.
+// keep_composed: take the composed operators whenever they exist (the PLR
+// form compresses Qc, not Q).
+template <typename T>
+void plan_jobs(hz_ctx* c, Plan<T>& pl, const std::vector<LayerJob<T>>& jobs, int B,
+               bool keep_composed = false) {
     const Dims& d = c->d;
     const int W = d.W;
     const int J = d.Lc - 1;
@@ -560,7 +599,8 @@ void plan_jobs(hz_ctx* c, Plan<T>& pl, const std::vector<LayerJob<T>>& jobs, int
     // with the composed output operators, only jobs that need the inner
     // traces themselves (no phase 3) run the block LU substitutions
     const bool pt = c->inner_pt && J > 0;
-    const bool comp = !pt && c->compose && J > 0 && o.Qc != nullptr;
+    const bool comp = !pt && J > 0 && o.Qc != nullptr && c->compose != 0 &&
+                      (keep_composed || compose_jobs<T>(c, jobs, B));
     std::vector<LayerJob<T>> p2;
     for (const auto& jb : jobs)
         if (!(comp && jb.phase3)) p2.push_back(jb);
@@ -1073,7 +1113,8 @@ void build_pre_plan(hz_ctx* c, Plan<T>& pl, int B) {
             jb.alpha = (T)1;
             jobs.push_back(jb);
         }
-        plan_jobs<T>(c, pl, jobs, B);
+        // the single-RHS PLR form keeps the composed operators it compressed
+        plan_jobs<T>(c, pl, jobs, B, c->prm.plr != 0 && B == 1);
     }
     for (int k = K - 2; k >= 0; --k) {                  // upward sweep (D_up^{-1})
         LayerJob<T> jb;
@@ -3366,11 +3407,12 @@ hz_status hz_setup(const double* model_dev, const hz_params* prm, hz_ctx** out) 
     c->prm = *prm;
     c->inner_pt = prm->inner == HZ_INNER_PT && prm->cells > 1;
     if (c->inner_pt) {
-        c->compose = false;
+        c->compose = 0;
         c->inner_tol_loose = prm->inner_tol > 0.0 ? prm->inner_tol : 1e-6;
     }
     if (const char* g = std::getenv("HZ_GRAPHS")) c->use_graphs = std::atoi(g) != 0;
-    if (const char* g = std::getenv("HZ_COMPOSE")) c->compose = !c->inner_pt && std::atoi(g) != 0;
+    if (const char* g = std::getenv("HZ_COMPOSE"))
+        c->compose = c->inner_pt ? 0 : std::min(2, std::max(0, std::atoi(g)));
     if (const char* g = std::getenv("HZ_TUNE")) c->tune = std::atoi(g) != 0;
     if (const char* g = std::getenv("HZ_GEMM_KIND")) {
         const int k = std::atoi(g);
