@@ -373,36 +373,50 @@ __global__ void __launch_bounds__(CS_THREADS) k_cs_gemv(CellSolveArgs<T> a) {
         return v;
     };
 
+    // thread tid owns entry q = tid of the column block (HLp NB <= 896 <
+    // 1024 entries); the loads of a step that do not depend on its product
+    // (the sources and e_k in the forward sweep, the stored iterate and
+    // e_{k+1} in the backward sweep) are issued before the product and are
+    // in flight during it
+    static_assert(CS_HLPMAX * 4 <= CS_THREADS, "one column-block entry per thread");
+    const int q = tid, qj = q / NB, qc = q % NB;
+    const bool mine = q < HLp * NB;
+    const C2<T> zero = mk<T>((T)0, (T)0);
     const int k0 = first_live_col<MODE>(cd, a.p);
     // ---- forward sweep
     for (int k = k0; k < Wc; ++k) {
+        C2<T> src = zero, ek = zero;
+        if (mine) {
+            if (bval(qc)) src = cell_source<T, MODE>(a, cd, ld, k, qj, b0 + qc);
+            if (k > k0) ek = e_coef<T>(ee, k, qj, HL);
+        }
         if (k > k0) matvec(Xf + (long long)(k - 1) * np2);
         __syncthreads();
-        for (int q = tid; q < HLp * NB; q += CS_THREADS) {
-            const int j = q / NB, c = q % NB;
-            C2<T> s = bval(c) ? cell_source<T, MODE>(a, cd, ld, k, j, b0 + c) : mk<T>((T)0, (T)0);
-            if (k > k0) s = csub(s, cmul(e_coef<T>(ee, k, j, HL), rowsum(j, c)));
+        if (mine) {
+            C2<T> s = src;
+            if (k > k0) s = csub(s, cmul(ek, rowsum(qj, qc)));
             vs[q] = s;
             Y[(long long)k * HLp * NB + q] = s;
         }
         __syncthreads();
     }
     // ---- backward sweep
+    C2<T> ynext = zero, enext = zero;      // Y_k and e_{k+1} of the next step down
     for (int k = Wc - 1; k >= k0; --k) {
         if (k < Wc - 1) {
-            for (int q = tid; q < HLp * NB; q += CS_THREADS) {
-                const int j = q / NB;
-                vs[q] = csub(Y[(long long)k * HLp * NB + q], cmul(e_coef<T>(ee, k + 1, j, HL), vs[q]));
-            }
+            if (mine) vs[q] = csub(ynext, cmul(enext, vs[q]));
             __syncthreads();
+        }
+        if (mine && k > k0) {
+            ynext = Y[(long long)(k - 1) * HLp * NB + q];
+            enext = e_coef<T>(ee, k, qj, HL);
         }
         matvec(Xf + (long long)k * np2);
         __syncthreads();
-        for (int q = tid; q < HLp * NB; q += CS_THREADS) {
-            const int j = q / NB, c = q % NB;
-            const C2<T> x = rowsum(j, c);
+        if (mine) {
+            const C2<T> x = rowsum(qj, qc);
             vs[q] = x;
-            if (bval(c)) cell_emit<T, MODE>(a, cd, ld, k, j, b0 + c, x);
+            if (bval(qc)) cell_emit<T, MODE>(a, cd, ld, k, qj, b0 + qc, x);
         }
         __syncthreads();
     }
