@@ -2742,7 +2742,10 @@ void dots_dev(hz_ctx* c, const double2* V, long long vstride, int nv, const doub
 void update_dots_dev(hz_ctx* c, const double2* V, long long vstride, int nv, const double2* coef,
                      double2* w, long long n, int B, int norm, double2* out_dev,
                      double2* part, int max_chunks) {
-    const int chunks = (int)std::min<long long>(max_chunks, std::max<long long>(1, n / 8));
+    // seven or eight vectors take three waves per SIMD: 768 workgroups of
+    // four waves then run in one round
+    const int cap = nv >= 7 ? std::min(max_chunks, 768) : max_chunks;
+    const int chunks = (int)std::min<long long>(cap, std::max<long long>(1, n / 8));
     if (launch_update_dots(w, V, vstride, nv, coef, -1.0, n, B, norm, part, chunks, c->st)) {
         launch_reduce_partials(part, chunks, (norm ? 1 : nv) * B, out_dev, c->st);
         return;

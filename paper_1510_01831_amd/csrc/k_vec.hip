@@ -228,12 +228,17 @@ __device__ inline void reduce_columns(double2 (&acc)[NV], int nout, int per, int
     __syncthreads();
 }
 
+// Partial sums of conj(V_v) w (or |w|^2 when V is null) for the up to NVT
+// vectors v0 .. v0 + NVT - 1 of this workgroup row (blockIdx.y); NVT is the
+// vector count itself for passes over at most DV vectors, so registers scale
+// with it, and for up to four vectors two rows per thread are in flight.
+template <int NVT>
 __global__ void __launch_bounds__(RD_THREADS)
 k_dots(const double2* V, long long vstride, int nv, const double2* w, long long n, int B,
        double2* partial, int nchunks) {
-    __shared__ double2 red[DV * RD_THREADS];
-    const int v0 = blockIdx.y * DV;
-    const int nvb = nv - v0 < DV ? nv - v0 : DV;
+    __shared__ double2 red[NVT * RD_THREADS];
+    const int v0 = blockIdx.y * NVT;
+    const int nvb = nv - v0 < NVT ? nv - v0 : NVT;
     const int tid = threadIdx.x;
     const int per = rd_per(B);                                    // threads per column
     const int bcols = B < RD_THREADS ? B : RD_THREADS;
@@ -241,27 +246,44 @@ k_dots(const double2* V, long long vstride, int nv, const double2* w, long long 
     const long long i0 = blockIdx.x * chunk;
     const long long i1 = (i0 + chunk < n) ? i0 + chunk : n;
     for (int bb = 0; bb < B; bb += bcols) {
-        double2 acc[DV];
+        double2 acc[NVT];
 #pragma unroll
-        for (int v = 0; v < DV; ++v) acc[v] = make_double2(0.0, 0.0);
+        for (int v = 0; v < NVT; ++v) acc[v] = make_double2(0.0, 0.0);
         const int b = bb + tid % bcols;
         const int sub = tid / bcols;
         if (sub < per && b < B) {
-            for (long long i = i0 + sub; i < i1; i += per) {
-                const long long q = i * B + b;
-                const double2 c = w[q];
+            auto row = [&](double2 c, const double2 (&a)[NVT]) {
 #pragma unroll
-                for (int v = 0; v < DV; ++v) {
+                for (int v = 0; v < NVT; ++v) {
                     if (v < nvb) {
-                        double2 a = c;
-                        if (V) a = gload<double>(V + (v0 + v) * vstride + q);
-                        acc[v].x += a.x * c.x + a.y * c.y;
-                        acc[v].y += a.x * c.y - a.y * c.x;
+                        acc[v].x += a[v].x * c.x + a[v].y * c.y;
+                        acc[v].y += a[v].x * c.y - a[v].y * c.x;
                     }
                 }
+            };
+            auto load = [&](long long q, double2 (&a)[NVT]) {
+                const double2 c = w[q];
+#pragma unroll
+                for (int v = 0; v < NVT; ++v)
+                    a[v] = (V && v < nvb) ? gload<double>(V + (v0 + v) * vstride + q) : c;
+                return c;
+            };
+            long long i = i0 + sub;
+            constexpr bool TWO = NVT <= 4;
+            for (; TWO && i + per < i1; i += 2 * per) {
+                double2 a0[NVT], a1[NVT];
+                const double2 c0 = load(i * B + b, a0);
+                const double2 c1 = load((i + per) * B + b, a1);
+                row(c0, a0);
+                row(c1, a1);
+            }
+            for (; i < i1; i += per) {
+                double2 a0[NVT];
+                const double2 c0 = load(i * B + b, a0);
+                row(c0, a0);
             }
         }
-        reduce_columns<DV>(acc, nvb, per, bcols, red);
+        reduce_columns<NVT>(acc, nvb, per, bcols, red);
         if (tid < bcols && bb + tid < B)
             for (int v = 0; v < nvb; ++v)
                 partial[((long long)blockIdx.x * nv + v0 + v) * B + bb + tid] = acc[v];
@@ -270,8 +292,20 @@ k_dots(const double2* V, long long vstride, int nv, const double2* w, long long 
 
 void launch_dots(const double2* V, long long vstride, int nv, const double2* w, long long n,
                  int B, double2* partial, int nchunks, hipStream_t st) {
-    hipLaunchKernelGGL(k_dots, dim3(nchunks, (nv + DV - 1) / DV), dim3(RD_THREADS), 0, st, V,
-                       vstride, nv, w, n, B, partial, nchunks);
+#define HZ_DOTS(NVC)                                                                           \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_dots<NVC>), dim3(nchunks, (nv + NVC - 1) / NVC),      \
+                       dim3(RD_THREADS), 0, st, V, vstride, nv, w, n, B, partial, nchunks)
+    switch (nv) {
+    case 1: HZ_DOTS(1); break;
+    case 2: HZ_DOTS(2); break;
+    case 3: HZ_DOTS(3); break;
+    case 4: HZ_DOTS(4); break;
+    case 5: HZ_DOTS(5); break;
+    case 6: HZ_DOTS(6); break;
+    case 7: HZ_DOTS(7); break;
+    default: HZ_DOTS(DV); break;
+    }
+#undef HZ_DOTS
 }
 
 // One Gram-Schmidt pass fused with the reductions of the next step:
@@ -282,56 +316,76 @@ void launch_dots(const double2* V, long long vstride, int nv, const double2* w, 
 // V and w are read once for both (nv <= UD_MAX = 8).
 constexpr int UD_MAX = 8;
 
+// NV (the number of basis vectors) is a template parameter, so that the
+// registers of a pass scale with it (all eight at once took 143 registers,
+// three waves per SIMD, and the 1024-workgroup launch ran in two rounds), and
+// for up to four vectors two rows per thread are in flight per loop step.
+template <int NV>
 __global__ void __launch_bounds__(RD_THREADS)
-k_update_dots(double2* __restrict__ w, const double2* __restrict__ V, long long vstride, int nv,
+k_update_dots(double2* __restrict__ w, const double2* __restrict__ V, long long vstride,
               const double2* __restrict__ coef, double sgn, long long n, int B, int norm,
               double2* __restrict__ partial, int nchunks) {
-    __shared__ double2 red[UD_MAX * RD_THREADS];
+    __shared__ double2 red[NV * RD_THREADS];
     const int tid = threadIdx.x;
     const int per = rd_per(B);
     const int bcols = B < RD_THREADS ? B : RD_THREADS;
     const long long chunk = (n + nchunks - 1) / nchunks;
     const long long i0 = blockIdx.x * chunk;
     const long long i1 = (i0 + chunk < n) ? i0 + chunk : n;
-    const int nout = norm ? 1 : nv;
+    const int nout = norm ? 1 : NV;
     for (int bb = 0; bb < B; bb += bcols) {
-        double2 acc[UD_MAX];
+        double2 acc[NV];
 #pragma unroll
-        for (int v = 0; v < UD_MAX; ++v) acc[v] = make_double2(0.0, 0.0);
+        for (int v = 0; v < NV; ++v) acc[v] = make_double2(0.0, 0.0);
         const int b = bb + tid % bcols;
         const int sub = tid / bcols;
         if (sub < per && b < B) {
-            double2 h[UD_MAX];
+            double2 h[NV];
 #pragma unroll
-            for (int v = 0; v < UD_MAX; ++v)
-                h[v] = v < nv ? coef[(long long)v * B + b] : make_double2(0.0, 0.0);
-            for (long long i = i0 + sub; i < i1; i += per) {
-                const long long q = i * B + b;
-                double2 x = w[q];
-                double2 vv[UD_MAX];
+            for (int v = 0; v < NV; ++v) h[v] = coef[(long long)v * B + b];
+            // one row: w <- w + sgn V h, then the products with the new w
+            auto row = [&](double2 x, const double2 (&vv)[NV], long long q) {
 #pragma unroll
-                for (int v = 0; v < UD_MAX; ++v) {
-                    if (v < nv) {
-                        vv[v] = gload<double>(V + v * vstride + q);
-                        x.x += sgn * (h[v].x * vv[v].x - h[v].y * vv[v].y);
-                        x.y += sgn * (h[v].x * vv[v].y + h[v].y * vv[v].x);
-                    }
+                for (int v = 0; v < NV; ++v) {
+                    x.x += sgn * (h[v].x * vv[v].x - h[v].y * vv[v].y);
+                    x.y += sgn * (h[v].x * vv[v].y + h[v].y * vv[v].x);
                 }
                 w[q] = x;
                 if (norm) {
                     acc[0].x += x.x * x.x + x.y * x.y;
                 } else {
 #pragma unroll
-                    for (int v = 0; v < UD_MAX; ++v) {
-                        if (v < nv) {
-                            acc[v].x += vv[v].x * x.x + vv[v].y * x.y;
-                            acc[v].y += vv[v].x * x.y - vv[v].y * x.x;
-                        }
+                    for (int v = 0; v < NV; ++v) {
+                        acc[v].x += vv[v].x * x.x + vv[v].y * x.y;
+                        acc[v].y += vv[v].x * x.y - vv[v].y * x.x;
                     }
                 }
+            };
+            long long i = i0 + sub;
+            // two rows per step only where the registers allow four waves
+            // per SIMD (the passes over many vectors have loads enough)
+            constexpr bool TWO = NV <= 4;
+            for (; TWO && i + per < i1; i += 2 * per) {
+                const long long q0 = i * B + b, q1 = (i + per) * B + b;
+                const double2 x0 = w[q0], x1 = w[q1];
+                double2 v0[NV], v1[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    v0[v] = gload<double>(V + v * vstride + q0);
+                    v1[v] = gload<double>(V + v * vstride + q1);
+                }
+                row(x0, v0, q0);
+                row(x1, v1, q1);
+            }
+            for (; i < i1; i += per) {
+                const long long q0 = i * B + b;
+                double2 v0[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) v0[v] = gload<double>(V + v * vstride + q0);
+                row(w[q0], v0, q0);
             }
         }
-        reduce_columns<UD_MAX>(acc, nout, per, bcols, red);
+        reduce_columns<NV>(acc, nout, per, bcols, red);
         if (tid < bcols && bb + tid < B)
             for (int v = 0; v < nout; ++v)
                 partial[((long long)blockIdx.x * nout + v) * B + bb + tid] = acc[v];
@@ -342,15 +396,21 @@ bool launch_update_dots(double2* w, const double2* V, long long vstride, int nv,
                         const double2* coef, double sgn, long long n, int B, int norm,
                         double2* partial, int nchunks, hipStream_t st) {
     if (nv < 1 || nv > UD_MAX) return false;
-    hipLaunchKernelGGL(k_update_dots, dim3(nchunks), dim3(RD_THREADS), 0, st, w, V, vstride, nv,
-                       coef, sgn, n, B, norm, partial, nchunks);
+#define HZ_UD(NVC)                                                                          \
+    case NVC:                                                                               \
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_update_dots<NVC>), dim3(nchunks), dim3(RD_THREADS), \
+                           0, st, w, V, vstride, coef, sgn, n, B, norm, partial, nchunks); \
+        break;
+    switch (nv) {
+        HZ_UD(1) HZ_UD(2) HZ_UD(3) HZ_UD(4) HZ_UD(5) HZ_UD(6) HZ_UD(7) HZ_UD(8)
+    }
+#undef HZ_UD
     return true;
 }
 
 void launch_norms(const double2* w, long long n, int B, double2* partial, int nchunks,
                   hipStream_t st) {
-    hipLaunchKernelGGL(k_dots, dim3(nchunks, 1), dim3(RD_THREADS), 0, st, nullptr, 0LL, 1, w, n,
-                       B, partial, nchunks);
+    launch_dots(nullptr, 0LL, 1, w, n, B, partial, nchunks, st);
 }
 
 // out[q] = sum_c partial[c * count + q]: one workgroup per output entry, a
