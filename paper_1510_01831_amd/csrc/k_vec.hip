@@ -751,10 +751,12 @@ k_residual_norms(const double2* __restrict__ u, const double2* __restrict__ f,
 // column would fetch each u entry three times, as the x neighbour of two
 // other workgroups).  Workgroups are numbered so that each XCD (slot L runs
 // on XCD L mod 8) takes one contiguous run of (band, column group): the
-// halo columns then come from the same L2.
-constexpr int RN_RX = 8;
+// halo columns then come from the same L2.  RX = 4 (u read 1.5 times) keeps
+// a thread within 128 registers, four waves per SIMD; RX = 8 took 212
+// registers, two waves per SIMD, and ran at half the HBM rate.
+constexpr int RN_RX = 4;
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 4)
 k_residual_norms_march(const double2* __restrict__ u, const double2* __restrict__ f,
                        const double2* __restrict__ gd, const double2* __restrict__ gcx,
                        const double2* __restrict__ gcz, int W, int B, int XW, int nxg, int zb,
