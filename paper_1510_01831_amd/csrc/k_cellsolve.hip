@@ -457,12 +457,32 @@ __device__ inline int probe_col(const CellDesc& cd, int p, int probe) {
     return cd.own_c0 + (probe - cd.ncol) % cd.s;
 }
 
+// Add (re, im) to entry v of a complex accumulator (Gauss's three-product
+// form: re = P1 - P2 and im = P3 - P1 - P2, so P1 += re and P3 += re + im).
+template <typename T>
+__device__ inline void acc_add(CAcc<T, true>& a, int v, T re, T im) {
+    a.p1[v] += re;
+    a.p3[v] += re + im;
+}
+template <typename T>
+__device__ inline void acc_add(CAcc<T, false>& a, int v, T re, T im) {
+    a.r[v] += re;
+    a.i[v] += im;
+}
+
+// NW = 12 (cells of 129-160 rows, up to ten row tiles): waves 0-7 own row
+// tiles 0-7; waves 8 + 2i and 9 + 2i share row tile 8 + i, each taking one
+// part of the k steps of its block products.  The second leaves its partial
+// sums in LDS (pbuf), the first adds them after the step's barrier and does
+// the tile's updates.  Three waves per SIMD then carry equal matrix-core
+// work; with ten waves two SIMDs held three of them and two held two.
 template <typename T, int NB, int MODE, int MC, int NW>
 __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const CellDesc& cd,
                                              const LayerDesc& ld, C2<T>* vs, double2* izs,
-                                             double2* ixs, int b0, long long slot) {
+                                             double2* ixs, C2<T>* pbuf, int b0, long long slot) {
     constexpr int NCT = NB / 16;
     constexpr int MCA = MC > 0 ? MC : 1;
+    constexpr bool SPLIT = NW == 12;
     // k steps per register group.  Ten waves run at three waves per SIMD,
     // 170 registers per lane: four k steps (4 KB of factor in flight per
     // wave) fit except for the FP64 volume solve and the 32-column FP32
@@ -475,6 +495,12 @@ __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const Ce
     const int KS = HLp >> 2;                  // multiple of 4
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int lc = lane & 15, lk = lane >> 4;
+    // first row tile of the wave, and its part of a shared tile (-1: whole)
+    const int tw = SPLIT && w >= 8 ? 8 + ((w - 8) >> 1) : w;
+    const int part = SPLIT && w >= 8 ? ((w - 8) & 1) : -1;
+    const bool owner = part <= 0;             // does the tile's updates
+    const int kmid = ((KS / 2) / U) * U;      // split point of a shared tile's k steps
+    const int ks0 = part == 1 ? kmid : 0, ks1 = part == 0 ? kmid : KS;
     const long long np2 = (long long)HLp * HLp;
     const long long nq = (long long)HLp * NB;
     const C2<T>* __restrict__ Xf = a.X + cd.off_X;
@@ -482,9 +508,9 @@ __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const Ce
     C2<T>* __restrict__ Y = a.Y + slot * a.y_stride;
     const C2<T> z = mk<T>((T)0, (T)0);
 
-    auto row_of = [&](int m, int v) { return (w + NW * m) * 16 + Mf<T>::row(lane, v); };
+    auto row_of = [&](int m, int v) { return (tw + NW * m) * 16 + Mf<T>::row(lane, v); };
     auto yidx = [&](int m, int t, int v) {
-        return ((long long)((w + NW * m) * NCT + t) * 4 + v) * 64 + lane;
+        return ((long long)((tw + NW * m) * NCT + t) * 4 + v) * 64 + lane;
     };
     auto bval = [&](int c) {
         const int b = b0 + c;
@@ -501,7 +527,7 @@ __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const Ce
             const C2<T>* xp[MC];
 #pragma unroll
             for (int m = 0; m < MC; ++m)
-                xp[m] = Xk + (((long long)(w + NW * m) * KS) << 6) + lane;
+                xp[m] = Xk + (((long long)(tw + NW * m) * KS) << 6) + lane;
             C2<T> xa[U][MC], xb[U][MC];
             auto load = [&](C2<T> (&dst)[U][MC], int s0) {
 #pragma unroll
@@ -522,14 +548,37 @@ __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const Ce
                             ac[m][t].add(src[u][m].x, src[u][m].y, bv[t].x, bv[t].y);
                 }
             };
-            load(xa, 0);
-            for (int s = 0; s < KS; s += 2 * U) {
-                if (s + U < KS) load(xb, s + U);
+            load(xa, ks0);
+            for (int s = ks0; s < ks1; s += 2 * U) {
+                if (s + U < ks1) load(xb, s + U);
                 mult(xa, s);
-                if (s + U >= KS) break;
-                if (s + 2 * U < KS) load(xa, s + 2 * U);
+                if (s + U >= ks1) break;
+                if (s + 2 * U < ks1) load(xa, s + 2 * U);
                 mult(xb, s + U);
             }
+        }
+    };
+    // a shared tile's partial sums: the second part stores them, the first
+    // adds them to its accumulators (after a barrier)
+    auto tval = [&](int m, int t, int v) { return mk<T>(ac[m][t].re(v), ac[m][t].im(v)); };
+    auto pidx = [&](int t, int v) { return (((tw - 8) * NCT + t) * 4 + v) * 64 + lane; };
+    auto put_part = [&]() {
+        if constexpr (SPLIT && MC > 0) {
+#pragma unroll
+            for (int t = 0; t < NCT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) pbuf[pidx(t, v)] = tval(0, t, v);
+        }
+    };
+    auto add_part = [&]() {
+        if constexpr (SPLIT && MC > 0) {
+#pragma unroll
+            for (int t = 0; t < NCT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const C2<T> q = pbuf[pidx(t, v)];
+                    acc_add(ac[0][t], v, q.x, q.y);
+                }
         }
     };
 
@@ -576,20 +625,7 @@ __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const Ce
     }
 
     // ---- forward sweep: y_0 = b_0, y_k = b_k - e_k o (X_{k-1} y_{k-1})
-    for (int k = kmin; k < Wc; ++k) {
-#pragma unroll
-        for (int m = 0; m < MC; ++m)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int j = row_of(m, v);
-                pe[m][v] = k > kmin ? e_coef<T>(ee, k, j, HL) : z;
-#pragma unroll
-                for (int t = 0; t < NCT; ++t) {
-                    const int c = t * 16 + lc;
-                    pv[m][t][v] = bval(c) ? cell_source_ctx<T, MODE>(a, cd, ld, sc, k, j, b0 + c) : z;
-                }
-            }
-        if (k > kmin) matmul(Xf + (long long)(k - 1) * np2);
+    auto fwd_update = [&](int k) {
 #pragma unroll
         for (int m = 0; m < MC; ++m)
 #pragma unroll
@@ -597,23 +633,63 @@ __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const Ce
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     C2<T> y = pv[m][t][v];
-                    if (k > kmin) y = csub(y, cmul(pe[m][v], mk<T>(ac[m][t].re(v), ac[m][t].im(v))));
+                    if (k > kmin) y = csub(y, cmul(pe[m][v], tval(m, t, v)));
                     pv[m][t][v] = y;
                     Y[(long long)k * nq + yidx(m, t, v)] = y;
                 }
+    };
+    for (int k = kmin; k < Wc; ++k) {
+        if (owner) {
+#pragma unroll
+            for (int m = 0; m < MC; ++m)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int j = row_of(m, v);
+                    pe[m][v] = k > kmin ? e_coef<T>(ee, k, j, HL) : z;
+#pragma unroll
+                    for (int t = 0; t < NCT; ++t) {
+                        const int c = t * 16 + lc;
+                        pv[m][t][v] = bval(c) ? cell_source_ctx<T, MODE>(a, cd, ld, sc, k, j, b0 + c) : z;
+                    }
+                }
+        }
+        if (k > kmin) {
+            matmul(Xf + (long long)(k - 1) * np2);
+            if (part == 1) put_part();
+        }
+        if (part < 0) fwd_update(k);
         __syncthreads();                      // all block products of this step done
+        if (part == 0) {
+            if (k > kmin) add_part();
+            fwd_update(k);
+        }
+        if (owner) {
+#pragma unroll
+            for (int m = 0; m < MC; ++m)
+#pragma unroll
+                for (int t = 0; t < NCT; ++t)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) vs[row_of(m, v) * NB + t * 16 + lc] = pv[m][t][v];
+        }
+        __syncthreads();
+    }
+    // ---- backward sweep: x_{W-1} = X_{W-1} y_{W-1}, x_k = X_k (y_k - e_{k+1} o x_{k+1}),
+    // down to the first live column
+    auto bwd_update = [&](int k) {
 #pragma unroll
         for (int m = 0; m < MC; ++m)
 #pragma unroll
             for (int t = 0; t < NCT; ++t)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) vs[row_of(m, v) * NB + t * 16 + lc] = pv[m][t][v];
-        __syncthreads();
-    }
-    // ---- backward sweep: x_{W-1} = X_{W-1} y_{W-1}, x_k = X_k (y_k - e_{k+1} o x_{k+1}),
-    // down to the first live column
+                for (int v = 0; v < 4; ++v) {
+                    const int c = t * 16 + lc;
+                    const C2<T> x = tval(m, t, v);
+                    if (bval(c)) cell_emit<T, MODE>(a, cd, ld, k, row_of(m, v), b0 + c, x);
+                    pv[m][t][v] = csub(pv[m][t][v], cmul(pe[m][v], x));
+                }
+    };
     for (int k = Wc - 1; k >= kstop; --k) {
-        if (k > kstop) {
+        if (k > kstop && owner) {
 #pragma unroll
             for (int m = 0; m < MC; ++m)
 #pragma unroll
@@ -625,25 +701,23 @@ __device__ __forceinline__ void cs_mfma_body(const CellSolveArgs<T>& a, const Ce
                 }
         }
         matmul(Xf + (long long)k * np2);
-#pragma unroll
-        for (int m = 0; m < MC; ++m)
-#pragma unroll
-            for (int t = 0; t < NCT; ++t)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int c = t * 16 + lc;
-                    const C2<T> x = mk<T>(ac[m][t].re(v), ac[m][t].im(v));
-                    if (bval(c)) cell_emit<T, MODE>(a, cd, ld, k, row_of(m, v), b0 + c, x);
-                    pv[m][t][v] = csub(pv[m][t][v], cmul(pe[m][v], x));
-                }
+        if (part == 1) put_part();
+        if (part < 0) bwd_update(k);
+        // the shared tiles' partial sums cross between waves at every step
+        if (SPLIT || k > kstop) __syncthreads();
+        if (part == 0) {
+            add_part();
+            bwd_update(k);
+        }
         if (k > kstop) {
-            __syncthreads();
+            if (owner) {
 #pragma unroll
-            for (int m = 0; m < MC; ++m)
+                for (int m = 0; m < MC; ++m)
 #pragma unroll
-                for (int t = 0; t < NCT; ++t)
+                    for (int t = 0; t < NCT; ++t)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) vs[row_of(m, v) * NB + t * 16 + lc] = pv[m][t][v];
+                        for (int v = 0; v < 4; ++v) vs[row_of(m, v) * NB + t * 16 + lc] = pv[m][t][v];
+            }
             __syncthreads();
         }
     }
@@ -658,6 +732,7 @@ __global__ void __launch_bounds__(NW * 64) k_cs_mfma(CellSolveArgs<T> a) {
     const int hlp_max = (a.HLmax + 15) / 16 * 16;
     double2* izs = reinterpret_cast<double2*>(cs_lds + (size_t)hlp_max * NB * sizeof(C2<T>));
     double2* ixs = izs + hlp_max;
+    C2<T>* pbuf = reinterpret_cast<C2<T>*>(ixs + a.Wcmax);     // NW = 12: shared-tile partials
     // 1-D grid over (cell, batch chunk), chunks fastest, in XCD-contiguous
     // order: the chunks of a cell stream the same factor blocks through one
     // XCD's L2 at about the same time
@@ -672,12 +747,14 @@ __global__ void __launch_bounds__(NW * 64) k_cs_mfma(CellSolveArgs<T> a) {
     const long long slot = (long long)ci * chunks + ch;
     const int RT = cd.HLp >> 4;
     const int w = threadIdx.x >> 6;
-    // tiles w and w + NW (HLp <= 224 gives at most 14 tiles)
-    const int mc = RT > w ? (RT - w + NW - 1) / NW : 0;
+    // tiles w and w + NW (HLp <= 224 gives at most 14 tiles); NW = 12: the
+    // wave's tile of at most ten
+    const int tw = NW == 12 && w >= 8 ? 8 + ((w - 8) >> 1) : w;
+    const int mc = NW == 12 ? (tw < RT ? 1 : 0) : (RT > w ? (RT - w + NW - 1) / NW : 0);
     // every branch passes the same sequence of barriers
-    if (mc == 0) cs_mfma_body<T, NB, MODE, 0, NW>(a, cd, ld, vs, izs, ixs, b0, slot);
-    else if (MCMAX == 1 || mc == 1) cs_mfma_body<T, NB, MODE, 1, NW>(a, cd, ld, vs, izs, ixs, b0, slot);
-    else cs_mfma_body<T, NB, MODE, MCMAX, NW>(a, cd, ld, vs, izs, ixs, b0, slot);
+    if (mc == 0) cs_mfma_body<T, NB, MODE, 0, NW>(a, cd, ld, vs, izs, ixs, pbuf, b0, slot);
+    else if (MCMAX == 1 || mc == 1) cs_mfma_body<T, NB, MODE, 1, NW>(a, cd, ld, vs, izs, ixs, pbuf, b0, slot);
+    else cs_mfma_body<T, NB, MODE, MCMAX, NW>(a, cd, ld, vs, izs, ixs, pbuf, b0, slot);
 }
 
 template <typename T, int NB, int MODE, int MCMAX, int NW>
@@ -700,7 +777,8 @@ void launch_cs_mfma(const CellSolveArgs<T>& a, dim3 grid, hipStream_t st) {
     // column block, then the row and column PML scalings
     const size_t lds = (size_t)hlp * NB * sizeof(C2<T>) + (size_t)(hlp + a.Wcmax) * sizeof(double2);
     if (hlp <= 16 * CS_MF_WAVES) launch_cs_mfma_mc<T, NB, MODE, 1, CS_MF_WAVES>(a, grid, lds, st);
-    else if (hlp <= 160) launch_cs_mfma_mc<T, NB, MODE, 1, 10>(a, grid, lds, st);
+    else if (hlp <= 160)        // plus the partial sums of the two shared tiles
+        launch_cs_mfma_mc<T, NB, MODE, 1, 12>(a, grid, lds + 2 * (NB / 16) * 4 * 64 * sizeof(C2<T>), st);
     else launch_cs_mfma_mc<T, NB, MODE, 2, CS_MF_WAVES>(a, grid, lds, st);
 }
 
