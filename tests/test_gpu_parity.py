@@ -125,8 +125,10 @@ def test_full_solve_fp64(setup):
 
 def test_uncomposed_inner_solve(monkeypatch):
     """The same operators with the inner SIE solved by block LU substitutions
-    at every application (HZ_COMPOSE=0) instead of through the composed
-    output operators: both match the oracle."""
+    at every application (HZ_COMPOSE=0), through the composed output
+    operators everywhere (2), and with the per-job-set choice (1, the
+    default: sweep steps composed, parallel batches where cheaper
+    substituted): all match the oracle."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     c, omega = media.small_problem(N, P, L, LC, seed=5)
@@ -136,7 +138,7 @@ def test_uncomposed_inner_solve(monkeypatch):
     x = _rand_pol(K, W, 2, 3)
     f = media.point_sources(N, (24, 7), 12)
     lu = spla.splu(prob.H.tocsc())
-    for flag in ("0", "1"):
+    for flag in ("0", "1", "2"):
         monkeypatch.setenv("HZ_COMPOSE", flag)
         _log(f"[compose={flag}] apply_sie / apply_precond / solve")
         s = hz.Solver(torch.from_numpy(c), omega, P, L, LC, max_batch=2)
