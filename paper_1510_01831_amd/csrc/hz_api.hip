@@ -1342,10 +1342,11 @@ k_inner_step(int j, int NB, const double2* __restrict__ hA, const double2* __res
     double2* Rc = R + (long long)j * (j + 1) / 2 * NB;     // packed column j
     for (int q = threadIdx.x; q < NB; q += blockDim.x) {
         if (done[q]) continue;
-        double2 a = cadd(hA[q], hB[q]);
+        // projections of the two Gram-Schmidt passes (hB null: one pass)
+        double2 a = hB ? cadd(hA[q], hB[q]) : hA[q];
         for (int i = 0; i < j; ++i) {
             const long long at = (long long)(i + 1) * NB + q;
-            const double2 b = cadd(hA[at], hB[at]);
+            const double2 b = hB ? cadd(hA[at], hB[at]) : hA[at];
             const double ci = cs[(long long)i * NB + q];
             const double2 si = sn[(long long)i * NB + q];
             Rc[(long long)i * NB + q] = cadd(cscale(a, ci), cmul(si, b));
@@ -1735,29 +1736,36 @@ void inner_solve(hz_ctx* c, InnerRec<T>& r, int B) {
         idots(nullptr, 1, V, c->ismall);
         hipLaunchKernelGGL(k_inner_start, dim3(1), dim3(INNER_STEP_THREADS), 0, c->st, c->ismall, NB,
                            c->ibeta, c->ig, c->idone, c->ikfin, c->icoef);
-        launch_scale_cols(V, V, c->icoef, n, NB, c->st);
+        launch_scale_cols(V, V, c->icoef, n, NB, c->st, r.wA);   // v_0, also the plans' input
         // The host reads one flag per iteration: every column done.  (Reading
         // it one iteration behind, so that the next one is already queued,
         // was slower: the extra iteration costs more than the wait.)
         int j = 0;
         for (; j < m; ++j) {
-            double2* Vj = V + (long long)j * nB;
             double2* Vn = V + (long long)(j + 1) * nB;
-            HIPCHK(hipMemcpyAsync(r.wA, Vj, sizeof(double2) * nB, hipMemcpyDeviceToDevice, c->st));
-            plan_run<T>(c, *r.M, B);
+            plan_run<T>(c, *r.M, B);                   // reads v_j from wA
             plan_run<T>(c, *r.P, B);                   // w = P M v_j in wC
             double2* w = r.wC;
             const size_t nh = (size_t)(j + 1) * NB;
             double2* hA = c->ih;
             double2* hB2 = c->ih + nh;
             double2* hN = c->ih + 2 * nh;
+            // classical Gram-Schmidt, twice for the tight inner solves and
+            // once for the preconditioner's (tolerance 1e-6: the loss of
+            // orthogonality of a single pass over a few vectors is far below
+            // it); the new vector also goes to wA, the plans' input
             idots(V, j + 1, w, hA);
-            update_dots_dev(c, V, nB, j + 1, hA, w, n, NB, 0, hB2, c->ipart, chunks);
-            update_dots_dev(c, V, nB, j + 1, hB2, w, n, NB, 1, hN, c->ipart, chunks);
-            launch_inv_norms(hN, c->icoef, NB, c->st);
-            launch_scale_cols(Vn, w, c->icoef, n, NB, c->st);
+            const bool cgs2 = !r.loose;
+            if (cgs2) {
+                update_dots_dev(c, V, nB, j + 1, hA, w, n, NB, 0, hB2, c->ipart, chunks);
+                update_dots_dev(c, V, nB, j + 1, hB2, w, n, NB, 1, hN, c->ipart, chunks);
+            } else {
+                update_dots_dev(c, V, nB, j + 1, hA, w, n, NB, 1, hN, c->ipart, chunks);
+            }
+            launch_scale_cols_inv_norm(Vn, r.wA, w, hN, n, NB, c->st);
             hipLaunchKernelGGL(k_inner_step, dim3(1), dim3(INNER_STEP_THREADS), 0, c->st, j, NB,
-                               (const double2*)hA, (const double2*)hB2, (const double2*)hN, c->iR,
+                               (const double2*)hA, cgs2 ? (const double2*)hB2 : nullptr,
+                               (const double2*)hN, c->iR,
                                c->ics, c->isn, c->ig, (const double*)c->ibeta, c->idone, c->ikfin,
                                tol, c->iflag);
             HIPCHK(hipMemcpyAsync(c->h_iflag + j, c->iflag + j, sizeof(int), hipMemcpyDeviceToHost,
@@ -2859,8 +2867,7 @@ void gmres(hz_ctx* c, const double2* b, double2* x, int B, double tol, int maxit
         update_dots_dev(c, V, vs, j + 1, hB, c->gw, n, B, 1, hN, c->gpart, c->gpart_chunks);
         // next basis vector scaled on the device (columns that have converged
         // keep being normalised; their coefficients beyond convergence are 0)
-        launch_inv_norms(hN, c->gcoef, B, c->st);
-        launch_scale_cols(Vn, c->gw, c->gcoef, n, B, c->st);
+        launch_scale_cols_inv_norm(Vn, nullptr, c->gw, hN, n, B, c->st);
         double2* hh = pinned(c, 2 * nh + B);
         HIPCHK(hipMemcpyAsync(hh, c->gh, sizeof(double2) * (2 * nh + B), hipMemcpyDeviceToHost,
                               c->st));

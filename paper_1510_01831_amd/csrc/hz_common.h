@@ -374,12 +374,13 @@ void launch_reduce_partials(const double2* partial, int nchunks, int count, doub
 void launch_lincomb3(double2* out, const double2* x0, const double2* x1, const double2* x2,
                      const double2* coef, long long n, int B, hipStream_t st);
 void launch_fill_zero(double2* y, long long n, hipStream_t st);
-void launch_inv_norms(const double2* n2, double2* s, int B, hipStream_t st);
 void launch_update_basis(double2* w, const double2* V, long long vstride, int nv,
                          const double2* coef, long long n, int B, hipStream_t st,
                          double sgn = 1.0);
 void launch_scale_cols(double2* y, const double2* x, const double2* s, long long n, int B,
-                       hipStream_t st);
+                       hipStream_t st, double2* y2 = nullptr);
+void launch_scale_cols_inv_norm(double2* y, double2* y2, const double2* x, const double2* n2,
+                                long long n, int B, hipStream_t st);
 void launch_norms(const double2* w, long long n, int B, double2* partial, int nchunks,
                   hipStream_t st);
 // w += sgn * V coef, then partial sums of V^H w (norm = 0) or |w|^2 (norm = 1);

@@ -479,16 +479,6 @@ void launch_fill_zero(double2* y, long long n, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_zero, dim3(blocks), dim3(256), 0, st, y, n);
 }
 
-// s[b] = 1 / sqrt(n2[b].x) (0 for a zero norm): column scales for GMRES from
-// the squared norms left on the device
-__global__ void k_inv_norms(const double2* n2, double2* s, int B) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < B) s[b] = make_double2(n2[b].x > 0.0 ? 1.0 / sqrt(n2[b].x) : 0.0, 0.0);
-}
-void launch_inv_norms(const double2* n2, double2* s, int B, hipStream_t st) {
-    hipLaunchKernelGGL(k_inv_norms, dim3((B + 255) / 256), dim3(256), 0, st, n2, s, B);
-}
-
 // w[i,b] += sgn * sum_v coef[v,b] V_v[i,b]
 __global__ void k_update_basis(double2* w, const double2* V, long long vstride, int nv,
                                const double2* coef, long long n, int B, double sgn) {
@@ -515,20 +505,47 @@ void launch_update_basis(double2* w, const double2* V, long long vstride, int nv
                        n, B, sgn);
 }
 
-__global__ void k_scale_cols(double2* y, const double2* x, const double2* s, long long n, int B) {
+// y[i,b] = s[b] x[i,b], also into y2 when given (a second copy of the new
+// Krylov vector for the operator plans' fixed input buffer)
+__global__ void k_scale_cols(double2* y, double2* y2, const double2* x, const double2* s,
+                             long long n, int B) {
     const long long total = n * B;
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
          q += (long long)gridDim.x * blockDim.x) {
         const double2 c = s[q % B];
         const double2 v = x[q];
-        y[q] = make_double2(c.x * v.x - c.y * v.y, c.x * v.y + c.y * v.x);
+        const double2 r = make_double2(c.x * v.x - c.y * v.y, c.x * v.y + c.y * v.x);
+        y[q] = r;
+        if (y2) y2[q] = r;
     }
 }
 void launch_scale_cols(double2* y, const double2* x, const double2* s, long long n, int B,
-                       hipStream_t st) {
+                       hipStream_t st, double2* y2) {
     const long long total = n * B;
     int blocks = (int)std::min<long long>((total + 255) / 256, 16384);
-    hipLaunchKernelGGL(k_scale_cols, dim3(blocks), dim3(256), 0, st, y, x, s, n, B);
+    hipLaunchKernelGGL(k_scale_cols, dim3(blocks), dim3(256), 0, st, y, y2, x, s, n, B);
+}
+
+// The same scaled by 1 / |x_b| from the squared norms n2[b].x (0 for a zero
+// norm), without a separate kernel for the scales
+__global__ void k_scale_cols_inv_norm(double2* y, double2* y2, const double2* x,
+                                      const double2* n2, long long n, int B) {
+    const long long total = n * B;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
+         q += (long long)gridDim.x * blockDim.x) {
+        const double m = n2[q % B].x;
+        const double c = m > 0.0 ? 1.0 / sqrt(m) : 0.0;
+        const double2 v = x[q];
+        const double2 r = make_double2(c * v.x, c * v.y);
+        y[q] = r;
+        if (y2) y2[q] = r;
+    }
+}
+void launch_scale_cols_inv_norm(double2* y, double2* y2, const double2* x, const double2* n2,
+                                long long n, int B, hipStream_t st) {
+    const long long total = n * B;
+    int blocks = (int)std::min<long long>((total + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_scale_cols_inv_norm, dim3(blocks), dim3(256), 0, st, y, y2, x, n2, n, B);
 }
 
 // ---------------------------------------------------------------------------
