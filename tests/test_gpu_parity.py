@@ -234,24 +234,33 @@ def test_every_gemm_kernel(kind, monkeypatch):
             assert _rel(u[bb], ref) < 1e-9
 
 
-@pytest.mark.parametrize("n,layers", [(60, 1), (100, 1), (140, 1), (160, 1)])
+@pytest.mark.parametrize("n,layers", [(60, 1), (100, 1), (124, 1), (140, 1), (160, 1)])
 def test_tall_cells(n, layers):
-    """Cells of height 72, 112, 152 and 172 (padded to 80, 112, 160 and 176):
-    the layouts of the register-resident cell factorisation (all columns in
-    registers up to order 128, part of them in LDS up to 160) and the general
-    Gauss-Jordan kernel beyond."""
+    """Cells of height 72, 112, 136, 152 and 172 (padded to 80, 112, 144, 160
+    and 176): the layouts of the register-resident cell factorisation (all
+    columns in registers up to order 128, part of them in LDS up to 160) and
+    the general Gauss-Jordan kernel beyond; for 136 and 152 the twelve-wave
+    matrix-core cell solve (nine and ten row tiles, the last one or two
+    shared by two waves), in the probes and, with 16 sources, in the batched
+    volume solve."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     c, omega = media.small_problem(n, 6, layers, 2, seed=11)
     prob = Problem(c, omega, 6)
+    lu = spla.splu(prob.H.tocsc())
     f = media.point_sources(n, (n // 3,), n // 2)
-    ref = prob.restrict(spla.splu(prob.H.tocsc()).solve(prob.extend(f[0]).ravel())
-                        .reshape(prob.W, prob.W))
+    ref = prob.restrict(lu.solve(prob.extend(f[0]).ravel()).reshape(prob.W, prob.W))
     _log(f"[solve] tall cells n={n} L={layers}")
-    s = hz.Solver(torch.from_numpy(c), omega, 6, layers, 2)
+    xs = tuple(int(v) for v in np.linspace(2, n - 1, 16).round())
+    fb = media.point_sources(n, xs, n // 2 + 3)
+    s = hz.Solver(torch.from_numpy(c), omega, 6, layers, 2, max_batch=16)
     u = s.solve(torch.from_numpy(f), tol=1e-12).cpu().numpy()[0]
+    ub = s.solve(torch.from_numpy(fb), tol=1e-12).cpu().numpy()
     s.close()
     assert _rel(u, ref) < 1e-9
+    for b in (0, 7, 15):
+        rb = prob.restrict(lu.solve(prob.extend(fb[b]).ravel()).reshape(prob.W, prob.W))
+        assert _rel(ub[b], rb) < 1e-9
 
 
 def test_residual_kernel(setup):
