@@ -41,6 +41,15 @@ __device__ inline void epilogue(const GemmTask<T>& t, int i, int b, C2<T> acc) {
     }
 }
 
+// A load of an operator entry that is streamed once per launch, marked
+// nontemporal (it should not displace the cached input vector).
+template <typename T>
+__device__ __forceinline__ C2<T> gload_stream(const C2<T>* p) {
+    using V = T __attribute__((ext_vector_type(2)));
+    const V v = __builtin_nontemporal_load((const __attribute__((address_space(1))) V*)p);
+    return mk<T>(v.x, v.y);
+}
+
 // B == 1: each wave reduces one row at a time, lanes run along k.
 template <typename T>
 __global__ void __launch_bounds__(GV_THREADS) k_gemv(const GemmTask<T>* __restrict__ tasks) {
@@ -69,7 +78,7 @@ __global__ void __launch_bounds__(GV_THREADS) k_gemv(const GemmTask<T>* __restri
 #pragma unroll
                 for (int u = 0; u < GV_U; ++u) {
                     const bool in = kk + 64 * u < len;
-                    av[u] = in ? gload<T>(Ar + k0 + kk + 64 * u) : mk<T>((T)0, (T)0);
+                    av[u] = in ? gload_stream<T>(Ar + k0 + kk + 64 * u) : mk<T>((T)0, (T)0);
                     xv[u] = in ? gload<T>(xp + (long long)(kk + 64 * u) * ldx) : mk<T>((T)0, (T)0);
                 }
 #pragma unroll
