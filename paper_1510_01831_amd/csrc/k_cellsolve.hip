@@ -383,18 +383,44 @@ __global__ void __launch_bounds__(CS_THREADS) k_cs_gemv(CellSolveArgs<T> a) {
     const bool mine = q < HLp * NB;
     const C2<T> zero = mk<T>((T)0, (T)0);
     const int k0 = first_live_col<MODE>(cd, a.p);
+    // SOLVE_SAMPLE with one or two columns (the volume source of a layer,
+    // point sources): the iterates are zero before the first column that
+    // holds a source of this workgroup's columns, so the forward sweep
+    // starts there (Wc: none); the backward sweep still runs down to k0.
+    // (Wider batches are set by their chunk whose first source lies near
+    // the first column; for them the scan would only cost time.)
+    int kf = k0;
+    if constexpr (MODE == SOLVE_SAMPLE && NB <= 2) {
+        __shared__ int kfirst;
+        if (tid == 0) kfirst = Wc;
+        __syncthreads();
+        const int ncols = Wc - k0;
+        int km = Wc;
+        for (long long e = tid; e < (long long)HL * ncols * NB; e += CS_THREADS) {
+            const int c = (int)(e % NB);
+            const long long r = e / NB;
+            const int k = k0 + (int)(r % ncols), j = (int)(r / ncols);
+            if (k < km && bval(c)) {
+                const C2<T> v = cell_source<T, MODE>(a, cd, ld, k, j, b0 + c);
+                if (v.x != (T)0 || v.y != (T)0) km = k;
+            }
+        }
+        atomicMin(&kfirst, km);
+        __syncthreads();
+        kf = kfirst;
+    }
     // ---- forward sweep
-    for (int k = k0; k < Wc; ++k) {
+    for (int k = kf; k < Wc; ++k) {
         C2<T> src = zero, ek = zero;
         if (mine) {
             if (bval(qc)) src = cell_source<T, MODE>(a, cd, ld, k, qj, b0 + qc);
-            if (k > k0) ek = e_coef<T>(ee, k, qj, HL);
+            if (k > kf) ek = e_coef<T>(ee, k, qj, HL);
         }
-        if (k > k0) matvec(Xf + (long long)(k - 1) * np2);
+        if (k > kf) matvec(Xf + (long long)(k - 1) * np2);
         __syncthreads();
         if (mine) {
             C2<T> s = src;
-            if (k > k0) s = csub(s, cmul(ek, rowsum(qj, qc)));
+            if (k > kf) s = csub(s, cmul(ek, rowsum(qj, qc)));
             vs[q] = s;
             Y[(long long)k * HLp * NB + q] = s;
         }
@@ -408,7 +434,7 @@ __global__ void __launch_bounds__(CS_THREADS) k_cs_gemv(CellSolveArgs<T> a) {
             __syncthreads();
         }
         if (mine && k > k0) {
-            ynext = Y[(long long)(k - 1) * HLp * NB + q];
+            ynext = k - 1 >= kf ? Y[(long long)(k - 1) * HLp * NB + q] : zero;
             enext = e_coef<T>(ee, k, qj, HL);
         }
         matvec(Xf + (long long)k * np2);
@@ -424,8 +450,8 @@ __global__ void __launch_bounds__(CS_THREADS) k_cs_gemv(CellSolveArgs<T> a) {
 
 // ===========================================================================
 // NB in {16, 32}: block products on the matrix cores, NW waves per workgroup
-// (8; 10 for cells of 129-160 rows, so that each wave owns one of their ten
-// row tiles).  Wave w owns the 16-row tiles w and w + NW (MC of them, a
+// (8; 12 for cells of 129-160 rows, see below).  Wave w owns the 16-row
+// tiles w and w + NW (MC of them, a
 // per-wave constant chosen once by a wave-uniform switch).  The A operand (factor tile) streams
 // from global memory in MFMA order with a two-group register double buffer;
 // the B operand (current column block) is read from LDS.  The elementwise
