@@ -217,6 +217,9 @@ hz_status hz_factor(hz_ctx* ctx);
  * relative error of the refined volume solution (HZ_MIXED_REFINE).
  * max_iter: GMRES iterations per solve (also the Krylov dimension).
  * stats_host: B entries or NULL.  timing: or NULL.
+ * HZ_EINVAL (nothing launched, the context unchanged): a NULL rhs_dev or
+ * u_dev, B < 1 or B > max_batch, tol <= 0 or NaN, max_iter < 1.
+ * HZ_ESTATE: the context is not factored.
  * HZ_ENOCONV: u_dev holds the last iterate; stats say which RHS failed. */
 hz_status hz_solve(hz_ctx* ctx, const void* rhs_dev, int B, void* u_dev,
                    double tol, int max_iter, hz_rhs_stats* stats_host,

@@ -85,3 +85,27 @@ def test_ragged_batch_matches_single_solves(small):
     _log(f"[edge] ragged batch of 19: worst err vs direct {worst:.2e}")
     assert worst <= 1e-9
     s.close()
+
+
+def test_rejected_batch_sizes_leave_context_usable(small):
+    """An empty batch, a batch above max_batch and a non-positive tolerance
+    are rejected with HZ_EINVAL before any launch; the context then solves
+    as before."""
+    c, omega, prob, lu = small
+    f = media.point_sources(N, (10, 30), 20)
+    s = hz.Solver(torch.from_numpy(c), omega, P, L, LC, max_batch=2)
+    u0 = s.solve(torch.from_numpy(f), tol=1e-12).cpu().numpy()
+    for bad in (np.zeros((0, N, N), dtype=complex), media.point_sources(N, (10, 20, 30), 20)):
+        with pytest.raises(hz.HzError) as e:
+            s.solve(torch.from_numpy(bad), tol=1e-12)
+        assert e.value.status == hz.HZ_EINVAL
+        _log(f"[edge] batch of {bad.shape[0]} rejected: {e.value}")
+    with pytest.raises(hz.HzError) as e:
+        s.solve(torch.from_numpy(f), tol=0.0)
+    assert e.value.status == hz.HZ_EINVAL
+    u1 = s.solve(torch.from_numpy(f), tol=1e-12).cpu().numpy()
+    assert np.linalg.norm(u1 - u0) <= 1e-12 * np.linalg.norm(u0)
+    for b in range(2):
+        ref = _direct(prob, lu, f[b])
+        assert np.linalg.norm(u1[b] - ref) / np.linalg.norm(ref) <= 1e-9
+    s.close()
