@@ -2697,9 +2697,10 @@ void apply_PM(hz_ctx* c, const double2* x, double2* y, int B) {
     }
 }
 
-// P on FP64 vectors (used for the preconditioned right-hand side)
+// P on FP64 vectors (used for the preconditioned right-hand side); y2, where
+// given, receives the result too
 template <typename T>
-void apply_P(hz_ctx* c, const double2* x, double2* y, int B) {
+void apply_P(hz_ctx* c, const double2* x, double2* y, int B, double2* y2 = nullptr) {
     Work<T>& w = work<T>(c);
     const long long n = 4LL * c->d.K * c->d.W * B;
     Plan<T>& pp = get_plan<T>(c, false, B);
@@ -2711,8 +2712,9 @@ void apply_P(hz_ctx* c, const double2* x, double2* y, int B) {
     plan_run<T>(c, pp, B);
     if constexpr (sizeof(T) == sizeof(double)) {
         HIPCHK(hipMemcpyAsync(y, w.pC, sizeof(double2) * n, hipMemcpyDeviceToDevice, c->st));
+        if (y2) HIPCHK(hipMemcpyAsync(y2, w.pC, sizeof(double2) * n, hipMemcpyDeviceToDevice, c->st));
     } else {
-        launch_cast_f2d(y, (const float2*)w.pC, n, c->st);
+        launch_cast_f2d(y, (const float2*)w.pC, n, c->st, y2);
     }
 }
 
@@ -2849,10 +2851,21 @@ void gmres(hz_ctx* c, const double2* b, double2* x, int B, double tol, int maxit
         if (std::all_of(done.begin(), done.end(), [](int v) { return v != 0; })) break;
         double2* Vj = V + (long long)j * vs;
         double2* Vn = V + (long long)(j + 1) * vs;
+        // the new vector w: where the last plan of the product runs in FP64,
+        // its output buffer itself (overwritten only by the next product)
+        double2* wv = c->gw;
         if (flex) {
-            if (c->inner_pt) apply_P<double>(c, Vj, Z + (long long)j * vs, B);
-            else apply_P<float>(c, Vj, Z + (long long)j * vs, B);
-            apply_M64(c, Z + (long long)j * vs, c->gw, B);
+            // z_j = P v_j is also written into the SIE plan's input
+            double2* Zj = Z + (long long)j * vs;
+            if (c->inner_pt) apply_P<double>(c, Vj, Zj, B, c->w64.pA);
+            else apply_P<float>(c, Vj, Zj, B, c->w64.pA);
+            plan_run<double>(c, get_plan<double>(c, true, B), B);
+            wv = c->w64.pB;
+        } else if constexpr (sizeof(T) == sizeof(double)) {
+            HIPCHK(hipMemcpyAsync(c->w64.pA, Vj, sizeof(double2) * nB, hipMemcpyDeviceToDevice, c->st));
+            plan_run<double>(c, get_plan<double>(c, true, B), B);
+            plan_run<double>(c, get_plan<double>(c, false, B), B);
+            wv = c->w64.pC;
         } else {
             apply_PM<T>(c, Vj, c->gw, B);
         }
@@ -2862,12 +2875,12 @@ void gmres(hz_ctx* c, const double2* b, double2* x, int B, double tol, int maxit
         double2* hA = c->gh;
         double2* hB = c->gh + nh;
         double2* hN = c->gh + 2 * nh;
-        dots_dev(c, V, vs, j + 1, c->gw, n, B, hA);
-        update_dots_dev(c, V, vs, j + 1, hA, c->gw, n, B, 0, hB, c->gpart, c->gpart_chunks);
-        update_dots_dev(c, V, vs, j + 1, hB, c->gw, n, B, 1, hN, c->gpart, c->gpart_chunks);
+        dots_dev(c, V, vs, j + 1, wv, n, B, hA);
+        update_dots_dev(c, V, vs, j + 1, hA, wv, n, B, 0, hB, c->gpart, c->gpart_chunks);
+        update_dots_dev(c, V, vs, j + 1, hB, wv, n, B, 1, hN, c->gpart, c->gpart_chunks);
         // next basis vector scaled on the device (columns that have converged
         // keep being normalised; their coefficients beyond convergence are 0)
-        launch_scale_cols_inv_norm(Vn, nullptr, c->gw, hN, n, B, c->st);
+        launch_scale_cols_inv_norm(Vn, nullptr, wv, hN, n, B, c->st);
         double2* hh = pinned(c, 2 * nh + B);
         HIPCHK(hipMemcpyAsync(hh, c->gh, sizeof(double2) * (2 * nh + B), hipMemcpyDeviceToHost,
                               c->st));

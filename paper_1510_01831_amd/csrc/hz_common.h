@@ -366,7 +366,8 @@ inline int cs_nb(int B, int ncells, int hlp, int elem) {
 template <typename T>
 void launch_axpby(C2<T>* y, const C2<T>* x, double2 a, double2 b, long long n, hipStream_t st);
 void launch_cast_d2f(float2* y, const double2* x, long long n, hipStream_t st);
-void launch_cast_f2d(double2* y, const float2* x, long long n, hipStream_t st);
+void launch_cast_f2d(double2* y, const float2* x, long long n, hipStream_t st,
+                     double2* y2 = nullptr);
 void launch_dots(const double2* V, long long vstride, int nv, const double2* w, long long n,
                  int B, double2* partial, int nchunks, hipStream_t st);
 void launch_reduce_partials(const double2* partial, int nchunks, int count, double2* out,

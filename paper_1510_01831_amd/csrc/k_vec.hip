@@ -147,11 +147,15 @@ __global__ void k_cast_d2f(float2* y, const double2* x, long long n) {
         y[i] = make_float2((float)v.x, (float)v.y);
     }
 }
-__global__ void k_cast_f2d(double2* y, const float2* x, long long n) {
+// y = x widened to FP64; also into y2 where given (one read of x for two
+// destinations)
+__global__ void k_cast_f2d(double2* y, double2* y2, const float2* x, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
         float2 v = x[i];
-        y[i] = make_double2((double)v.x, (double)v.y);
+        const double2 d = make_double2((double)v.x, (double)v.y);
+        y[i] = d;
+        if (y2) y2[i] = d;
     }
 }
 void launch_cast_d2f(float2* y, const double2* x, long long n, hipStream_t st) {
@@ -159,10 +163,10 @@ void launch_cast_d2f(float2* y, const double2* x, long long n, hipStream_t st) {
     int blocks = (int)std::min<long long>((n + 255) / 256, 8192);
     hipLaunchKernelGGL(k_cast_d2f, dim3(blocks), dim3(256), 0, st, y, x, n);
 }
-void launch_cast_f2d(double2* y, const float2* x, long long n, hipStream_t st) {
+void launch_cast_f2d(double2* y, const float2* x, long long n, hipStream_t st, double2* y2) {
     if (n <= 0) return;
     int blocks = (int)std::min<long long>((n + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_cast_f2d, dim3(blocks), dim3(256), 0, st, y, x, n);
+    hipLaunchKernelGGL(k_cast_f2d, dim3(blocks), dim3(256), 0, st, y, y2, x, n);
 }
 
 __global__ void k_conj_copy(double2* y, const double2* x, long long n) {
