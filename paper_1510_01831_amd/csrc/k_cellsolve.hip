@@ -297,6 +297,12 @@ __device__ inline int first_live_col(const CellDesc& cd, int p) {
 // ===========================================================================
 // NB <= 4: lanes run along the tile's 4 columns, each lane owning one row of
 // a 16-row tile; the 4 partial sums of a row are combined with two shuffles.
+#ifndef CS_GV_UL4
+#define CS_GV_UL4 4
+#endif
+#ifndef CS_GV_UL1
+#define CS_GV_UL1 10
+#endif
 template <typename T, int NB, int MODE>
 __global__ void __launch_bounds__(CS_THREADS) k_cs_gemv(CellSolveArgs<T> a) {
     // A step's matrix-vector product reads a whole HLp x HLp factor block
@@ -339,24 +345,24 @@ __global__ void __launch_bounds__(CS_THREADS) k_cs_gemv(CellSolveArgs<T> a) {
 #pragma unroll
             for (int c = 0; c < NB; ++c) acc[c] = mk<T>((T)0, (T)0);
             const C2<T>* base = Xk + ((long long)R * KS << 6) + lane;
-            constexpr int UL = NB >= 4 ? 4 : 8;     // loads in flight per lane
-            int s = s0;
-            for (; s + UL <= s1; s += UL) {
+            // loads in flight per lane; a last partial group re-reads its
+            // final quad for the missing ones (same cache line) and zeroes
+            // them, so it is issued as one group too (no branch between the
+            // loads and their products)
+            constexpr int UL = NB >= 4 ? CS_GV_UL4 : CS_GV_UL1;
+            for (int s = s0; s < s1; s += UL) {
                 C2<T> x[UL];
 #pragma unroll
-                for (int u = 0; u < UL; ++u) x[u] = gload<T>(base + ((long long)(s + u) << 6));
+                for (int u = 0; u < UL; ++u)
+                    x[u] = gload<T>(base + ((long long)min(s + u, s1 - 1) << 6));
 #pragma unroll
                 for (int u = 0; u < UL; ++u) {
-                    const int cc = 4 * (s + u) + (lane >> 4);
+                    const bool live = s + u < s1;
+                    const int cc = 4 * min(s + u, s1 - 1) + (lane >> 4);
+                    const C2<T> xv = mk<T>(live ? x[u].x : (T)0, live ? x[u].y : (T)0);
 #pragma unroll
-                    for (int c = 0; c < NB; ++c) acc[c] = cfma(x[u], vs[cc * NB + c], acc[c]);
+                    for (int c = 0; c < NB; ++c) acc[c] = cfma(xv, vs[cc * NB + c], acc[c]);
                 }
-            }
-            for (; s < s1; ++s) {
-                const C2<T> x = gload<T>(base + ((long long)s << 6));
-                const int cc = 4 * s + (lane >> 4);
-#pragma unroll
-                for (int c = 0; c < NB; ++c) acc[c] = cfma(x, vs[cc * NB + c], acc[c]);
             }
 #pragma unroll
             for (int c = 0; c < NB; ++c) {
